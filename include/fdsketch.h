@@ -1,0 +1,151 @@
+/*
+ * fdsketch.h -- C ABI of libfdsketch.so: the Frequent Directions family of
+ * row-streaming matrix sketches on one MI355X (gfx950) GPU.
+ *
+ * Problem (Section 1.1 of Desai, Ghashami, Phillips, "Improved Practical
+ * Matrix Sketching with Guarantees"): rows a_i in R^d of an n x d matrix A
+ * arrive as a stream; keep an l x d matrix B such that the covariance error
+ * ||A^T A - B^T B||_2 / ||A||_F^2 is small.  The sketch follows the generic
+ * iterative scheme of Section 2.3 (Algorithm 1): rows fill free rows of an
+ * m-row buffer; when it is full the buffer is factored, its singular values
+ * are changed by a ReduceRank rule and the buffer is rebuilt as S'V^T.
+ *
+ * Rules (sigma_1 >= sigma_2 >= ... the buffer's singular values):
+ *   FDSK_FD          delta = sigma_l^2, every sigma'^2 = max(sigma^2 - delta, 0)
+ *                    (Section 2.3, Frequent Directions / its fast variant).
+ *   FDSK_ISVD        keep sigma_1..sigma_{l-1}, zero the rest (Section 2.3).
+ *   FDSK_ALPHA       Algorithm 2 (Section 3.1): the leading l - ceil(alpha*l)
+ *                    values untouched, the rest shrunk by delta = sigma_l^2.
+ *   FDSK_FAST_ALPHA  Section 3.1, fast parameterized FD: delta = sigma_t^2 with
+ *                    t = r + ceil(s/2), s = ceil(alpha*l), r = l - s; the
+ *                    trailing s values are shrunk, clamped at zero.
+ * Shrunk values are clamped at 0; after a reduction the first t-1 rows are
+ * kept (t = l except for the fast variant) and the next rows go after them.
+ *
+ * Conventions for every entry point:
+ *  - Return 0 on success or a negative FDSK_E* code.  Errors are sticky per
+ *    sketch; the message is available from sketch_last_error().  Nothing
+ *    throws across the ABI.  A sketch is not thread-safe; distinct sketches
+ *    are independent.
+ *  - hip_stream is a hipStream_t (NULL = the default stream).  Every device
+ *    pointer passed in is read in stream order on that stream; the caller
+ *    must not overwrite it until the stream passes the call.  Host pointers
+ *    are consumed before the call returns.
+ *  - Row-major matrices: element (i, j) of a matrix with leading dimension
+ *    ld (in elements) is at p[i*ld + j].
+ *  - The library owns all sketch state (buffers, Gram/eigen workspaces, FP64
+ *    accumulators); it is allocated in *_create and freed in *_destroy.
+ */
+#ifndef FDSKETCH_H
+#define FDSKETCH_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct fdsk_sketch fdsk_sketch;           /* opaque */
+
+typedef enum { FDSK_FD = 0, FDSK_ISVD = 1, FDSK_ALPHA = 2, FDSK_FAST_ALPHA = 3 } fdsk_variant;
+typedef enum { FDSK_F64 = 0, FDSK_F32 = 1, FDSK_BF16 = 2 } fdsk_dtype;  /* BF16 = raw uint16 bits */
+/* Arithmetic of the Gram and rebuild products.  The eigensolver, the shrink
+ * subtraction and every accumulator are FP64 in all modes. */
+typedef enum { FDSK_P_FP64 = 0, FDSK_P_BF16 = 1, FDSK_P_BF16X3 = 2 } fdsk_precision;
+typedef enum { FDSK_MEM_HOST = 0, FDSK_MEM_DEVICE = 1 } fdsk_mem;
+
+enum {
+  FDSK_OK = 0,
+  FDSK_EINVAL = -1,       /* bad argument or configuration */
+  FDSK_ESTATE = -2,       /* call not allowed in the sketch's state (e.g. append after finalize) */
+  FDSK_ENOMEM = -3,       /* device allocation failed */
+  FDSK_EDEVICE = -4,      /* a HIP call failed or a kernel reported a fault */
+  FDSK_ENONFINITE = -5,   /* NaN/Inf reached the sketch */
+  FDSK_EUNSUPPORTED = -6  /* size or dtype/precision combination not supported */
+};
+
+typedef struct {
+  int64_t d;              /* row length, >= 1 */
+  int32_t l;              /* sketch rows, >= 1 */
+  int32_t buffer_rows;    /* m: 0 -> 2l; l -> Algorithm 1 literally; any m in [l, 1024] */
+  fdsk_variant variant;
+  double alpha;           /* (0, 1]; used by FDSK_ALPHA and FDSK_FAST_ALPHA */
+  fdsk_precision precision;
+  uint32_t flags;         /* reserved, must be 0 */
+} fdsk_config;
+
+typedef struct {
+  double cov_err;             /* ||A^T A - B^T B||_2 / ||A||_F^2            (Section 1.1) */
+  double proj_err_k;          /* ||A - pi_{B_k}(A)||_F^2 / ||A - A_k||_F^2   (Section 1.1) */
+  double proj_full_over_fro2; /* ||A - pi_B(A)||_F^2 / ||A||_F^2 */
+  double fro2_A;              /* ||A||_F^2 (FP64 accumulation) */
+  double fro2_B;              /* ||B||_F^2 */
+  double delta_sum;           /* Delta = sum of delta_i (Section 3.1) */
+  double shrink_total;        /* total squared mass removed by the rules */
+  double lambda_max;          /* largest eigenvalue of A^T A - B^T B */
+  double lambda_min;          /* smallest eigenvalue of A^T A - B^T B */
+  int64_t n_rows;             /* rows appended */
+  int64_t n_reduce;           /* ReduceRank steps run */
+  int32_t k;                  /* rank used by proj_err_k */
+  int32_t rows_out;           /* rows of the sketch that may be nonzero */
+  int32_t eig_unconverged;    /* eigensolves that hit their sweep cap */
+  int32_t reserved;
+} fdsk_report;
+
+/* Create a sketch (Algorithm 1 state, all rows free).  hip_stream is kept and
+ * used by every later call on this sketch.  Sizes: 1 <= l, l <= m <= 1024,
+ * d <= 65536.  Errors: EINVAL, EUNSUPPORTED, ENOMEM, EDEVICE. */
+int sketch_create(const fdsk_config* cfg, void* hip_stream, fdsk_sketch** out);
+
+/* Append n_rows rows (Algorithm 1, "insert a_i into a zero valued row"); runs
+ * every ReduceRank the schedule calls for, asynchronously on the stream.
+ * rows: n_rows x d, leading dimension row_stride (elements, >= d), in the
+ * given dtype, on the host or on the device.  n_rows = 0 is a no-op.
+ * Errors: EINVAL, ESTATE (after finalize), EDEVICE, ENOMEM. */
+int sketch_append_rows(fdsk_sketch* s, const void* rows, int64_t n_rows, int64_t row_stride,
+                       fdsk_dtype dtype, fdsk_mem mem);
+
+/* Finish the stream: if more than l rows are occupied, one more ReduceRank;
+ * then write the l x d sketch B (rows beyond *rows_out are zero) to B_out
+ * (leading dimension ldb >= d, dtype FDSK_F64 or FDSK_F32).  Synchronises the
+ * stream and reports sticky device errors.  Afterwards only sketch_stats,
+ * sketch_error, sketch_last_error and sketch_destroy are allowed.
+ * Errors: EINVAL, ESTATE (twice), EDEVICE, ENONFINITE. */
+int sketch_finalize(fdsk_sketch* s, void* B_out, int64_t ldb, fdsk_dtype out_dtype, fdsk_mem mem,
+                    int32_t* rows_out);
+
+/* Error measures of Section 1.1 for the finalized sketch against A (n x d,
+ * leading dimension lda): cov-err, proj-err with rank k (the experiments use
+ * k = 10) and ||A - pi_B(A)||_F^2/||A||_F^2.  method 0: dense d x d A^T A in
+ * FP64 on the device (d <= 8192); method 1: matrix-free (each Lanczos step
+ * streams A twice).  cov-err is undefined for ||A||_F = 0 -> EINVAL.
+ * Fills *out (also the fields of sketch_stats).  Synchronises the stream. */
+int sketch_error(fdsk_sketch* s, const void* A, int64_t n, int64_t lda, fdsk_dtype dtype,
+                 fdsk_mem mem, int32_t k, int32_t method, fdsk_report* out);
+
+/* Evaluate the same error measures for an arbitrary B (rows_b x d, ldb)
+ * against A, without a sketch object.  Device or host pointers (same mem for
+ * both).  Used to score any sketch with the device evaluator. */
+int fdsk_evaluate(const void* A, int64_t n, int64_t lda, fdsk_dtype a_dtype,
+                  const void* B, int64_t rows_b, int64_t ldb, fdsk_dtype b_dtype,
+                  int64_t d, fdsk_mem mem, int32_t k, int32_t method, void* hip_stream,
+                  fdsk_report* out);
+
+/* Accumulators so far (||A||_F^2, Delta, shrink total, rows, reductions).
+ * Synchronises the stream. */
+int sketch_stats(const fdsk_sketch* s, fdsk_report* out);
+
+/* Free everything the sketch owns (waits for its stream first). NULL is ok. */
+void sketch_destroy(fdsk_sketch* s);
+
+/* Message of the last error on this sketch ("" if none); valid until the
+ * next call on it.  s == NULL gives the last create/evaluate failure. */
+const char* sketch_last_error(const fdsk_sketch* s);
+
+/* Library build information (static string). */
+const char* fdsk_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FDSKETCH_H */

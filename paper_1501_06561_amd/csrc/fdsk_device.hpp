@@ -1,0 +1,99 @@
+// Device-side helpers shared by the FD-family kernels (gfx950 / CDNA4).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef short bf16x8 __attribute__((ext_vector_type(8)));
+
+namespace fdsk {
+
+// Row dtypes accepted at the boundary (mirrors fdsk_dtype in fdsketch.h).
+enum { DT_F64 = 0, DT_F32 = 1, DT_BF16 = 2 };
+
+__device__ __forceinline__ double load_as_f64(const void* p, int64_t i, int dt) {
+  if (dt == DT_F64) return static_cast<const double*>(p)[i];
+  if (dt == DT_F32) return static_cast<double>(static_cast<const float*>(p)[i]);
+  uint32_t b = static_cast<uint32_t>(static_cast<const uint16_t*>(p)[i]) << 16;
+  return static_cast<double>(__uint_as_float(b));
+}
+
+// Round-to-nearest-even float -> bfloat16 bits.
+__device__ __forceinline__ uint16_t f32_to_bf16_bits(float x) {
+  uint32_t u = __float_as_uint(x);
+  if ((u & 0x7fffffffu) > 0x7f800000u) return 0x7fc0;  // NaN
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return static_cast<uint16_t>(u >> 16);
+}
+__device__ __forceinline__ float bf16_bits_to_f32(uint16_t b) {
+  return __uint_as_float(static_cast<uint32_t>(b) << 16);
+}
+
+// Wave-wide (64 lanes) sum.
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// 16x16x4 FP64 matrix-core step: D(16x16) += A(16x4) * B(4x16).
+// Lane layout (wave64): lane = i + 16*k holds A[i][k] and B[k][i];
+// the result lane = j + 16*q holds D[4q + v][j] in element v.
+__device__ __forceinline__ f64x4 mfma_f64(double a, double b, f64x4 c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+// Grid-wide barrier for a cooperatively launched grid.  Generation counter
+// scheme: counters return to zero at every completed barrier, so the pair can
+// be reused by later launches without a reset.  The spin is bounded: on
+// timeout an error bit is set and the wave proceeds, so the grid always drains.
+struct GridBar {
+  unsigned* count;
+  unsigned* gen;
+  int* err;
+};
+
+__device__ __forceinline__ void grid_barrier(const GridBar& b, unsigned nblocks) {
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned g = __hip_atomic_load(b.gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+    unsigned arrived = __hip_atomic_fetch_add(b.count, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+    if (arrived == nblocks - 1) {
+      __hip_atomic_store(b.count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_fetch_add(b.gen, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    } else {
+      // Once any barrier has timed out every later one falls through at once.
+      long spins = 0;
+      while (__hip_atomic_load(b.gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == g) {
+        __builtin_amdgcn_s_sleep(1);
+        if ((++spins & 1023) == 0 &&
+            __hip_atomic_load(b.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0)
+          break;
+        if (spins > (1L << 25)) {
+          __hip_atomic_fetch_or(b.err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          break;
+        }
+      }
+    }
+  }
+  __syncthreads();
+  __threadfence();
+}
+
+// Stable Jacobi rotation (Rutishauser) annihilating the (p,q) entry of the
+// symmetric 2x2 [[app, apq], [apq, aqq]]:  J = [[c, s], [-s, c]], and
+// J^T [[app, apq],[apq, aqq]] J is diagonal.
+__device__ __forceinline__ void jacobi_rotation(double app, double aqq, double apq,
+                                                double& c, double& s) {
+  if (apq == 0.0) { c = 1.0; s = 0.0; return; }
+  double theta = (aqq - app) / (2.0 * apq);
+  double t = 1.0 / (fabs(theta) + sqrt(1.0 + theta * theta));
+  if (theta < 0.0) t = -t;
+  c = 1.0 / sqrt(1.0 + t * t);
+  s = t * c;
+}
+
+}  // namespace fdsk

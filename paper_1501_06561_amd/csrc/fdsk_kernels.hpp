@@ -1,0 +1,61 @@
+// Host-visible declarations of the device kernels' launchers and the small
+// structs shared between the host runtime and the kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <algorithm>
+
+namespace fdsk {
+
+// FP64 accumulators kept on the device (updated in stream order, no host sync).
+struct DevStats {
+  double fro2A;      // ||A||_F^2 of every appended row
+  double Delta;      // sum of delta_i
+  double Stot;       // squared mass removed by the ReduceRank rules
+  long long n_rr;    // ReduceRank steps
+  int nonfinite;     // a NaN/Inf reached the accumulators or the spectrum
+  int bar_err;       // a grid barrier timed out
+  int eig_unconv;    // eigensolves that hit their sweep cap
+  int pad;
+};
+
+// ReduceRank rule: delta = lambda_t (1-based t); indices < r are untouched;
+// variant 1 (iSVD) keeps the first l-1 and zeroes the rest; keep = t-1 rows survive.
+struct RuleParams {
+  int variant;
+  int l;
+  int t;
+  int r;
+  int keep;
+};
+
+hipError_t launch_ingest(const void* src, int dt, int64_t stride, int f, int d, double* C, int ldc,
+                         int row0, double* rownorm, hipStream_t s);
+hipError_t launch_gram(const double* C, int ldc, int mp, double* Gpart, int ksplit_max, double* G,
+                       hipStream_t s);
+hipError_t launch_shrink(const double* lam, const double* V, int m, int mp, RuleParams rp,
+                         const double* rownorm, int new0, int new1, double* Ut, DevStats* st,
+                         hipStream_t s);
+hipError_t launch_rebuild(const double* Ut, const double* C, int ldc, int mp, int keep, double* out,
+                          hipStream_t s);
+hipError_t launch_zero_rows(double* C, int ldc, int r0, int r1, hipStream_t s);
+hipError_t launch_add_pending_norms(const double* rownorm, int new0, int new1, DevStats* st,
+                                    hipStream_t s);
+hipError_t launch_copy_out(const double* C, int ldc, int valid_rows, int l, int d, void* out,
+                           int64_t ldb, int out_dt, hipStream_t s);
+
+// Symmetric eigensolver for the m x m Gram matrix (G is mp x mp, zero padded).
+// Output: lam[j] (j < m) and V column-major (column j = eigenvector j, ld mp,
+// entries of rows >= m zero).  ws: workspace of eig_workspace_doubles(mp).
+struct EigWork {
+  double* W;        // mp x mp
+  unsigned* bar;    // 2 counters (grid barrier)
+  int* rot;         // per-sweep rotation counts (kMaxSweeps)
+  DevStats* st;
+};
+constexpr int kMaxSweeps = 40;
+constexpr int kLdsEigMax = 100;   // single-workgroup solver limit (G and V in LDS)
+hipError_t launch_eig(const double* G, int m, int mp, double* lam, double* V, EigWork wk,
+                      hipStream_t s);
+
+}  // namespace fdsk

@@ -1,0 +1,348 @@
+// Host runtime and C ABI of libfdsketch.so (see include/fdsketch.h).
+//
+// A sketch owns an m-row FP64 buffer on the device (double-buffered for the
+// rebuild), the Gram / eigen / rebuild workspaces and FP64 accumulators.  The
+// schedule of Algorithm 1 is data independent (rows go after the first t-1
+// surviving rows; a ReduceRank runs when all m rows are occupied), so the host
+// plans every launch without reading anything back: ingest, Gram, eigensolve,
+// shrink and rebuild are enqueued on the sketch's stream in order and the
+// host only synchronises in finalize / stats / error.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+
+#include "fdsk_kernels.hpp"
+#include "fdsk_eval.hpp"
+#include "fdsketch.h"
+
+using namespace fdsk;
+
+struct fdsk_sketch {
+  fdsk_config cfg;
+  int d = 0, l = 0, m = 0, mp = 0, ldc = 0;
+  RuleParams rp{};
+  hipStream_t stream = nullptr;
+  void* arena = nullptr;
+  double* C[2] = {nullptr, nullptr};
+  int cur = 0;
+  double *G = nullptr, *Gpart = nullptr, *W = nullptr, *V = nullptr, *lam = nullptr,
+         *Ut = nullptr, *rownorm = nullptr;
+  int ksplit_max = 1;
+  DevStats* st = nullptr;
+  unsigned* bar = nullptr;
+  int* rot = nullptr;
+  void* stage = nullptr;
+  size_t stage_bytes = 0;
+  int occ = 0;      // occupied rows
+  int new0 = 0;     // first row appended since the last ReduceRank
+  int64_t n_rows = 0;
+  int64_t n_rr_host = 0;
+  bool finalized = false;
+  int rows_out = 0;
+  int err = 0;
+  std::string msg;
+};
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int set_err(fdsk_sketch* s, int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  if (s) {
+    s->err = code;
+    s->msg = buf;
+  } else {
+    g_last_error = buf;
+  }
+  return code;
+}
+
+#define HIPCHK(s, expr)                                                                    \
+  do {                                                                                     \
+    hipError_t e_ = (expr);                                                                \
+    if (e_ != hipSuccess)                                                                  \
+      return set_err((s), FDSK_EDEVICE, "%s failed: %s", #expr, hipGetErrorString(e_));   \
+  } while (0)
+
+size_t dtype_size(fdsk_dtype dt) {
+  switch (dt) {
+    case FDSK_F64: return 8;
+    case FDSK_F32: return 4;
+    case FDSK_BF16: return 2;
+  }
+  return 0;
+}
+
+int round_up(int x, int a) { return (x + a - 1) / a * a; }
+
+RuleParams make_rule(const fdsk_config& c) {
+  RuleParams rp{};
+  rp.variant = static_cast<int>(c.variant);
+  rp.l = c.l;
+  int s = static_cast<int>(std::ceil(c.alpha * c.l * (1.0 - 1e-12)));
+  s = std::min(std::max(s, 1), c.l);
+  int r = c.l - s;
+  switch (c.variant) {
+    case FDSK_FD: rp.t = c.l; rp.r = 0; break;
+    case FDSK_ISVD: rp.t = c.l; rp.r = c.l - 1; break;
+    case FDSK_ALPHA: rp.t = c.l; rp.r = r; break;
+    case FDSK_FAST_ALPHA: rp.t = r + (s + 1) / 2; rp.r = r; break;
+  }
+  rp.keep = rp.t - 1;
+  return rp;
+}
+
+int reduce(fdsk_sketch* s) {
+  EigWork wk{s->W, s->bar, s->rot, s->st};
+  HIPCHK(s, launch_gram(s->C[s->cur], s->ldc, s->mp, s->Gpart, s->ksplit_max, s->G, s->stream));
+  HIPCHK(s, launch_eig(s->G, s->m, s->mp, s->lam, s->V, wk, s->stream));
+  HIPCHK(s, launch_shrink(s->lam, s->V, s->m, s->mp, s->rp, s->rownorm, s->new0, s->occ, s->Ut,
+                          s->st, s->stream));
+  HIPCHK(s, launch_rebuild(s->Ut, s->C[s->cur], s->ldc, s->mp, s->rp.keep, s->C[1 - s->cur],
+                           s->stream));
+  s->cur = 1 - s->cur;
+  s->occ = s->rp.keep;
+  s->new0 = s->occ;
+  s->n_rr_host += 1;
+  return 0;
+}
+
+int ingest_device(fdsk_sketch* s, const char* src, int64_t n, int64_t stride, fdsk_dtype dt) {
+  const size_t es = dtype_size(dt);
+  int64_t i = 0;
+  while (i < n) {
+    int f = static_cast<int>(std::min<int64_t>(s->m - s->occ, n - i));
+    HIPCHK(s, launch_ingest(src + i * stride * es, static_cast<int>(dt), stride, f, s->d,
+                            s->C[s->cur], s->ldc, s->occ, s->rownorm, s->stream));
+    s->occ += f;
+    i += f;
+    s->n_rows += f;
+    if (s->occ == s->m) {
+      int rc = reduce(s);
+      if (rc) return rc;
+    }
+  }
+  return 0;
+}
+
+int check_device_flags(fdsk_sketch* s) {
+  DevStats h{};
+  HIPCHK(s, hipMemcpyAsync(&h, s->st, sizeof h, hipMemcpyDeviceToHost, s->stream));
+  HIPCHK(s, hipStreamSynchronize(s->stream));
+  if (h.bar_err) return set_err(s, FDSK_EDEVICE, "grid barrier timed out in the eigensolver");
+  if (h.nonfinite) return set_err(s, FDSK_ENONFINITE, "a NaN or Inf reached the sketch");
+  return 0;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* fdsk_version(void) { return "fdsketch 0.1 (gfx950, FP64 Gram + Jacobi path)"; }
+
+const char* sketch_last_error(const fdsk_sketch* s) {
+  if (!s) return g_last_error.c_str();
+  return s->msg.c_str();
+}
+
+int sketch_create(const fdsk_config* cfg, void* hip_stream, fdsk_sketch** out) {
+  if (!cfg || !out) return set_err(nullptr, FDSK_EINVAL, "null argument");
+  *out = nullptr;
+  const fdsk_config& c = *cfg;
+  if (c.d < 1 || c.d > 65536) return set_err(nullptr, FDSK_EINVAL, "d must be in [1, 65536]");
+  if (c.l < 1) return set_err(nullptr, FDSK_EINVAL, "l must be >= 1");
+  int m = c.buffer_rows == 0 ? 2 * c.l : c.buffer_rows;
+  if (m < c.l) return set_err(nullptr, FDSK_EINVAL, "buffer_rows must be 0 or >= l");
+  if (m > 1024) return set_err(nullptr, FDSK_EUNSUPPORTED, "buffer rows %d > 1024", m);
+  if (c.variant < FDSK_FD || c.variant > FDSK_FAST_ALPHA)
+    return set_err(nullptr, FDSK_EINVAL, "unknown variant");
+  if ((c.variant == FDSK_ALPHA || c.variant == FDSK_FAST_ALPHA) && !(c.alpha > 0.0 && c.alpha <= 1.0))
+    return set_err(nullptr, FDSK_EINVAL, "alpha must lie in (0, 1]");
+  if (c.precision != FDSK_P_FP64)
+    return set_err(nullptr, FDSK_EUNSUPPORTED, "precision %d not available", (int)c.precision);
+  if (c.flags != 0) return set_err(nullptr, FDSK_EINVAL, "flags must be 0");
+
+  fdsk_sketch* s = new fdsk_sketch;
+  s->cfg = c;
+  s->d = static_cast<int>(c.d);
+  s->l = c.l;
+  s->m = m;
+  s->mp = round_up(m, 32);
+  s->ldc = round_up(s->d, 64);
+  s->rp = make_rule(c);
+  s->stream = static_cast<hipStream_t>(hip_stream);
+  const int T = s->mp / 32;
+  const int ntiles = T * (T + 1) / 2;
+  s->ksplit_max = std::max(1, std::min({(256 + ntiles - 1) / ntiles, s->ldc / 256, 16}));
+
+  const size_t mp2 = static_cast<size_t>(s->mp) * s->mp;
+  const size_t cbuf = static_cast<size_t>(s->mp) * s->ldc;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    size_t o = off;
+    off += (bytes + 255) / 256 * 256;
+    return o;
+  };
+  size_t oC0 = take(cbuf * 8), oC1 = take(cbuf * 8), oG = take(mp2 * 8),
+         oGp = take(mp2 * 8 * s->ksplit_max), oW = take(mp2 * 8), oV = take(mp2 * 8),
+         oUt = take(mp2 * 8), oLam = take(s->mp * 8), oRn = take(s->mp * 8),
+         oSt = take(sizeof(DevStats)), oBar = take(4 * sizeof(unsigned)),
+         oRot = take(kMaxSweeps * sizeof(int));
+  hipError_t e = hipMalloc(&s->arena, off);
+  if (e != hipSuccess) {
+    delete s;
+    return set_err(nullptr, FDSK_ENOMEM, "hipMalloc(%zu) failed: %s", off, hipGetErrorString(e));
+  }
+  char* a = static_cast<char*>(s->arena);
+  s->C[0] = reinterpret_cast<double*>(a + oC0);
+  s->C[1] = reinterpret_cast<double*>(a + oC1);
+  s->G = reinterpret_cast<double*>(a + oG);
+  s->Gpart = reinterpret_cast<double*>(a + oGp);
+  s->W = reinterpret_cast<double*>(a + oW);
+  s->V = reinterpret_cast<double*>(a + oV);
+  s->Ut = reinterpret_cast<double*>(a + oUt);
+  s->lam = reinterpret_cast<double*>(a + oLam);
+  s->rownorm = reinterpret_cast<double*>(a + oRn);
+  s->st = reinterpret_cast<DevStats*>(a + oSt);
+  s->bar = reinterpret_cast<unsigned*>(a + oBar);
+  s->rot = reinterpret_cast<int*>(a + oRot);
+  e = hipMemsetAsync(s->arena, 0, off, s->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+  if (e != hipSuccess) {
+    (void)hipFree(s->arena);
+    delete s;
+    return set_err(nullptr, FDSK_EDEVICE, "initialising sketch memory failed: %s",
+                   hipGetErrorString(e));
+  }
+  *out = s;
+  return 0;
+}
+
+int sketch_append_rows(fdsk_sketch* s, const void* rows, int64_t n_rows, int64_t row_stride,
+                       fdsk_dtype dtype, fdsk_mem mem) {
+  if (!s) return set_err(nullptr, FDSK_EINVAL, "null sketch");
+  if (s->err) return s->err;
+  if (s->finalized) return set_err(s, FDSK_ESTATE, "append after finalize");
+  if (n_rows < 0) return set_err(s, FDSK_EINVAL, "n_rows < 0");
+  if (n_rows == 0) return 0;
+  if (!rows) return set_err(s, FDSK_EINVAL, "null rows");
+  if (dtype_size(dtype) == 0) return set_err(s, FDSK_EINVAL, "bad dtype");
+  if (row_stride < s->d) return set_err(s, FDSK_EINVAL, "row_stride < d");
+  if (mem == FDSK_MEM_DEVICE)
+    return ingest_device(s, static_cast<const char*>(rows), n_rows, row_stride, dtype);
+  if (mem != FDSK_MEM_HOST) return set_err(s, FDSK_EINVAL, "bad mem kind");
+  // Host rows: staged through a device buffer, chunk by chunk.
+  const size_t es = dtype_size(dtype);
+  const size_t row_bytes = static_cast<size_t>(s->d) * es;
+  int64_t chunk = std::max<int64_t>(1, std::min<int64_t>(n_rows, (64 << 20) / row_bytes));
+  if (s->stage_bytes < chunk * row_bytes) {
+    HIPCHK(s, hipStreamSynchronize(s->stream));
+    if (s->stage) HIPCHK(s, hipFree(s->stage));
+    s->stage = nullptr;
+    s->stage_bytes = 0;
+    hipError_t e = hipMalloc(&s->stage, chunk * row_bytes);
+    if (e != hipSuccess) return set_err(s, FDSK_ENOMEM, "staging buffer: %s", hipGetErrorString(e));
+    s->stage_bytes = chunk * row_bytes;
+  }
+  const char* h = static_cast<const char*>(rows);
+  for (int64_t i = 0; i < n_rows; i += chunk) {
+    int64_t c = std::min(chunk, n_rows - i);
+    HIPCHK(s, hipMemcpy2DAsync(s->stage, row_bytes, h + i * row_stride * es, row_stride * es,
+                               row_bytes, c, hipMemcpyHostToDevice, s->stream));
+    int rc = ingest_device(s, static_cast<const char*>(s->stage), c, s->d, dtype);
+    if (rc) return rc;
+  }
+  HIPCHK(s, hipStreamSynchronize(s->stream));
+  return 0;
+}
+
+int sketch_finalize(fdsk_sketch* s, void* B_out, int64_t ldb, fdsk_dtype out_dtype, fdsk_mem mem,
+                    int32_t* rows_out) {
+  if (!s) return set_err(nullptr, FDSK_EINVAL, "null sketch");
+  if (s->err) return s->err;
+  if (s->finalized) return set_err(s, FDSK_ESTATE, "finalize called twice");
+  if (!B_out) return set_err(s, FDSK_EINVAL, "null B_out");
+  if (ldb < s->d) return set_err(s, FDSK_EINVAL, "ldb < d");
+  if (out_dtype != FDSK_F64 && out_dtype != FDSK_F32)
+    return set_err(s, FDSK_EINVAL, "output dtype must be F64 or F32");
+  if (s->occ > s->l) {
+    HIPCHK(s, launch_zero_rows(s->C[s->cur], s->ldc, s->occ, s->m, s->stream));
+    int rc = reduce(s);
+    if (rc) return rc;
+  } else if (s->occ > s->new0) {
+    HIPCHK(s, launch_add_pending_norms(s->rownorm, s->new0, s->occ, s->st, s->stream));
+    s->new0 = s->occ;
+  }
+  s->finalized = true;
+  s->rows_out = std::min(s->occ, s->l);
+  const size_t es = dtype_size(out_dtype);
+  if (mem == FDSK_MEM_DEVICE) {
+    HIPCHK(s, launch_copy_out(s->C[s->cur], s->ldc, s->rows_out, s->l, s->d, B_out, ldb,
+                              static_cast<int>(out_dtype), s->stream));
+  } else {
+    void* tmp = nullptr;
+    size_t bytes = static_cast<size_t>(s->l) * s->d * es;
+    hipError_t e = hipMalloc(&tmp, bytes);
+    if (e != hipSuccess) return set_err(s, FDSK_ENOMEM, "output staging: %s", hipGetErrorString(e));
+    e = launch_copy_out(s->C[s->cur], s->ldc, s->rows_out, s->l, s->d, tmp, s->d,
+                        static_cast<int>(out_dtype), s->stream);
+    if (e == hipSuccess)
+      e = hipMemcpy2DAsync(B_out, ldb * es, tmp, s->d * es, s->d * es, s->l,
+                           hipMemcpyDeviceToHost, s->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+    (void)hipFree(tmp);
+    if (e != hipSuccess) return set_err(s, FDSK_EDEVICE, "copy-out: %s", hipGetErrorString(e));
+  }
+  if (rows_out) *rows_out = s->rows_out;
+  return check_device_flags(s);
+}
+
+int sketch_stats(const fdsk_sketch* cs, fdsk_report* out) {
+  fdsk_sketch* s = const_cast<fdsk_sketch*>(cs);
+  if (!s || !out) return set_err(s, FDSK_EINVAL, "null argument");
+  DevStats h{};
+  HIPCHK(s, hipMemcpyAsync(&h, s->st, sizeof h, hipMemcpyDeviceToHost, s->stream));
+  HIPCHK(s, hipStreamSynchronize(s->stream));
+  std::memset(out, 0, sizeof *out);
+  out->fro2_A = h.fro2A;
+  out->delta_sum = h.Delta;
+  out->shrink_total = h.Stot;
+  out->n_rows = s->n_rows;
+  out->n_reduce = h.n_rr;
+  out->rows_out = s->finalized ? s->rows_out : std::min(s->occ, s->l);
+  out->eig_unconverged = h.eig_unconv;
+  out->cov_err = out->proj_err_k = out->proj_full_over_fro2 = std::nan("");
+  out->fro2_B = std::nan("");
+  out->lambda_max = out->lambda_min = std::nan("");
+  return 0;
+}
+
+void sketch_destroy(fdsk_sketch* s) {
+  if (!s) return;
+  (void)hipStreamSynchronize(s->stream);
+  if (s->stage) (void)hipFree(s->stage);
+  if (s->arena) (void)hipFree(s->arena);
+  delete s;
+}
+
+}  // extern "C"
+
+extern "C" int sketch_error(fdsk_sketch* s, const void*, int64_t, int64_t, fdsk_dtype, fdsk_mem,
+                            int32_t, int32_t, fdsk_report*) {
+  return set_err(s, FDSK_EUNSUPPORTED, "error evaluation not built yet");
+}
+extern "C" int fdsk_evaluate(const void*, int64_t, int64_t, fdsk_dtype, const void*, int64_t,
+                             int64_t, fdsk_dtype, int64_t, fdsk_mem, int32_t, int32_t, void*,
+                             fdsk_report*) {
+  return set_err(nullptr, FDSK_EUNSUPPORTED, "error evaluation not built yet");
+}

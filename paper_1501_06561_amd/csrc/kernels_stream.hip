@@ -1,0 +1,330 @@
+// Streaming-path kernels: row ingest, FP64 Gram (matrix cores), shrink
+// (ReduceRank rules), rebuild (matrix cores), finalize helpers.
+//
+// Buffer layout: C is mp x ldc FP64 row-major; mp = m rounded up to 32 rows
+// (rows >= m are zero forever), ldc = d rounded up to 64 columns (columns >= d
+// are zero).  Rows [0, occ) are occupied.
+#include "fdsk_device.hpp"
+#include "fdsk_kernels.hpp"
+
+namespace fdsk {
+
+// ----------------------------------------------------------------- ingest
+// One workgroup per row: convert to FP64, zero the pad columns, and store the
+// row's squared norm (FP64) for the ||A||_F^2 accumulator.
+__global__ __launch_bounds__(256) void k_ingest(const void* __restrict__ src, int dt,
+                                                int64_t stride, int d, double* __restrict__ C,
+                                                int ldc, int row0, double* __restrict__ rownorm) {
+  const int i = blockIdx.x;
+  const int64_t base = static_cast<int64_t>(i) * stride;
+  double* dst = C + static_cast<int64_t>(row0 + i) * ldc;
+  double acc = 0.0;
+  for (int c = threadIdx.x; c < ldc; c += blockDim.x) {
+    double v = (c < d) ? load_as_f64(src, base + c, dt) : 0.0;
+    dst[c] = v;
+    acc += v * v;
+  }
+  __shared__ double red[4];
+  acc = wave_sum(acc);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) rownorm[row0 + i] = (red[0] + red[1]) + (red[2] + red[3]);
+}
+
+// ------------------------------------------------------------------- Gram
+// G = C C^T on lower-triangular 32x32 tiles with split-K.  Four waves per
+// workgroup, each owning a 16x16 sub-tile fed by 16x16x4 FP64 MFMA.
+constexpr int GT = 32;   // output tile
+constexpr int GK = 32;   // K chunk staged in LDS
+
+__global__ __launch_bounds__(256) void k_gram_f64(const double* __restrict__ C, int ldc,
+                                                  int mp, int kchunk, double* __restrict__ Gpart) {
+  const int tile = blockIdx.x;
+  int ti = static_cast<int>((sqrtf(8.0f * tile + 1.0f) - 1.0f) * 0.5f);
+  while ((ti + 1) * (ti + 2) / 2 <= tile) ++ti;
+  while (ti * (ti + 1) / 2 > tile) --ti;
+  const int tj = tile - ti * (ti + 1) / 2;
+  const int k0 = blockIdx.y * kchunk;
+  const int k1 = min(ldc, k0 + kchunk);
+
+  __shared__ double As[GT][GK + 1];
+  __shared__ double Bs[GT][GK + 1];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int wi = w >> 1, wj = w & 1;
+  const int li = lane & 15, lk = lane >> 4;
+  f64x4 acc = {0.0, 0.0, 0.0, 0.0};
+  const double* Ca = C + static_cast<int64_t>(ti * GT) * ldc;
+  const double* Cb = C + static_cast<int64_t>(tj * GT) * ldc;
+
+  for (int kk = k0; kk < k1; kk += GK) {
+    // 32 rows x 32 cols per operand: 256 threads x 4 doubles.
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      int idx = threadIdx.x + e * 256;
+      int r = idx >> 5, c = idx & 31;
+      As[r][c] = Ca[static_cast<int64_t>(r) * ldc + kk + c];
+      Bs[r][c] = Cb[static_cast<int64_t>(r) * ldc + kk + c];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k4 = 0; k4 < GK / 4; ++k4) {
+      double a = As[wi * 16 + li][k4 * 4 + lk];
+      double b = Bs[wj * 16 + li][k4 * 4 + lk];
+      acc = mfma_f64(a, b, acc);
+    }
+    __syncthreads();
+  }
+  double* out = Gpart + static_cast<int64_t>(blockIdx.y) * mp * mp;
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    int row = ti * GT + wi * 16 + 4 * lk + v;
+    int col = tj * GT + wj * 16 + li;
+    out[static_cast<int64_t>(row) * mp + col] = acc[v];
+  }
+}
+
+// Sum the split-K partials in a fixed order and mirror the lower triangle.
+__global__ void k_gram_reduce(const double* __restrict__ Gpart, int ksplit, int mp,
+                              double* __restrict__ G) {
+  const int64_t n = static_cast<int64_t>(mp) * mp;
+  for (int64_t e = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; e < n;
+       e += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    int r = static_cast<int>(e / mp), c = static_cast<int>(e % mp);
+    if ((r >> 5) < (c >> 5)) continue;   // upper tiles are written by the mirror
+    double v = 0.0;
+    for (int k = 0; k < ksplit; ++k) v += Gpart[static_cast<int64_t>(k) * n + e];
+    if (r >= c) {
+      G[static_cast<int64_t>(r) * mp + c] = v;
+      G[static_cast<int64_t>(c) * mp + r] = v;
+    }
+  }
+}
+
+// ----------------------------------------------------------------- shrink
+// One workgroup.  Ranks the eigenvalues (descending, ties by index), applies
+// the variant's ReduceRank rule in FP64, updates the accumulators and writes
+// Ut = diag(rho) * U^T for the keep surviving rows, rho_j = sigma'_j/sigma_j.
+__global__ __launch_bounds__(1024) void k_shrink(const double* __restrict__ lam_raw,
+                                                 const double* __restrict__ V, int m, int mp,
+                                                 RuleParams rp, const double* __restrict__ rownorm,
+                                                 int new0, int new1, double* __restrict__ Ut,
+                                                 DevStats* __restrict__ st) {
+  __shared__ double lam[1024];
+  __shared__ int perm[1024];
+  __shared__ double rho[1024];
+  __shared__ double red[1024];
+  __shared__ double raw[1024];
+  __shared__ int bad;
+  const int tid = threadIdx.x;
+  if (tid == 0) bad = 0;
+  __syncthreads();
+  // NaN is ranked as -inf so the ranking stays a permutation (indices read
+  // through perm[] are always in range); the flag reports it.
+  for (int j = tid; j < m; j += blockDim.x) {
+    double x = lam_raw[j];
+    if (!(x == x) || isinf(x)) bad = 1;
+    raw[j] = (x == x) ? x : -INFINITY;
+  }
+  __syncthreads();
+  for (int j = tid; j < m; j += blockDim.x) {
+    double x = raw[j];
+    int rank = 0;
+    for (int i = 0; i < m; ++i) {
+      double y = raw[i];
+      rank += (y > x) || (y == x && i < j);
+    }
+    perm[rank] = j;
+  }
+  __syncthreads();
+  for (int q = tid; q < m; q += blockDim.x) lam[q] = fmax(raw[perm[q]], 0.0);
+  __syncthreads();
+  const double delta = (rp.t - 1 < m) ? lam[rp.t - 1] : 0.0;
+  double removed = 0.0;
+  for (int q = tid; q < m; q += blockDim.x) {
+    double x = lam[q];
+    double y;
+    bool untouched;
+    if (rp.variant == 1) {            // iSVD: keep the first l-1, drop the rest
+      untouched = q < rp.l - 1;
+      y = untouched ? x : 0.0;
+    } else {                          // FD / alpha / fast alpha: shrink from index r on
+      untouched = q < rp.r;
+      y = untouched ? x : fmax(x - delta, 0.0);
+    }
+    removed += x - y;
+    rho[q] = untouched ? 1.0 : ((x > 0.0 && y > 0.0) ? sqrt(y / x) : 0.0);
+  }
+  red[tid] = removed;
+  __syncthreads();
+  for (int s = blockDim.x >> 1; s > 0; s >>= 1) {
+    if (tid < s) red[tid] += red[tid + s];
+    __syncthreads();
+  }
+  if (tid == 0) {
+    double nrm = 0.0;
+    for (int i = new0; i < new1; ++i) nrm += rownorm[i];
+    st->fro2A += nrm;
+    st->Delta += delta;
+    st->Stot += red[0];
+    st->n_rr += 1;
+    if (bad || !(nrm == nrm)) st->nonfinite = 1;
+  }
+  // Ut rows [0, keep) ; rows up to the next multiple of 32 are zero.
+  const int rows = (rp.keep + 31) & ~31;
+  for (int64_t e = tid; e < static_cast<int64_t>(rows) * mp; e += blockDim.x) {
+    int q = static_cast<int>(e / mp), i = static_cast<int>(e % mp);
+    double v = 0.0;
+    if (q < rp.keep && q < m && i < m) v = rho[q] * V[static_cast<int64_t>(perm[q]) * mp + i];
+    Ut[e] = v;
+  }
+}
+
+// ---------------------------------------------------------------- rebuild
+// out[0:keep, :] = Ut[0:keep, 0:mp] * C[0:mp, :].  Tile 32 rows x 64 cols;
+// wave w owns rows (w>>1)*16.. and cols (w&1)*32.. (two 16x16 MFMA tiles).
+__global__ __launch_bounds__(256) void k_rebuild_f64(const double* __restrict__ Ut,
+                                                     const double* __restrict__ C, int ldc,
+                                                     int mp, int keep, double* __restrict__ out) {
+  const int r0 = blockIdx.y * 32, c0 = blockIdx.x * 64;
+  __shared__ double As[32][33];
+  __shared__ double Bs[32][65];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int wi = w >> 1, wj = w & 1;
+  const int li = lane & 15, lk = lane >> 4;
+  f64x4 acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = {0.0, 0.0, 0.0, 0.0};
+  for (int k0 = 0; k0 < mp; k0 += 32) {
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      int idx = threadIdx.x + e * 256;
+      int r = idx >> 5, c = idx & 31;
+      As[r][c] = Ut[static_cast<int64_t>(r0 + r) * mp + k0 + c];
+    }
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      int idx = threadIdx.x + e * 256;
+      int r = idx >> 6, c = idx & 63;
+      Bs[r][c] = C[static_cast<int64_t>(k0 + r) * ldc + c0 + c];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k4 = 0; k4 < 8; ++k4) {
+      double a = As[wi * 16 + li][k4 * 4 + lk];
+      double b0 = Bs[k4 * 4 + lk][wj * 32 + li];
+      double b1 = Bs[k4 * 4 + lk][wj * 32 + 16 + li];
+      acc0 = mfma_f64(a, b0, acc0);
+      acc1 = mfma_f64(a, b1, acc1);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    int row = r0 + wi * 16 + 4 * lk + v;
+    if (row < keep) {
+      int64_t o = static_cast<int64_t>(row) * ldc + c0 + wj * 32 + li;
+      out[o] = acc0[v];
+      out[o + 16] = acc1[v];
+    }
+  }
+}
+
+// --------------------------------------------------------------- helpers
+__global__ void k_zero_rows(double* __restrict__ C, int ldc, int r0, int r1) {
+  const int64_t n = static_cast<int64_t>(r1 - r0) * ldc;
+  double* p = C + static_cast<int64_t>(r0) * ldc;
+  for (int64_t e = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; e < n;
+       e += static_cast<int64_t>(gridDim.x) * blockDim.x)
+    p[e] = 0.0;
+}
+
+__global__ void k_add_pending_norms(const double* __restrict__ rownorm, int new0, int new1,
+                                    DevStats* __restrict__ st) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    double nrm = 0.0;
+    for (int i = new0; i < new1; ++i) nrm += rownorm[i];
+    st->fro2A += nrm;
+    if (!(nrm == nrm) || isinf(nrm)) st->nonfinite = 1;
+  }
+}
+
+__global__ void k_copy_out(const double* __restrict__ C, int ldc, int valid_rows, int l, int d,
+                           void* __restrict__ out, int64_t ldb, int out_dt) {
+  const int64_t n = static_cast<int64_t>(l) * d;
+  for (int64_t e = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; e < n;
+       e += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    int r = static_cast<int>(e / d), c = static_cast<int>(e % d);
+    double v = (r < valid_rows) ? C[static_cast<int64_t>(r) * ldc + c] : 0.0;
+    if (out_dt == DT_F64)
+      static_cast<double*>(out)[r * ldb + c] = v;
+    else
+      static_cast<float*>(out)[r * ldb + c] = static_cast<float>(v);
+  }
+}
+
+// ------------------------------------------------------------ launchers
+hipError_t launch_ingest(const void* src, int dt, int64_t stride, int f, int d, double* C,
+                         int ldc, int row0, double* rownorm, hipStream_t s) {
+  if (f <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_ingest, dim3(f), dim3(256), 0, s, src, dt, stride, d, C, ldc, row0, rownorm);
+  return hipGetLastError();
+}
+
+hipError_t launch_gram(const double* C, int ldc, int mp, double* Gpart, int ksplit_max, double* G,
+                       hipStream_t s) {
+  const int T = mp / GT;
+  const int ntiles = T * (T + 1) / 2;
+  int ksplit = (256 + ntiles - 1) / ntiles;
+  ksplit = std::min(ksplit, std::max(1, ldc / 256));
+  ksplit = std::min(ksplit, ksplit_max);
+  int kchunk = (ldc + ksplit - 1) / ksplit;
+  kchunk = (kchunk + GK - 1) / GK * GK;
+  ksplit = (ldc + kchunk - 1) / kchunk;
+  hipLaunchKernelGGL(k_gram_f64, dim3(ntiles, ksplit), dim3(256), 0, s, C, ldc, mp, kchunk, Gpart);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const int64_t n = static_cast<int64_t>(mp) * mp;
+  int blocks = static_cast<int>(std::min<int64_t>((n + 255) / 256, 2048));
+  hipLaunchKernelGGL(k_gram_reduce, dim3(blocks), dim3(256), 0, s, Gpart, ksplit, mp, G);
+  return hipGetLastError();
+}
+
+hipError_t launch_shrink(const double* lam, const double* V, int m, int mp, RuleParams rp,
+                         const double* rownorm, int new0, int new1, double* Ut, DevStats* st,
+                         hipStream_t s) {
+  hipLaunchKernelGGL(k_shrink, dim3(1), dim3(1024), 0, s, lam, V, m, mp, rp, rownorm, new0, new1,
+                     Ut, st);
+  return hipGetLastError();
+}
+
+hipError_t launch_rebuild(const double* Ut, const double* C, int ldc, int mp, int keep, double* out,
+                          hipStream_t s) {
+  if (keep <= 0) return hipSuccess;
+  dim3 grid(ldc / 64, (keep + 31) / 32);
+  hipLaunchKernelGGL(k_rebuild_f64, grid, dim3(256), 0, s, Ut, C, ldc, mp, keep, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_zero_rows(double* C, int ldc, int r0, int r1, hipStream_t s) {
+  if (r1 <= r0) return hipSuccess;
+  int64_t n = static_cast<int64_t>(r1 - r0) * ldc;
+  int blocks = static_cast<int>(std::min<int64_t>((n + 255) / 256, 4096));
+  hipLaunchKernelGGL(k_zero_rows, dim3(blocks), dim3(256), 0, s, C, ldc, r0, r1);
+  return hipGetLastError();
+}
+
+hipError_t launch_add_pending_norms(const double* rownorm, int new0, int new1, DevStats* st,
+                                    hipStream_t s) {
+  hipLaunchKernelGGL(k_add_pending_norms, dim3(1), dim3(64), 0, s, rownorm, new0, new1, st);
+  return hipGetLastError();
+}
+
+hipError_t launch_copy_out(const double* C, int ldc, int valid_rows, int l, int d, void* out,
+                           int64_t ldb, int out_dt, hipStream_t s) {
+  int64_t n = static_cast<int64_t>(l) * d;
+  int blocks = static_cast<int>(std::min<int64_t>((n + 255) / 256, 4096));
+  if (blocks <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_copy_out, dim3(blocks), dim3(256), 0, s, C, ldc, valid_rows, l, d, out, ldb,
+                     out_dt);
+  return hipGetLastError();
+}
+
+}  // namespace fdsk

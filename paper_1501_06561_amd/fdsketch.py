@@ -1,0 +1,190 @@
+"""ctypes binding of libfdsketch.so (argument marshalling only).
+
+Every step of the sketch runs in the library's HIP kernels; this module only
+converts tensors to pointers, strides and enum codes.  PyTorch supplies device
+memory and the HIP stream.  If the library is missing the binding raises: it
+has no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libfdsketch.so")
+
+VARIANTS = {"fd": 0, "isvd": 1, "alpha": 2, "fast_alpha": 3}
+PRECISIONS = {"fp64": 0, "bf16": 1, "bf16x3": 2}
+F64, F32, BF16 = 0, 1, 2
+MEM_HOST, MEM_DEVICE = 0, 1
+ERRORS = {0: "OK", -1: "EINVAL", -2: "ESTATE", -3: "ENOMEM", -4: "EDEVICE", -5: "ENONFINITE",
+          -6: "EUNSUPPORTED"}
+
+# Every symbol the header declares (checked by the CPU test-suite).
+EXPORTS = ("sketch_create", "sketch_append_rows", "sketch_finalize", "sketch_error",
+           "fdsk_evaluate", "sketch_stats", "sketch_destroy", "sketch_last_error", "fdsk_version")
+
+
+class FdskConfig(ctypes.Structure):
+    _fields_ = [("d", ctypes.c_int64), ("l", ctypes.c_int32), ("buffer_rows", ctypes.c_int32),
+                ("variant", ctypes.c_int), ("alpha", ctypes.c_double), ("precision", ctypes.c_int),
+                ("flags", ctypes.c_uint32)]
+
+
+class FdskReport(ctypes.Structure):
+    _fields_ = [("cov_err", ctypes.c_double), ("proj_err_k", ctypes.c_double),
+                ("proj_full_over_fro2", ctypes.c_double), ("fro2_A", ctypes.c_double),
+                ("fro2_B", ctypes.c_double), ("delta_sum", ctypes.c_double),
+                ("shrink_total", ctypes.c_double), ("lambda_max", ctypes.c_double),
+                ("lambda_min", ctypes.c_double), ("n_rows", ctypes.c_int64),
+                ("n_reduce", ctypes.c_int64), ("k", ctypes.c_int32), ("rows_out", ctypes.c_int32),
+                ("eig_unconverged", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_ if name != "reserved"}
+
+
+class FdskError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{ERRORS.get(code, code)}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+
+def lib():
+    """Load libfdsketch.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_1501_06561_amd.build`")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i64, i32, cint = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_int
+    L.sketch_create.argtypes = [ctypes.POINTER(FdskConfig), vp, ctypes.POINTER(vp)]
+    L.sketch_append_rows.argtypes = [vp, vp, i64, i64, cint, cint]
+    L.sketch_finalize.argtypes = [vp, vp, i64, cint, cint, ctypes.POINTER(i32)]
+    L.sketch_error.argtypes = [vp, vp, i64, i64, cint, cint, i32, i32, ctypes.POINTER(FdskReport)]
+    L.fdsk_evaluate.argtypes = [vp, i64, i64, cint, vp, i64, i64, cint, i64, cint, i32, i32, vp,
+                                ctypes.POINTER(FdskReport)]
+    L.sketch_stats.argtypes = [vp, ctypes.POINTER(FdskReport)]
+    L.sketch_destroy.argtypes = [vp]
+    L.sketch_destroy.restype = None
+    L.sketch_last_error.argtypes = [vp]
+    L.sketch_last_error.restype = ctypes.c_char_p
+    L.fdsk_version.restype = ctypes.c_char_p
+    for f in ("sketch_create", "sketch_append_rows", "sketch_finalize", "sketch_error",
+              "fdsk_evaluate", "sketch_stats"):
+        getattr(L, f).restype = cint
+    _lib = L
+    return L
+
+
+def _check(rc, handle=None):
+    if rc != 0:
+        msg = lib().sketch_last_error(handle)
+        raise FdskError(rc, msg.decode() if msg else "")
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _dtype_code(t):
+    torch = _torch()
+    if isinstance(t, np.ndarray):
+        return {np.dtype(np.float64): F64, np.dtype(np.float32): F32}[t.dtype]
+    return {torch.float64: F64, torch.float32: F32, torch.bfloat16: BF16}[t.dtype]
+
+
+def _stream_handle(stream):
+    torch = _torch()
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _rows_arg(rows):
+    """(pointer, n, stride, dtype code, mem kind, keepalive) for a 2-D matrix."""
+    if isinstance(rows, np.ndarray):
+        if rows.ndim != 2 or rows.strides[1] != rows.itemsize:
+            rows = np.ascontiguousarray(rows)
+        return (rows.ctypes.data, rows.shape[0], rows.strides[0] // rows.itemsize,
+                _dtype_code(rows), MEM_HOST, rows)
+    torch = _torch()
+    if rows.dim() != 2:
+        raise ValueError("rows must be a 2-D matrix")
+    if rows.stride(1) != 1:
+        rows = rows.contiguous()
+    mem = MEM_DEVICE if rows.is_cuda else MEM_HOST
+    return rows.data_ptr(), rows.shape[0], rows.stride(0), _dtype_code(rows), mem, rows
+
+
+class FDSketch:
+    """One streaming sketch (Algorithm 1 with the chosen ReduceRank rule)."""
+
+    def __init__(self, d, l, variant="fd", alpha=0.2, buffer_rows=0, precision="fp64",
+                 stream=None):
+        self.d, self.l = int(d), int(l)
+        cfg = FdskConfig(self.d, self.l, int(buffer_rows), VARIANTS[variant], float(alpha),
+                         PRECISIONS[precision], 0)
+        self._stream = stream
+        h = ctypes.c_void_p()
+        _check(lib().sketch_create(ctypes.byref(cfg), _stream_handle(stream), ctypes.byref(h)))
+        self._h = h
+
+    def append(self, rows):
+        ptr, n, stride, dt, mem, keep = _rows_arg(rows)
+        _check(lib().sketch_append_rows(self._h, ctypes.c_void_p(ptr), n, stride, dt, mem), self._h)
+        return self
+
+    def finalize(self, dtype=None, device="cuda"):
+        torch = _torch()
+        dtype = dtype or torch.float64
+        out = torch.empty((self.l, self.d), dtype=dtype, device=device)
+        rows = ctypes.c_int32()
+        mem = MEM_DEVICE if out.is_cuda else MEM_HOST
+        _check(lib().sketch_finalize(self._h, ctypes.c_void_p(out.data_ptr()), out.stride(0),
+                                     _dtype_code(out), mem, ctypes.byref(rows)), self._h)
+        self.rows_out = rows.value
+        return out
+
+    def stats(self):
+        rep = FdskReport()
+        _check(lib().sketch_stats(self._h, ctypes.byref(rep)), self._h)
+        return rep.as_dict()
+
+    def error(self, A, k=10, method=0):
+        ptr, n, stride, dt, mem, keep = _rows_arg(A)
+        rep = FdskReport()
+        _check(lib().sketch_error(self._h, ctypes.c_void_p(ptr), n, stride, dt, mem, k, method,
+                                  ctypes.byref(rep)), self._h)
+        return rep.as_dict()
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().sketch_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def evaluate(A, B, k=10, method=0, stream=None):
+    """Device evaluator of the Section 1.1 error measures for any sketch B."""
+    pa, n, lda, dta, mema, ka = _rows_arg(A)
+    pb, nb, ldb, dtb, memb, kb = _rows_arg(B)
+    if mema != memb:
+        raise ValueError("A and B must both be on the device or both on the host")
+    rep = FdskReport()
+    _check(lib().fdsk_evaluate(ctypes.c_void_p(pa), n, lda, dta, ctypes.c_void_p(pb), nb, ldb, dtb,
+                               A.shape[1], mema, k, method, _stream_handle(stream),
+                               ctypes.byref(rep)))
+    return rep.as_dict()

@@ -1,0 +1,173 @@
+"""GPU parity: the HIP sketch against the CPU oracle on the same seeded inputs.
+
+B is defined only up to a left rotation (Algorithm 1 stores S'V^T; any
+orthogonal mix of its rows is the same sketch), so what is compared is what is
+unique: B^T B, the singular values of B, the covariance error and the FP64
+accumulators.  Tolerance for the FP64 path: covariance error within 1e-6
+relative (absolute floor 1e-12 for exact sketches); B^T B elementwise within
+1e-9 ||A||_F^2 for FD, whose update is a Lipschitz spectral map of the buffer.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1501_06561_amd import synth
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from paper_1501_06561_amd import fdsketch as F  # noqa: E402
+
+
+def gpu_sketch(A, l, variant="fd", alpha=0.2, m=0, dtype=torch.float64, chunks=None,
+               host=False):
+    sk = F.FDSketch(A.shape[1], l, variant, alpha, buffer_rows=m)
+    if dtype == torch.bfloat16:
+        src = torch.from_numpy(synth.bf16_bits(A).view(np.int16)).view(torch.bfloat16)
+    else:
+        src = torch.from_numpy(np.ascontiguousarray(A)).to(dtype)
+    if not host:
+        src = src.cuda()
+    if chunks is None:
+        sk.append(src)
+    else:
+        lo = 0
+        for c in chunks:
+            sk.append(src[lo:lo + c])
+            lo += c
+        sk.append(src[lo:])
+    B = sk.finalize().cpu().numpy()
+    st = sk.stats()
+    sk.close()
+    return B, st
+
+
+def compare(A, l, variant, alpha=0.2, m=0, dtype=torch.float64, cov_rtol=1e-6, gram_tol=1e-9,
+            **kw):
+    Bg, st = gpu_sketch(A, l, variant, alpha, m, dtype, **kw)
+    A64 = np.asarray(A, dtype=np.float64)
+    if dtype == torch.float32:
+        A64 = A.astype(np.float32).astype(np.float64)
+    elif dtype == torch.bfloat16:
+        A64 = synth.to_bf16(A).astype(np.float64)
+    Bo, so = oracle.fd_sketch(A64, l, variant, alpha, m=(m or None), return_state=True)
+    fa = oracle.fro2(A64)
+    ce_g, ce_o = oracle.cov_err(A64, Bg), oracle.cov_err(A64, Bo)
+    assert abs(ce_g - ce_o) <= cov_rtol * ce_o + 1e-12, (ce_g, ce_o)
+    if gram_tol is not None:
+        assert np.max(np.abs(Bg.T @ Bg - Bo.T @ Bo)) <= gram_tol * fa
+    assert st["n_reduce"] == so.n_rr
+    assert st["n_rows"] == so.n_rows
+    assert abs(st["fro2_A"] - so.fro2A) <= 1e-12 * fa
+    assert abs(st["delta_sum"] - so.Delta) <= 1e-8 * max(so.Delta, 1e-300) + 1e-12 * fa
+    assert abs(st["shrink_total"] - so.Stot) <= 1e-9 * fa
+    # Mass identity on the GPU's own sketch: ||A||^2 - ||B||^2 = shrink total.
+    assert abs(fa - oracle.fro2(Bg) - st["shrink_total"]) <= 1e-9 * fa
+    assert st["eig_unconverged"] == 0
+    return ce_g, ce_o
+
+
+def test_config1_random_noisy_fd_l20():
+    """10,000 x 100 Random Noisy (k=10, zeta=10, seed 0), FD with l = 20."""
+    A = synth.random_noisy(10_000, 100, 10, 10.0, seed=0)
+    compare(A, 20, "fd")
+
+
+@pytest.mark.parametrize("variant", oracle.VARIANTS)
+@pytest.mark.parametrize("l", [6, 24, 50, 64, 100])
+def test_variants_across_solver_sizes(variant, l):
+    """l = 6..50 use the single-workgroup LDS eigensolver (m <= 100), l = 64
+    and 100 the multi-workgroup block solver.  d = 300 (ragged against the
+    64-column padding), n ragged against the schedule."""
+    A = synth.random_noisy(2_345, 300, 12, 10.0, seed=(21, l))
+    gram = 1e-9 if variant == "fd" else 1e-7
+    compare(A, l, variant, 0.2, gram_tol=gram, cov_rtol=1e-6)
+
+
+@pytest.mark.parametrize("variant", oracle.VARIANTS)
+def test_paper_literal_buffer(variant):
+    """m = l: one ReduceRank per row after the first l-1 (Algorithm 1 as printed)."""
+    A = synth.random_noisy(400, 50, 5, 10.0, seed=(22, 0))
+    compare(A, 10, variant, 0.3, m=10, gram_tol=1e-8)
+
+
+@pytest.mark.parametrize("dtype", [torch.float32, torch.bfloat16])
+def test_input_dtypes(dtype):
+    A = synth.random_noisy(1_500, 130, 8, 10.0, seed=(23, 0))
+    compare(A, 16, "fd", dtype=dtype)
+
+
+def test_host_rows_and_ragged_chunks():
+    A = synth.random_noisy(3_001, 77, 6, 10.0, seed=(24, 0))
+    compare(A, 11, "fd", host=True)
+    compare(A, 11, "alpha", 0.2, chunks=[1, 2, 3, 500, 999, 7], gram_tol=1e-8)
+
+
+def test_strided_device_rows():
+    A = synth.random_noisy(900, 40, 4, 10.0, seed=(25, 0))
+    wide = np.zeros((900, 64))
+    wide[:, :40] = A
+    sk = F.FDSketch(40, 8)
+    sk.append(torch.from_numpy(wide).cuda()[:, :40])
+    B = sk.finalize().cpu().numpy()
+    Bo = oracle.fd_sketch(A, 8)
+    assert np.max(np.abs(B.T @ B - Bo.T @ Bo)) <= 1e-9 * oracle.fro2(A)
+
+
+@pytest.mark.parametrize("variant", oracle.VARIANTS)
+def test_short_stream_exact(variant):
+    A = synth.random_noisy(9, 33, 3, seed=(26, 0))
+    B, st = gpu_sketch(A, 12, variant)
+    assert st["n_reduce"] == 0
+    assert np.array_equal(B[:9], A) and not B[9:].any()
+
+
+def test_empty_stream():
+    sk = F.FDSketch(20, 5)
+    B = sk.finalize().cpu().numpy()
+    assert not B.any()
+    assert sk.stats()["fro2_A"] == 0.0
+
+
+@pytest.mark.parametrize("variant", oracle.VARIANTS)
+def test_rank_deficient_and_narrow(variant):
+    rng = np.random.default_rng(27)
+    low = rng.standard_normal((1_000, 3)) @ rng.standard_normal((3, 90))
+    B, _ = gpu_sketch(low, 10, variant, 0.25)
+    assert oracle.cov_err(low, B) <= 1e-10
+    narrow = synth.random_noisy(1_000, 7, 3, seed=(27, 1))      # d < m
+    compare(narrow, 10, variant, 0.25, gram_tol=1e-8)
+
+
+def test_l1_empties_sketch():
+    A = synth.random_noisy(300, 20, 3, seed=(28, 0))
+    B, st = gpu_sketch(A, 1, "fd")
+    assert not B.any()
+    assert st["n_reduce"] == 150
+
+
+def test_basis_rows_counter_view():
+    A, j, c = synth.basis_rows(3_000, 60, seed=(29, 0))
+    B, _ = gpu_sketch(A, 9, "fd")
+    counters = oracle.counter_simulation(j, c, 60, 9, "fd")
+    G = B.T @ B
+    assert np.max(np.abs(G - np.diag(counters))) <= 1e-9 * oracle.fro2(A)
+
+
+def test_nonfinite_rows_are_reported():
+    A = synth.random_noisy(200, 30, 3, seed=(30, 0))
+    A[57, 3] = np.nan
+    sk = F.FDSketch(30, 8)
+    sk.append(torch.from_numpy(A).cuda())
+    with pytest.raises(F.FdskError) as e:
+        sk.finalize()
+    assert e.value.code == -5
+
+
+def test_append_after_finalize_is_rejected():
+    sk = F.FDSketch(10, 4)
+    sk.append(torch.ones(3, 10, dtype=torch.float64, device="cuda"))
+    sk.finalize()
+    with pytest.raises(F.FdskError) as e:
+        sk.append(torch.ones(3, 10, dtype=torch.float64, device="cuda"))
+    assert e.value.code == -2
