@@ -142,6 +142,20 @@ void sketch_destroy(fdsk_sketch* s);
  * next call on it.  s == NULL gives the last create/evaluate failure. */
 const char* sketch_last_error(const fdsk_sketch* s);
 
+/* Kernel-level entry points: the two hot steps of a ReduceRank on their own.
+ * Device pointers, FP64, stream-ordered on hip_stream, synchronous on return.
+ *
+ * fdsk_gram: G = C C^T (rows x rows) for C rows x d (leading dimension ldc),
+ *   written to G with leading dimension ldg.  This is the Gram matrix whose
+ *   eigenvalues are the squared singular values of Algorithm 1's buffer.
+ * fdsk_eigh: eigen-decomposition G = V diag(lam) V^T of a symmetric m x m
+ *   matrix (m <= 1024); lam unsorted, V's column j (V[i*ldv + j]) belongs to
+ *   lam[j].  Errors: EINVAL, EUNSUPPORTED (m > 1024), ENOMEM, EDEVICE. */
+int fdsk_gram(const double* C, int32_t rows, int64_t d, int64_t ldc, double* G, int64_t ldg,
+              void* hip_stream);
+int fdsk_eigh(const double* G, int32_t m, int64_t ldg, double* lam, double* V, int64_t ldv,
+              void* hip_stream);
+
 /* Library build information (static string). */
 const char* fdsk_version(void);
 

@@ -40,7 +40,8 @@ __device__ __forceinline__ double wave_sum(double v) {
 
 // 16x16x4 FP64 matrix-core step: D(16x16) += A(16x4) * B(4x16).
 // Lane layout (wave64): lane = i + 16*k holds A[i][k] and B[k][i];
-// the result lane = j + 16*q holds D[4q + v][j] in element v.
+// the result lane = j + 16*q holds D[q + 4v][j] in element v (rows of a lane
+// group are interleaved by 4 for the FP64 instruction).
 __device__ __forceinline__ f64x4 mfma_f64(double a, double b, f64x4 c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }

@@ -41,6 +41,8 @@ hipError_t launch_rebuild(const double* Ut, const double* C, int ldc, int mp, in
 hipError_t launch_zero_rows(double* C, int ldc, int r0, int r1, hipStream_t s);
 hipError_t launch_add_pending_norms(const double* rownorm, int new0, int new1, DevStats* st,
                                     hipStream_t s);
+// out (mp x mp) = in^T for the leading n x n block of an mp x mp matrix.
+hipError_t launch_transpose(const double* in, int mp, int n, double* out, hipStream_t s);
 hipError_t launch_copy_out(const double* C, int ldc, int valid_rows, int l, int d, void* out,
                            int64_t ldb, int out_dt, hipStream_t s);
 

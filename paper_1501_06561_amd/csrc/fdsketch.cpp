@@ -346,3 +346,68 @@ extern "C" int fdsk_evaluate(const void*, int64_t, int64_t, fdsk_dtype, const vo
                              fdsk_report*) {
   return set_err(nullptr, FDSK_EUNSUPPORTED, "error evaluation not built yet");
 }
+
+namespace {
+struct DevBuf {
+  void* p = nullptr;
+  ~DevBuf() { if (p) (void)hipFree(p); }
+};
+}  // namespace
+
+extern "C" int fdsk_gram(const double* C, int32_t rows, int64_t d, int64_t ldc, double* G,
+                         int64_t ldg, void* hip_stream) {
+  if (!C || !G || rows < 1 || rows > 1024 || d < 1 || d > 65536 || ldc < d || ldg < rows)
+    return set_err(nullptr, FDSK_EINVAL, "fdsk_gram: bad arguments");
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  const int mp = round_up(rows, 32), ld = round_up(static_cast<int>(d), 64);
+  const int T = mp / 32, ntiles = T * (T + 1) / 2;
+  const int ks = std::max(1, std::min({(256 + ntiles - 1) / ntiles, ld / 256, 16}));
+  DevBuf buf;
+  const size_t nC = static_cast<size_t>(mp) * ld, nG = static_cast<size_t>(mp) * mp;
+  if (hipMalloc(&buf.p, (nC + nG * (1 + ks)) * 8) != hipSuccess)
+    return set_err(nullptr, FDSK_ENOMEM, "fdsk_gram: workspace");
+  double* Cp = static_cast<double*>(buf.p);
+  double* Gp = Cp + nC;
+  double* Gpart = Gp + nG;
+  HIPCHK(nullptr, hipMemsetAsync(Cp, 0, nC * 8, st));
+  HIPCHK(nullptr, hipMemcpy2DAsync(Cp, ld * 8, C, ldc * 8, d * 8, rows, hipMemcpyDeviceToDevice, st));
+  HIPCHK(nullptr, launch_gram(Cp, ld, mp, Gpart, ks, Gp, st));
+  HIPCHK(nullptr, hipMemcpy2DAsync(G, ldg * 8, Gp, mp * 8, rows * 8, rows, hipMemcpyDeviceToDevice, st));
+  HIPCHK(nullptr, hipStreamSynchronize(st));
+  return 0;
+}
+
+extern "C" int fdsk_eigh(const double* G, int32_t m, int64_t ldg, double* lam, double* V,
+                         int64_t ldv, void* hip_stream) {
+  if (!G || !lam || !V || m < 1 || ldg < m || ldv < m)
+    return set_err(nullptr, FDSK_EINVAL, "fdsk_eigh: bad arguments");
+  if (m > 1024) return set_err(nullptr, FDSK_EUNSUPPORTED, "fdsk_eigh: m > 1024");
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  const int mp = round_up(m, 32);
+  const size_t nG = static_cast<size_t>(mp) * mp;
+  DevBuf buf;
+  const size_t bytes = (4 * nG + mp) * 8 + sizeof(DevStats) + 4 * sizeof(unsigned) +
+                       kMaxSweeps * sizeof(int) + 256;
+  if (hipMalloc(&buf.p, bytes) != hipSuccess) return set_err(nullptr, FDSK_ENOMEM, "fdsk_eigh: workspace");
+  HIPCHK(nullptr, hipMemsetAsync(buf.p, 0, bytes, st));
+  double* Gp = static_cast<double*>(buf.p);
+  double* Wp = Gp + nG;
+  double* Vp = Wp + nG;
+  double* Vt = Vp + nG;
+  double* lp = Vt + nG;
+  DevStats* ds = reinterpret_cast<DevStats*>(lp + mp);
+  unsigned* bar = reinterpret_cast<unsigned*>(ds + 1);
+  int* rot = reinterpret_cast<int*>(bar + 4);
+  HIPCHK(nullptr, hipMemcpy2DAsync(Gp, mp * 8, G, ldg * 8, m * 8, m, hipMemcpyDeviceToDevice, st));
+  EigWork wk{Wp, bar, rot, ds};
+  HIPCHK(nullptr, launch_eig(Gp, m, mp, lp, Vp, wk, st));
+  // V is column-major inside the library; hand it out row-major.
+  HIPCHK(nullptr, launch_transpose(Vp, mp, m, Vt, st));
+  HIPCHK(nullptr, hipMemcpyAsync(lam, lp, m * 8, hipMemcpyDeviceToDevice, st));
+  HIPCHK(nullptr, hipMemcpy2DAsync(V, ldv * 8, Vt, mp * 8, m * 8, m, hipMemcpyDeviceToDevice, st));
+  DevStats h{};
+  HIPCHK(nullptr, hipMemcpyAsync(&h, ds, sizeof h, hipMemcpyDeviceToHost, st));
+  HIPCHK(nullptr, hipStreamSynchronize(st));
+  if (h.bar_err) return set_err(nullptr, FDSK_EDEVICE, "fdsk_eigh: grid barrier timed out");
+  return 0;
+}

@@ -196,9 +196,9 @@ __device__ void panel_times_q(const double* Ps, int ldp, int mp, double (*Qs)[17
       double b = Qs[k0 + lk][li];
       acc = mfma_f64(a, b, acc);
     }
-    double* o = out + static_cast<int64_t>(cols[li]) * mp + i0 + 4 * lk;
+    double* o = out + static_cast<int64_t>(cols[li]) * mp + i0 + lk;
 #pragma unroll
-    for (int v = 0; v < 4; ++v) o[v] = acc[v];
+    for (int v = 0; v < 4; ++v) o[4 * v] = acc[v];
   }
 }
 
@@ -250,7 +250,7 @@ __global__ __launch_bounds__(256) void k_eig_blk(BlkArgs A) {
           acc = mfma_f64(a, a, acc);
         }
 #pragma unroll
-        for (int v = 0; v < 4; ++v) Hp[w][(4 * lk + v) * 16 + li] = acc[v];
+        for (int v = 0; v < 4; ++v) Hp[w][(lk + 4 * v) * 16 + li] = acc[v];
       }
       if (tid == 0) flag = 0;
       __syncthreads();

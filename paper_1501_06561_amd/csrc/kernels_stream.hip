@@ -77,7 +77,7 @@ __global__ __launch_bounds__(256) void k_gram_f64(const double* __restrict__ C, 
   double* out = Gpart + static_cast<int64_t>(blockIdx.y) * mp * mp;
 #pragma unroll
   for (int v = 0; v < 4; ++v) {
-    int row = ti * GT + wi * 16 + 4 * lk + v;
+    int row = ti * GT + wi * 16 + lk + 4 * v;
     int col = tj * GT + wj * 16 + li;
     out[static_cast<int64_t>(row) * mp + col] = acc[v];
   }
@@ -218,7 +218,7 @@ __global__ __launch_bounds__(256) void k_rebuild_f64(const double* __restrict__ 
   }
 #pragma unroll
   for (int v = 0; v < 4; ++v) {
-    int row = r0 + wi * 16 + 4 * lk + v;
+    int row = r0 + wi * 16 + lk + 4 * v;
     if (row < keep) {
       int64_t o = static_cast<int64_t>(row) * ldc + c0 + wj * 32 + li;
       out[o] = acc0[v];
@@ -260,7 +260,23 @@ __global__ void k_copy_out(const double* __restrict__ C, int ldc, int valid_rows
   }
 }
 
+__global__ void k_transpose(const double* __restrict__ in, int mp, int n, double* __restrict__ out) {
+  const int64_t tot = static_cast<int64_t>(n) * n;
+  for (int64_t e = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; e < tot;
+       e += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    int i = static_cast<int>(e / n), j = static_cast<int>(e % n);
+    out[static_cast<int64_t>(i) * mp + j] = in[static_cast<int64_t>(j) * mp + i];
+  }
+}
+
 // ------------------------------------------------------------ launchers
+hipError_t launch_transpose(const double* in, int mp, int n, double* out, hipStream_t s) {
+  int64_t tot = static_cast<int64_t>(n) * n;
+  int blocks = static_cast<int>(std::min<int64_t>((tot + 255) / 256, 4096));
+  hipLaunchKernelGGL(k_transpose, dim3(blocks), dim3(256), 0, s, in, mp, n, out);
+  return hipGetLastError();
+}
+
 hipError_t launch_ingest(const void* src, int dt, int64_t stride, int f, int d, double* C,
                          int ldc, int row0, double* rownorm, hipStream_t s) {
   if (f <= 0) return hipSuccess;

@@ -24,7 +24,8 @@ ERRORS = {0: "OK", -1: "EINVAL", -2: "ESTATE", -3: "ENOMEM", -4: "EDEVICE", -5: 
 
 # Every symbol the header declares (checked by the CPU test-suite).
 EXPORTS = ("sketch_create", "sketch_append_rows", "sketch_finalize", "sketch_error",
-           "fdsk_evaluate", "sketch_stats", "sketch_destroy", "sketch_last_error", "fdsk_version")
+           "fdsk_evaluate", "sketch_stats", "sketch_destroy", "sketch_last_error", "fdsk_version",
+           "fdsk_gram", "fdsk_eigh")
 
 
 class FdskConfig(ctypes.Structure):
@@ -55,6 +56,17 @@ class FdskError(RuntimeError):
 _lib = None
 
 
+def _init_device_runtime():
+    """Bring up torch's HIP runtime (the library shares it) before the first
+    library call, so the device is open when the library allocates."""
+    try:
+        import torch
+    except ImportError:
+        return
+    if torch.cuda.is_available():
+        torch.empty(1, device="cuda")
+
+
 def lib():
     """Load libfdsketch.so (raises if it has not been built)."""
     global _lib
@@ -62,6 +74,7 @@ def lib():
         return _lib
     if not os.path.exists(LIB_PATH):
         raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_1501_06561_amd.build`")
+    _init_device_runtime()
     L = ctypes.CDLL(LIB_PATH)
     vp, i64, i32, cint = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_int
     L.sketch_create.argtypes = [ctypes.POINTER(FdskConfig), vp, ctypes.POINTER(vp)]
@@ -76,8 +89,10 @@ def lib():
     L.sketch_last_error.argtypes = [vp]
     L.sketch_last_error.restype = ctypes.c_char_p
     L.fdsk_version.restype = ctypes.c_char_p
+    L.fdsk_gram.argtypes = [vp, i32, i64, i64, vp, i64, vp]
+    L.fdsk_eigh.argtypes = [vp, i32, i64, vp, vp, i64, vp]
     for f in ("sketch_create", "sketch_append_rows", "sketch_finalize", "sketch_error",
-              "fdsk_evaluate", "sketch_stats"):
+              "fdsk_evaluate", "sketch_stats", "fdsk_gram", "fdsk_eigh"):
         getattr(L, f).restype = cint
     _lib = L
     return L
@@ -188,3 +203,28 @@ def evaluate(A, B, k=10, method=0, stream=None):
                                A.shape[1], mema, k, method, _stream_handle(stream),
                                ctypes.byref(rep)))
     return rep.as_dict()
+
+
+def gram(C, stream=None):
+    """G = C C^T on the device (FP64 matrix cores); C: cuda float64 2-D tensor."""
+    torch = _torch()
+    if C.dtype != torch.float64 or not C.is_cuda or C.stride(1) != 1:
+        raise ValueError("C must be a row-major cuda float64 matrix")
+    G = torch.empty((C.shape[0], C.shape[0]), dtype=torch.float64, device=C.device)
+    _check(lib().fdsk_gram(ctypes.c_void_p(C.data_ptr()), C.shape[0], C.shape[1], C.stride(0),
+                           ctypes.c_void_p(G.data_ptr()), G.stride(0), _stream_handle(stream)))
+    return G
+
+
+def eigh(G, stream=None):
+    """(lam, V) with G = V diag(lam) V^T, unsorted, from the device Jacobi solver."""
+    torch = _torch()
+    if G.dtype != torch.float64 or not G.is_cuda or G.stride(1) != 1:
+        raise ValueError("G must be a row-major cuda float64 matrix")
+    m = G.shape[0]
+    lam = torch.empty(m, dtype=torch.float64, device=G.device)
+    V = torch.empty((m, m), dtype=torch.float64, device=G.device)
+    _check(lib().fdsk_eigh(ctypes.c_void_p(G.data_ptr()), m, G.stride(0),
+                           ctypes.c_void_p(lam.data_ptr()), ctypes.c_void_p(V.data_ptr()),
+                           V.stride(0), _stream_handle(stream)))
+    return lam, V
