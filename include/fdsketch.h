@@ -54,6 +54,8 @@ typedef enum { FDSK_F64 = 0, FDSK_F32 = 1, FDSK_BF16 = 2 } fdsk_dtype;  /* BF16 
 typedef enum { FDSK_P_FP64 = 0, FDSK_P_BF16 = 1, FDSK_P_BF16X3 = 2 } fdsk_precision;
 typedef enum { FDSK_MEM_HOST = 0, FDSK_MEM_DEVICE = 1 } fdsk_mem;
 
+#define FDSK_FLAG_PROFILE 1u   /* record per-stage HIP events (see sketch_profile) */
+
 enum {
   FDSK_OK = 0,
   FDSK_EINVAL = -1,       /* bad argument or configuration */
@@ -71,7 +73,7 @@ typedef struct {
   fdsk_variant variant;
   double alpha;           /* (0, 1]; used by FDSK_ALPHA and FDSK_FAST_ALPHA */
   fdsk_precision precision;
-  uint32_t flags;         /* reserved, must be 0 */
+  uint32_t flags;         /* 0 or FDSK_FLAG_PROFILE */
 } fdsk_config;
 
 typedef struct {
@@ -90,6 +92,7 @@ typedef struct {
   int32_t rows_out;           /* rows of the sketch that may be nonzero */
   int32_t eig_unconverged;    /* eigensolves that hit their sweep cap */
   int32_t reserved;
+  int64_t eig_sweeps;         /* Jacobi sweeps summed over all eigensolves */
 } fdsk_report;
 
 /* Create a sketch (Algorithm 1 state, all rows free).  hip_stream is kept and
@@ -134,6 +137,21 @@ int fdsk_evaluate(const void* A, int64_t n, int64_t lda, fdsk_dtype a_dtype,
 /* Accumulators so far (||A||_F^2, Delta, shrink total, rows, reductions).
  * Synchronises the stream. */
 int sketch_stats(const fdsk_sketch* s, fdsk_report* out);
+
+/* Return the sketch to its empty state (all rows free, accumulators zero,
+ * not finalized) keeping its allocations and stream.  Stream-ordered. */
+int sketch_reset(fdsk_sketch* s);
+
+/* Per-stage device time, measured with HIP events on the sketch's stream
+ * when the sketch was created with FDSK_FLAG_PROFILE (otherwise zeros).
+ * Totals since create/reset; synchronises the stream. */
+enum { FDSK_STAGE_INGEST = 0, FDSK_STAGE_GRAM = 1, FDSK_STAGE_EIG = 2, FDSK_STAGE_SHRINK = 3,
+       FDSK_STAGE_REBUILD = 4, FDSK_STAGE_COUNT = 5 };
+typedef struct {
+  double ms[FDSK_STAGE_COUNT];       /* summed stage durations */
+  int64_t launches[FDSK_STAGE_COUNT];
+} fdsk_profile;
+int sketch_profile(fdsk_sketch* s, fdsk_profile* out);
 
 /* Free everything the sketch owns (waits for its stream first). NULL is ok. */
 void sketch_destroy(fdsk_sketch* s);

@@ -57,9 +57,14 @@ struct GridBar {
 };
 
 __device__ __forceinline__ void grid_barrier(const GridBar& b, unsigned nblocks) {
-  __threadfence();
+  // Every wave waits for its own stores to complete (they are then in L2);
+  // one thread publishes the workgroup's writes to the device with an
+  // agent-scope release, arrives, waits, and acquires (which also drops stale
+  // lines of this CU's caches for every wave of the workgroup).
+  __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
   if (threadIdx.x == 0) {
+    __threadfence();
     unsigned g = __hip_atomic_load(b.gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
     unsigned arrived = __hip_atomic_fetch_add(b.count, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
     if (arrived == nblocks - 1) {
@@ -79,9 +84,9 @@ __device__ __forceinline__ void grid_barrier(const GridBar& b, unsigned nblocks)
         }
       }
     }
+    __threadfence();
   }
   __syncthreads();
-  __threadfence();
 }
 
 // Stable Jacobi rotation (Rutishauser) annihilating the (p,q) entry of the

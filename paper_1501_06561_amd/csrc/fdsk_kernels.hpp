@@ -17,6 +17,7 @@ struct DevStats {
   int bar_err;       // a grid barrier timed out
   int eig_unconv;    // eigensolves that hit their sweep cap
   int pad;
+  unsigned long long eig_sweeps;  // Jacobi sweeps summed over eigensolves
 };
 
 // ReduceRank rule: delta = lambda_t (1-based t); indices < r are untouched;
@@ -43,6 +44,9 @@ hipError_t launch_add_pending_norms(const double* rownorm, int new0, int new1, D
                                     hipStream_t s);
 // out (mp x mp) = in^T for the leading n x n block of an mp x mp matrix.
 hipError_t launch_transpose(const double* in, int mp, int n, double* out, hipStream_t s);
+// out (rows x d, ld d, FP64) = X converted from dtype dt (ld ldx).
+hipError_t launch_convert_f64(const void* X, int dt, int64_t ldx, int64_t rows, int d, double* out,
+                              hipStream_t s);
 hipError_t launch_copy_out(const double* C, int ldc, int valid_rows, int l, int d, void* out,
                            int64_t ldb, int out_dt, hipStream_t s);
 

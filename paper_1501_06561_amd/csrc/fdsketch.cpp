@@ -15,9 +15,11 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <vector>
 
 #include "fdsk_kernels.hpp"
 #include "fdsk_eval.hpp"
+#include "fdsk_eval_api.hpp"
 #include "fdsketch.h"
 
 using namespace fdsk;
@@ -46,6 +48,11 @@ struct fdsk_sketch {
   int rows_out = 0;
   int err = 0;
   std::string msg;
+  // Stage profiling (FDSK_FLAG_PROFILE): event pairs recorded on the stream.
+  bool profile = false;
+  std::vector<hipEvent_t> ev_pool;
+  struct Mark { int stage; hipEvent_t a, b; };
+  std::vector<Mark> marks;
 };
 
 namespace {
@@ -102,14 +109,46 @@ RuleParams make_rule(const fdsk_config& c) {
   return rp;
 }
 
+hipEvent_t take_event(fdsk_sketch* s) {
+  hipEvent_t e = nullptr;
+  if (!s->ev_pool.empty()) {
+    e = s->ev_pool.back();
+    s->ev_pool.pop_back();
+  } else if (hipEventCreate(&e) != hipSuccess) {
+    e = nullptr;
+  }
+  return e;
+}
+
+// Record an event on the stream (profiling only); returns it or nullptr.
+hipEvent_t mark(fdsk_sketch* s) {
+  if (!s->profile) return nullptr;
+  hipEvent_t e = take_event(s);
+  if (e && hipEventRecord(e, s->stream) != hipSuccess) return nullptr;
+  return e;
+}
+
+void add_mark(fdsk_sketch* s, int stage, hipEvent_t a, hipEvent_t b) {
+  if (a && b) s->marks.push_back({stage, a, b});
+}
+
 int reduce(fdsk_sketch* s) {
   EigWork wk{s->W, s->bar, s->rot, s->st};
+  hipEvent_t e0 = mark(s);
   HIPCHK(s, launch_gram(s->C[s->cur], s->ldc, s->mp, s->Gpart, s->ksplit_max, s->G, s->stream));
+  hipEvent_t e1 = mark(s);
   HIPCHK(s, launch_eig(s->G, s->m, s->mp, s->lam, s->V, wk, s->stream));
+  hipEvent_t e2 = mark(s);
   HIPCHK(s, launch_shrink(s->lam, s->V, s->m, s->mp, s->rp, s->rownorm, s->new0, s->occ, s->Ut,
                           s->st, s->stream));
+  hipEvent_t e3 = mark(s);
   HIPCHK(s, launch_rebuild(s->Ut, s->C[s->cur], s->ldc, s->mp, s->rp.keep, s->C[1 - s->cur],
                            s->stream));
+  hipEvent_t e4 = mark(s);
+  add_mark(s, 1, e0, e1);
+  add_mark(s, 2, e1, e2);
+  add_mark(s, 3, e2, e3);
+  add_mark(s, 4, e3, e4);
   s->cur = 1 - s->cur;
   s->occ = s->rp.keep;
   s->new0 = s->occ;
@@ -122,8 +161,10 @@ int ingest_device(fdsk_sketch* s, const char* src, int64_t n, int64_t stride, fd
   int64_t i = 0;
   while (i < n) {
     int f = static_cast<int>(std::min<int64_t>(s->m - s->occ, n - i));
+    hipEvent_t a = mark(s);
     HIPCHK(s, launch_ingest(src + i * stride * es, static_cast<int>(dt), stride, f, s->d,
                             s->C[s->cur], s->ldc, s->occ, s->rownorm, s->stream));
+    add_mark(s, 0, a, mark(s));
     s->occ += f;
     i += f;
     s->n_rows += f;
@@ -170,7 +211,7 @@ int sketch_create(const fdsk_config* cfg, void* hip_stream, fdsk_sketch** out) {
     return set_err(nullptr, FDSK_EINVAL, "alpha must lie in (0, 1]");
   if (c.precision != FDSK_P_FP64)
     return set_err(nullptr, FDSK_EUNSUPPORTED, "precision %d not available", (int)c.precision);
-  if (c.flags != 0) return set_err(nullptr, FDSK_EINVAL, "flags must be 0");
+  if (c.flags & ~FDSK_FLAG_PROFILE) return set_err(nullptr, FDSK_EINVAL, "unknown flags");
 
   fdsk_sketch* s = new fdsk_sketch;
   s->cfg = c;
@@ -181,6 +222,7 @@ int sketch_create(const fdsk_config* cfg, void* hip_stream, fdsk_sketch** out) {
   s->ldc = round_up(s->d, 64);
   s->rp = make_rule(c);
   s->stream = static_cast<hipStream_t>(hip_stream);
+  s->profile = (c.flags & FDSK_FLAG_PROFILE) != 0;
   const int T = s->mp / 32;
   const int ntiles = T * (T + 1) / 2;
   s->ksplit_max = std::max(1, std::min({(256 + ntiles - 1) / ntiles, s->ldc / 256, 16}));
@@ -321,15 +363,65 @@ int sketch_stats(const fdsk_sketch* cs, fdsk_report* out) {
   out->n_reduce = h.n_rr;
   out->rows_out = s->finalized ? s->rows_out : std::min(s->occ, s->l);
   out->eig_unconverged = h.eig_unconv;
+  out->eig_sweeps = static_cast<int64_t>(h.eig_sweeps);
   out->cov_err = out->proj_err_k = out->proj_full_over_fro2 = std::nan("");
   out->fro2_B = std::nan("");
   out->lambda_max = out->lambda_min = std::nan("");
   return 0;
 }
 
+int sketch_reset(fdsk_sketch* s) {
+  if (!s) return set_err(nullptr, FDSK_EINVAL, "null sketch");
+  // Counters of the grid barrier and the buffers' zero padding are kept; the
+  // accumulators and occupancy start over.  Rows beyond occ are never read
+  // before they are written again, so the buffers need no clearing.
+  HIPCHK(s, hipMemsetAsync(s->st, 0, sizeof(DevStats), s->stream));
+  s->cur = 0;
+  s->occ = 0;
+  s->new0 = 0;
+  s->n_rows = 0;
+  s->n_rr_host = 0;
+  s->finalized = false;
+  s->rows_out = 0;
+  s->err = 0;
+  s->msg.clear();
+  return 0;
+}
+
+int sketch_profile(fdsk_sketch* s, fdsk_profile* out) {
+  if (!s || !out) return set_err(s, FDSK_EINVAL, "null argument");
+  HIPCHK(s, hipStreamSynchronize(s->stream));
+  std::memset(out, 0, sizeof *out);
+  for (auto& mk : s->marks) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, mk.a, mk.b) == hipSuccess) {
+      out->ms[mk.stage] += ms;
+      out->launches[mk.stage] += 1;
+    }
+  }
+  // Events are shared between neighbouring marks; return each once.
+  std::vector<hipEvent_t> seen;
+  for (auto& mk : s->marks) {
+    seen.push_back(mk.a);
+    seen.push_back(mk.b);
+  }
+  std::sort(seen.begin(), seen.end());
+  seen.erase(std::unique(seen.begin(), seen.end()), seen.end());
+  for (auto e : seen) s->ev_pool.push_back(e);
+  s->marks.clear();
+  return 0;
+}
+
 void sketch_destroy(fdsk_sketch* s) {
   if (!s) return;
   (void)hipStreamSynchronize(s->stream);
+  for (auto& mk : s->marks) {
+    s->ev_pool.push_back(mk.a);
+    s->ev_pool.push_back(mk.b);
+  }
+  std::sort(s->ev_pool.begin(), s->ev_pool.end());
+  s->ev_pool.erase(std::unique(s->ev_pool.begin(), s->ev_pool.end()), s->ev_pool.end());
+  for (auto e : s->ev_pool) (void)hipEventDestroy(e);
   if (s->stage) (void)hipFree(s->stage);
   if (s->arena) (void)hipFree(s->arena);
   delete s;
@@ -337,14 +429,129 @@ void sketch_destroy(fdsk_sketch* s) {
 
 }  // extern "C"
 
-extern "C" int sketch_error(fdsk_sketch* s, const void*, int64_t, int64_t, fdsk_dtype, fdsk_mem,
-                            int32_t, int32_t, fdsk_report*) {
-  return set_err(s, FDSK_EUNSUPPORTED, "error evaluation not built yet");
+namespace {
+
+// Run the device evaluator; A may be on the host (staged to the device).
+int run_evaluator(fdsk_sketch* owner, const void* A, int64_t n, int64_t lda, fdsk_dtype a_dt,
+                  fdsk_mem mem, const double* Bdev, int64_t rows_b, int64_t ldb, int d, int k,
+                  int method, hipStream_t st, fdsk_report* out) {
+  if (n < 1) return set_err(owner, FDSK_EINVAL, "A has no rows");
+  if (lda < d) return set_err(owner, FDSK_EINVAL, "lda < d");
+  if (k < 0) return set_err(owner, FDSK_EINVAL, "k < 0");
+  if (method != 0 && method != 1) return set_err(owner, FDSK_EINVAL, "method must be 0 or 1");
+  if (method == 0 && d > 8192) return set_err(owner, FDSK_EUNSUPPORTED, "dense evaluation needs d <= 8192");
+  if (rows_b > 1024) return set_err(owner, FDSK_EUNSUPPORTED, "B has more than 1024 rows");
+  const size_t es = dtype_size(a_dt);
+  if (es == 0) return set_err(owner, FDSK_EINVAL, "bad dtype");
+  const void* Adev = A;
+  void* stage = nullptr;
+  int64_t ld = lda;
+  if (mem == FDSK_MEM_HOST) {
+    size_t bytes = static_cast<size_t>(n) * d * es;
+    if (hipMalloc(&stage, bytes) != hipSuccess) return set_err(owner, FDSK_ENOMEM, "staging A");
+    hipError_t e = hipMemcpy2DAsync(stage, d * es, A, lda * es, d * es, n, hipMemcpyHostToDevice, st);
+    if (e != hipSuccess) {
+      (void)hipFree(stage);
+      return set_err(owner, FDSK_EDEVICE, "copying A: %s", hipGetErrorString(e));
+    }
+    Adev = stage;
+    ld = d;
+  } else if (mem != FDSK_MEM_DEVICE) {
+    return set_err(owner, FDSK_EINVAL, "bad mem kind");
+  }
+  EvalResult r{};
+  const char* msg = "";
+  hipError_t e = evaluate_device(Adev, static_cast<int>(a_dt), n, ld, Bdev, rows_b, ldb, d, k,
+                                 method, st, &r, &msg);
+  if (stage) {
+    (void)hipStreamSynchronize(st);
+    (void)hipFree(stage);
+  }
+  if (e != hipSuccess)
+    return set_err(owner, e == hipErrorOutOfMemory ? FDSK_ENOMEM : FDSK_EDEVICE, "evaluator: %s: %s",
+                   msg, hipGetErrorString(e));
+  if (r.barrier_error) return set_err(owner, FDSK_EDEVICE, "evaluator: grid barrier timed out");
+  if (!(r.fro2_A > 0.0)) return set_err(owner, FDSK_EINVAL, "||A||_F = 0: cov-err is undefined");
+  out->cov_err = r.cov_err;
+  out->proj_err_k = r.tail_k > 0.0 ? r.proj_err_k : std::nan("");
+  out->proj_full_over_fro2 = r.proj_full;
+  out->fro2_A = r.fro2_A;
+  out->fro2_B = r.fro2_B;
+  out->lambda_max = r.lambda_max;
+  out->lambda_min = r.lambda_min;
+  out->k = k;
+  out->eig_unconverged += r.eig_unconverged;
+  if (!(r.cov_err == r.cov_err)) return set_err(owner, FDSK_ENONFINITE, "non-finite error measure");
+  return 0;
 }
-extern "C" int fdsk_evaluate(const void*, int64_t, int64_t, fdsk_dtype, const void*, int64_t,
-                             int64_t, fdsk_dtype, int64_t, fdsk_mem, int32_t, int32_t, void*,
-                             fdsk_report*) {
-  return set_err(nullptr, FDSK_EUNSUPPORTED, "error evaluation not built yet");
+
+}  // namespace
+
+extern "C" int sketch_error(fdsk_sketch* s, const void* A, int64_t n, int64_t lda, fdsk_dtype dtype,
+                            fdsk_mem mem, int32_t k, int32_t method, fdsk_report* out) {
+  if (!s || !A || !out) return set_err(s, FDSK_EINVAL, "null argument");
+  if (s->err) return s->err;
+  if (!s->finalized) return set_err(s, FDSK_ESTATE, "sketch_error needs a finalized sketch");
+  int rc = sketch_stats(s, out);
+  if (rc) return rc;
+  return run_evaluator(s, A, n, lda, dtype, mem, s->C[s->cur], s->rows_out, s->ldc, s->d, k,
+                       method, s->stream, out);
+}
+
+extern "C" int fdsk_evaluate(const void* A, int64_t n, int64_t lda, fdsk_dtype a_dtype,
+                             const void* B, int64_t rows_b, int64_t ldb, fdsk_dtype b_dtype,
+                             int64_t d, fdsk_mem mem, int32_t k, int32_t method, void* hip_stream,
+                             fdsk_report* out) {
+  if (!A || !out || (rows_b > 0 && !B)) return set_err(nullptr, FDSK_EINVAL, "null argument");
+  if (d < 1 || d > 65536 || rows_b < 0 || (rows_b > 0 && ldb < d))
+    return set_err(nullptr, FDSK_EINVAL, "bad sizes");
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  std::memset(out, 0, sizeof *out);
+  out->delta_sum = out->shrink_total = std::nan("");
+  // B as FP64 on the device.
+  const size_t esb = dtype_size(b_dtype);
+  if (rows_b > 0 && (esb == 0 || b_dtype == FDSK_BF16))
+    return set_err(nullptr, FDSK_EINVAL, "B must be F64 or F32");
+  double* Bd = nullptr;
+  size_t bbytes = static_cast<size_t>(std::max<int64_t>(rows_b, 1)) * d * 8;
+  if (hipMalloc(&Bd, bbytes) != hipSuccess) return set_err(nullptr, FDSK_ENOMEM, "staging B");
+  hipError_t e = hipSuccess;
+  if (rows_b > 0) {
+    if (b_dtype == FDSK_F64) {
+      e = hipMemcpy2DAsync(Bd, d * 8, B, ldb * 8, d * 8, rows_b,
+                           mem == FDSK_MEM_HOST ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice, st);
+    } else {
+      const void* Bsrc = B;
+      void* tmp = nullptr;
+      if (mem == FDSK_MEM_HOST) {
+        e = hipMalloc(&tmp, static_cast<size_t>(rows_b) * d * 4);
+        if (e == hipSuccess)
+          e = hipMemcpy2DAsync(tmp, d * 4, B, ldb * 4, d * 4, rows_b, hipMemcpyHostToDevice, st);
+        Bsrc = tmp;
+      }
+      int64_t ld = (mem == FDSK_MEM_HOST) ? d : ldb;
+      if (e == hipSuccess) e = launch_convert_f64(Bsrc, FDSK_F32, ld, rows_b, static_cast<int>(d), Bd, st);
+      if (tmp) {
+        (void)hipStreamSynchronize(st);
+        (void)hipFree(tmp);
+      }
+    }
+  }
+  int rc = 0;
+  if (e != hipSuccess) {
+    rc = set_err(nullptr, FDSK_EDEVICE, "staging B: %s", hipGetErrorString(e));
+  } else {
+    fdsk_report rep{};
+    rc = run_evaluator(nullptr, A, n, lda, a_dtype, mem, Bd, rows_b, d, static_cast<int>(d), k,
+                       method, st, &rep);
+    rep.delta_sum = rep.shrink_total = std::nan("");
+    rep.n_rows = n;
+    rep.rows_out = static_cast<int32_t>(rows_b);
+    *out = rep;
+  }
+  (void)hipStreamSynchronize(st);
+  (void)hipFree(Bd);
+  return rc;
 }
 
 namespace {

@@ -27,6 +27,15 @@ __device__ __forceinline__ int rr_slot(int pos, int step, int n) {
 // ------------------------------------------------------------- LDS solver
 constexpr int LN = kLdsEigMax;       // max n
 constexpr int LLD = LN + 1;
+constexpr double kLdsTol = 1e-15;    // rotate (p,q) only if |g_pq| > tol*sqrt(|g_pp g_qq|)
+
+// Index at slot `pos` of the round-robin ordering (no integer division).
+__device__ __forceinline__ int rr_fast(int pos, int step, int n) {
+  if (pos == 0) return 0;
+  int s = pos - 1 + step;
+  if (s >= n - 1) s -= n - 1;
+  return 1 + s;
+}
 
 __global__ __launch_bounds__(1024) void k_eig_lds(const double* __restrict__ G, int m, int mp,
                                                   double* __restrict__ lam,
@@ -35,79 +44,103 @@ __global__ __launch_bounds__(1024) void k_eig_lds(const double* __restrict__ G, 
   __shared__ double Gs[LN * LLD];
   __shared__ double Vs[LN * LLD];
   __shared__ double cs[LN];
-  __shared__ double red[32];
-  __shared__ int done;
+  __shared__ short pi[LN / 2], qi[LN / 2];
+  __shared__ int nrot;
+  __shared__ double gmax;
   const int n = (m + 1) & ~1;
   const int np2 = n / 2;
   const int tid = threadIdx.x, nt = blockDim.x;
+  if (tid == 0) gmax = 0.0;
+  __syncthreads();
+  double lmax = 0.0;
   for (int e = tid; e < n * n; e += nt) {
     int i = e / n, j = e % n;
-    Gs[i * LLD + j] = (i < m && j < m) ? G[static_cast<int64_t>(i) * mp + j] : 0.0;
-    Vs[i * LLD + j] = (i == j) ? 1.0 : 0.0;
+    double g = (i < m && j < m) ? G[static_cast<int64_t>(i) * mp + j] : 0.0;
+    Gs[i * LLD + j] = g;
+    Vs[j * LLD + i] = (i == j) ? 1.0 : 0.0;   // column-major: column j contiguous
+    lmax = fmax(lmax, fabs(g));
   }
+  lmax = fmax(lmax, __shfl_xor(lmax, 32, 64));
+  lmax = fmax(lmax, __shfl_xor(lmax, 16, 64));
+  lmax = fmax(lmax, __shfl_xor(lmax, 8, 64));
+  lmax = fmax(lmax, __shfl_xor(lmax, 4, 64));
+  lmax = fmax(lmax, __shfl_xor(lmax, 2, 64));
+  lmax = fmax(lmax, __shfl_xor(lmax, 1, 64));
+  if ((tid & 63) == 0) atomicMax(reinterpret_cast<unsigned long long*>(&gmax),
+                                 __double_as_longlong(lmax));   // non-negative doubles order as integers
   __syncthreads();
+  // Entries below this are rounding noise of the largest one; never rotate on them.
+  const double floor_abs = 1e-300 + 1e-17 * gmax;
 
   int sweep = 0;
   for (; sweep < kMaxSweeps; ++sweep) {
-    // Convergence: off-diagonal mass against the whole matrix.
-    double off = 0.0, all = 0.0;
-    for (int e = tid; e < n * n; e += nt) {
-      int i = e / n, j = e % n;
-      double g = Gs[i * LLD + j];
-      all += g * g;
-      if (i != j) off += g * g;
-    }
-    off = wave_sum(off);
-    all = wave_sum(all);
-    if ((tid & 63) == 0) { red[tid >> 6] = off; red[16 + (tid >> 6)] = all; }
+    if (tid == 0) nrot = 0;
     __syncthreads();
-    if (tid == 0) {
-      double o = 0.0, a = 0.0;
-      for (int w = 0; w < nt / 64; ++w) { o += red[w]; a += red[16 + w]; }
-      done = (o <= 1e-30 * a) ? 1 : 0;
-    }
-    __syncthreads();
-    if (done) break;
-
     for (int step = 0; step < n - 1; ++step) {
       if (tid < np2) {
-        int p = rr_slot(tid, step, n), q = rr_slot(n - 1 - tid, step, n);
-        double c, s;
-        jacobi_rotation(Gs[p * LLD + p], Gs[q * LLD + q], Gs[p * LLD + q], c, s);
+        int p = rr_fast(tid, step, n), q = rr_fast(n - 1 - tid, step, n);
+        double app = Gs[p * LLD + p], aqq = Gs[q * LLD + q], apq = Gs[p * LLD + q];
+        double c = 1.0, s = 0.0;
+        if (fabs(apq) > floor_abs && fabs(apq) > kLdsTol * sqrt(fabs(app) * fabs(aqq))) {
+          jacobi_rotation(app, aqq, apq, c, s);
+          nrot = 1;
+        }
         cs[tid] = c;
-        cs[np2 + tid] = s;
+        cs[LN / 2 + tid] = s;
+        pi[tid] = static_cast<short>(p);
+        qi[tid] = static_cast<short>(q);
       }
       __syncthreads();
-      for (int e = tid; e < np2 * np2; e += nt) {
-        int a = e / np2, b = e % np2;
-        int pa = rr_slot(a, step, n), qa = rr_slot(n - 1 - a, step, n);
-        int pb = rr_slot(b, step, n), qb = rr_slot(n - 1 - b, step, n);
-        double ca = cs[a], sa = cs[np2 + a], cb = cs[b], sb = cs[np2 + b];
-        double g11 = Gs[pa * LLD + pb], g12 = Gs[pa * LLD + qb];
-        double g21 = Gs[qa * LLD + pb], g22 = Gs[qa * LLD + qb];
-        double r11 = ca * g11 - sa * g21, r12 = ca * g12 - sa * g22;
-        double r21 = sa * g11 + ca * g21, r22 = sa * g12 + ca * g22;
-        Gs[pa * LLD + pb] = cb * r11 - sb * r12;
-        Gs[pa * LLD + qb] = sb * r11 + cb * r12;
-        Gs[qa * LLD + pb] = cb * r21 - sb * r22;
-        Gs[qa * LLD + qb] = sb * r21 + cb * r22;
+      // G <- J^T G J on 2x2 blocks (a <= b; the mirror block is written too).
+      for (int a = tid >> 5; a < np2; a += 32) {
+        const int pa = pi[a], qa = qi[a];
+        const double ca = cs[a], sa = cs[LN / 2 + a];
+        for (int b = (tid & 31) + 0; b < np2; b += 32) {
+          if (b < a) continue;
+          const int pb = pi[b], qb = qi[b];
+          const double cb = cs[b], sb = cs[LN / 2 + b];
+          double g11 = Gs[pa * LLD + pb], g12 = Gs[pa * LLD + qb];
+          double g21 = Gs[qa * LLD + pb], g22 = Gs[qa * LLD + qb];
+          double r11 = ca * g11 - sa * g21, r12 = ca * g12 - sa * g22;
+          double r21 = sa * g11 + ca * g21, r22 = sa * g12 + ca * g22;
+          double n11 = cb * r11 - sb * r12, n12 = sb * r11 + cb * r12;
+          double n21 = cb * r21 - sb * r22, n22 = sb * r21 + cb * r22;
+          Gs[pa * LLD + pb] = n11;
+          Gs[pa * LLD + qb] = n12;
+          Gs[qa * LLD + pb] = n21;
+          Gs[qa * LLD + qb] = n22;
+          if (b != a) {
+            Gs[pb * LLD + pa] = n11;
+            Gs[qb * LLD + pa] = n12;
+            Gs[pb * LLD + qa] = n21;
+            Gs[qb * LLD + qa] = n22;
+          }
+        }
       }
-      for (int e = tid; e < n * np2; e += nt) {
-        int i = e / np2, b = e % np2;
-        int pb = rr_slot(b, step, n), qb = rr_slot(n - 1 - b, step, n);
-        double cb = cs[b], sb = cs[np2 + b];
-        double vp = Vs[i * LLD + pb], vq = Vs[i * LLD + qb];
-        Vs[i * LLD + pb] = cb * vp - sb * vq;
-        Vs[i * LLD + qb] = sb * vp + cb * vq;
+      // V <- V J: lanes run along a column pair, so accesses are contiguous.
+      for (int b = tid >> 7; b < np2; b += 8) {
+        const int pb = pi[b], qb = qi[b];
+        const double cb = cs[b], sb = cs[LN / 2 + b];
+        for (int i = tid & 127; i < n; i += 128) {
+          double vp = Vs[pb * LLD + i], vq = Vs[qb * LLD + i];
+          Vs[pb * LLD + i] = cb * vp - sb * vq;
+          Vs[qb * LLD + i] = sb * vp + cb * vq;
+        }
       }
       __syncthreads();
     }
+    const int rotated = nrot;
+    __syncthreads();            // every thread has read nrot before it is reset
+    if (rotated == 0) break;
   }
-  if (sweep == kMaxSweeps && tid == 0) atomicAdd(&st->eig_unconv, 1);
+  if (tid == 0) {
+    atomicAdd(&st->eig_sweeps, static_cast<unsigned long long>(sweep + 1));
+    if (sweep == kMaxSweeps) atomicAdd(&st->eig_unconv, 1);
+  }
   for (int j = tid; j < m; j += nt) lam[j] = Gs[j * LLD + j];
   for (int64_t e = tid; e < static_cast<int64_t>(mp) * mp; e += nt) {
     int j = static_cast<int>(e / mp), i = static_cast<int>(e % mp);
-    Vout[e] = (i < m && j < m) ? Vs[i * LLD + j] : 0.0;
+    Vout[e] = (i < m && j < m) ? Vs[j * LLD + i] : 0.0;
   }
 }
 
@@ -116,7 +149,7 @@ constexpr int BW = 8;            // block width; a task owns 2 blocks = 16 colum
 constexpr int PMAX = 1024;       // largest mp
 constexpr double kOuterTol = 1e-14;
 constexpr double kInnerTol = 1e-15;
-constexpr int kInnerSweeps = 8;
+constexpr int kInnerSweeps = 1;
 
 struct BlkArgs {
   const double* G;
@@ -129,56 +162,53 @@ struct BlkArgs {
   DevStats* st;
 };
 
-// Inner two-sided Jacobi on the 16x16 H (LDS), accumulating Q.  All 256
-// threads call it; returns after convergence or kInnerSweeps sweeps.
-__device__ void inner_jacobi16(double (*Hs)[17], double (*Qs)[17], double* cs, int* flag) {
-  const int tid = threadIdx.x;
-  for (int e = tid; e < 256; e += blockDim.x) Qs[e >> 4][e & 15] = ((e >> 4) == (e & 15)) ? 1.0 : 0.0;
-  __syncthreads();
+// Inner two-sided Jacobi on the 16x16 H (LDS), accumulating Q, run by wave 0
+// alone (wave-synchronous: LDS operations of one wave complete in order, so a
+// compiler fence is enough between phases).  One sweep per call; the outer
+// iteration revisits the pair until it is orthogonal.
+__device__ __forceinline__ void wave_sync() {
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+  __builtin_amdgcn_wave_barrier();
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+}
+
+__device__ void inner_jacobi16(double (*Hs)[17], double (*Qs)[17], double* cs) {
+  const int lane = threadIdx.x;          // caller guarantees threadIdx.x < 64
+  for (int e = lane; e < 256; e += 64) Qs[e >> 4][e & 15] = ((e >> 4) == (e & 15)) ? 1.0 : 0.0;
+  wave_sync();
   for (int sw = 0; sw < kInnerSweeps; ++sw) {
-    if (tid == 0) *flag = 0;
-    __syncthreads();
-    if (tid < 256) {
-      int p = tid >> 4, q = tid & 15;
-      if (p < q) {
-        double hpq = Hs[p][q], hpp = Hs[p][p], hqq = Hs[q][q];
-        if (fabs(hpq) > kInnerTol * sqrt(fabs(hpp) * fabs(hqq))) *flag = 1;
-      }
-    }
-    __syncthreads();
-    if (*flag == 0) break;
     for (int step = 0; step < 15; ++step) {
-      if (tid < 8) {
-        int p = rr_slot(tid, step, 16), q = rr_slot(15 - tid, step, 16);
+      if (lane < 8) {
+        int p = rr_slot(lane, step, 16), q = rr_slot(15 - lane, step, 16);
         double hpq = Hs[p][q], hpp = Hs[p][p], hqq = Hs[q][q];
-        double c = 1.0, s = 0.0;
-        if (fabs(hpq) > 0.25 * kInnerTol * sqrt(fabs(hpp) * fabs(hqq))) jacobi_rotation(hpp, hqq, hpq, c, s);
-        cs[tid] = c;
-        cs[8 + tid] = s;
+        double c = 1.0, sn = 0.0;
+        if (fabs(hpq) > 0.25 * kInnerTol * sqrt(fabs(hpp) * fabs(hqq))) jacobi_rotation(hpp, hqq, hpq, c, sn);
+        cs[lane] = c;
+        cs[8 + lane] = sn;
       }
-      __syncthreads();
-      if (tid < 64) {
-        int a = tid >> 3, b = tid & 7;
-        int pa = rr_slot(a, step, 16), qa = rr_slot(15 - a, step, 16);
-        int pb = rr_slot(b, step, 16), qb = rr_slot(15 - b, step, 16);
-        double ca = cs[a], sa = cs[8 + a], cb = cs[b], sb = cs[8 + b];
+      wave_sync();
+      {
+        const int a = lane >> 3, b = lane & 7;
+        const int pa = rr_slot(a, step, 16), qa = rr_slot(15 - a, step, 16);
+        const int pb = rr_slot(b, step, 16), qb = rr_slot(15 - b, step, 16);
+        const double ca = cs[a], sa = cs[8 + a], cb = cs[b], sb = cs[8 + b];
         double g11 = Hs[pa][pb], g12 = Hs[pa][qb], g21 = Hs[qa][pb], g22 = Hs[qa][qb];
         double r11 = ca * g11 - sa * g21, r12 = ca * g12 - sa * g22;
         double r21 = sa * g11 + ca * g21, r22 = sa * g12 + ca * g22;
+        // Q <- Q J for rows (lane >> 3) and (lane >> 3) + 8, pair b.
+        const int i0 = lane >> 3;
+        double v0p = Qs[i0][pb], v0q = Qs[i0][qb], v1p = Qs[i0 + 8][pb], v1q = Qs[i0 + 8][qb];
+        wave_sync();
         Hs[pa][pb] = cb * r11 - sb * r12;
         Hs[pa][qb] = sb * r11 + cb * r12;
         Hs[qa][pb] = cb * r21 - sb * r22;
         Hs[qa][qb] = sb * r21 + cb * r22;
-      } else if (tid < 192) {
-        int e = tid - 64;
-        int i = e >> 3, b = e & 7;
-        int pb = rr_slot(b, step, 16), qb = rr_slot(15 - b, step, 16);
-        double cb = cs[b], sb = cs[8 + b];
-        double vp = Qs[i][pb], vq = Qs[i][qb];
-        Qs[i][pb] = cb * vp - sb * vq;
-        Qs[i][qb] = sb * vp + cb * vq;
+        Qs[i0][pb] = cb * v0p - sb * v0q;
+        Qs[i0][qb] = sb * v0p + cb * v0q;
+        Qs[i0 + 8][pb] = cb * v1p - sb * v1q;
+        Qs[i0 + 8][qb] = sb * v1p + cb * v1q;
       }
-      __syncthreads();
+      wave_sync();
     }
   }
 }
@@ -202,6 +232,35 @@ __device__ void panel_times_q(const double* Ps, int ldp, int mp, double (*Qs)[17
   }
 }
 
+// Ps[c*ldp + i] = X[col(c)*mp + i] for the two 8-column blocks bi, bj of a
+// column-major mp x mp matrix; 16-byte loads, 8 in flight per thread.
+__device__ __forceinline__ void load_panel(const double* __restrict__ X, int mp, int ldp, int bi,
+                                           int bj, double* __restrict__ Ps) {
+  const int half = mp >> 1;                       // double2 per column
+  const int total = 16 * half;
+  for (int base = threadIdx.x; base < total; base += 256 * 8) {
+    double2 v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      int e = base + u * 256;
+      if (e < total) {
+        int c = e / half, i2 = e - c * half;
+        int col = (c < 8) ? bi * BW + c : bj * BW + (c - 8);
+        v[u] = reinterpret_cast<const double2*>(X + static_cast<int64_t>(col) * mp)[i2];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      int e = base + u * 256;
+      if (e < total) {
+        int c = e / half, i2 = e - c * half;
+        Ps[c * ldp + 2 * i2] = v[u].x;
+        Ps[c * ldp + 2 * i2 + 1] = v[u].y;
+      }
+    }
+  }
+}
+
 __global__ __launch_bounds__(256) void k_eig_blk(BlkArgs A) {
   const int mp = A.mp;
   const int ldp = mp + 1;
@@ -214,7 +273,6 @@ __global__ __launch_bounds__(256) void k_eig_blk(BlkArgs A) {
   __shared__ double cs[16];
   __shared__ int cols[16];
   __shared__ int flag;
-  __shared__ int iflag;
   const int tid = threadIdx.x;
   const int lane = tid & 63, w = tid >> 6;
   const int li = lane & 15, lk = lane >> 4;
@@ -233,13 +291,9 @@ __global__ __launch_bounds__(256) void k_eig_blk(BlkArgs A) {
     for (int step = 0; step < nb - 1; ++step) {
       const int bi = rr_slot(blockIdx.x, step, nb);
       const int bj = rr_slot(nb - 1 - blockIdx.x, step, nb);
+      // Stage the W panel: every load is issued before any is consumed.
+      load_panel(A.W, mp, ldp, bi, bj, Ps);
       if (tid < 16) cols[tid] = (tid < 8) ? bi * BW + tid : bj * BW + (tid - 8);
-      __syncthreads();
-      // Stage the W panel.
-      for (int e = tid; e < 16 * mp; e += 256) {
-        int c = e / mp, i = e % mp;
-        Ps[c * ldp + i] = A.W[static_cast<int64_t>(cols[c]) * mp + i];
-      }
       __syncthreads();
       // H = P^T P, split over the four waves along the rows.
       {
@@ -268,13 +322,11 @@ __global__ __launch_bounds__(256) void k_eig_blk(BlkArgs A) {
       }
       __syncthreads();
       if (flag) {
-        inner_jacobi16(Hs, Qs, cs, &iflag);
+        if (tid < 64) inner_jacobi16(Hs, Qs, cs);
+        __syncthreads();
         panel_times_q(Ps, ldp, mp, Qs, A.W, cols);
         __syncthreads();
-        for (int e = tid; e < 16 * mp; e += 256) {
-          int c = e / mp, i = e % mp;
-          Ps[c * ldp + i] = A.V[static_cast<int64_t>(cols[c]) * mp + i];
-        }
+        load_panel(A.V, mp, ldp, bi, bj, Ps);
         __syncthreads();
         panel_times_q(Ps, ldp, mp, Qs, A.V, cols);
         if (tid == 0) atomicAdd(&A.rot[sweep], 1);
@@ -284,7 +336,10 @@ __global__ __launch_bounds__(256) void k_eig_blk(BlkArgs A) {
     int r = __hip_atomic_load(&A.rot[sweep], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
     if (r == 0) break;
   }
-  if (sweep == kMaxSweeps && blockIdx.x == 0 && tid == 0) atomicAdd(&A.st->eig_unconv, 1);
+  if (blockIdx.x == 0 && tid == 0) {
+    atomicAdd(&A.st->eig_sweeps, static_cast<unsigned long long>(sweep + 1));
+    if (sweep == kMaxSweeps) atomicAdd(&A.st->eig_unconv, 1);
+  }
   if (blockIdx.x == 0 && tid == 0) {
     int e = __hip_atomic_load(A.bar.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     if (e) A.st->bar_err = 1;

@@ -269,7 +269,27 @@ __global__ void k_transpose(const double* __restrict__ in, int mp, int n, double
   }
 }
 
+__global__ void k_convert_f64(const void* __restrict__ X, int dt, int64_t ldx, int64_t rows, int d,
+                              double* __restrict__ out) {
+  const int64_t n = rows * d;
+  for (int64_t e = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; e < n;
+       e += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    int64_t r = e / d;
+    int c = static_cast<int>(e % d);
+    out[e] = load_as_f64(X, r * ldx + c, dt);
+  }
+}
+
 // ------------------------------------------------------------ launchers
+hipError_t launch_convert_f64(const void* X, int dt, int64_t ldx, int64_t rows, int d, double* out,
+                              hipStream_t s) {
+  int64_t n = rows * d;
+  int blocks = static_cast<int>(std::min<int64_t>((n + 255) / 256, 4096));
+  if (blocks <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_convert_f64, dim3(blocks), dim3(256), 0, s, X, dt, ldx, rows, d, out);
+  return hipGetLastError();
+}
+
 hipError_t launch_transpose(const double* in, int mp, int n, double* out, hipStream_t s) {
   int64_t tot = static_cast<int64_t>(n) * n;
   int blocks = static_cast<int>(std::min<int64_t>((tot + 255) / 256, 4096));

@@ -25,7 +25,7 @@ ERRORS = {0: "OK", -1: "EINVAL", -2: "ESTATE", -3: "ENOMEM", -4: "EDEVICE", -5: 
 # Every symbol the header declares (checked by the CPU test-suite).
 EXPORTS = ("sketch_create", "sketch_append_rows", "sketch_finalize", "sketch_error",
            "fdsk_evaluate", "sketch_stats", "sketch_destroy", "sketch_last_error", "fdsk_version",
-           "fdsk_gram", "fdsk_eigh")
+           "fdsk_gram", "fdsk_eigh", "sketch_reset", "sketch_profile")
 
 
 class FdskConfig(ctypes.Structure):
@@ -41,10 +41,19 @@ class FdskReport(ctypes.Structure):
                 ("shrink_total", ctypes.c_double), ("lambda_max", ctypes.c_double),
                 ("lambda_min", ctypes.c_double), ("n_rows", ctypes.c_int64),
                 ("n_reduce", ctypes.c_int64), ("k", ctypes.c_int32), ("rows_out", ctypes.c_int32),
-                ("eig_unconverged", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("eig_unconverged", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("eig_sweeps", ctypes.c_int64)]
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_ if name != "reserved"}
+
+
+STAGES = ("ingest", "gram", "eig", "shrink", "rebuild")
+FLAG_PROFILE = 1
+
+
+class FdskProfile(ctypes.Structure):
+    _fields_ = [("ms", ctypes.c_double * 5), ("launches", ctypes.c_int64 * 5)]
 
 
 class FdskError(RuntimeError):
@@ -90,9 +99,12 @@ def lib():
     L.sketch_last_error.restype = ctypes.c_char_p
     L.fdsk_version.restype = ctypes.c_char_p
     L.fdsk_gram.argtypes = [vp, i32, i64, i64, vp, i64, vp]
+    L.sketch_reset.argtypes = [vp]
+    L.sketch_profile.argtypes = [vp, ctypes.POINTER(FdskProfile)]
     L.fdsk_eigh.argtypes = [vp, i32, i64, vp, vp, i64, vp]
     for f in ("sketch_create", "sketch_append_rows", "sketch_finalize", "sketch_error",
-              "fdsk_evaluate", "sketch_stats", "fdsk_gram", "fdsk_eigh"):
+              "fdsk_evaluate", "sketch_stats", "fdsk_gram", "fdsk_eigh", "sketch_reset",
+              "sketch_profile"):
         getattr(L, f).restype = cint
     _lib = L
     return L
@@ -143,10 +155,10 @@ class FDSketch:
     """One streaming sketch (Algorithm 1 with the chosen ReduceRank rule)."""
 
     def __init__(self, d, l, variant="fd", alpha=0.2, buffer_rows=0, precision="fp64",
-                 stream=None):
+                 stream=None, profile=False):
         self.d, self.l = int(d), int(l)
         cfg = FdskConfig(self.d, self.l, int(buffer_rows), VARIANTS[variant], float(alpha),
-                         PRECISIONS[precision], 0)
+                         PRECISIONS[precision], FLAG_PROFILE if profile else 0)
         self._stream = stream
         h = ctypes.c_void_p()
         _check(lib().sketch_create(ctypes.byref(cfg), _stream_handle(stream), ctypes.byref(h)))
@@ -167,6 +179,16 @@ class FDSketch:
                                      _dtype_code(out), mem, ctypes.byref(rows)), self._h)
         self.rows_out = rows.value
         return out
+
+    def reset(self):
+        _check(lib().sketch_reset(self._h), self._h)
+        return self
+
+    def profile(self):
+        """{stage: (total_ms, launches)} since create/reset (needs profile=True)."""
+        p = FdskProfile()
+        _check(lib().sketch_profile(self._h, ctypes.byref(p)), self._h)
+        return {name: (p.ms[i], p.launches[i]) for i, name in enumerate(STAGES)}
 
     def stats(self):
         rep = FdskReport()

@@ -35,7 +35,7 @@ def test_library_exports_every_declared_symbol():
     (dict(d=10, l=8, variant=7), -1),
     (dict(d=10, l=8, variant=2, alpha=0.0), -1),
     (dict(d=10, l=8, variant=3, alpha=1.5), -1),
-    (dict(d=10, l=8, flags=1), -1),
+    (dict(d=10, l=8, flags=6), -1),
     (dict(d=70000, l=8), -1),
 ])
 def test_create_rejects_bad_config(cfg, code):
@@ -60,4 +60,4 @@ def test_null_handles_are_rejected():
 
 def test_struct_layouts_match_header():
     assert ctypes.sizeof(F.FdskConfig) == 40
-    assert ctypes.sizeof(F.FdskReport) == 9 * 8 + 2 * 8 + 4 * 4
+    assert ctypes.sizeof(F.FdskReport) == 9 * 8 + 2 * 8 + 4 * 4 + 8

@@ -1,0 +1,64 @@
+"""Device evaluator of the Section 1.1 error measures against the oracle's
+dense FP64 evaluator on the same (A, B)."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1501_06561_amd import synth
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from paper_1501_06561_amd import fdsketch as F  # noqa: E402
+
+
+def _ref(A, B, k=10):
+    return oracle.cov_err(A, B), oracle.proj_err(A, B, k), oracle.proj_full(A, B)
+
+
+@pytest.mark.parametrize("method", [0, 1])
+@pytest.mark.parametrize("n,d,l", [(3000, 150, 20), (2500, 700, 40), (800, 64, 70)])
+def test_evaluate_matches_oracle(method, n, d, l):
+    A = synth.random_noisy(n, d, 8, 10.0, seed=(40, d))
+    B = oracle.fd_sketch(A, l)
+    rep = F.evaluate(torch.from_numpy(A).cuda(), torch.from_numpy(B).cuda(), k=10, method=method)
+    ce, pe, pf = _ref(A, B)
+    assert abs(rep["cov_err"] - ce) <= 1e-9 * ce + 1e-13
+    assert abs(rep["proj_err_k"] - pe) <= 1e-8 * pe
+    assert abs(rep["proj_full_over_fro2"] - pf) <= 1e-8 * max(pf, 1e-6) + 1e-12
+    assert abs(rep["fro2_A"] - oracle.fro2(A)) <= 1e-12 * oracle.fro2(A)
+
+
+def test_evaluate_host_inputs_and_fp32():
+    A = synth.random_noisy(1200, 90, 6, 10.0, seed=(41, 0)).astype(np.float32)
+    B = oracle.fd_sketch(A.astype(np.float64), 12).astype(np.float32)
+    rep = F.evaluate(A, B, k=5)
+    ce = oracle.cov_err(A.astype(np.float64), B.astype(np.float64))
+    assert abs(rep["cov_err"] - ce) <= 1e-9 * ce
+
+
+def test_empty_sketch_gives_numeric_rank_inverse():
+    A = synth.random_noisy(900, 50, 5, 10.0, seed=(42, 0))
+    s = np.linalg.svd(A, compute_uv=False)
+    rep = F.evaluate(torch.from_numpy(A).cuda(), torch.zeros(0, 50, dtype=torch.float64, device="cuda"))
+    assert abs(rep["cov_err"] - s[0] ** 2 / np.sum(s ** 2)) <= 1e-10
+
+
+def test_sketch_error_end_to_end():
+    A = synth.random_noisy(5000, 120, 10, 10.0, seed=(43, 0))
+    sk = F.FDSketch(120, 16, "alpha", 0.2)
+    At = torch.from_numpy(A).cuda()
+    sk.append(At)
+    B = sk.finalize().cpu().numpy()
+    rep = sk.error(At, k=10, method=0)
+    ce, pe, pf = _ref(A, B)
+    assert abs(rep["cov_err"] - ce) <= 1e-9 * ce
+    assert abs(rep["proj_err_k"] - pe) <= 1e-8 * pe
+    assert rep["n_reduce"] > 0 and rep["delta_sum"] > 0
+
+
+def test_zero_matrix_is_rejected():
+    with pytest.raises(F.FdskError) as e:
+        F.evaluate(torch.zeros(10, 8, dtype=torch.float64, device="cuda"),
+                   torch.zeros(2, 8, dtype=torch.float64, device="cuda"))
+    assert e.value.code == -1
