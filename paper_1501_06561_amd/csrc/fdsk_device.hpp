@@ -89,16 +89,44 @@ __device__ __forceinline__ void grid_barrier(const GridBar& b, unsigned nblocks)
   __syncthreads();
 }
 
+// Reciprocal and reciprocal square root from the hardware estimates refined
+// by two Newton steps (each doubles the correct bits), in place of the longer
+// IEEE-exact division and square-root sequences.  Arguments are >= 1 or
+// well inside the normal range where they are used.
+__device__ __forceinline__ double rcp_nr(double x) {
+  double y = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, y, 1.0);
+  y = fma(y, e, y);
+  e = fma(-x, y, 1.0);
+  return fma(y, e, y);
+}
+__device__ __forceinline__ double rsq_nr(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  const double h = 0.5 * x;
+  y = y * fma(-h * y, y, 1.5);
+  return y * fma(-h * y, y, 1.5);
+}
+
 // Stable Jacobi rotation (Rutishauser) annihilating the (p,q) entry of the
 // symmetric 2x2 [[app, apq], [apq, aqq]]:  J = [[c, s], [-s, c]], and
-// J^T [[app, apq],[apq, aqq]] J is diagonal.
+// J^T [[app, apq],[apq, aqq]] J is diagonal.  With zeta = (aqq-app)/(2 apq),
+// t = sign(zeta) / (|zeta| + sqrt(1 + zeta^2)) is the smaller root of
+// t^2 + 2 zeta t - 1 = 0, c = 1/sqrt(1+t^2), s = t c.
 __device__ __forceinline__ void jacobi_rotation(double app, double aqq, double apq,
                                                 double& c, double& s) {
   if (apq == 0.0) { c = 1.0; s = 0.0; return; }
-  double theta = (aqq - app) / (2.0 * apq);
-  double t = 1.0 / (fabs(theta) + sqrt(1.0 + theta * theta));
-  if (theta < 0.0) t = -t;
-  c = 1.0 / sqrt(1.0 + t * t);
+  const double diff = aqq - app;
+  double t;
+  if (fabs(diff) > 1e150 * fabs(apq)) {
+    t = apq / diff;                       // |zeta| huge: t -> 1/(2 zeta)
+  } else {
+    const double zeta = diff * rcp_nr(2.0 * apq);
+    const double z2 = fma(zeta, zeta, 1.0);
+    const double w = z2 * rsq_nr(z2);    // sqrt(1 + zeta^2)
+    t = rcp_nr(fabs(zeta) + w);
+    if (zeta < 0.0) t = -t;
+  }
+  c = rsq_nr(fma(t, t, 1.0));
   s = t * c;
 }
 

@@ -81,7 +81,7 @@ __global__ __launch_bounds__(1024) void k_eig_lds(const double* __restrict__ G, 
         int p = rr_fast(tid, step, n), q = rr_fast(n - 1 - tid, step, n);
         double app = Gs[p * LLD + p], aqq = Gs[q * LLD + q], apq = Gs[p * LLD + q];
         double c = 1.0, s = 0.0;
-        if (fabs(apq) > floor_abs && fabs(apq) > kLdsTol * sqrt(fabs(app) * fabs(aqq))) {
+        if (fabs(apq) > floor_abs && apq * apq > (kLdsTol * kLdsTol) * fabs(app * aqq)) {
           jacobi_rotation(app, aqq, apq, c, s);
           nrot = 1;
         }
@@ -182,7 +182,7 @@ __device__ void inner_jacobi16(double (*Hs)[17], double (*Qs)[17], double* cs) {
         int p = rr_slot(lane, step, 16), q = rr_slot(15 - lane, step, 16);
         double hpq = Hs[p][q], hpp = Hs[p][p], hqq = Hs[q][q];
         double c = 1.0, sn = 0.0;
-        if (fabs(hpq) > 0.25 * kInnerTol * sqrt(fabs(hpp) * fabs(hqq))) jacobi_rotation(hpp, hqq, hpq, c, sn);
+        if (hpq * hpq > (0.0625 * kInnerTol * kInnerTol) * fabs(hpp * hqq)) jacobi_rotation(hpp, hqq, hpq, c, sn);
         cs[lane] = c;
         cs[8 + lane] = sn;
       }
@@ -261,6 +261,9 @@ __device__ __forceinline__ void load_panel(const double* __restrict__ X, int mp,
   }
 }
 
+// PREF: the V panel (mp <= 512) is fetched into registers together with the W
+// panel, so its latency overlaps the Gram and inner solve.
+template <bool PREF>
 __global__ __launch_bounds__(256) void k_eig_blk(BlkArgs A) {
   const int mp = A.mp;
   const int ldp = mp + 1;
@@ -292,6 +295,19 @@ __global__ __launch_bounds__(256) void k_eig_blk(BlkArgs A) {
       const int bi = rr_slot(blockIdx.x, step, nb);
       const int bj = rr_slot(nb - 1 - blockIdx.x, step, nb);
       // Stage the W panel: every load is issued before any is consumed.
+      double2 vreg[PREF ? 16 : 1];
+      const int half = mp >> 1;
+      if (PREF) {
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+          int e = tid + u * 256;
+          if (e < 16 * half) {
+            int c = e / half, i2 = e - c * half;
+            int col = (c < 8) ? bi * BW + c : bj * BW + (c - 8);
+            vreg[u] = reinterpret_cast<const double2*>(A.V + static_cast<int64_t>(col) * mp)[i2];
+          }
+        }
+      }
       load_panel(A.W, mp, ldp, bi, bj, Ps);
       if (tid < 16) cols[tid] = (tid < 8) ? bi * BW + tid : bj * BW + (tid - 8);
       __syncthreads();
@@ -317,7 +333,7 @@ __global__ __launch_bounds__(256) void k_eig_blk(BlkArgs A) {
         int p = tid >> 4, q = tid & 15;
         if (p < q) {
           double hpq = Hs[p][q], hpp = Hs[p][p], hqq = Hs[q][q];
-          if (hpp > 0.0 && hqq > 0.0 && fabs(hpq) > kOuterTol * sqrt(hpp * hqq)) flag = 1;
+          if (hpp > 0.0 && hqq > 0.0 && hpq * hpq > (kOuterTol * kOuterTol) * (hpp * hqq)) flag = 1;
         }
       }
       __syncthreads();
@@ -326,7 +342,19 @@ __global__ __launch_bounds__(256) void k_eig_blk(BlkArgs A) {
         __syncthreads();
         panel_times_q(Ps, ldp, mp, Qs, A.W, cols);
         __syncthreads();
-        load_panel(A.V, mp, ldp, bi, bj, Ps);
+        if (PREF) {
+#pragma unroll
+          for (int u = 0; u < 16; ++u) {
+            int e = tid + u * 256;
+            if (e < 16 * half) {
+              int c = e / half, i2 = e - c * half;
+              Ps[c * ldp + 2 * i2] = vreg[u].x;
+              Ps[c * ldp + 2 * i2 + 1] = vreg[u].y;
+            }
+          }
+        } else {
+          load_panel(A.V, mp, ldp, bi, bj, Ps);
+        }
         __syncthreads();
         panel_times_q(Ps, ldp, mp, Qs, A.V, cols);
         if (tid == 0) atomicAdd(&A.rot[sweep], 1);
@@ -368,8 +396,9 @@ hipError_t launch_eig(const double* G, int m, int mp, double* lam, double* V, Ei
   a.bar.count = wk.bar; a.bar.gen = wk.bar + 1; a.bar.err = reinterpret_cast<int*>(wk.bar + 2);
   a.rot = wk.rot; a.st = wk.st;
   void* args[] = {&a};
-  return hipLaunchCooperativeKernel(reinterpret_cast<void*>(k_eig_blk), dim3(mp / 16), dim3(256),
-                                    args, 0, s);
+  void* fn = (mp <= 512) ? reinterpret_cast<void*>(k_eig_blk<true>)
+                         : reinterpret_cast<void*>(k_eig_blk<false>);
+  return hipLaunchCooperativeKernel(fn, dim3(mp / 16), dim3(256), args, 0, s);
 }
 
 }  // namespace fdsk
