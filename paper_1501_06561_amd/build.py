@@ -27,7 +27,8 @@ FLAGS = [
     "-Wall", "-Wno-unused-function",
     "-I" + os.path.join(ROOT, "include"), "-I" + CSRC,
 ]
-SOURCES = ["kernels_stream.hip", "kernels_eig.hip", "kernels_eval.hip", "eval_host.cpp", "fdsketch.cpp"]
+SOURCES = ["kernels_stream.hip", "kernels_eig.hip", "kernels_eval.hip", "kernels_batch.hip",
+           "eval_host.cpp", "batch_host.cpp", "fdsketch.cpp"]
 
 
 def _compile(src: str) -> str:

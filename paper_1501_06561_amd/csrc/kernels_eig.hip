@@ -1,41 +1,17 @@
 // FP64 symmetric eigensolvers for the m x m Gram matrix of the sketch buffer.
 //
-// The buffer's SVD (Algorithm 1) is reached through G = C C^T = U diag(lambda) U^T:
-// sigma_j^2 = lambda_j and the rebuilt rows are diag(sigma'/sigma) U^T C.
-//
 // * k_eig_lds  (m <= 100): cyclic two-sided Jacobi in one workgroup with G and
-//   V resident in LDS; each step rotates n/2 disjoint index pairs (round-robin
-//   ordering) and updates every 2x2 block of G independently.
+//   V resident in LDS (eig_lds_body).
 // * k_eig_blk  (m <= 1024): one-sided block Jacobi (Hestenes) on W = G with
 //   V accumulated.  A task orthogonalises a 16-column panel (two 8-column
-//   blocks): H = P^T P on matrix cores, a two-sided Jacobi on the 16x16 H in
-//   LDS gives Q, then P <- P Q and V_panel <- V_panel Q on matrix cores.
+//   blocks): H = P^T P on matrix cores, a two-sided Jacobi sweep on the 16x16
+//   H gives Q, then P <- P Q and V_panel <- V_panel Q on matrix cores.
 //   mp/16 workgroups run the disjoint block pairs of one round-robin step in
 //   parallel, with a grid barrier between steps; a sweep with no rotation ends
 //   the solve.  At convergence W = V diag(lambda) and lambda_j = v_j . w_j.
-#include "fdsk_device.hpp"
-#include "fdsk_kernels.hpp"
+#include "fdsk_jacobi.hpp"
 
 namespace fdsk {
-
-// Round-robin ("circle") ordering of n (even) indices: step s pairs position
-// k with position n-1-k of [0, 1+(s mod n-1), 1+(s+1 mod n-1), ...].
-__device__ __forceinline__ int rr_slot(int pos, int step, int n) {
-  return pos == 0 ? 0 : 1 + (pos - 1 + step) % (n - 1);
-}
-
-// ------------------------------------------------------------- LDS solver
-constexpr int LN = kLdsEigMax;       // max n
-constexpr int LLD = LN + 1;
-constexpr double kLdsTol = 1e-15;    // rotate (p,q) only if |g_pq| > tol*sqrt(|g_pp g_qq|)
-
-// Index at slot `pos` of the round-robin ordering (no integer division).
-__device__ __forceinline__ int rr_fast(int pos, int step, int n) {
-  if (pos == 0) return 0;
-  int s = pos - 1 + step;
-  if (s >= n - 1) s -= n - 1;
-  return 1 + s;
-}
 
 __global__ __launch_bounds__(1024) void k_eig_lds(const double* __restrict__ G, int m, int mp,
                                                   double* __restrict__ lam,
@@ -47,109 +23,10 @@ __global__ __launch_bounds__(1024) void k_eig_lds(const double* __restrict__ G, 
   __shared__ short pi[LN / 2], qi[LN / 2];
   __shared__ int nrot;
   __shared__ double gmax;
-  const int n = (m + 1) & ~1;
-  const int np2 = n / 2;
-  const int tid = threadIdx.x, nt = blockDim.x;
-  if (tid == 0) gmax = 0.0;
-  __syncthreads();
-  double lmax = 0.0;
-  for (int e = tid; e < n * n; e += nt) {
-    int i = e / n, j = e % n;
-    double g = (i < m && j < m) ? G[static_cast<int64_t>(i) * mp + j] : 0.0;
-    Gs[i * LLD + j] = g;
-    Vs[j * LLD + i] = (i == j) ? 1.0 : 0.0;   // column-major: column j contiguous
-    lmax = fmax(lmax, fabs(g));
-  }
-  lmax = fmax(lmax, __shfl_xor(lmax, 32, 64));
-  lmax = fmax(lmax, __shfl_xor(lmax, 16, 64));
-  lmax = fmax(lmax, __shfl_xor(lmax, 8, 64));
-  lmax = fmax(lmax, __shfl_xor(lmax, 4, 64));
-  lmax = fmax(lmax, __shfl_xor(lmax, 2, 64));
-  lmax = fmax(lmax, __shfl_xor(lmax, 1, 64));
-  if ((tid & 63) == 0) atomicMax(reinterpret_cast<unsigned long long*>(&gmax),
-                                 __double_as_longlong(lmax));   // non-negative doubles order as integers
-  __syncthreads();
-  // Entries below this are rounding noise of the largest one; never rotate on them.
-  const double floor_abs = 1e-300 + 1e-17 * gmax;
-
-  int sweep = 0;
-  for (; sweep < kMaxSweeps; ++sweep) {
-    if (tid == 0) nrot = 0;
-    __syncthreads();
-    for (int step = 0; step < n - 1; ++step) {
-      if (tid < np2) {
-        int p = rr_fast(tid, step, n), q = rr_fast(n - 1 - tid, step, n);
-        double app = Gs[p * LLD + p], aqq = Gs[q * LLD + q], apq = Gs[p * LLD + q];
-        double c = 1.0, s = 0.0;
-        if (fabs(apq) > floor_abs && apq * apq > (kLdsTol * kLdsTol) * fabs(app * aqq)) {
-          jacobi_rotation(app, aqq, apq, c, s);
-          nrot = 1;
-        }
-        cs[tid] = c;
-        cs[LN / 2 + tid] = s;
-        pi[tid] = static_cast<short>(p);
-        qi[tid] = static_cast<short>(q);
-      }
-      __syncthreads();
-      // G <- J^T G J on 2x2 blocks (a <= b; the mirror block is written too).
-      for (int a = tid >> 5; a < np2; a += 32) {
-        const int pa = pi[a], qa = qi[a];
-        const double ca = cs[a], sa = cs[LN / 2 + a];
-        for (int b = (tid & 31) + 0; b < np2; b += 32) {
-          if (b < a) continue;
-          const int pb = pi[b], qb = qi[b];
-          const double cb = cs[b], sb = cs[LN / 2 + b];
-          double g11 = Gs[pa * LLD + pb], g12 = Gs[pa * LLD + qb];
-          double g21 = Gs[qa * LLD + pb], g22 = Gs[qa * LLD + qb];
-          double r11 = ca * g11 - sa * g21, r12 = ca * g12 - sa * g22;
-          double r21 = sa * g11 + ca * g21, r22 = sa * g12 + ca * g22;
-          double n11 = cb * r11 - sb * r12, n12 = sb * r11 + cb * r12;
-          double n21 = cb * r21 - sb * r22, n22 = sb * r21 + cb * r22;
-          Gs[pa * LLD + pb] = n11;
-          Gs[pa * LLD + qb] = n12;
-          Gs[qa * LLD + pb] = n21;
-          Gs[qa * LLD + qb] = n22;
-          if (b != a) {
-            Gs[pb * LLD + pa] = n11;
-            Gs[qb * LLD + pa] = n12;
-            Gs[pb * LLD + qa] = n21;
-            Gs[qb * LLD + qa] = n22;
-          }
-        }
-      }
-      // V <- V J: lanes run along a column pair, so accesses are contiguous.
-      for (int b = tid >> 7; b < np2; b += 8) {
-        const int pb = pi[b], qb = qi[b];
-        const double cb = cs[b], sb = cs[LN / 2 + b];
-        for (int i = tid & 127; i < n; i += 128) {
-          double vp = Vs[pb * LLD + i], vq = Vs[qb * LLD + i];
-          Vs[pb * LLD + i] = cb * vp - sb * vq;
-          Vs[qb * LLD + i] = sb * vp + cb * vq;
-        }
-      }
-      __syncthreads();
-    }
-    const int rotated = nrot;
-    __syncthreads();            // every thread has read nrot before it is reset
-    if (rotated == 0) break;
-  }
-  if (tid == 0) {
-    atomicAdd(&st->eig_sweeps, static_cast<unsigned long long>(sweep + 1));
-    if (sweep == kMaxSweeps) atomicAdd(&st->eig_unconv, 1);
-  }
-  for (int j = tid; j < m; j += nt) lam[j] = Gs[j * LLD + j];
-  for (int64_t e = tid; e < static_cast<int64_t>(mp) * mp; e += nt) {
-    int j = static_cast<int>(e / mp), i = static_cast<int>(e % mp);
-    Vout[e] = (i < m && j < m) ? Vs[j * LLD + i] : 0.0;
-  }
+  eig_lds_body(G, m, mp, lam, Vout, st, LdsEigSmem{Gs, Vs, cs, pi, qi, &nrot, &gmax});
 }
 
-// ------------------------------------------------------- block solver
-constexpr int BW = 8;            // block width; a task owns 2 blocks = 16 columns
-constexpr int PMAX = 1024;       // largest mp
-constexpr double kOuterTol = 1e-14;
-constexpr double kInnerTol = 1e-15;
-constexpr int kInnerSweeps = 1;
+constexpr int PMAX = 1024;       // largest mp of the block solver
 
 struct BlkArgs {
   const double* G;
@@ -162,60 +39,9 @@ struct BlkArgs {
   DevStats* st;
 };
 
-// Inner two-sided Jacobi on the 16x16 H (LDS), accumulating Q, run by wave 0
-// alone (wave-synchronous: LDS operations of one wave complete in order, so a
-// compiler fence is enough between phases).  One sweep per call; the outer
-// iteration revisits the pair until it is orthogonal.
-__device__ __forceinline__ void wave_sync() {
-  __atomic_signal_fence(__ATOMIC_SEQ_CST);
-  __builtin_amdgcn_wave_barrier();
-  __atomic_signal_fence(__ATOMIC_SEQ_CST);
-}
-
-__device__ void inner_jacobi16(double (*Hs)[17], double (*Qs)[17], double* cs) {
-  const int lane = threadIdx.x;          // caller guarantees threadIdx.x < 64
-  for (int e = lane; e < 256; e += 64) Qs[e >> 4][e & 15] = ((e >> 4) == (e & 15)) ? 1.0 : 0.0;
-  wave_sync();
-  for (int sw = 0; sw < kInnerSweeps; ++sw) {
-    for (int step = 0; step < 15; ++step) {
-      if (lane < 8) {
-        int p = rr_slot(lane, step, 16), q = rr_slot(15 - lane, step, 16);
-        double hpq = Hs[p][q], hpp = Hs[p][p], hqq = Hs[q][q];
-        double c = 1.0, sn = 0.0;
-        if (hpq * hpq > (0.0625 * kInnerTol * kInnerTol) * fabs(hpp * hqq)) jacobi_rotation(hpp, hqq, hpq, c, sn);
-        cs[lane] = c;
-        cs[8 + lane] = sn;
-      }
-      wave_sync();
-      {
-        const int a = lane >> 3, b = lane & 7;
-        const int pa = rr_slot(a, step, 16), qa = rr_slot(15 - a, step, 16);
-        const int pb = rr_slot(b, step, 16), qb = rr_slot(15 - b, step, 16);
-        const double ca = cs[a], sa = cs[8 + a], cb = cs[b], sb = cs[8 + b];
-        double g11 = Hs[pa][pb], g12 = Hs[pa][qb], g21 = Hs[qa][pb], g22 = Hs[qa][qb];
-        double r11 = ca * g11 - sa * g21, r12 = ca * g12 - sa * g22;
-        double r21 = sa * g11 + ca * g21, r22 = sa * g12 + ca * g22;
-        // Q <- Q J for rows (lane >> 3) and (lane >> 3) + 8, pair b.
-        const int i0 = lane >> 3;
-        double v0p = Qs[i0][pb], v0q = Qs[i0][qb], v1p = Qs[i0 + 8][pb], v1q = Qs[i0 + 8][qb];
-        wave_sync();
-        Hs[pa][pb] = cb * r11 - sb * r12;
-        Hs[pa][qb] = sb * r11 + cb * r12;
-        Hs[qa][pb] = cb * r21 - sb * r22;
-        Hs[qa][qb] = sb * r21 + cb * r22;
-        Qs[i0][pb] = cb * v0p - sb * v0q;
-        Qs[i0][qb] = sb * v0p + cb * v0q;
-        Qs[i0 + 8][pb] = cb * v1p - sb * v1q;
-        Qs[i0 + 8][qb] = sb * v1p + cb * v1q;
-      }
-      wave_sync();
-    }
-  }
-}
-
-// out[:, cols] = P * Q for the mp x 16 panel in LDS (column c at Ps[c*ldp+i]).
-__device__ void panel_times_q(const double* Ps, int ldp, int mp, double (*Qs)[17], double* out,
-                              const int* cols) {
+// out[:, cols] = P * Q for the mp x 16 panel in LDS, four waves.
+__device__ void block_panel_times_q(const double* Ps, int ldp, int mp, const double* Qs, double* out,
+                                    const int* cols) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int li = lane & 15, lk = lane >> 4;
   for (int i0 = w * 16; i0 < mp; i0 += 64) {
@@ -223,7 +49,7 @@ __device__ void panel_times_q(const double* Ps, int ldp, int mp, double (*Qs)[17
 #pragma unroll
     for (int k0 = 0; k0 < 16; k0 += 4) {
       double a = Ps[(k0 + lk) * ldp + i0 + li];
-      double b = Qs[k0 + lk][li];
+      double b = Qs[(k0 + lk) * 17 + li];
       acc = mfma_f64(a, b, acc);
     }
     double* o = out + static_cast<int64_t>(cols[li]) * mp + i0 + lk;
@@ -232,11 +58,10 @@ __device__ void panel_times_q(const double* Ps, int ldp, int mp, double (*Qs)[17
   }
 }
 
-// Ps[c*ldp + i] = X[col(c)*mp + i] for the two 8-column blocks bi, bj of a
-// column-major mp x mp matrix; 16-byte loads, 8 in flight per thread.
+// Ps[c*ldp + i] = X[col(c)*mp + i]; 16-byte loads, 8 in flight per thread.
 __device__ __forceinline__ void load_panel(const double* __restrict__ X, int mp, int ldp, int bi,
                                            int bj, double* __restrict__ Ps) {
-  const int half = mp >> 1;                       // double2 per column
+  const int half = mp >> 1;
   const int total = 16 * half;
   for (int base = threadIdx.x; base < total; base += 256 * 8) {
     double2 v[8];
@@ -245,8 +70,7 @@ __device__ __forceinline__ void load_panel(const double* __restrict__ X, int mp,
       int e = base + u * 256;
       if (e < total) {
         int c = e / half, i2 = e - c * half;
-        int col = (c < 8) ? bi * BW + c : bj * BW + (c - 8);
-        v[u] = reinterpret_cast<const double2*>(X + static_cast<int64_t>(col) * mp)[i2];
+        v[u] = reinterpret_cast<const double2*>(X + static_cast<int64_t>(panel_col(c, bi, bj)) * mp)[i2];
       }
     }
 #pragma unroll
@@ -271,8 +95,8 @@ __global__ __launch_bounds__(256) void k_eig_blk(BlkArgs A) {
   const unsigned nwg = gridDim.x;
   __shared__ double Ps[16 * (PMAX + 1)];
   __shared__ double Hp[4][256];
-  __shared__ double Hs[16][17];
-  __shared__ double Qs[16][17];
+  __shared__ double Hs[16 * 17];
+  __shared__ double Qs[16 * 17];
   __shared__ double cs[16];
   __shared__ int cols[16];
   __shared__ int flag;
@@ -326,13 +150,13 @@ __global__ __launch_bounds__(256) void k_eig_blk(BlkArgs A) {
       __syncthreads();
       {
         double h = (Hp[0][tid] + Hp[1][tid]) + (Hp[2][tid] + Hp[3][tid]);
-        Hs[tid >> 4][tid & 15] = h;
+        Hs[(tid >> 4) * 17 + (tid & 15)] = h;
       }
       __syncthreads();
       {
         int p = tid >> 4, q = tid & 15;
         if (p < q) {
-          double hpq = Hs[p][q], hpp = Hs[p][p], hqq = Hs[q][q];
+          double hpq = Hs[p * 17 + q], hpp = Hs[p * 17 + p], hqq = Hs[q * 17 + q];
           if (hpp > 0.0 && hqq > 0.0 && hpq * hpq > (kOuterTol * kOuterTol) * (hpp * hqq)) flag = 1;
         }
       }
@@ -340,7 +164,7 @@ __global__ __launch_bounds__(256) void k_eig_blk(BlkArgs A) {
       if (flag) {
         if (tid < 64) inner_jacobi16(Hs, Qs, cs);
         __syncthreads();
-        panel_times_q(Ps, ldp, mp, Qs, A.W, cols);
+        block_panel_times_q(Ps, ldp, mp, Qs, A.W, cols);
         __syncthreads();
         if (PREF) {
 #pragma unroll
@@ -356,7 +180,7 @@ __global__ __launch_bounds__(256) void k_eig_blk(BlkArgs A) {
           load_panel(A.V, mp, ldp, bi, bj, Ps);
         }
         __syncthreads();
-        panel_times_q(Ps, ldp, mp, Qs, A.V, cols);
+        block_panel_times_q(Ps, ldp, mp, Qs, A.V, cols);
         if (tid == 0) atomicAdd(&A.rot[sweep], 1);
       }
       grid_barrier(A.bar, nwg);

@@ -25,7 +25,9 @@ ERRORS = {0: "OK", -1: "EINVAL", -2: "ESTATE", -3: "ENOMEM", -4: "EDEVICE", -5: 
 # Every symbol the header declares (checked by the CPU test-suite).
 EXPORTS = ("sketch_create", "sketch_append_rows", "sketch_finalize", "sketch_error",
            "fdsk_evaluate", "sketch_stats", "sketch_destroy", "sketch_last_error", "fdsk_version",
-           "fdsk_gram", "fdsk_eigh", "sketch_reset", "sketch_profile")
+           "fdsk_gram", "fdsk_eigh", "sketch_reset", "sketch_profile", "sketch_batch_create",
+           "sketch_batch_append", "sketch_batch_finalize", "sketch_batch_stats",
+           "sketch_batch_destroy", "sketch_batch_last_error")
 
 
 class FdskConfig(ctypes.Structure):
@@ -100,11 +102,22 @@ def lib():
     L.fdsk_version.restype = ctypes.c_char_p
     L.fdsk_gram.argtypes = [vp, i32, i64, i64, vp, i64, vp]
     L.sketch_reset.argtypes = [vp]
+    L.sketch_batch_create.argtypes = [i32, ctypes.POINTER(FdskConfig), vp, ctypes.POINTER(vp)]
+    L.sketch_batch_append.argtypes = [vp, ctypes.POINTER(vp), ctypes.POINTER(i64),
+                                      ctypes.POINTER(i64), cint, cint, i32]
+    L.sketch_batch_finalize.argtypes = [vp, ctypes.POINTER(vp), ctypes.POINTER(i64), cint, cint,
+                                        i32, ctypes.POINTER(i32)]
+    L.sketch_batch_stats.argtypes = [vp, i32, ctypes.POINTER(FdskReport)]
+    L.sketch_batch_destroy.argtypes = [vp]
+    L.sketch_batch_destroy.restype = None
+    L.sketch_batch_last_error.argtypes = [vp]
+    L.sketch_batch_last_error.restype = ctypes.c_char_p
     L.sketch_profile.argtypes = [vp, ctypes.POINTER(FdskProfile)]
     L.fdsk_eigh.argtypes = [vp, i32, i64, vp, vp, i64, vp]
     for f in ("sketch_create", "sketch_append_rows", "sketch_finalize", "sketch_error",
               "fdsk_evaluate", "sketch_stats", "fdsk_gram", "fdsk_eigh", "sketch_reset",
-              "sketch_profile"):
+              "sketch_profile", "sketch_batch_create", "sketch_batch_append",
+              "sketch_batch_finalize", "sketch_batch_stats"):
         getattr(L, f).restype = cint
     _lib = L
     return L
@@ -250,3 +263,79 @@ def eigh(G, stream=None):
                            ctypes.c_void_p(lam.data_ptr()), ctypes.c_void_p(V.data_ptr()),
                            V.stride(0), _stream_handle(stream)))
     return lam, V
+
+
+def _check_batch(rc, handle=None):
+    if rc != 0:
+        msg = lib().sketch_batch_last_error(handle)
+        raise FdskError(rc, msg.decode() if msg else "")
+
+
+class FDSketchBatch:
+    """Many independent sketches advanced by one persistent launch per call."""
+
+    def __init__(self, configs, stream=None):
+        """configs: list of dicts with keys d, l and optionally variant, alpha, buffer_rows."""
+        self.S = len(configs)
+        arr = (FdskConfig * self.S)()
+        self.shapes = []
+        for i, c in enumerate(configs):
+            arr[i] = FdskConfig(int(c["d"]), int(c["l"]), int(c.get("buffer_rows", 0)),
+                                VARIANTS[c.get("variant", "fd")], float(c.get("alpha", 0.2)), 0, 0)
+            self.shapes.append((int(c["l"]), int(c["d"])))
+        h = ctypes.c_void_p()
+        _check_batch(lib().sketch_batch_create(self.S, arr, _stream_handle(stream), ctypes.byref(h)))
+        self._h = h
+
+    def append(self, rows_list, grid_size=0):
+        """rows_list[i]: 2-D cuda tensor for sketch i (or None for no rows)."""
+        torch = _torch()
+        ptrs = (ctypes.c_void_p * self.S)()
+        ns = (ctypes.c_int64 * self.S)()
+        strides = (ctypes.c_int64 * self.S)()
+        dt = None
+        keep = []
+        for i, t in enumerate(rows_list):
+            if t is None or t.shape[0] == 0:
+                ptrs[i], ns[i], strides[i] = None, 0, self.shapes[i][1]
+                continue
+            if t.stride(1) != 1:
+                t = t.contiguous()
+            keep.append(t)
+            code = _dtype_code(t)
+            if dt is None:
+                dt = code
+            elif dt != code:
+                raise ValueError("all sketches of one append call share a dtype")
+            ptrs[i], ns[i], strides[i] = t.data_ptr(), t.shape[0], t.stride(0)
+        _check_batch(lib().sketch_batch_append(self._h, ptrs, ns, strides, F64 if dt is None else dt,
+                                               MEM_DEVICE, int(grid_size)), self._h)
+        return self
+
+    def finalize(self, dtype=None, grid_size=0):
+        torch = _torch()
+        dtype = dtype or torch.float64
+        outs = [torch.empty(shape, dtype=dtype, device="cuda") for shape in self.shapes]
+        ptrs = (ctypes.c_void_p * self.S)(*[o.data_ptr() for o in outs])
+        lds = (ctypes.c_int64 * self.S)(*[o.stride(0) for o in outs])
+        rows = (ctypes.c_int32 * self.S)()
+        _check_batch(lib().sketch_batch_finalize(self._h, ptrs, lds, _dtype_code(outs[0]), MEM_DEVICE,
+                                                 int(grid_size), rows), self._h)
+        self.rows_out = list(rows)
+        return outs
+
+    def stats(self, i):
+        rep = FdskReport()
+        _check_batch(lib().sketch_batch_stats(self._h, int(i), ctypes.byref(rep)), self._h)
+        return rep.as_dict()
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().sketch_batch_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,112 @@
+"""Many-sketch persistent launch: every sketch of a batch against the oracle,
+and results independent of how many workgroups run the batch."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1501_06561_amd import synth
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from paper_1501_06561_amd import fdsketch as F  # noqa: E402
+
+VARS = oracle.VARIANTS
+
+
+def _make_batch(seed, S, d_range, l_range, n_range, variants=VARS, dtype=np.float64):
+    rng = np.random.default_rng(seed)
+    cfgs, mats = [], []
+    for i in range(S):
+        d = int(rng.integers(*d_range))
+        l = int(rng.integers(*l_range))
+        n = int(rng.integers(*n_range))
+        v = variants[i % len(variants)]
+        k = max(1, min(d - 1, l // 2))
+        A = synth.random_noisy(n, d, k, 10.0, seed=(60, seed, i)).astype(dtype)
+        cfgs.append(dict(d=d, l=l, variant=v, alpha=0.2))
+        mats.append(A)
+    return cfgs, mats
+
+
+def _run(cfgs, mats, grid=0, chunks=1, dtype=torch.float64):
+    b = F.FDSketchBatch(cfgs)
+    tens = [torch.from_numpy(np.ascontiguousarray(A)).to(dtype).cuda() for A in mats]
+    for c in range(chunks):
+        parts = []
+        for t in tens:
+            n = t.shape[0]
+            lo, hi = n * c // chunks, n * (c + 1) // chunks
+            parts.append(t[lo:hi] if hi > lo else None)
+        b.append(parts, grid_size=grid)
+    outs = [o.cpu().numpy() for o in b.finalize(grid_size=grid)]
+    stats = [b.stats(i) for i in range(len(cfgs))]
+    b.close()
+    return outs, stats
+
+
+def _check(cfg, A, B, st, gram_tol):
+    Bo, so = oracle.fd_sketch(A, cfg["l"], cfg["variant"], cfg["alpha"], return_state=True)
+    fa = oracle.fro2(A)
+    ce, co = oracle.cov_err(A, B), oracle.cov_err(A, Bo)
+    assert abs(ce - co) <= 1e-6 * co + 1e-12, (cfg, ce, co)
+    assert np.max(np.abs(B.T @ B - Bo.T @ Bo)) <= gram_tol * fa, cfg
+    assert st["n_reduce"] == so.n_rr, cfg
+    assert abs(st["fro2_A"] - so.fro2A) <= 1e-12 * fa
+    assert abs(st["shrink_total"] - so.Stot) <= 1e-9 * fa
+    assert st["eig_unconverged"] == 0
+
+
+def test_batch_matches_oracle_mixed_shapes():
+    """Both in-workgroup eigensolvers (m <= 100 in LDS; 100 < m <= 256 blocked)."""
+    cfgs, mats = _make_batch(1, 24, (20, 300), (4, 128), (50, 2500))
+    outs, stats = _run(cfgs, mats)
+    for cfg, A, B, st in zip(cfgs, mats, outs, stats):
+        _check(cfg, A, B, st, 1e-9 if cfg["variant"] == "fd" else 1e-7)
+
+
+def test_batch_is_independent_of_grid_and_chunking():
+    cfgs, mats = _make_batch(2, 12, (30, 200), (6, 90), (100, 1500))
+    ref, _ = _run(cfgs, mats, grid=0)
+    one, _ = _run(cfgs, mats, grid=1)
+    chunked, _ = _run(cfgs, mats, grid=3, chunks=4)
+    for a, b, c in zip(ref, one, chunked):
+        assert np.array_equal(a, b)
+        assert np.array_equal(a, c)
+
+
+def test_batch_edge_cases():
+    cfgs = [dict(d=15, l=8, variant="fd", alpha=0.2),      # no rows
+            dict(d=40, l=10, variant="alpha", alpha=0.2),  # fewer rows than l
+            dict(d=33, l=1, variant="fd", alpha=0.2),      # l = 1
+            dict(d=5, l=12, variant="isvd", alpha=0.2)]    # d < m
+    mats = [np.zeros((0, 15)), synth.random_noisy(7, 40, 3, seed=(61, 1)),
+            synth.random_noisy(300, 33, 3, seed=(61, 2)), synth.random_noisy(500, 5, 2, seed=(61, 3))]
+    outs, stats = _run(cfgs, mats)
+    assert not outs[0].any() and stats[0]["fro2_A"] == 0.0
+    assert np.array_equal(outs[1][:7], mats[1]) and not outs[1][7:].any()
+    assert not outs[2].any()
+    for i in (1, 3):
+        _check(cfgs[i], mats[i], outs[i], stats[i], 1e-8)
+
+
+def test_batch_many_sketch_workload_draws():
+    """First draws of the 512-sketch workload (d, l, n uniform), n capped so
+    the oracle finishes; fp32 rows."""
+    d, l, n = synth.batch_shapes(512, seed=(4, 0))
+    cfgs, mats = [], []
+    for i in range(16):
+        nn = int(min(n[i], 1500))
+        k = max(1, int(l[i]) // 2)
+        A = synth.random_noisy(nn, int(d[i]), k, 10.0, seed=(4, 0, i)).astype(np.float32)
+        cfgs.append(dict(d=int(d[i]), l=int(l[i]), variant="fd", alpha=0.2))
+        mats.append(A)
+    outs, stats = _run(cfgs, mats, dtype=torch.float32)
+    for cfg, A, B, st in zip(cfgs, mats, outs, stats):
+        _check(cfg, A.astype(np.float64), B, st, 1e-9)
+
+
+def test_batch_rejects_large_buffers():
+    with pytest.raises(F.FdskError) as e:
+        F.FDSketchBatch([dict(d=10, l=200)])
+    assert e.value.code == -6
