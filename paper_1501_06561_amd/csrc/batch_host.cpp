@@ -38,6 +38,12 @@ struct fdsk_batch {
 
 namespace {
 
+// The persistent many-sketch launch is switched off: its first GPU run ended
+// in a device memory fault whose cause has not been shown (a CPU emulation of
+// the kernel under AddressSanitizer finds every access in bounds).  Creation
+// and stats work; append/finalize report FDSK_EUNSUPPORTED until then.
+constexpr bool kBatchLaunchEnabled = false;
+
 thread_local std::string g_batch_err;
 
 int berr(fdsk_batch* b, int code, const char* fmt, ...) {
@@ -77,6 +83,8 @@ RuleParams rule_for(const fdsk_config& c) {
 // Launch with a queue order that starts with the most expensive sketches
 // (estimated ReduceRank count times the cost of one ReduceRank).
 int launch(fdsk_batch* b, const std::vector<int64_t>& n, int finalize, int grid_size) {
+  if (!kBatchLaunchEnabled)
+    return berr(b, FDSK_EUNSUPPORTED, "the persistent many-sketch launch is disabled in this build");
   std::vector<double> cost(b->S);
   for (int i = 0; i < b->S; ++i) {
     const BatchDesc& D = b->desc[i];
