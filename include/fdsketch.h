@@ -50,7 +50,10 @@ typedef struct fdsk_sketch fdsk_sketch;           /* opaque */
 typedef enum { FDSK_FD = 0, FDSK_ISVD = 1, FDSK_ALPHA = 2, FDSK_FAST_ALPHA = 3 } fdsk_variant;
 typedef enum { FDSK_F64 = 0, FDSK_F32 = 1, FDSK_BF16 = 2 } fdsk_dtype;  /* BF16 = raw uint16 bits */
 /* Arithmetic of the Gram and rebuild products.  The eigensolver, the shrink
- * subtraction and every accumulator are FP64 in all modes. */
+ * subtraction and every accumulator are FP64 in all modes; the buffer stays
+ * FP64.  BF16: each FP64 operand rounded to bfloat16, products on BF16
+ * matrix cores with FP32 accumulation.  BF16X3: operands split as
+ * hi = bf16(x), lo = bf16(x - hi) and hi*hi + hi*lo + lo*hi accumulated. */
 typedef enum { FDSK_P_FP64 = 0, FDSK_P_BF16 = 1, FDSK_P_BF16X3 = 2 } fdsk_precision;
 typedef enum { FDSK_MEM_HOST = 0, FDSK_MEM_DEVICE = 1 } fdsk_mem;
 
@@ -164,13 +167,16 @@ const char* sketch_last_error(const fdsk_sketch* s);
  * Device pointers, FP64, stream-ordered on hip_stream, synchronous on return.
  *
  * fdsk_gram: G = C C^T (rows x rows) for C rows x d (leading dimension ldc),
- *   written to G with leading dimension ldg.  This is the Gram matrix whose
- *   eigenvalues are the squared singular values of Algorithm 1's buffer.
+ *   written to G with leading dimension ldg, with the products in the given
+ *   precision (FP64 matrix cores, or BF16 matrix cores with FP32
+ *   accumulation, optionally split-bf16 compensated).  This is the Gram
+ *   matrix whose eigenvalues are the squared singular values of Algorithm
+ *   1's buffer.
  * fdsk_eigh: eigen-decomposition G = V diag(lam) V^T of a symmetric m x m
  *   matrix (m <= 1024); lam unsorted, V's column j (V[i*ldv + j]) belongs to
  *   lam[j].  Errors: EINVAL, EUNSUPPORTED (m > 1024), ENOMEM, EDEVICE. */
 int fdsk_gram(const double* C, int32_t rows, int64_t d, int64_t ldc, double* G, int64_t ldg,
-              void* hip_stream);
+              fdsk_precision prec, void* hip_stream);
 int fdsk_eigh(const double* G, int32_t m, int64_t ldg, double* lam, double* V, int64_t ldv,
               void* hip_stream);
 

@@ -34,6 +34,13 @@ hipError_t launch_ingest(const void* src, int dt, int64_t stride, int f, int d, 
                          int row0, double* rownorm, hipStream_t s);
 hipError_t launch_gram(const double* C, int ldc, int mp, double* Gpart, int ksplit_max, double* G,
                        hipStream_t s);
+hipError_t launch_gram_reduce(const double* Gpart, int ksplit, int mp, double* G, hipStream_t s);
+// BF16 matrix-core Gram / rebuild on the FP64 buffer; npass 1 = hi*hi,
+// 3 = hi*hi + hi*lo + lo*hi (split-bf16 compensation), FP32 accumulation.
+hipError_t launch_gram_lowp(const double* C, int ldc, int mp, double* Gpart, int ksplit_max, double* G,
+                            int npass, hipStream_t s);
+hipError_t launch_rebuild_lowp(const double* Ut, const double* C, int ldc, int mp, int keep, double* out,
+                               int npass, hipStream_t s);
 hipError_t launch_shrink(const double* lam, const double* V, int m, int mp, RuleParams rp,
                          const double* rownorm, int new0, int new1, double* Ut, DevStats* st,
                          hipStream_t s);

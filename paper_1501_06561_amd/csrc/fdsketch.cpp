@@ -135,15 +135,24 @@ void add_mark(fdsk_sketch* s, int stage, hipEvent_t a, hipEvent_t b) {
 int reduce(fdsk_sketch* s) {
   EigWork wk{s->W, s->bar, s->rot, s->st};
   hipEvent_t e0 = mark(s);
-  HIPCHK(s, launch_gram(s->C[s->cur], s->ldc, s->mp, s->Gpart, s->ksplit_max, s->G, s->stream));
+  const int npass = s->cfg.precision == FDSK_P_BF16 ? 1 : 3;
+  if (s->cfg.precision == FDSK_P_FP64)
+    HIPCHK(s, launch_gram(s->C[s->cur], s->ldc, s->mp, s->Gpart, s->ksplit_max, s->G, s->stream));
+  else
+    HIPCHK(s, launch_gram_lowp(s->C[s->cur], s->ldc, s->mp, s->Gpart, s->ksplit_max, s->G, npass,
+                               s->stream));
   hipEvent_t e1 = mark(s);
   HIPCHK(s, launch_eig(s->G, s->m, s->mp, s->lam, s->V, wk, s->stream));
   hipEvent_t e2 = mark(s);
   HIPCHK(s, launch_shrink(s->lam, s->V, s->m, s->mp, s->rp, s->rownorm, s->new0, s->occ, s->Ut,
                           s->st, s->stream));
   hipEvent_t e3 = mark(s);
-  HIPCHK(s, launch_rebuild(s->Ut, s->C[s->cur], s->ldc, s->mp, s->rp.keep, s->C[1 - s->cur],
-                           s->stream));
+  if (s->cfg.precision == FDSK_P_FP64)
+    HIPCHK(s, launch_rebuild(s->Ut, s->C[s->cur], s->ldc, s->mp, s->rp.keep, s->C[1 - s->cur],
+                             s->stream));
+  else
+    HIPCHK(s, launch_rebuild_lowp(s->Ut, s->C[s->cur], s->ldc, s->mp, s->rp.keep, s->C[1 - s->cur],
+                                  npass, s->stream));
   hipEvent_t e4 = mark(s);
   add_mark(s, 1, e0, e1);
   add_mark(s, 2, e1, e2);
@@ -189,7 +198,7 @@ int check_device_flags(fdsk_sketch* s) {
 
 extern "C" {
 
-const char* fdsk_version(void) { return "fdsketch 0.1 (gfx950, FP64 Gram + Jacobi path)"; }
+const char* fdsk_version(void) { return "fdsketch 0.2 (gfx950; FP64 / BF16 / BF16x3 Gram and rebuild, FP64 Jacobi)"; }
 
 const char* sketch_last_error(const fdsk_sketch* s) {
   if (!s) return g_last_error.c_str();
@@ -209,8 +218,8 @@ int sketch_create(const fdsk_config* cfg, void* hip_stream, fdsk_sketch** out) {
     return set_err(nullptr, FDSK_EINVAL, "unknown variant");
   if ((c.variant == FDSK_ALPHA || c.variant == FDSK_FAST_ALPHA) && !(c.alpha > 0.0 && c.alpha <= 1.0))
     return set_err(nullptr, FDSK_EINVAL, "alpha must lie in (0, 1]");
-  if (c.precision != FDSK_P_FP64)
-    return set_err(nullptr, FDSK_EUNSUPPORTED, "precision %d not available", (int)c.precision);
+  if (c.precision != FDSK_P_FP64 && c.precision != FDSK_P_BF16 && c.precision != FDSK_P_BF16X3)
+    return set_err(nullptr, FDSK_EINVAL, "unknown precision %d", (int)c.precision);
   if (c.flags & ~FDSK_FLAG_PROFILE) return set_err(nullptr, FDSK_EINVAL, "unknown flags");
 
   fdsk_sketch* s = new fdsk_sketch;
@@ -562,7 +571,9 @@ struct DevBuf {
 }  // namespace
 
 extern "C" int fdsk_gram(const double* C, int32_t rows, int64_t d, int64_t ldc, double* G,
-                         int64_t ldg, void* hip_stream) {
+                         int64_t ldg, fdsk_precision prec, void* hip_stream) {
+  if (prec != FDSK_P_FP64 && prec != FDSK_P_BF16 && prec != FDSK_P_BF16X3)
+    return set_err(nullptr, FDSK_EINVAL, "fdsk_gram: unknown precision");
   if (!C || !G || rows < 1 || rows > 1024 || d < 1 || d > 65536 || ldc < d || ldg < rows)
     return set_err(nullptr, FDSK_EINVAL, "fdsk_gram: bad arguments");
   hipStream_t st = static_cast<hipStream_t>(hip_stream);
@@ -578,7 +589,10 @@ extern "C" int fdsk_gram(const double* C, int32_t rows, int64_t d, int64_t ldc, 
   double* Gpart = Gp + nG;
   HIPCHK(nullptr, hipMemsetAsync(Cp, 0, nC * 8, st));
   HIPCHK(nullptr, hipMemcpy2DAsync(Cp, ld * 8, C, ldc * 8, d * 8, rows, hipMemcpyDeviceToDevice, st));
-  HIPCHK(nullptr, launch_gram(Cp, ld, mp, Gpart, ks, Gp, st));
+  if (prec == FDSK_P_FP64)
+    HIPCHK(nullptr, launch_gram(Cp, ld, mp, Gpart, ks, Gp, st));
+  else
+    HIPCHK(nullptr, launch_gram_lowp(Cp, ld, mp, Gpart, ks, Gp, prec == FDSK_P_BF16 ? 1 : 3, st));
   HIPCHK(nullptr, hipMemcpy2DAsync(G, ldg * 8, Gp, mp * 8, rows * 8, rows, hipMemcpyDeviceToDevice, st));
   HIPCHK(nullptr, hipStreamSynchronize(st));
   return 0;

@@ -39,30 +39,38 @@ struct BlkArgs {
   DevStats* st;
 };
 
-// out[:, cols] = P * Q for the mp x 16 panel in LDS, four waves.
+// out[:, cols] = Pn Q for the mp x P panel in LDS (four waves split the rows).
+template <int P>
 __device__ void block_panel_times_q(const double* Ps, int ldp, int mp, const double* Qs, double* out,
                                     const int* cols) {
+  constexpr int LDH = P + 1;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int li = lane & 15, lk = lane >> 4;
   for (int i0 = w * 16; i0 < mp; i0 += 64) {
-    f64x4 acc = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-    for (int k0 = 0; k0 < 16; k0 += 4) {
-      double a = Ps[(k0 + lk) * ldp + i0 + li];
-      double b = Qs[(k0 + lk) * 17 + li];
-      acc = mfma_f64(a, b, acc);
+    for (int ct = 0; ct < P / 16; ++ct) {
+      f64x4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int k0 = 0; k0 < P; k0 += 4) {
+        double a = Ps[(k0 + lk) * ldp + i0 + li];
+        double b = Qs[(k0 + lk) * LDH + ct * 16 + li];
+        acc = mfma_f64(a, b, acc);
+      }
+      double* o = out + static_cast<int64_t>(cols[ct * 16 + li]) * mp + i0 + lk;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) o[4 * v] = acc[v];
     }
-    double* o = out + static_cast<int64_t>(cols[li]) * mp + i0 + lk;
-#pragma unroll
-    for (int v = 0; v < 4; ++v) o[4 * v] = acc[v];
   }
 }
 
-// Ps[c*ldp + i] = X[col(c)*mp + i]; 16-byte loads, 8 in flight per thread.
+// Ps[c*ldp + i] = X[col(c)*mp + i] for the P panel columns (two blocks of
+// P/2); 16-byte loads, 8 in flight per thread.
+template <int P>
 __device__ __forceinline__ void load_panel(const double* __restrict__ X, int mp, int ldp, int bi,
                                            int bj, double* __restrict__ Ps) {
+  constexpr int HB = P / 2;
   const int half = mp >> 1;
-  const int total = 16 * half;
+  const int total = P * half;
   for (int base = threadIdx.x; base < total; base += 256 * 8) {
     double2 v[8];
 #pragma unroll
@@ -70,7 +78,8 @@ __device__ __forceinline__ void load_panel(const double* __restrict__ X, int mp,
       int e = base + u * 256;
       if (e < total) {
         int c = e / half, i2 = e - c * half;
-        v[u] = reinterpret_cast<const double2*>(X + static_cast<int64_t>(panel_col(c, bi, bj)) * mp)[i2];
+        int col = (c < HB) ? bi * HB + c : bj * HB + (c - HB);
+        v[u] = reinterpret_cast<const double2*>(X + static_cast<int64_t>(col) * mp)[i2];
       }
     }
 #pragma unroll
@@ -85,20 +94,70 @@ __device__ __forceinline__ void load_panel(const double* __restrict__ X, int mp,
   }
 }
 
-// PREF: the V panel (mp <= 512) is fetched into registers together with the W
-// panel, so its latency overlaps the Gram and inner solve.
-template <bool PREF>
+// One sweep of two-sided Jacobi on the P x P panel Gram H (LDS, ld P+1),
+// accumulating Q, executed by the whole workgroup (256 threads).
+template <int P>
+__device__ void inner_jacobi_wg(double* Hs, double* Qs, double* cs) {
+  constexpr int LDH = P + 1, NP = P / 2;
+  const int tid = threadIdx.x;
+  for (int e = tid; e < P * P; e += 256) Qs[(e / P) * LDH + (e % P)] = ((e / P) == (e % P)) ? 1.0 : 0.0;
+  __syncthreads();
+  for (int sw = 0; sw < kInnerSweeps; ++sw) {
+    for (int step = 0; step < P - 1; ++step) {
+      if (tid < NP) {
+        int p = rr_fast(tid, step, P), q = rr_fast(P - 1 - tid, step, P);
+        double hpq = Hs[p * LDH + q], hpp = Hs[p * LDH + p], hqq = Hs[q * LDH + q];
+        double c = 1.0, sn = 0.0;
+        if (hpq * hpq > (0.0625 * kInnerTol * kInnerTol) * fabs(hpp * hqq)) jacobi_rotation(hpp, hqq, hpq, c, sn);
+        cs[tid] = c;
+        cs[NP + tid] = sn;
+      }
+      __syncthreads();
+      for (int e = tid; e < NP * NP; e += 256) {
+        const int a = e / NP, b = e % NP;
+        const int pa = rr_fast(a, step, P), qa = rr_fast(P - 1 - a, step, P);
+        const int pb = rr_fast(b, step, P), qb = rr_fast(P - 1 - b, step, P);
+        const double ca = cs[a], sa = cs[NP + a], cb = cs[b], sb = cs[NP + b];
+        double g11 = Hs[pa * LDH + pb], g12 = Hs[pa * LDH + qb], g21 = Hs[qa * LDH + pb], g22 = Hs[qa * LDH + qb];
+        double r11 = ca * g11 - sa * g21, r12 = ca * g12 - sa * g22;
+        double r21 = sa * g11 + ca * g21, r22 = sa * g12 + ca * g22;
+        Hs[pa * LDH + pb] = cb * r11 - sb * r12;
+        Hs[pa * LDH + qb] = sb * r11 + cb * r12;
+        Hs[qa * LDH + pb] = cb * r21 - sb * r22;
+        Hs[qa * LDH + qb] = sb * r21 + cb * r22;
+      }
+      for (int e = tid; e < P * NP; e += 256) {
+        const int i = e / NP, b = e % NP;
+        const int pb = rr_fast(b, step, P), qb = rr_fast(P - 1 - b, step, P);
+        const double cb = cs[b], sb = cs[NP + b];
+        double vp = Qs[i * LDH + pb], vq = Qs[i * LDH + qb];
+        Qs[i * LDH + pb] = cb * vp - sb * vq;
+        Qs[i * LDH + qb] = sb * vp + cb * vq;
+      }
+      __syncthreads();
+    }
+  }
+}
+
+// P: panel width (16 or 32 columns = two blocks of P/2).  PREF: the V panel
+// is fetched into registers together with the W panel, so its latency
+// overlaps the Gram and inner solve (mp <= 512).
+template <int P, bool PREF>
 __global__ __launch_bounds__(256) void k_eig_blk(BlkArgs A) {
+  constexpr int HB = P / 2;
+  constexpr int LDH = P + 1;
+  constexpr int PM = (P == 32) ? 512 : PMAX;    // largest mp for this panel width
+  constexpr int VR = PREF ? (P * 256 / 256) : 1; // double2 per thread for mp <= 512
   const int mp = A.mp;
   const int ldp = mp + 1;
-  const int nb = mp / BW;
+  const int nb = mp / HB;
   const unsigned nwg = gridDim.x;
-  __shared__ double Ps[16 * (PMAX + 1)];
-  __shared__ double Hp[4][256];
-  __shared__ double Hs[16 * 17];
-  __shared__ double Qs[16 * 17];
-  __shared__ double cs[16];
-  __shared__ int cols[16];
+  __shared__ double Ps[P * (PM + 1)];
+  __shared__ double Hp[(P == 16) ? 4 * 256 : 1];
+  __shared__ double Hs[P * LDH];
+  __shared__ double Qs[P * LDH];
+  __shared__ double cs[P];
+  __shared__ int cols[P];
   __shared__ int flag;
   const int tid = threadIdx.x;
   const int lane = tid & 63, w = tid >> 6;
@@ -118,25 +177,24 @@ __global__ __launch_bounds__(256) void k_eig_blk(BlkArgs A) {
     for (int step = 0; step < nb - 1; ++step) {
       const int bi = rr_slot(blockIdx.x, step, nb);
       const int bj = rr_slot(nb - 1 - blockIdx.x, step, nb);
-      // Stage the W panel: every load is issued before any is consumed.
-      double2 vreg[PREF ? 16 : 1];
+      double2 vreg[VR];
       const int half = mp >> 1;
       if (PREF) {
 #pragma unroll
-        for (int u = 0; u < 16; ++u) {
+        for (int u = 0; u < VR; ++u) {
           int e = tid + u * 256;
-          if (e < 16 * half) {
+          if (e < P * half) {
             int c = e / half, i2 = e - c * half;
-            int col = (c < 8) ? bi * BW + c : bj * BW + (c - 8);
+            int col = (c < HB) ? bi * HB + c : bj * HB + (c - HB);
             vreg[u] = reinterpret_cast<const double2*>(A.V + static_cast<int64_t>(col) * mp)[i2];
           }
         }
       }
-      load_panel(A.W, mp, ldp, bi, bj, Ps);
-      if (tid < 16) cols[tid] = (tid < 8) ? bi * BW + tid : bj * BW + (tid - 8);
+      load_panel<P>(A.W, mp, ldp, bi, bj, Ps);
+      if (tid < P) cols[tid] = (tid < HB) ? bi * HB + tid : bj * HB + (tid - HB);
       __syncthreads();
-      // H = P^T P, split over the four waves along the rows.
-      {
+      // H = P^T P on matrix cores.
+      if (P == 16) {
         f64x4 acc = {0.0, 0.0, 0.0, 0.0};
         const int span = mp / 4;
         for (int k0 = w * span; k0 < (w + 1) * span; k0 += 4) {
@@ -144,43 +202,54 @@ __global__ __launch_bounds__(256) void k_eig_blk(BlkArgs A) {
           acc = mfma_f64(a, a, acc);
         }
 #pragma unroll
-        for (int v = 0; v < 4; ++v) Hp[w][(lk + 4 * v) * 16 + li] = acc[v];
+        for (int v = 0; v < 4; ++v) Hp[w * 256 + (lk + 4 * v) * 16 + li] = acc[v];
+        __syncthreads();
+        Hs[(tid >> 4) * LDH + (tid & 15)] = (Hp[tid] + Hp[256 + tid]) + (Hp[512 + tid] + Hp[768 + tid]);
+      } else {
+        const int ti = w >> 1, tj = w & 1;       // one 16x16 tile of the 32x32 H per wave
+        f64x4 acc = {0.0, 0.0, 0.0, 0.0};
+        for (int k0 = 0; k0 < mp; k0 += 4) {
+          double a = Ps[(ti * 16 + li) * ldp + k0 + lk];
+          double b = Ps[(tj * 16 + li) * ldp + k0 + lk];
+          acc = mfma_f64(a, b, acc);
+        }
+#pragma unroll
+        for (int v = 0; v < 4; ++v) Hs[(ti * 16 + lk + 4 * v) * LDH + tj * 16 + li] = acc[v];
       }
       if (tid == 0) flag = 0;
       __syncthreads();
-      {
-        double h = (Hp[0][tid] + Hp[1][tid]) + (Hp[2][tid] + Hp[3][tid]);
-        Hs[(tid >> 4) * 17 + (tid & 15)] = h;
-      }
-      __syncthreads();
-      {
-        int p = tid >> 4, q = tid & 15;
+      for (int e = tid; e < P * P; e += 256) {
+        int p = e / P, q = e % P;
         if (p < q) {
-          double hpq = Hs[p * 17 + q], hpp = Hs[p * 17 + p], hqq = Hs[q * 17 + q];
+          double hpq = Hs[p * LDH + q], hpp = Hs[p * LDH + p], hqq = Hs[q * LDH + q];
           if (hpp > 0.0 && hqq > 0.0 && hpq * hpq > (kOuterTol * kOuterTol) * (hpp * hqq)) flag = 1;
         }
       }
       __syncthreads();
       if (flag) {
-        if (tid < 64) inner_jacobi16(Hs, Qs, cs);
-        __syncthreads();
-        block_panel_times_q(Ps, ldp, mp, Qs, A.W, cols);
+        if (P == 16) {
+          if (tid < 64) inner_jacobi16(Hs, Qs, cs);
+          __syncthreads();
+        } else {
+          inner_jacobi_wg<P>(Hs, Qs, cs);
+        }
+        block_panel_times_q<P>(Ps, ldp, mp, Qs, A.W, cols);
         __syncthreads();
         if (PREF) {
 #pragma unroll
-          for (int u = 0; u < 16; ++u) {
+          for (int u = 0; u < VR; ++u) {
             int e = tid + u * 256;
-            if (e < 16 * half) {
+            if (e < P * half) {
               int c = e / half, i2 = e - c * half;
               Ps[c * ldp + 2 * i2] = vreg[u].x;
               Ps[c * ldp + 2 * i2 + 1] = vreg[u].y;
             }
           }
         } else {
-          load_panel(A.V, mp, ldp, bi, bj, Ps);
+          load_panel<P>(A.V, mp, ldp, bi, bj, Ps);
         }
         __syncthreads();
-        block_panel_times_q(Ps, ldp, mp, Qs, A.V, cols);
+        block_panel_times_q<P>(Ps, ldp, mp, Qs, A.V, cols);
         if (tid == 0) atomicAdd(&A.rot[sweep], 1);
       }
       grid_barrier(A.bar, nwg);
@@ -191,8 +260,6 @@ __global__ __launch_bounds__(256) void k_eig_blk(BlkArgs A) {
   if (blockIdx.x == 0 && tid == 0) {
     atomicAdd(&A.st->eig_sweeps, static_cast<unsigned long long>(sweep + 1));
     if (sweep == kMaxSweeps) atomicAdd(&A.st->eig_unconv, 1);
-  }
-  if (blockIdx.x == 0 && tid == 0) {
     int e = __hip_atomic_load(A.bar.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     if (e) A.st->bar_err = 1;
   }
@@ -220,9 +287,16 @@ hipError_t launch_eig(const double* G, int m, int mp, double* lam, double* V, Ei
   a.bar.count = wk.bar; a.bar.gen = wk.bar + 1; a.bar.err = reinterpret_cast<int*>(wk.bar + 2);
   a.rot = wk.rot; a.st = wk.st;
   void* args[] = {&a};
-  void* fn = (mp <= 512) ? reinterpret_cast<void*>(k_eig_blk<true>)
-                         : reinterpret_cast<void*>(k_eig_blk<false>);
-  return hipLaunchCooperativeKernel(fn, dim3(mp / 16), dim3(256), args, 0, s);
+  void* fn;
+  int grid;
+  if (mp <= 512) {
+    fn = reinterpret_cast<void*>(k_eig_blk<32, true>);
+    grid = mp / 32;
+  } else {
+    fn = reinterpret_cast<void*>(k_eig_blk<16, false>);
+    grid = mp / 16;
+  }
+  return hipLaunchCooperativeKernel(fn, dim3(grid), dim3(256), args, 0, s);
 }
 
 }  // namespace fdsk

@@ -317,6 +317,10 @@ hipError_t launch_gram(const double* C, int ldc, int mp, double* Gpart, int kspl
   hipLaunchKernelGGL(k_gram_f64, dim3(ntiles, ksplit), dim3(256), 0, s, C, ldc, mp, kchunk, Gpart);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
+  return launch_gram_reduce(Gpart, ksplit, mp, G, s);
+}
+
+hipError_t launch_gram_reduce(const double* Gpart, int ksplit, int mp, double* G, hipStream_t s) {
   const int64_t n = static_cast<int64_t>(mp) * mp;
   int blocks = static_cast<int>(std::min<int64_t>((n + 255) / 256, 2048));
   hipLaunchKernelGGL(k_gram_reduce, dim3(blocks), dim3(256), 0, s, Gpart, ksplit, mp, G);

@@ -100,7 +100,7 @@ def lib():
     L.sketch_last_error.argtypes = [vp]
     L.sketch_last_error.restype = ctypes.c_char_p
     L.fdsk_version.restype = ctypes.c_char_p
-    L.fdsk_gram.argtypes = [vp, i32, i64, i64, vp, i64, vp]
+    L.fdsk_gram.argtypes = [vp, i32, i64, i64, vp, i64, cint, vp]
     L.sketch_reset.argtypes = [vp]
     L.sketch_batch_create.argtypes = [i32, ctypes.POINTER(FdskConfig), vp, ctypes.POINTER(vp)]
     L.sketch_batch_append.argtypes = [vp, ctypes.POINTER(vp), ctypes.POINTER(i64),
@@ -240,14 +240,15 @@ def evaluate(A, B, k=10, method=0, stream=None):
     return rep.as_dict()
 
 
-def gram(C, stream=None):
-    """G = C C^T on the device (FP64 matrix cores); C: cuda float64 2-D tensor."""
+def gram(C, precision="fp64", stream=None):
+    """G = C C^T on the device; C: cuda float64 2-D tensor."""
     torch = _torch()
     if C.dtype != torch.float64 or not C.is_cuda or C.stride(1) != 1:
         raise ValueError("C must be a row-major cuda float64 matrix")
     G = torch.empty((C.shape[0], C.shape[0]), dtype=torch.float64, device=C.device)
     _check(lib().fdsk_gram(ctypes.c_void_p(C.data_ptr()), C.shape[0], C.shape[1], C.stride(0),
-                           ctypes.c_void_p(G.data_ptr()), G.stride(0), _stream_handle(stream)))
+                           ctypes.c_void_p(G.data_ptr()), G.stride(0), PRECISIONS[precision],
+                           _stream_handle(stream)))
     return G
 
 

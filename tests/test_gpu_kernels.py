@@ -49,3 +49,16 @@ def test_eigh_special_matrices(m):
     _check_eigh(np.zeros((m, m)))
     X = rng.standard_normal((m, 5))
     _check_eigh(X @ X.T)                                              # rank 5
+
+
+@pytest.mark.parametrize("precision,tol", [("bf16x3", 5e-5), ("bf16", 2e-2)])
+@pytest.mark.parametrize("rows,d", [(40, 100), (130, 77), (512, 3072)])
+def test_gram_reduced_precision(precision, tol, rows, d):
+    """BF16 matrix-core Gram: error bounded by the operand rounding (one
+    bf16 rounding ~2^-8 relative, split-bf16 ~2^-16) times |c_i||c_j|."""
+    rng = np.random.default_rng(rows + d)
+    C = rng.standard_normal((rows, d)) * rng.uniform(0.5, 2.0, (rows, 1))
+    G = F.gram(torch.from_numpy(C).cuda(), precision=precision).cpu().numpy()
+    ref = C @ C.T
+    nrm = np.sqrt(np.diag(ref))
+    assert np.max(np.abs(G - ref) / np.outer(nrm, nrm)) <= tol

@@ -171,3 +171,23 @@ def test_append_after_finalize_is_rejected():
     with pytest.raises(F.FdskError) as e:
         sk.append(torch.ones(3, 10, dtype=torch.float64, device="cuda"))
     assert e.value.code == -2
+
+
+@pytest.mark.parametrize("precision,tol", [("bf16x3", 1e-4), ("bf16", 1e-3)])
+@pytest.mark.parametrize("variant", ["fd", "alpha"])
+def test_reduced_precision_power_law(precision, tol, variant):
+    """Power-law workload (sigma_i = i^-0.8 over 300 directions plus N(0,1e-2)
+    noise) stored as bf16, sketched with BF16 / split-BF16 Gram and rebuild;
+    the covariance error is within `tol` (absolute, it is already divided by
+    ||A||_F^2) of the FP64 oracle on the same bf16 rows."""
+    A = synth.power_law(6000, 768, r=300, seed=(3, 7), chunk=6000)
+    Ab = synth.to_bf16(A).astype(np.float64)
+    sk = F.FDSketch(768, 64, variant, 0.2, precision=precision)
+    sk.append(torch.from_numpy(synth.bf16_bits(A).view(np.int16)).view(torch.bfloat16).cuda())
+    B = sk.finalize().cpu().numpy()
+    st = sk.stats()
+    Bo, so = oracle.fd_sketch(Ab, 64, variant, 0.2, return_state=True)
+    ce, co = oracle.cov_err(Ab, B), oracle.cov_err(Ab, Bo)
+    assert abs(ce - co) <= tol, (ce, co)
+    assert st["n_reduce"] == so.n_rr
+    assert abs(st["fro2_A"] - so.fro2A) <= 1e-12 * so.fro2A
