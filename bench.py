@@ -10,9 +10,14 @@ l = 100, buffer 2l = 200 rows).  Arithmetic is FP64.
 
 Prints one JSON line with the metric, the dominant kernel's roofline (stage
 times come from HIP events the library records on its stream during the
-timed steps) and the CPU oracle timed on a bounded prefix of the same stream.
+timed steps), the covariance error of the GPU sketch (device evaluator) and the
+CPU oracle timed on the same stream, with the oracle's own covariance error.
+
+`--copy-calibration` instead runs a plain device copy of a known size (the
+reference kernel for scaling the FETCH_SIZE / WRITE_SIZE hardware counters).
 """
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -23,12 +28,76 @@ sys.path.insert(0, ROOT)
 
 PEAK_FP64 = 78.6e12      # MI355X FP64 vector and matrix peak, FLOP/s
 PEAK_HBM = 8.0e12        # bytes/s
+METRIC = "rows/sec sketched at fixed cov-err/||A||_F^2; batched+bf16 vs plain FD, 1 GPU"
+CSRC = os.path.join(ROOT, "paper_1501_06561_amd", "csrc")
+# Sources that define each stage's kernels; a traffic figure measured with the
+# hardware counters is only quoted while these are unchanged.
+STAGE_SOURCES = {
+    "eig": ["kernels_eig.hip", "fdsk_jacobi.hpp", "fdsk_device.hpp", "fdsk_kernels.hpp"],
+    "gram": ["kernels_stream.hip", "fdsk_device.hpp", "fdsk_kernels.hpp"],
+    "rebuild": ["kernels_stream.hip", "fdsk_device.hpp", "fdsk_kernels.hpp"],
+    "shrink": ["kernels_stream.hip", "fdsk_device.hpp", "fdsk_kernels.hpp"],
+    "ingest": ["kernels_stream.hip", "fdsk_device.hpp", "fdsk_kernels.hpp"],
+    "tridiag": ["kernels_trid.hip", "fdsk_device.hpp", "fdsk_kernels.hpp"],
+    "dc": ["kernels_trid.hip", "fdsk_device.hpp", "fdsk_kernels.hpp"],
+    "backtr": ["kernels_trid.hip", "fdsk_device.hpp", "fdsk_kernels.hpp"],
+}
+KERNELS = {"eig": "k_eig_lds/k_eig_blk (Jacobi)", "gram": "k_gram_f64+k_gram_reduce",
+           "rebuild": "k_rebuild_f64", "shrink": "k_shrink", "ingest": "k_ingest",
+           "tridiag": "k_tridiag", "dc": "k_dc", "backtr": "k_backtr"}
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_random_noisy_100k_x1000.json")
+
+
+def sources_digest(stage):
+    h = hashlib.sha256()
+    for name in STAGE_SOURCES[stage]:
+        with open(os.path.join(CSRC, name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(stage, l, variant):
+    """HBM bytes per launch of the stage's kernel from the committed counter
+    summary, or None if there is none for this configuration or the kernel
+    sources changed since it was taken."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            rec = json.load(f)
+    except (OSError, ValueError):
+        return None
+    for e in rec.get("entries", []):
+        if e.get("stage") == stage and e.get("l") == l and e.get("variant") == variant:
+            if e.get("sources_sha256_16") != sources_digest(stage):
+                return None
+            return e.get("bytes_per_launch")
+    return None
+
+
+def copy_calibration(nbytes, reps):
+    """A plain device-to-device copy of `nbytes`, `reps` times (counter reference)."""
+    import torch
+    src = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / reps
+    print(json.dumps({"copy_bytes_read": nbytes, "copy_bytes_written": nbytes, "reps": reps,
+                      "ms_per_copy": dt * 1e3, "GBps_read_plus_write": 2 * nbytes / dt / 1e9}))
 
 
 def stage_work(stage, m, keep, d, new_rows):
     """Algorithmic work of one launch of a stage: (amount, unit kind, bound)."""
     if stage == "eig":
         return 9.0 * m ** 3, "flop", "alu"          # dense symmetric eigendecomposition
+    if stage == "tridiag":
+        return 4.0 / 3.0 * m ** 3, "flop", "alu"    # Householder reduction to tridiagonal
+    if stage == "dc":
+        return 8.0 / 3.0 * m ** 3, "flop", "alu"    # divide-and-conquer products, no deflation
+    if stage == "backtr":
+        return 2.0 * m ** 3, "flop", "alu"          # m-2 reflectors applied to m vectors
     if stage == "gram":
         return float(m * (m + 1) * d), "flop", "mfma"   # symmetric m x m x d
     if stage == "rebuild":
@@ -46,10 +115,19 @@ def main():
     ap.add_argument("--variant", default="fd", choices=["fd", "isvd", "alpha", "fast_alpha"])
     ap.add_argument("--l", type=int, default=100)
     ap.add_argument("--alpha", type=float, default=0.2)
-    ap.add_argument("--cpu-rows", type=int, default=20_000,
+    ap.add_argument("--cpu-rows", type=int, default=100_000,
                     help="prefix of the stream the CPU oracle sketches for the baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--eig", default="auto", choices=["auto", "jacobi"],
+                    help="eigensolver: tridiagonal divide and conquer (m <= 200) or Jacobi")
+    ap.add_argument("--rows", type=int, default=100_000,
+                    help="rows of the stream to sketch (profiling runs use a prefix)")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
+                    help="only run a plain device copy of BYTES (counter reference) and exit")
     args = ap.parse_args()
+    if args.copy_calibration:
+        copy_calibration(args.copy_calibration, max(args.steps, 1))
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the sketch of one "
               "stream is a sequential chain of ReduceRank steps and this build has no "
@@ -61,11 +139,13 @@ def main():
 
     from paper_1501_06561_amd import fdsketch, synth
 
-    n, d, k, zeta, seed = 100_000, 1000, 50, 10.0, (2, 0)
-    A = synth.random_noisy(n, d, k, zeta, seed=seed, dtype=np.float32)
+    N, d, k, zeta, seed = 100_000, 1000, 50, 10.0, (2, 0)
+    A = synth.random_noisy(N, d, k, zeta, seed=seed, dtype=np.float32)
+    n = max(1, min(args.rows, N))
+    A = A[:n]
     At = torch.from_numpy(A).cuda()
     l = args.l
-    sk = fdsketch.FDSketch(d, l, args.variant, args.alpha, profile=True)
+    sk = fdsketch.FDSketch(d, l, args.variant, args.alpha, profile=True, eig=args.eig)
     m = 2 * l
 
     def step():
@@ -77,7 +157,6 @@ def main():
         step()
     torch.cuda.synchronize()
     sk.profile()                      # drop warmup marks
-    stats_before = None
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
@@ -94,7 +173,11 @@ def main():
     if keep is None:
         s_ = int(np.ceil(args.alpha * l * (1 - 1e-12)))
         keep = (l - s_) + (s_ + 1) // 2 - 1
-    dom = max(prof, key=lambda s: prof[s][0])
+    # The dominant kernel: the eigensolve is timed per kernel when it is the
+    # tridiagonal route, as one stage when it is a Jacobi solver.
+    split = prof["tridiag"][1] > 0
+    kernel_stages = [s_ for s_ in prof if prof[s_][1] > 0 and not (split and s_ == "eig")]
+    dom = max(kernel_stages, key=lambda s_: prof[s_][0])
     tot_ms, launches = prof[dom]
     avg_s = tot_ms / max(launches, 1) / 1e3
     work, kind, bound = stage_work(dom, m, keep, d, m - keep)
@@ -105,14 +188,17 @@ def main():
         roof = {"bound": bound, "achieved": work / avg_s / 1e12, "peak": PEAK_FP64 / 1e12,
                 "unit": "TFLOP/s"}
     roof["frac"] = roof["achieved"] / roof["peak"]
-    roof["traffic"] = None
-    roof["kernel"] = {"eig": "k_eig_lds/k_eig_blk", "gram": "k_gram_f64+k_gram_reduce",
-                      "rebuild": "k_rebuild_f64", "shrink": "k_shrink", "ingest": "k_ingest"}[dom]
+    roof["traffic"] = measured_traffic(dom, l, args.variant)
+    roof["kernel"] = KERNELS[dom]
     roof["stage"] = dom
     roof["avg_launch_us"] = avg_s * 1e6
     roof["work_per_launch"] = work
 
+    # Covariance error of the GPU sketch on the device evaluator (untimed).
+    ev = sk.error(At, k=10, method=0)
+
     cpu = None
+    cov_oracle = None
     if not args.no_cpu_baseline:
         import oracle
         try:
@@ -121,15 +207,19 @@ def main():
         except Exception:
             cores = os.cpu_count()
         rows = min(args.cpu_rows, n)
+        A64 = A[:rows].astype(np.float64)
         t = time.perf_counter()
-        oracle.fd_sketch(A[:rows].astype(np.float64), l, args.variant, args.alpha)
+        Bo = oracle.fd_sketch(A64, l, args.variant, args.alpha)
         dt = time.perf_counter() - t
+        if rows == n:
+            cov_oracle = oracle.cov_err(A64, Bo)
         cpu = {"value": rows / dt, "unit": "rows/s", "cores": cores, "kind": "oracle",
-               "sample": f"first {rows} rows of the same stream, same variant and l "
-                         f"(NumPy FP64, LAPACK SVD of the buffer), {dt:.1f} s"}
+               "sample": (f"first {rows} of the {n} rows of the same stream" if rows < n
+                          else f"the whole {n}-row stream") +
+                         f", same variant and l (NumPy FP64, LAPACK SVD of the buffer), {dt:.1f} s"}
 
     out = {
-        "metric": "rows/sec sketched at fixed cov-err/||A||_F^2 (FP64-faithful FD path)",
+        "metric": METRIC,
         "value": value,
         "unit": "rows/s",
         "n_gpus": 1,
@@ -141,12 +231,16 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": "random_noisy_100k_x1000_fp32", "n": n, "d": d, "k": k,
+        "config": {"workload": "random_noisy_100k_x1000_fp32" if n == N else
+                   f"random_noisy_100k_x1000_fp32_first_{n}_rows", "n": n, "d": d, "k": k,
                    "zeta": zeta, "variant": args.variant, "l": l, "buffer_rows": m,
-                   "alpha": args.alpha if args.variant in ("alpha", "fast_alpha") else None},
+                   "alpha": args.alpha if args.variant in ("alpha", "fast_alpha") else None,
+                   "eigensolver": "tridiagonal divide and conquer" if split else "Jacobi"},
         "roofline": roof,
         "cpu_baseline": cpu,
         "stages_ms_per_step": {s: prof[s][0] / args.steps for s in prof},
+        "cov_err": ev["cov_err"],
+        "cov_err_oracle": cov_oracle,
         "reduce_steps": st["n_reduce"],
         "eig_sweeps_avg": st["eig_sweeps"] / max(st["n_reduce"], 1),
     }

@@ -57,7 +57,8 @@ typedef enum { FDSK_F64 = 0, FDSK_F32 = 1, FDSK_BF16 = 2 } fdsk_dtype;  /* BF16 
 typedef enum { FDSK_P_FP64 = 0, FDSK_P_BF16 = 1, FDSK_P_BF16X3 = 2 } fdsk_precision;
 typedef enum { FDSK_MEM_HOST = 0, FDSK_MEM_DEVICE = 1 } fdsk_mem;
 
-#define FDSK_FLAG_PROFILE 1u   /* record per-stage HIP events (see sketch_profile) */
+#define FDSK_FLAG_PROFILE 1u       /* record per-stage HIP events (see sketch_profile) */
+#define FDSK_FLAG_EIG_JACOBI 2u    /* always use the Jacobi eigensolver (see fdsk_eigh) */
 
 enum {
   FDSK_OK = 0,
@@ -147,9 +148,12 @@ int sketch_reset(fdsk_sketch* s);
 
 /* Per-stage device time, measured with HIP events on the sketch's stream
  * when the sketch was created with FDSK_FLAG_PROFILE (otherwise zeros).
- * Totals since create/reset; synchronises the stream. */
+ * Totals since create/reset; synchronises the stream.  EIG is the whole
+ * eigensolve; with the tridiagonal route its three kernels are also timed on
+ * their own (TRIDIAG + DC + BACKTR = EIG up to event overhead). */
 enum { FDSK_STAGE_INGEST = 0, FDSK_STAGE_GRAM = 1, FDSK_STAGE_EIG = 2, FDSK_STAGE_SHRINK = 3,
-       FDSK_STAGE_REBUILD = 4, FDSK_STAGE_COUNT = 5 };
+       FDSK_STAGE_REBUILD = 4, FDSK_STAGE_TRIDIAG = 5, FDSK_STAGE_DC = 6, FDSK_STAGE_BACKTR = 7,
+       FDSK_STAGE_COUNT = 8 };
 typedef struct {
   double ms[FDSK_STAGE_COUNT];       /* summed stage durations */
   int64_t launches[FDSK_STAGE_COUNT];
@@ -174,11 +178,17 @@ const char* sketch_last_error(const fdsk_sketch* s);
  *   1's buffer.
  * fdsk_eigh: eigen-decomposition G = V diag(lam) V^T of a symmetric m x m
  *   matrix (m <= 1024); lam unsorted, V's column j (V[i*ldv + j]) belongs to
- *   lam[j].  Errors: EINVAL, EUNSUPPORTED (m > 1024), ENOMEM, EDEVICE. */
+ *   lam[j].  method FDSK_EIG_AUTO: Householder tridiagonalisation, divide and
+ *   conquer and back-transformation for m <= 200, one-sided block Jacobi
+ *   above; FDSK_EIG_JACOBI: the Jacobi solvers at every m (cyclic two-sided in
+ *   LDS for m <= 100).  Errors: EINVAL, EUNSUPPORTED (m > 1024), ENOMEM,
+ *   EDEVICE. */
+#define FDSK_EIG_AUTO 0
+#define FDSK_EIG_JACOBI 1
 int fdsk_gram(const double* C, int32_t rows, int64_t d, int64_t ldc, double* G, int64_t ldg,
               fdsk_precision prec, void* hip_stream);
 int fdsk_eigh(const double* G, int32_t m, int64_t ldg, double* lam, double* V, int64_t ldv,
-              void* hip_stream);
+              int32_t method, void* hip_stream);
 
 /* ------------------------------------------------------------------------
  * Many independent sketches advanced by one persistent launch.

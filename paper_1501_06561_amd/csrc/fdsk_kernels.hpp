@@ -65,10 +65,31 @@ struct EigWork {
   unsigned* bar;    // 2 counters (grid barrier)
   int* rot;         // per-sweep rotation counts (kMaxSweeps)
   DevStats* st;
+  double* S1;       // mp x mp scratch (divide and conquer)
+  double* S2;       // mp x mp scratch
+  int method;       // EIG_AUTO or EIG_JACOBI
 };
+enum { EIG_AUTO = 0, EIG_JACOBI = 1 };
 constexpr int kMaxSweeps = 40;
 constexpr int kLdsEigMax = 100;   // single-workgroup solver limit (G and V in LDS)
+constexpr int kTridMax = 200;     // tridiagonal route: packed lower triangle in LDS
+constexpr int kDcMax = 256;       // divide and conquer: O(n) state in LDS
+// Eigen-decomposition of the symmetric m x m G (leading dimension mp): lam
+// (m values, any order) and V (column j = eigenvector of lam[j], leading
+// dimension mp).  m <= kTridMax goes through the tridiagonal route unless
+// wk.method is EIG_JACOBI; larger m through the Jacobi solvers.
 hipError_t launch_eig(const double* G, int m, int mp, double* lam, double* V, EigWork wk,
                       hipStream_t s);
+hipError_t launch_eig_jacobi(const double* G, int m, int mp, double* lam, double* V, EigWork wk,
+                             hipStream_t s);
+hipError_t launch_eig_trid(const double* G, int m, int mp, double* lam, double* V, EigWork wk,
+                           hipStream_t s);
+// The three kernels of the tridiagonal route on their own (same arguments).
+hipError_t launch_tridiag(const double* G, int m, int mp, EigWork wk, hipStream_t s);
+hipError_t launch_dc(int m, int mp, double* lam, double* V, EigWork wk, hipStream_t s);
+hipError_t launch_backtr(int m, int mp, double* V, EigWork wk, hipStream_t s);
+inline bool eig_uses_trid(int m, const EigWork& wk) {
+  return wk.method != EIG_JACOBI && m <= kTridMax && wk.S1 && wk.S2;
+}
 
 }  // namespace fdsk

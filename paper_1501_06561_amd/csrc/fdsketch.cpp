@@ -33,7 +33,7 @@ struct fdsk_sketch {
   double* C[2] = {nullptr, nullptr};
   int cur = 0;
   double *G = nullptr, *Gpart = nullptr, *W = nullptr, *V = nullptr, *lam = nullptr,
-         *Ut = nullptr, *rownorm = nullptr;
+         *Ut = nullptr, *rownorm = nullptr, *S1 = nullptr, *S2 = nullptr;
   int ksplit_max = 1;
   DevStats* st = nullptr;
   unsigned* bar = nullptr;
@@ -133,7 +133,8 @@ void add_mark(fdsk_sketch* s, int stage, hipEvent_t a, hipEvent_t b) {
 }
 
 int reduce(fdsk_sketch* s) {
-  EigWork wk{s->W, s->bar, s->rot, s->st};
+  EigWork wk{s->W, s->bar, s->rot, s->st, s->S1, s->S2,
+             (s->cfg.flags & FDSK_FLAG_EIG_JACOBI) ? EIG_JACOBI : EIG_AUTO};
   hipEvent_t e0 = mark(s);
   const int npass = s->cfg.precision == FDSK_P_BF16 ? 1 : 3;
   if (s->cfg.precision == FDSK_P_FP64)
@@ -142,7 +143,19 @@ int reduce(fdsk_sketch* s) {
     HIPCHK(s, launch_gram_lowp(s->C[s->cur], s->ldc, s->mp, s->Gpart, s->ksplit_max, s->G, npass,
                                s->stream));
   hipEvent_t e1 = mark(s);
-  HIPCHK(s, launch_eig(s->G, s->m, s->mp, s->lam, s->V, wk, s->stream));
+  if (eig_uses_trid(s->m, wk)) {
+    HIPCHK(s, launch_tridiag(s->G, s->m, s->mp, wk, s->stream));
+    hipEvent_t t1 = mark(s);
+    HIPCHK(s, launch_dc(s->m, s->mp, s->lam, s->V, wk, s->stream));
+    hipEvent_t t2 = mark(s);
+    HIPCHK(s, launch_backtr(s->m, s->mp, s->V, wk, s->stream));
+    hipEvent_t t3 = mark(s);
+    add_mark(s, FDSK_STAGE_TRIDIAG, e1, t1);
+    add_mark(s, FDSK_STAGE_DC, t1, t2);
+    add_mark(s, FDSK_STAGE_BACKTR, t2, t3);
+  } else {
+    HIPCHK(s, launch_eig(s->G, s->m, s->mp, s->lam, s->V, wk, s->stream));
+  }
   hipEvent_t e2 = mark(s);
   HIPCHK(s, launch_shrink(s->lam, s->V, s->m, s->mp, s->rp, s->rownorm, s->new0, s->occ, s->Ut,
                           s->st, s->stream));
@@ -198,7 +211,10 @@ int check_device_flags(fdsk_sketch* s) {
 
 extern "C" {
 
-const char* fdsk_version(void) { return "fdsketch 0.2 (gfx950; FP64 / BF16 / BF16x3 Gram and rebuild, FP64 Jacobi)"; }
+const char* fdsk_version(void) {
+  return "fdsketch 0.3 (gfx950; FP64 / BF16 / BF16x3 Gram and rebuild; FP64 tridiagonal divide-and-conquer "
+         "and Jacobi eigensolvers)";
+}
 
 const char* sketch_last_error(const fdsk_sketch* s) {
   if (!s) return g_last_error.c_str();
@@ -220,7 +236,8 @@ int sketch_create(const fdsk_config* cfg, void* hip_stream, fdsk_sketch** out) {
     return set_err(nullptr, FDSK_EINVAL, "alpha must lie in (0, 1]");
   if (c.precision != FDSK_P_FP64 && c.precision != FDSK_P_BF16 && c.precision != FDSK_P_BF16X3)
     return set_err(nullptr, FDSK_EINVAL, "unknown precision %d", (int)c.precision);
-  if (c.flags & ~FDSK_FLAG_PROFILE) return set_err(nullptr, FDSK_EINVAL, "unknown flags");
+  if (c.flags & ~(FDSK_FLAG_PROFILE | FDSK_FLAG_EIG_JACOBI))
+    return set_err(nullptr, FDSK_EINVAL, "unknown flags");
 
   fdsk_sketch* s = new fdsk_sketch;
   s->cfg = c;
@@ -248,7 +265,7 @@ int sketch_create(const fdsk_config* cfg, void* hip_stream, fdsk_sketch** out) {
          oGp = take(mp2 * 8 * s->ksplit_max), oW = take(mp2 * 8), oV = take(mp2 * 8),
          oUt = take(mp2 * 8), oLam = take(s->mp * 8), oRn = take(s->mp * 8),
          oSt = take(sizeof(DevStats)), oBar = take(4 * sizeof(unsigned)),
-         oRot = take(kMaxSweeps * sizeof(int));
+         oRot = take(kMaxSweeps * sizeof(int)), oS1 = take(mp2 * 8), oS2 = take(mp2 * 8);
   hipError_t e = hipMalloc(&s->arena, off);
   if (e != hipSuccess) {
     delete s;
@@ -267,6 +284,8 @@ int sketch_create(const fdsk_config* cfg, void* hip_stream, fdsk_sketch** out) {
   s->st = reinterpret_cast<DevStats*>(a + oSt);
   s->bar = reinterpret_cast<unsigned*>(a + oBar);
   s->rot = reinterpret_cast<int*>(a + oRot);
+  s->S1 = reinterpret_cast<double*>(a + oS1);
+  s->S2 = reinterpret_cast<double*>(a + oS2);
   e = hipMemsetAsync(s->arena, 0, off, s->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
   if (e != hipSuccess) {
@@ -599,15 +618,17 @@ extern "C" int fdsk_gram(const double* C, int32_t rows, int64_t d, int64_t ldc, 
 }
 
 extern "C" int fdsk_eigh(const double* G, int32_t m, int64_t ldg, double* lam, double* V,
-                         int64_t ldv, void* hip_stream) {
+                         int64_t ldv, int32_t method, void* hip_stream) {
   if (!G || !lam || !V || m < 1 || ldg < m || ldv < m)
     return set_err(nullptr, FDSK_EINVAL, "fdsk_eigh: bad arguments");
+  if (method != FDSK_EIG_AUTO && method != FDSK_EIG_JACOBI)
+    return set_err(nullptr, FDSK_EINVAL, "fdsk_eigh: unknown method %d", (int)method);
   if (m > 1024) return set_err(nullptr, FDSK_EUNSUPPORTED, "fdsk_eigh: m > 1024");
   hipStream_t st = static_cast<hipStream_t>(hip_stream);
   const int mp = round_up(m, 32);
   const size_t nG = static_cast<size_t>(mp) * mp;
   DevBuf buf;
-  const size_t bytes = (4 * nG + mp) * 8 + sizeof(DevStats) + 4 * sizeof(unsigned) +
+  const size_t bytes = (6 * nG + mp) * 8 + sizeof(DevStats) + 4 * sizeof(unsigned) +
                        kMaxSweeps * sizeof(int) + 256;
   if (hipMalloc(&buf.p, bytes) != hipSuccess) return set_err(nullptr, FDSK_ENOMEM, "fdsk_eigh: workspace");
   HIPCHK(nullptr, hipMemsetAsync(buf.p, 0, bytes, st));
@@ -615,12 +636,14 @@ extern "C" int fdsk_eigh(const double* G, int32_t m, int64_t ldg, double* lam, d
   double* Wp = Gp + nG;
   double* Vp = Wp + nG;
   double* Vt = Vp + nG;
-  double* lp = Vt + nG;
+  double* S1 = Vt + nG;
+  double* S2 = S1 + nG;
+  double* lp = S2 + nG;
   DevStats* ds = reinterpret_cast<DevStats*>(lp + mp);
   unsigned* bar = reinterpret_cast<unsigned*>(ds + 1);
   int* rot = reinterpret_cast<int*>(bar + 4);
   HIPCHK(nullptr, hipMemcpy2DAsync(Gp, mp * 8, G, ldg * 8, m * 8, m, hipMemcpyDeviceToDevice, st));
-  EigWork wk{Wp, bar, rot, ds};
+  EigWork wk{Wp, bar, rot, ds, S1, S2, method == FDSK_EIG_JACOBI ? EIG_JACOBI : EIG_AUTO};
   HIPCHK(nullptr, launch_eig(Gp, m, mp, lp, Vp, wk, st));
   // V is column-major inside the library; hand it out row-major.
   HIPCHK(nullptr, launch_transpose(Vp, mp, m, Vt, st));

@@ -276,6 +276,12 @@ __global__ __launch_bounds__(256) void k_eig_blk(BlkArgs A) {
 
 hipError_t launch_eig(const double* G, int m, int mp, double* lam, double* V, EigWork wk,
                       hipStream_t s) {
+  if (eig_uses_trid(m, wk)) return launch_eig_trid(G, m, mp, lam, V, wk, s);
+  return launch_eig_jacobi(G, m, mp, lam, V, wk, s);
+}
+
+hipError_t launch_eig_jacobi(const double* G, int m, int mp, double* lam, double* V, EigWork wk,
+                             hipStream_t s) {
   const int n = (m + 1) & ~1;
   if (n <= kLdsEigMax) {
     hipLaunchKernelGGL(k_eig_lds, dim3(1), dim3(1024), 0, s, G, m, mp, lam, V, wk.st);

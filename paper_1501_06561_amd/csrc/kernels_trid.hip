@@ -1,0 +1,588 @@
+// FP64 symmetric eigensolver by tridiagonal reduction and divide and conquer.
+//
+// The m x m Gram matrix G of a ReduceRank (m <= kTridMax) goes through three
+// kernels, all in FP64 and all in stream order:
+//
+// * k_tridiag: Householder reduction Q^T G Q = T (T tridiagonal) in one
+//   workgroup, the lower triangle of G packed by columns in LDS.  Reflector
+//   H_k = I - tau_k u_k u_k^T with u_k = (0,..,0, 1, v_k) zeroes column k below
+//   the subdiagonal; the trailing block is updated by the symmetric rank-2
+//   form A <- A - v w^T - w v^T, w = p - (tau/2)(p.v) v, p = tau A v.
+//
+// * k_dc: eigen-decomposition T = Z diag(lambda) Z^T by Cuppen's divide and
+//   conquer, bottom up from 1 x 1 blocks.  Every off-diagonal e_b is a tear:
+//   the two neighbouring diagonal entries lose |e_b|, and merging the blocks on
+//   both sides of b is the rank-one problem D + rho z z^T with rho = |e_b| and
+//   z = (last row of the left block's eigenvectors, sign(e_b) x first row of
+//   the right block's).  Per merge: sort, deflate (negligible rho z_i, or two
+//   close d's after a Givens rotation), solve the secular equation
+//   1 + rho sum_j z_j^2 / (d_j - lambda) = 0 for each remaining root (each root
+//   kept as an offset tau from its nearer pole so that lambda - d_j is exact),
+//   recompute z from the roots (Gu-Eisenstat) so the vectors
+//   u_i = z_i / (d_i - lambda) are orthogonal to working precision, and
+//   multiply them into the block's eigenvectors on matrix cores.  All merges
+//   of one level run together.
+//
+// * k_backtr: V = H_0 H_1 ... H_{m-3} Z, one wave per eigenvector with the
+//   column in registers and the reflectors staged in LDS.
+#include "fdsk_device.hpp"
+#include "fdsk_kernels.hpp"
+
+namespace fdsk {
+
+namespace {
+
+constexpr int TNT = 1024;                       // threads of the one-workgroup kernels
+constexpr int TRI_PACK = kTridMax * (kTridMax + 1) / 2;
+
+__device__ __forceinline__ int colstart(int j, int n) { return j * n - (j * (j - 1)) / 2; }
+
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
+  return v;
+}
+
+}  // namespace
+
+// ----------------------------------------------------------------- reduce
+// Output in W (doubles): [0, P) packed columns (column k holds v_k below the
+// subdiagonal, P = n(n+1)/2), then tau[n], d[n], e[n], scale.  d and e are of
+// G * 2^-s (an exact power-of-two scaling by the largest |g|); scale = 2^s.
+__global__ __launch_bounds__(TNT) void k_tridiag(const double* __restrict__ G, int n, int ldg,
+                                                 double* __restrict__ W) {
+  __shared__ double A[TRI_PACK];
+  __shared__ double p[kTridMax];
+  __shared__ double red[16];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int P = n * (n + 1) / 2;
+  double amax = 0.0;
+  for (int j = w; j < n; j += TNT / 64) {
+    const int cj = colstart(j, n);
+    for (int i = j + lane; i < n; i += 64) {
+      const double g = G[static_cast<int64_t>(i) * ldg + j];
+      A[cj + i - j] = g;
+      amax = fmax(amax, fabs(g));
+    }
+  }
+  amax = wave_max(amax);
+  if (lane == 0) red[w] = amax;
+  __syncthreads();
+  double gmax = 0.0;
+  for (int i = 0; i < TNT / 64; ++i) gmax = fmax(gmax, red[i]);
+  const int sexp = (gmax > 0.0 && gmax < INFINITY) ? ilogb(gmax) : 0;
+  const double sc = ldexp(1.0, -sexp);
+  for (int e = tid; e < P; e += TNT) A[e] *= sc;
+  __syncthreads();
+  double* tauG = W + P;
+  double* dG = tauG + n;
+  double* eG = dG + n;
+  for (int k = 0; k + 2 < n; ++k) {
+    const int L = n - k - 1;            // length of the column below the diagonal
+    const int ck = colstart(k, n);      // A(k,k); A(k+1+t, k) at ck + 1 + t
+    if (w == 0) {
+      const double alpha = A[ck + 1];   // read by every lane before lane 0 overwrites it
+      double s2 = 0.0;
+      for (int t = 1 + lane; t < L; t += 64) {
+        const double x = A[ck + 1 + t];
+        s2 += x * x;
+      }
+      s2 = wave_sum(s2);
+      double tau = 0.0, beta = alpha;
+      if (s2 > 0.0) {
+        const double mu = sqrt(alpha * alpha + s2);
+        beta = (alpha >= 0.0) ? -mu : mu;
+        tau = (beta - alpha) / beta;
+        const double scale = 1.0 / (alpha - beta);
+        for (int t = 1 + lane; t < L; t += 64) A[ck + 1 + t] *= scale;
+      }
+      if (lane == 0) {
+        dG[k] = A[ck];
+        eG[k] = beta;
+        tauG[k] = tau;
+        red[k & 1] = tau;     // two slots: a step without reflection has no later barrier
+        A[ck + 1] = 1.0;
+      }
+    }
+    __syncthreads();
+    const double tau = red[k & 1];
+    if (tau != 0.0) {
+      // p = tau * A22 v: four threads per row, each on every fourth column.
+      {
+        const int r = tid >> 2, q = tid & 3;
+        double acc = 0.0;
+        if (r < L) {
+          const int i = k + 1 + r;
+          const int ci = colstart(i, n);
+          for (int jj = q; jj < L; jj += 4) {
+            const int j = k + 1 + jj;
+            const double a = (i >= j) ? A[colstart(j, n) + i - j] : A[ci + j - i];
+            acc = fma(a, A[ck + 1 + jj], acc);
+          }
+        }
+        acc += __shfl_xor(acc, 1, 64);
+        acc += __shfl_xor(acc, 2, 64);
+        if (r < L && q == 0) p[r] = tau * acc;
+      }
+      __syncthreads();
+      // c = (tau/2) p.v, w = p - c v, A22 -= v w^T + w v^T (lower part).
+      double dot = 0.0;
+      for (int t = lane; t < L; t += 64) dot = fma(p[t], A[ck + 1 + t], dot);
+      dot = wave_sum(dot);
+      const double c = 0.5 * tau * dot;
+      for (int jj = w; jj < L; jj += TNT / 64) {
+        const int cj = colstart(k + 1 + jj, n);
+        const double vj = A[ck + 1 + jj];
+        const double wj = fma(-c, vj, p[jj]);
+        for (int ii = jj + lane; ii < L; ii += 64) {
+          const double vi = A[ck + 1 + ii];
+          const double wi = fma(-c, vi, p[ii]);
+          A[cj + ii - jj] -= fma(vi, wj, wi * vj);
+        }
+      }
+      __syncthreads();
+    }
+  }
+  if (tid == 0) {
+    if (n >= 2) {
+      const int c2 = colstart(n - 2, n);
+      dG[n - 2] = A[c2];
+      eG[n - 2] = A[c2 + 1];
+      tauG[n - 2] = 0.0;
+    }
+    dG[n - 1] = A[colstart(n - 1, n)];
+    tauG[n - 1] = 0.0;
+    eG[n - 1] = 0.0;
+    W[P + 3 * n] = ldexp(1.0, sexp);
+  }
+  for (int e = tid; e < P; e += TNT) W[e] = A[e];
+}
+
+// ------------------------------------------------------ divide and conquer
+namespace {
+
+struct DcSmem {
+  double D[kDcMax];      // eigenvalues per position of the current blocks
+  double Ds[kDcMax];     // sorted d (deflation rotations applied)
+  double Zs[kDcMax];     // sorted z
+  double dh[kDcMax];     // compact non-deflated d
+  double zh[kDcMax];     // compact non-deflated z (then the recomputed z)
+  double ddf[kDcMax];    // compact deflated eigenvalues
+  double rc[kDcMax];     // rotation (c, s) recorded at a sorted position
+  double rs[kDcMax];
+  double tau[kDcMax];    // root offsets from their poles
+  int perm[kDcMax];      // sorted position -> local column
+  int kind[kDcMax];      // 0 z-deflated, 1 new pending, 2 rotated with the pending one
+  int dest[kDcMax];      // sorted position -> compact column
+  int org[kDcMax];       // root -> compact index of its pole
+  int kk[kDcMax / 2];    // non-deflated count per merge
+  int tile0[kDcMax / 2 + 1];
+};
+
+// Merge b of the level with half-size s: block [a, a+k1+k2).
+__device__ __forceinline__ void merge_geom(int b, int s, int n, int& a, int& k1, int& k2) {
+  a = 2 * s * b;
+  k1 = min(s, n - a);
+  k2 = max(0, min(s, n - a - s));
+}
+
+// Root `i` of 1 + rho sum_j zz_j^2 / (dd_j - lambda) = 0 over the sorted,
+// distinct dd (kk of them).  Returns the pole index `o` and tau with
+// lambda = dd_o + tau; every difference dd_j - lambda is (dd_j - dd_o) - tau.
+__device__ int secular_root(const double* dd, const double* zz, int kk, int i, double rho,
+                            double& tau_out) {
+  int o;
+  double lo, hi;
+  if (i < kk - 1) {
+    const double h = 0.5 * (dd[i + 1] - dd[i]);
+    double f = 0.0;
+    for (int j = 0; j < kk; ++j) f += zz[j] * zz[j] / ((dd[j] - dd[i]) - h);
+    f = 1.0 + rho * f;
+    if (f >= 0.0) {
+      o = i; lo = 0.0; hi = h;
+    } else {
+      o = i + 1; lo = -h; hi = 0.0;
+    }
+  } else {
+    double z2 = 0.0;
+    for (int j = 0; j < kk; ++j) z2 += zz[j] * zz[j];
+    o = kk - 1; lo = 0.0; hi = rho * z2;
+  }
+  const double d0 = dd[o];
+  // Start from the one-pole model: the other terms frozen at tau = 0.
+  double rest = 0.0;
+  for (int j = 0; j < kk; ++j)
+    if (j != o) rest += zz[j] * zz[j] / (dd[j] - d0);
+  double t = rho * zz[o] * zz[o] / (1.0 + rho * rest);
+  if (!(t > lo && t < hi)) t = 0.5 * (lo + hi);
+  const double eps = 1.1102230246251565e-16;
+  for (int it = 0; it < 200; ++it) {
+    double psi = 0.0, dpsi = 0.0;
+    for (int j = 0; j < kk; ++j) {
+      const double del = (dd[j] - d0) - t;
+      const double r = zz[j] / del;
+      psi = fma(zz[j], r, psi);
+      dpsi = fma(r, r, dpsi);
+    }
+    const double g = 1.0 + rho * psi;
+    if (g == 0.0) break;
+    if (g > 0.0) hi = t; else lo = t;
+    const double step = g / (rho * dpsi);
+    double tn = t - step;
+    if (fabs(step) <= 2.0 * eps * fabs(t)) { t = tn; break; }
+    if (!(tn > lo && tn < hi)) {
+      // Bisect, geometrically when the bracket spans orders of magnitude.
+      if (lo > 0.0 && hi > 16.0 * lo) tn = sqrt(lo * hi);
+      else if (hi < 0.0 && lo < 16.0 * hi) tn = -sqrt(lo * hi);
+      else tn = 0.5 * (lo + hi);
+    }
+    if (tn == t || !(hi - lo > 2.0 * eps * fmax(fabs(lo), fabs(hi)))) { t = tn; break; }
+    t = tn;
+  }
+  tau_out = t;
+  return o;
+}
+
+}  // namespace
+
+// T = Z diag(lambda) Z^T for the tridiagonal (d, e) written by k_tridiag in W.
+// Z (n x n, column-major, leading dimension ldz) and lambda are the outputs;
+// Qc, U (ldz) are scratch.
+__global__ __launch_bounds__(TNT) void k_dc(const double* __restrict__ W, int n, double* __restrict__ Z,
+                                            int ldz, double* __restrict__ Qc, double* __restrict__ U,
+                                            double* __restrict__ lam, DevStats* __restrict__ st) {
+  __shared__ DcSmem S;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int P = n * (n + 1) / 2;
+  const double* dG = W + P + n;
+  const double* eG = dG + n;
+  const double scale = W[P + 3 * n];
+  // Z = I; torn diagonal.
+  for (int64_t e = tid; e < static_cast<int64_t>(n) * n; e += TNT) {
+    const int c = static_cast<int>(e / n), r = static_cast<int>(e % n);
+    Z[static_cast<int64_t>(c) * ldz + r] = (r == c) ? 1.0 : 0.0;
+  }
+  for (int i = tid; i < n; i += TNT) {
+    const double el = (i > 0) ? fabs(eG[i - 1]) : 0.0;
+    const double er = (i < n - 1) ? fabs(eG[i]) : 0.0;
+    S.D[i] = dG[i] - el - er;
+  }
+  __syncthreads();
+  const double eps = 1.1102230246251565e-16;
+  for (int s = 1; s < n; s *= 2) {
+    const int nm = (n + 2 * s - 1) / (2 * s);
+    // 1. z from the boundary rows, sorted by eigenvalue within each merge.
+    for (int g = tid; g < n; g += TNT) {
+      const int b = g / (2 * s);
+      int a, k1, k2;
+      merge_geom(b, s, n, a, k1, k2);
+      if (k2 == 0) continue;
+      const int k = k1 + k2, j = g - a;
+      const double beta = eG[a + k1 - 1];
+      const double zj = (j < k1) ? Z[static_cast<int64_t>(a + j) * ldz + a + k1 - 1]
+                                 : ((beta >= 0.0) ? 1.0 : -1.0) * Z[static_cast<int64_t>(a + j) * ldz + a + k1];
+      const double dj = S.D[g];
+      int rank = 0;
+      for (int i = 0; i < k; ++i) {
+        const double di = S.D[a + i];
+        rank += (di < dj) || (di == dj && i < j);
+      }
+      S.perm[a + rank] = j;
+      S.Ds[a + rank] = dj;
+      S.Zs[a + rank] = zj * 0.70710678118654752440;
+    }
+    __syncthreads();
+    // 2. Deflation scan, one thread per merge.
+    for (int b = tid; b < nm; b += TNT) {
+      int a, k1, k2;
+      merge_geom(b, s, n, a, k1, k2);
+      if (k2 == 0) continue;
+      const int k = k1 + k2;
+      const double rho = 2.0 * fabs(eG[a + k1 - 1]);
+      double dmax = 0.0;
+      for (int j = 0; j < k; ++j) dmax = fmax(dmax, fabs(S.Ds[a + j]));
+      const double tol = 8.0 * eps * fmax(dmax, rho);
+      int nk = 0, nd = 0, last = -1;
+      for (int j = 0; j < k; ++j) {
+        const int pj = a + j;
+        if (rho * fabs(S.Zs[pj]) <= tol) {
+          S.kind[pj] = 0;
+          S.dest[pj] = -1 - nd;             // deflated, slot nd (fixed up below)
+          S.ddf[a + nd] = S.Ds[pj];
+          ++nd;
+          continue;
+        }
+        if (last >= 0) {
+          const int pl = a + last;
+          const double zl = S.Zs[pl], zj = S.Zs[pj];
+          const double th = hypot(zl, zj);
+          const double c = zj / th, sn = zl / th;
+          const double t = S.Ds[pj] - S.Ds[pl];
+          if (fabs(t * c * sn) <= tol) {
+            const double dl = S.Ds[pl], dj = S.Ds[pj];
+            S.Ds[pl] = c * c * dl + sn * sn * dj;
+            S.Ds[pj] = sn * sn * dl + c * c * dj;
+            S.Zs[pj] = th;
+            S.Zs[pl] = 0.0;
+            S.kind[pj] = 2;
+            S.rc[pj] = c;
+            S.rs[pj] = sn;
+            S.dest[pl] = -1 - nd;
+            S.ddf[a + nd] = S.Ds[pl];
+            ++nd;
+            last = j;
+            continue;
+          }
+          S.dest[pl] = nk;
+          S.dh[a + nk] = S.Ds[pl];
+          S.zh[a + nk] = S.Zs[pl];
+          ++nk;
+        }
+        S.kind[pj] = 1;
+        last = j;
+      }
+      if (last >= 0) {
+        const int pl = a + last;
+        S.dest[pl] = nk;
+        S.dh[a + nk] = S.Ds[pl];
+        S.zh[a + nk] = S.Zs[pl];
+        ++nk;
+      }
+      for (int j = 0; j < k; ++j)
+        if (S.dest[a + j] < 0) S.dest[a + j] = nk + (-1 - S.dest[a + j]);
+      S.kk[b] = nk;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      int acc = 0;
+      for (int b = 0; b < nm; ++b) {
+        int a, k1, k2;
+        merge_geom(b, s, n, a, k1, k2);
+        S.tile0[b] = acc;
+        if (k2 > 0) acc += ((k1 + k2 + 15) / 16) * ((S.kk[b] + 15) / 16);
+      }
+      S.tile0[nm] = acc;
+    }
+    // 3. Qc = block eigenvectors in sorted order with the deflation rotations
+    //    applied, columns in compact order (non-deflated first).  One thread
+    //    per row replays the scan with the pending column in a register.
+    for (int g = tid; g < n; g += TNT) {
+      const int b = g / (2 * s);
+      int a, k1, k2;
+      merge_geom(b, s, n, a, k1, k2);
+      if (k2 == 0) continue;
+      const int k = k1 + k2, r = g;
+      double carry = 0.0;
+      int plast = -1;
+      for (int j = 0; j < k; ++j) {
+        const int pj = a + j;
+        const double q = Z[static_cast<int64_t>(a + S.perm[pj]) * ldz + r];
+        const int kd = S.kind[pj];
+        if (kd == 0) {
+          Qc[static_cast<int64_t>(a + S.dest[pj]) * ldz + r] = q;
+        } else if (kd == 1) {
+          if (plast >= 0) Qc[static_cast<int64_t>(a + S.dest[plast]) * ldz + r] = carry;
+          carry = q;
+          plast = pj;
+        } else {
+          const double c = S.rc[pj], sn = S.rs[pj];
+          Qc[static_cast<int64_t>(a + S.dest[plast]) * ldz + r] = c * carry - sn * q;
+          carry = sn * carry + c * q;
+          plast = pj;
+        }
+      }
+      if (plast >= 0) Qc[static_cast<int64_t>(a + S.dest[plast]) * ldz + r] = carry;
+    }
+    // 4. Secular roots, one thread per root.
+    for (int g = tid; g < n; g += TNT) {
+      const int b = g / (2 * s);
+      int a, k1, k2;
+      merge_geom(b, s, n, a, k1, k2);
+      if (k2 == 0) continue;
+      const int i = g - a;
+      const int nk = S.kk[b];
+      if (i >= nk) continue;
+      const double rho = 2.0 * fabs(eG[a + k1 - 1]);
+      double t;
+      const int o = secular_root(S.dh + a, S.zh + a, nk, i, rho, t);
+      S.org[a + i] = o;
+      S.tau[a + i] = t;
+    }
+    __syncthreads();
+    // 5. Recompute z from the roots (Gu-Eisenstat); keep the signs of z.
+    for (int g = tid; g < n; g += TNT) {
+      const int b = g / (2 * s);
+      int a, k1, k2;
+      merge_geom(b, s, n, a, k1, k2);
+      if (k2 == 0) continue;
+      const int i = g - a;
+      const int nk = S.kk[b];
+      if (i >= nk) continue;
+      const double rho = 2.0 * fabs(eG[a + k1 - 1]);
+      const double* dd = S.dh + a;
+      const double di = dd[i];
+      double prod = ((dd[S.org[a + i]] - di) + S.tau[a + i]) / rho;
+      for (int j = 0; j < nk; ++j) {
+        if (j == i) continue;
+        prod *= ((dd[S.org[a + j]] - di) + S.tau[a + j]) / (dd[j] - di);
+      }
+      const double zn = sqrt(fabs(prod));
+      S.rc[g] = (S.zh[a + i] >= 0.0) ? zn : -zn;     // rc is free after step 3
+    }
+    __syncthreads();
+    // 6. Secular eigenvectors, one thread per root: U(i, j) = z_i/(d_i - lambda_j),
+    //    normalised; U row-major within the merge's block.
+    for (int g = tid; g < n; g += TNT) {
+      const int b = g / (2 * s);
+      int a, k1, k2;
+      merge_geom(b, s, n, a, k1, k2);
+      if (k2 == 0) continue;
+      const int j = g - a;
+      const int nk = S.kk[b];
+      if (j >= nk) continue;
+      const double* dd = S.dh + a;
+      const double dj = dd[S.org[g]], tj = S.tau[g];
+      double nrm = 0.0;
+      for (int i = 0; i < nk; ++i) {
+        const double u = S.rc[a + i] / ((dd[i] - dj) - tj);
+        nrm = fma(u, u, nrm);
+      }
+      const double inv = 1.0 / sqrt(nrm);
+      for (int i = 0; i < nk; ++i) {
+        const double u = S.rc[a + i] / ((dd[i] - dj) - tj);
+        U[static_cast<int64_t>(a + i) * ldz + a + j] = u * inv;
+      }
+      S.Ds[g] = dj + tj;                                // root value
+    }
+    __syncthreads();
+    // 7. Z block = Qc[:, 0:nk] U on matrix cores; deflated columns copied;
+    //    eigenvalues in compact order.
+    const int ntile = S.tile0[nm];
+    for (int t = w; t < ntile; t += TNT / 64) {
+      int b = 0;
+      while (S.tile0[b + 1] <= t) ++b;
+      int a, k1, k2;
+      merge_geom(b, s, n, a, k1, k2);
+      const int k = k1 + k2, nk = S.kk[b];
+      const int nct = (nk + 15) / 16;
+      const int tl = t - S.tile0[b];
+      const int r0 = (tl / nct) * 16, c0 = (tl % nct) * 16;
+      const int li = lane & 15, lk = lane >> 4;
+      f64x4 acc = {0.0, 0.0, 0.0, 0.0};
+      const bool rok = (r0 + li) < k, cok = (c0 + li) < nk;
+      for (int i0 = 0; i0 < nk; i0 += 4) {
+        const int ii = i0 + lk;
+        const double av = (rok && ii < nk) ? Qc[static_cast<int64_t>(a + ii) * ldz + a + r0 + li] : 0.0;
+        const double bv = (cok && ii < nk) ? U[static_cast<int64_t>(a + ii) * ldz + a + c0 + li] : 0.0;
+        acc = mfma_f64(av, bv, acc);
+      }
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int row = r0 + lk + 4 * v;
+        if (row < k && cok) Z[static_cast<int64_t>(a + c0 + li) * ldz + a + row] = acc[v];
+      }
+    }
+    for (int b = 0; b < nm; ++b) {
+      int a, k1, k2;
+      merge_geom(b, s, n, a, k1, k2);
+      if (k2 == 0) continue;
+      const int k = k1 + k2, nk = S.kk[b];
+      const int nd = k - nk;
+      for (int e = tid; e < nd * k; e += TNT) {
+        const int c = nk + e / k, r = e % k;
+        Z[static_cast<int64_t>(a + c) * ldz + a + r] = Qc[static_cast<int64_t>(a + c) * ldz + a + r];
+      }
+    }
+    __syncthreads();
+    for (int g = tid; g < n; g += TNT) {
+      const int b = g / (2 * s);
+      int a, k1, k2;
+      merge_geom(b, s, n, a, k1, k2);
+      if (k2 == 0) continue;
+      const int j = g - a;
+      const int nk = S.kk[b];
+      S.D[g] = (j < nk) ? S.Ds[g] : S.ddf[a + (j - nk)];
+    }
+    __syncthreads();
+  }
+  for (int i = tid; i < n; i += TNT) lam[i] = S.D[i] * scale;
+  if (tid == 0 && st) atomicAdd(&st->eig_sweeps, 1ull);
+}
+
+// ---------------------------------------------------------- back-transform
+// Z <- H_0 H_1 ... H_{n-3} Z for every column (in place): one wave per
+// column, NPL elements per lane, the packed reflectors staged in LDS.
+template <int NPL>
+__global__ __launch_bounds__(TNT) void k_backtr(const double* __restrict__ W, int n,
+                                                double* __restrict__ Z, int ldz) {
+  __shared__ double R[TRI_PACK];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int P = n * (n + 1) / 2;
+  const double* tauG = W + P;
+  for (int e = tid; e < P; e += TNT) R[e] = W[e];
+  __syncthreads();
+  const int col = blockIdx.x * (TNT / 64) + w;
+  if (col >= n) return;
+  double z[NPL];
+  double* zc = Z + static_cast<int64_t>(col) * ldz;
+#pragma unroll
+  for (int t = 0; t < NPL; ++t) {
+    const int i = lane + 64 * t;
+    z[t] = (i < n) ? zc[i] : 0.0;
+  }
+  for (int k = n - 3; k >= 0; --k) {
+    const double tk = tauG[k];
+    if (tk == 0.0) continue;
+    const int ck = colstart(k, n);
+    double v[NPL];
+    double dot = 0.0;
+#pragma unroll
+    for (int t = 0; t < NPL; ++t) {
+      const int i = lane + 64 * t;
+      v[t] = (i == k + 1) ? 1.0 : ((i > k + 1 && i < n) ? R[ck + i - k] : 0.0);
+      dot = fma(v[t], z[t], dot);
+    }
+    dot = wave_sum(dot) * tk;
+#pragma unroll
+    for (int t = 0; t < NPL; ++t) z[t] = fma(-dot, v[t], z[t]);
+  }
+#pragma unroll
+  for (int t = 0; t < NPL; ++t) {
+    const int i = lane + 64 * t;
+    if (i < n) zc[i] = z[t];
+  }
+}
+
+hipError_t launch_tridiag(const double* G, int m, int mp, EigWork wk, hipStream_t s) {
+  if (m < 1 || m > kTridMax || mp < m) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_tridiag, dim3(1), dim3(TNT), 0, s, G, m, mp, wk.W);
+  return hipGetLastError();
+}
+
+hipError_t launch_dc(int m, int mp, double* lam, double* V, EigWork wk, hipStream_t s) {
+  if (m < 1 || m > kTridMax || mp < m) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_dc, dim3(1), dim3(TNT), 0, s, wk.W, m, V, mp, wk.S1, wk.S2, lam, wk.st);
+  return hipGetLastError();
+}
+
+hipError_t launch_backtr(int m, int mp, double* V, EigWork wk, hipStream_t s) {
+  if (m < 1 || m > kTridMax || mp < m) return hipErrorInvalidValue;
+  const int grid = (m + TNT / 64 - 1) / (TNT / 64);
+  if (m <= 64)
+    hipLaunchKernelGGL(k_backtr<1>, dim3(grid), dim3(TNT), 0, s, wk.W, m, V, mp);
+  else if (m <= 128)
+    hipLaunchKernelGGL(k_backtr<2>, dim3(grid), dim3(TNT), 0, s, wk.W, m, V, mp);
+  else
+    hipLaunchKernelGGL(k_backtr<4>, dim3(grid), dim3(TNT), 0, s, wk.W, m, V, mp);
+  return hipGetLastError();
+}
+
+hipError_t launch_eig_trid(const double* G, int m, int mp, double* lam, double* V, EigWork wk,
+                           hipStream_t s) {
+  hipError_t e = launch_tridiag(G, m, mp, wk, s);
+  if (e == hipSuccess) e = launch_dc(m, mp, lam, V, wk, s);
+  if (e == hipSuccess) e = launch_backtr(m, mp, V, wk, s);
+  return e;
+}
+
+}  // namespace fdsk

@@ -50,12 +50,14 @@ class FdskReport(ctypes.Structure):
         return {name: getattr(self, name) for name, _ in self._fields_ if name != "reserved"}
 
 
-STAGES = ("ingest", "gram", "eig", "shrink", "rebuild")
+STAGES = ("ingest", "gram", "eig", "shrink", "rebuild", "tridiag", "dc", "backtr")
 FLAG_PROFILE = 1
+FLAG_EIG_JACOBI = 2
+EIG_METHODS = {"auto": 0, "jacobi": 1}
 
 
 class FdskProfile(ctypes.Structure):
-    _fields_ = [("ms", ctypes.c_double * 5), ("launches", ctypes.c_int64 * 5)]
+    _fields_ = [("ms", ctypes.c_double * 8), ("launches", ctypes.c_int64 * 8)]
 
 
 class FdskError(RuntimeError):
@@ -113,7 +115,7 @@ def lib():
     L.sketch_batch_last_error.argtypes = [vp]
     L.sketch_batch_last_error.restype = ctypes.c_char_p
     L.sketch_profile.argtypes = [vp, ctypes.POINTER(FdskProfile)]
-    L.fdsk_eigh.argtypes = [vp, i32, i64, vp, vp, i64, vp]
+    L.fdsk_eigh.argtypes = [vp, i32, i64, vp, vp, i64, i32, vp]
     for f in ("sketch_create", "sketch_append_rows", "sketch_finalize", "sketch_error",
               "fdsk_evaluate", "sketch_stats", "fdsk_gram", "fdsk_eigh", "sketch_reset",
               "sketch_profile", "sketch_batch_create", "sketch_batch_append",
@@ -168,10 +170,13 @@ class FDSketch:
     """One streaming sketch (Algorithm 1 with the chosen ReduceRank rule)."""
 
     def __init__(self, d, l, variant="fd", alpha=0.2, buffer_rows=0, precision="fp64",
-                 stream=None, profile=False):
+                 stream=None, profile=False, eig="auto"):
         self.d, self.l = int(d), int(l)
+        flags = (FLAG_PROFILE if profile else 0) | (FLAG_EIG_JACOBI if eig == "jacobi" else 0)
+        if eig not in EIG_METHODS:
+            raise ValueError(f"eig must be one of {sorted(EIG_METHODS)}")
         cfg = FdskConfig(self.d, self.l, int(buffer_rows), VARIANTS[variant], float(alpha),
-                         PRECISIONS[precision], FLAG_PROFILE if profile else 0)
+                         PRECISIONS[precision], flags)
         self._stream = stream
         h = ctypes.c_void_p()
         _check(lib().sketch_create(ctypes.byref(cfg), _stream_handle(stream), ctypes.byref(h)))
@@ -252,8 +257,10 @@ def gram(C, precision="fp64", stream=None):
     return G
 
 
-def eigh(G, stream=None):
-    """(lam, V) with G = V diag(lam) V^T, unsorted, from the device Jacobi solver."""
+def eigh(G, method="auto", stream=None):
+    """(lam, V) with G = V diag(lam) V^T, unsorted, from the device solver
+    ("auto": tridiagonal divide and conquer for m <= 200, else Jacobi;
+    "jacobi": the Jacobi solvers at every size)."""
     torch = _torch()
     if G.dtype != torch.float64 or not G.is_cuda or G.stride(1) != 1:
         raise ValueError("G must be a row-major cuda float64 matrix")
@@ -262,7 +269,7 @@ def eigh(G, stream=None):
     V = torch.empty((m, m), dtype=torch.float64, device=G.device)
     _check(lib().fdsk_eigh(ctypes.c_void_p(G.data_ptr()), m, G.stride(0),
                            ctypes.c_void_p(lam.data_ptr()), ctypes.c_void_p(V.data_ptr()),
-                           V.stride(0), _stream_handle(stream)))
+                           V.stride(0), EIG_METHODS[method], _stream_handle(stream)))
     return lam, V
 
 

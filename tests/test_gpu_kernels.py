@@ -20,8 +20,8 @@ def test_gram_matches_numpy(rows, d):
     assert np.array_equal(G, G.T)
 
 
-def _check_eigh(Gm, tol=1e-11):
-    lam, V = F.eigh(torch.from_numpy(Gm).cuda())
+def _check_eigh(Gm, tol=1e-11, method="auto"):
+    lam, V = F.eigh(torch.from_numpy(Gm).cuda(), method)
     lam, V = lam.cpu().numpy(), V.cpu().numpy()
     ref = np.linalg.eigvalsh(Gm)
     scale = max(np.max(np.abs(ref)), 1e-300)
@@ -32,23 +32,31 @@ def _check_eigh(Gm, tol=1e-11):
     return lam, V
 
 
-@pytest.mark.parametrize("m", [1, 2, 7, 40, 99, 100, 101, 128, 200, 333, 513, 1024])
-def test_eigh_random_psd(m):
+@pytest.mark.parametrize("method", ["auto", "jacobi"])
+@pytest.mark.parametrize("m", [1, 2, 3, 7, 33, 40, 64, 99, 100, 101, 128, 199, 200, 333, 513, 1024])
+def test_eigh_random_psd(m, method):
+    """"auto" is the tridiagonal divide-and-conquer route up to m = 200."""
+    if method == "jacobi" and m in (3, 33, 64, 199):
+        pytest.skip("sizes added for the divide-and-conquer route")
     rng = np.random.default_rng(m)
     X = rng.standard_normal((m, 2 * m + 3)) * np.geomspace(1, 1e-3, 2 * m + 3)
-    _check_eigh(X @ X.T)
+    _check_eigh(X @ X.T, method=method)
 
 
-@pytest.mark.parametrize("m", [40, 160])
-def test_eigh_special_matrices(m):
+@pytest.mark.parametrize("method", ["auto", "jacobi"])
+@pytest.mark.parametrize("m", [40, 160, 200])
+def test_eigh_special_matrices(m, method):
     rng = np.random.default_rng(m + 1)
-    _check_eigh(np.diag(rng.uniform(0, 5, m)))                      # already diagonal
+    _check_eigh(np.diag(rng.uniform(0, 5, m)), method=method)       # already diagonal
     Q, _ = np.linalg.qr(rng.standard_normal((m, m)))
     lam = np.repeat([3.0, 1.0, 0.0], [m // 4, m // 4, m - 2 * (m // 4)])
-    _check_eigh((Q * lam) @ Q.T)                                      # repeated + zero
-    _check_eigh(np.zeros((m, m)))
+    _check_eigh((Q * lam) @ Q.T, method=method)                       # repeated + zero
+    _check_eigh(np.zeros((m, m)), method=method)
     X = rng.standard_normal((m, 5))
-    _check_eigh(X @ X.T)                                              # rank 5
+    _check_eigh(X @ X.T, method=method)                               # rank 5
+    d = rng.uniform(1, 2, m)
+    _check_eigh(np.diag(d) + 1e-9 * np.outer(d, d), method=method)    # clustered, near-diagonal
+    _check_eigh(np.diag(np.r_[np.full(m // 2, 1e4), np.full(m - m // 2, 1e-6)]), method=method)  # two clusters
 
 
 @pytest.mark.parametrize("precision,tol", [("bf16x3", 5e-5), ("bf16", 2e-2)])

@@ -20,8 +20,8 @@ from paper_1501_06561_amd import fdsketch as F  # noqa: E402
 
 
 def gpu_sketch(A, l, variant="fd", alpha=0.2, m=0, dtype=torch.float64, chunks=None,
-               host=False):
-    sk = F.FDSketch(A.shape[1], l, variant, alpha, buffer_rows=m)
+               host=False, eig="auto"):
+    sk = F.FDSketch(A.shape[1], l, variant, alpha, buffer_rows=m, eig=eig)
     if dtype == torch.bfloat16:
         src = torch.from_numpy(synth.bf16_bits(A).view(np.int16)).view(torch.bfloat16)
     else:
@@ -73,15 +73,20 @@ def test_config1_random_noisy_fd_l20():
     compare(A, 20, "fd")
 
 
+@pytest.mark.parametrize("eig", ["auto", "jacobi"])
 @pytest.mark.parametrize("variant", oracle.VARIANTS)
-@pytest.mark.parametrize("l", [6, 24, 50, 64, 100])
-def test_variants_across_solver_sizes(variant, l):
-    """l = 6..50 use the single-workgroup LDS eigensolver (m <= 100), l = 64
-    and 100 the multi-workgroup block solver.  d = 300 (ragged against the
-    64-column padding), n ragged against the schedule."""
+@pytest.mark.parametrize("l", [6, 24, 50, 64, 100, 128])
+def test_variants_across_solver_sizes(variant, l, eig):
+    """Both eigensolvers end to end.  "auto": tridiagonal divide and conquer
+    up to m = 200 (l <= 100), block Jacobi at l = 128.  "jacobi": the LDS
+    two-sided solver for m <= 100, the multi-workgroup block solver above.
+    d = 300 (ragged against the 64-column padding), n ragged against the
+    schedule."""
+    if eig == "jacobi" and l == 128:
+        pytest.skip("same path as auto at this size")
     A = synth.random_noisy(2_345, 300, 12, 10.0, seed=(21, l))
     gram = 1e-9 if variant == "fd" else 1e-7
-    compare(A, l, variant, 0.2, gram_tol=gram, cov_rtol=1e-6)
+    compare(A, l, variant, 0.2, gram_tol=gram, cov_rtol=1e-6, eig=eig)
 
 
 @pytest.mark.parametrize("variant", oracle.VARIANTS)
