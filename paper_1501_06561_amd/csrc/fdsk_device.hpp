@@ -31,11 +31,46 @@ __device__ __forceinline__ float bf16_bits_to_f32(uint16_t b) {
   return __uint_as_float(static_cast<uint32_t>(b) << 16);
 }
 
-// Wave-wide (64 lanes) sum.
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+// Data-parallel-primitive (DPP) move of a double: both 32-bit halves go
+// through the same lane permutation.  Lanes whose row is masked off (or whose
+// source does not exist) get `old`.
+template <int CTRL, int ROWMASK = 0xF>
+__device__ __forceinline__ double dpp_f64(double v, double old) {
+  const long long u = __double_as_longlong(v), o = __double_as_longlong(old);
+  const int lo = __builtin_amdgcn_update_dpp(static_cast<int>(o), static_cast<int>(u), CTRL, ROWMASK,
+                                             0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(static_cast<int>(o >> 32), static_cast<int>(u >> 32), CTRL,
+                                             ROWMASK, 0xF, false);
+  return __longlong_as_double((static_cast<long long>(hi) << 32) |
+                              static_cast<long long>(static_cast<unsigned>(lo)));
+}
+
+// Sum over each quad of lanes (4i .. 4i+3); every lane of the quad gets it.
+__device__ __forceinline__ double quad_sum(double v) {
+  v += dpp_f64<0xB1>(v, 0.0);   // quad_perm [1,0,3,2]
+  v += dpp_f64<0x4E>(v, 0.0);   // quad_perm [2,3,0,1]
   return v;
+}
+__device__ __forceinline__ double quad_prod(double v) {
+  v *= dpp_f64<0xB1>(v, 1.0);
+  v *= dpp_f64<0x4E>(v, 1.0);
+  return v;
+}
+
+// Wave-wide (64 lanes, all active) sum, returned in every lane: quad
+// butterflies and row mirrors give each row of 16 its total, two row
+// broadcasts accumulate the rows into lane 63, which is read back.
+__device__ __forceinline__ double wave_sum(double v) {
+  v = quad_sum(v);
+  v += dpp_f64<0x141>(v, 0.0);          // row_half_mirror
+  v += dpp_f64<0x140>(v, 0.0);          // row_mirror
+  v += dpp_f64<0x142, 0xA>(v, 0.0);     // row_bcast:15 into rows 1 and 3
+  v += dpp_f64<0x143, 0xC>(v, 0.0);     // row_bcast:31 into rows 2 and 3
+  const long long u = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane(static_cast<int>(u), 63);
+  const int hi = __builtin_amdgcn_readlane(static_cast<int>(u >> 32), 63);
+  return __longlong_as_double((static_cast<long long>(hi) << 32) |
+                              static_cast<long long>(static_cast<unsigned>(lo)));
 }
 
 // 16x16x4 FP64 matrix-core step: D(16x16) += A(16x4) * B(4x16).

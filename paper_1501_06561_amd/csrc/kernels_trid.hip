@@ -107,37 +107,51 @@ __global__ __launch_bounds__(TNT) void k_tridiag(const double* __restrict__ G, i
     __syncthreads();
     const double tau = red[k & 1];
     if (tau != 0.0) {
-      // p = tau * A22 v: four threads per row, each on every fourth column.
+      // p = tau * A22 v: four threads per row, each on every fourth column;
+      // the lower part of the row (A(i, j), j <= i) and the upper part read
+      // from column i (A(j, i), j > i, contiguous) in two loops.
       {
         const int r = tid >> 2, q = tid & 3;
-        double acc = 0.0;
+        double acc0 = 0.0, acc1 = 0.0;
         if (r < L) {
           const int i = k + 1 + r;
-          const int ci = colstart(i, n);
-          for (int jj = q; jj < L; jj += 4) {
+          int jj = q;
+          int cj = colstart(k + 1 + jj, n);
+#pragma unroll 4
+          for (; jj <= r; jj += 4) {
+            acc0 = fma(A[cj + r - jj], A[ck + 1 + jj], acc0);
             const int j = k + 1 + jj;
-            const double a = (i >= j) ? A[colstart(j, n) + i - j] : A[ci + j - i];
-            acc = fma(a, A[ck + 1 + jj], acc);
+            cj += 4 * n - 4 * j - 6;              // colstart(j + 4) - colstart(j)
           }
+          const int ci = colstart(i, n) - r;
+#pragma unroll 4
+          for (; jj < L; jj += 4) acc1 = fma(A[ci + jj], A[ck + 1 + jj], acc1);
         }
+        double acc = acc0 + acc1;
         acc += __shfl_xor(acc, 1, 64);
         acc += __shfl_xor(acc, 2, 64);
         if (r < L && q == 0) p[r] = tau * acc;
       }
       __syncthreads();
-      // c = (tau/2) p.v, w = p - c v, A22 -= v w^T + w v^T (lower part).
+      // c = (tau/2) p.v, w = p - c v, A22 -= v w^T + w v^T (lower part).  A
+      // wave owns every 16th column; its lanes take up to four row chunks
+      // of the column at once.
       double dot = 0.0;
       for (int t = lane; t < L; t += 64) dot = fma(p[t], A[ck + 1 + t], dot);
       dot = wave_sum(dot);
       const double c = 0.5 * tau * dot;
       for (int jj = w; jj < L; jj += TNT / 64) {
-        const int cj = colstart(k + 1 + jj, n);
+        const int cj = colstart(k + 1 + jj, n) - jj;
         const double vj = A[ck + 1 + jj];
         const double wj = fma(-c, vj, p[jj]);
-        for (int ii = jj + lane; ii < L; ii += 64) {
-          const double vi = A[ck + 1 + ii];
-          const double wi = fma(-c, vi, p[ii]);
-          A[cj + ii - jj] -= fma(vi, wj, wi * vj);
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+          const int ii = jj + lane + 64 * t;
+          if (ii < L) {
+            const double vi = A[ck + 1 + ii];
+            const double wi = fma(-c, vi, p[ii]);
+            A[cj + ii] -= fma(vi, wj, wi * vj);
+          }
         }
       }
       __syncthreads();
@@ -163,19 +177,22 @@ namespace {
 
 struct DcSmem {
   double D[kDcMax];      // eigenvalues per position of the current blocks
-  double Ds[kDcMax];     // sorted d (deflation rotations applied)
+  double Ds[kDcMax];     // sorted d (deflation rotations applied), then the roots
   double Zs[kDcMax];     // sorted z
   double dh[kDcMax];     // compact non-deflated d
-  double zh[kDcMax];     // compact non-deflated z (then the recomputed z)
+  double zh[kDcMax];     // compact non-deflated z
+  double zg[kDcMax];     // z recomputed from the roots
   double ddf[kDcMax];    // compact deflated eigenvalues
-  double rc[kDcMax];     // rotation (c, s) recorded at a sorted position
+  double rc[kDcMax];     // deflation rotations of a merge, in scan order
   double rs[kDcMax];
   double tau[kDcMax];    // root offsets from their poles
-  int perm[kDcMax];      // sorted position -> local column
-  int kind[kDcMax];      // 0 z-deflated, 1 new pending, 2 rotated with the pending one
-  int dest[kDcMax];      // sorted position -> compact column
-  int org[kDcMax];       // root -> compact index of its pole
+  short rp[kDcMax];      // rotation operands (sorted positions)
+  short rj[kDcMax];
+  short perm[kDcMax];    // sorted position -> local column
+  short dest[kDcMax];    // sorted position -> compact column
+  short org[kDcMax];     // root -> compact index of its pole
   int kk[kDcMax / 2];    // non-deflated count per merge
+  int nrot[kDcMax / 2];  // deflation rotations per merge
   int tile0[kDcMax / 2 + 1];
 };
 
@@ -187,17 +204,22 @@ __device__ __forceinline__ void merge_geom(int b, int s, int n, int& a, int& k1,
 }
 
 // Root `i` of 1 + rho sum_j zz_j^2 / (dd_j - lambda) = 0 over the sorted,
-// distinct dd (kk of them).  Returns the pole index `o` and tau with
+// distinct dd (kk of them), evaluated by the four lanes of a quad (each sums
+// every fourth term; the quad totals are identical in all four lanes, so the
+// lanes take the same decisions).  Returns the pole index o and tau with
 // lambda = dd_o + tau; every difference dd_j - lambda is (dd_j - dd_o) - tau.
-__device__ int secular_root(const double* dd, const double* zz, int kk, int i, double rho,
+// Safeguarded Newton on tau inside the bracket that the pole and the
+// midpoint (or the bound rho |z|^2 for the last root) give, falling back to
+// bisection -- geometric when the bracket spans orders of magnitude.
+__device__ int secular_root(const double* dd, const double* zz, int kk, int i, double rho, int q,
                             double& tau_out) {
   int o;
   double lo, hi;
   if (i < kk - 1) {
     const double h = 0.5 * (dd[i + 1] - dd[i]);
     double f = 0.0;
-    for (int j = 0; j < kk; ++j) f += zz[j] * zz[j] / ((dd[j] - dd[i]) - h);
-    f = 1.0 + rho * f;
+    for (int j = q; j < kk; j += 4) f += zz[j] * zz[j] * rcp_nr((dd[j] - dd[i]) - h);
+    f = 1.0 + rho * quad_sum(f);
     if (f >= 0.0) {
       o = i; lo = 0.0; hi = h;
     } else {
@@ -205,25 +227,27 @@ __device__ int secular_root(const double* dd, const double* zz, int kk, int i, d
     }
   } else {
     double z2 = 0.0;
-    for (int j = 0; j < kk; ++j) z2 += zz[j] * zz[j];
-    o = kk - 1; lo = 0.0; hi = rho * z2;
+    for (int j = q; j < kk; j += 4) z2 += zz[j] * zz[j];
+    o = kk - 1; lo = 0.0; hi = rho * quad_sum(z2);
   }
   const double d0 = dd[o];
   // Start from the one-pole model: the other terms frozen at tau = 0.
   double rest = 0.0;
-  for (int j = 0; j < kk; ++j)
-    if (j != o) rest += zz[j] * zz[j] / (dd[j] - d0);
+  for (int j = q; j < kk; j += 4)
+    if (j != o) rest += zz[j] * zz[j] * rcp_nr(dd[j] - d0);
+  rest = quad_sum(rest);
   double t = rho * zz[o] * zz[o] / (1.0 + rho * rest);
   if (!(t > lo && t < hi)) t = 0.5 * (lo + hi);
   const double eps = 1.1102230246251565e-16;
-  for (int it = 0; it < 200; ++it) {
+  for (int it = 0; it < 100; ++it) {
     double psi = 0.0, dpsi = 0.0;
-    for (int j = 0; j < kk; ++j) {
-      const double del = (dd[j] - d0) - t;
-      const double r = zz[j] / del;
+    for (int j = q; j < kk; j += 4) {
+      const double r = zz[j] * rcp_nr((dd[j] - d0) - t);
       psi = fma(zz[j], r, psi);
       dpsi = fma(r, r, dpsi);
     }
+    psi = quad_sum(psi);
+    dpsi = quad_sum(dpsi);
     const double g = 1.0 + rho * psi;
     if (g == 0.0) break;
     if (g > 0.0) hi = t; else lo = t;
@@ -231,7 +255,6 @@ __device__ int secular_root(const double* dd, const double* zz, int kk, int i, d
     double tn = t - step;
     if (fabs(step) <= 2.0 * eps * fabs(t)) { t = tn; break; }
     if (!(tn > lo && tn < hi)) {
-      // Bisect, geometrically when the bracket spans orders of magnitude.
       if (lo > 0.0 && hi > 16.0 * lo) tn = sqrt(lo * hi);
       else if (hi < 0.0 && lo < 16.0 * hi) tn = -sqrt(lo * hi);
       else tn = 0.5 * (lo + hi);
@@ -269,6 +292,8 @@ __global__ __launch_bounds__(TNT) void k_dc(const double* __restrict__ W, int n,
   }
   __syncthreads();
   const double eps = 1.1102230246251565e-16;
+  // Four lanes per root in the per-root steps.
+  const int g4 = tid >> 2, q4 = tid & 3;
   for (int s = 1; s < n; s *= 2) {
     const int nm = (n + 2 * s - 1) / (2 * s);
     // 1. z from the boundary rows, sorted by eigenvalue within each merge.
@@ -287,12 +312,13 @@ __global__ __launch_bounds__(TNT) void k_dc(const double* __restrict__ W, int n,
         const double di = S.D[a + i];
         rank += (di < dj) || (di == dj && i < j);
       }
-      S.perm[a + rank] = j;
+      S.perm[a + rank] = static_cast<short>(j);
       S.Ds[a + rank] = dj;
       S.Zs[a + rank] = zj * 0.70710678118654752440;
     }
     __syncthreads();
-    // 2. Deflation scan, one thread per merge.
+    // 2. Deflation scan, one thread per merge: negligible rho |z_j|, or a
+    //    Givens rotation of the pending entry into j when their d's are close.
     for (int b = tid; b < nm; b += TNT) {
       int a, k1, k2;
       merge_geom(b, s, n, a, k1, k2);
@@ -302,12 +328,11 @@ __global__ __launch_bounds__(TNT) void k_dc(const double* __restrict__ W, int n,
       double dmax = 0.0;
       for (int j = 0; j < k; ++j) dmax = fmax(dmax, fabs(S.Ds[a + j]));
       const double tol = 8.0 * eps * fmax(dmax, rho);
-      int nk = 0, nd = 0, last = -1;
+      int nk = 0, nd = 0, nr = 0, last = -1;
       for (int j = 0; j < k; ++j) {
         const int pj = a + j;
         if (rho * fabs(S.Zs[pj]) <= tol) {
-          S.kind[pj] = 0;
-          S.dest[pj] = -1 - nd;             // deflated, slot nd (fixed up below)
+          S.dest[pj] = static_cast<short>(-1 - nd);
           S.ddf[a + nd] = S.Ds[pj];
           ++nd;
           continue;
@@ -324,33 +349,35 @@ __global__ __launch_bounds__(TNT) void k_dc(const double* __restrict__ W, int n,
             S.Ds[pj] = sn * sn * dl + c * c * dj;
             S.Zs[pj] = th;
             S.Zs[pl] = 0.0;
-            S.kind[pj] = 2;
-            S.rc[pj] = c;
-            S.rs[pj] = sn;
-            S.dest[pl] = -1 - nd;
+            S.rp[a + nr] = static_cast<short>(pl);
+            S.rj[a + nr] = static_cast<short>(pj);
+            S.rc[a + nr] = c;
+            S.rs[a + nr] = sn;
+            ++nr;
+            S.dest[pl] = static_cast<short>(-1 - nd);
             S.ddf[a + nd] = S.Ds[pl];
             ++nd;
             last = j;
             continue;
           }
-          S.dest[pl] = nk;
+          S.dest[pl] = static_cast<short>(nk);
           S.dh[a + nk] = S.Ds[pl];
           S.zh[a + nk] = S.Zs[pl];
           ++nk;
         }
-        S.kind[pj] = 1;
         last = j;
       }
       if (last >= 0) {
         const int pl = a + last;
-        S.dest[pl] = nk;
+        S.dest[pl] = static_cast<short>(nk);
         S.dh[a + nk] = S.Ds[pl];
         S.zh[a + nk] = S.Zs[pl];
         ++nk;
       }
       for (int j = 0; j < k; ++j)
-        if (S.dest[a + j] < 0) S.dest[a + j] = nk + (-1 - S.dest[a + j]);
+        if (S.dest[a + j] < 0) S.dest[a + j] = static_cast<short>(nk + (-1 - S.dest[a + j]));
       S.kk[b] = nk;
+      S.nrot[b] = nr;
     }
     __syncthreads();
     if (tid == 0) {
@@ -363,38 +390,22 @@ __global__ __launch_bounds__(TNT) void k_dc(const double* __restrict__ W, int n,
       }
       S.tile0[nm] = acc;
     }
-    // 3. Qc = block eigenvectors in sorted order with the deflation rotations
-    //    applied, columns in compact order (non-deflated first).  One thread
-    //    per row replays the scan with the pending column in a register.
-    for (int g = tid; g < n; g += TNT) {
-      const int b = g / (2 * s);
-      int a, k1, k2;
-      merge_geom(b, s, n, a, k1, k2);
-      if (k2 == 0) continue;
-      const int k = k1 + k2, r = g;
-      double carry = 0.0;
-      int plast = -1;
-      for (int j = 0; j < k; ++j) {
-        const int pj = a + j;
-        const double q = Z[static_cast<int64_t>(a + S.perm[pj]) * ldz + r];
-        const int kd = S.kind[pj];
-        if (kd == 0) {
-          Qc[static_cast<int64_t>(a + S.dest[pj]) * ldz + r] = q;
-        } else if (kd == 1) {
-          if (plast >= 0) Qc[static_cast<int64_t>(a + S.dest[plast]) * ldz + r] = carry;
-          carry = q;
-          plast = pj;
-        } else {
-          const double c = S.rc[pj], sn = S.rs[pj];
-          Qc[static_cast<int64_t>(a + S.dest[plast]) * ldz + r] = c * carry - sn * q;
-          carry = sn * carry + c * q;
-          plast = pj;
-        }
+    // 3. Qc = the block's eigenvectors in compact column order (column
+    //    dest[j] <- old column perm[j]), rows of the merge only.
+    {
+      const int K2 = 2 * s;
+      const int64_t tot = static_cast<int64_t>(n) * K2;
+      for (int64_t e = tid; e < tot; e += TNT) {
+        const int g = static_cast<int>(e / K2), r = static_cast<int>(e % K2);
+        const int b = g / K2;
+        int a, k1, k2;
+        merge_geom(b, s, n, a, k1, k2);
+        if (k2 == 0 || r >= k1 + k2) continue;
+        Qc[static_cast<int64_t>(a + S.dest[g]) * ldz + a + r] = Z[static_cast<int64_t>(a + S.perm[g]) * ldz + a + r];
       }
-      if (plast >= 0) Qc[static_cast<int64_t>(a + S.dest[plast]) * ldz + r] = carry;
     }
-    // 4. Secular roots, one thread per root.
-    for (int g = tid; g < n; g += TNT) {
+    // 4. Secular roots, four lanes per root.
+    for (int g = g4; g < n; g += TNT / 4) {
       const int b = g / (2 * s);
       int a, k1, k2;
       merge_geom(b, s, n, a, k1, k2);
@@ -404,13 +415,32 @@ __global__ __launch_bounds__(TNT) void k_dc(const double* __restrict__ W, int n,
       if (i >= nk) continue;
       const double rho = 2.0 * fabs(eG[a + k1 - 1]);
       double t;
-      const int o = secular_root(S.dh + a, S.zh + a, nk, i, rho, t);
-      S.org[a + i] = o;
-      S.tau[a + i] = t;
+      const int o = secular_root(S.dh + a, S.zh + a, nk, i, rho, q4, t);
+      if (q4 == 0) {
+        S.org[g] = static_cast<short>(o);
+        S.tau[g] = t;
+      }
     }
     __syncthreads();
-    // 5. Recompute z from the roots (Gu-Eisenstat); keep the signs of z.
+    // 3b. Deflation rotations on the copied columns, one thread per row.
     for (int g = tid; g < n; g += TNT) {
+      const int b = g / (2 * s);
+      int a, k1, k2;
+      merge_geom(b, s, n, a, k1, k2);
+      if (k2 == 0) continue;
+      const int nr = S.nrot[b];
+      for (int t = 0; t < nr; ++t) {
+        double* xp = Qc + static_cast<int64_t>(a + S.dest[S.rp[a + t]]) * ldz + g;
+        double* xj = Qc + static_cast<int64_t>(a + S.dest[S.rj[a + t]]) * ldz + g;
+        const double c = S.rc[a + t], sn = S.rs[a + t];
+        const double x = *xp, y = *xj;
+        *xp = c * x - sn * y;
+        *xj = sn * x + c * y;
+      }
+    }
+    // 5. z recomputed from the roots (Gu-Eisenstat), signs of z kept:
+    //    rho z_i^2 = prod_j (lambda_j - d_i) / prod_{j != i} (d_j - d_i).
+    for (int g = g4; g < n; g += TNT / 4) {
       const int b = g / (2 * s);
       int a, k1, k2;
       merge_geom(b, s, n, a, k1, k2);
@@ -421,18 +451,19 @@ __global__ __launch_bounds__(TNT) void k_dc(const double* __restrict__ W, int n,
       const double rho = 2.0 * fabs(eG[a + k1 - 1]);
       const double* dd = S.dh + a;
       const double di = dd[i];
-      double prod = ((dd[S.org[a + i]] - di) + S.tau[a + i]) / rho;
-      for (int j = 0; j < nk; ++j) {
+      double prod = (q4 == 0) ? ((dd[S.org[g]] - di) + S.tau[g]) / rho : 1.0;
+      for (int j = q4; j < nk; j += 4) {
         if (j == i) continue;
         prod *= ((dd[S.org[a + j]] - di) + S.tau[a + j]) / (dd[j] - di);
       }
+      prod = quad_prod(prod);
       const double zn = sqrt(fabs(prod));
-      S.rc[g] = (S.zh[a + i] >= 0.0) ? zn : -zn;     // rc is free after step 3
+      if (q4 == 0) S.zg[g] = (S.zh[g] >= 0.0) ? zn : -zn;
     }
     __syncthreads();
-    // 6. Secular eigenvectors, one thread per root: U(i, j) = z_i/(d_i - lambda_j),
-    //    normalised; U row-major within the merge's block.
-    for (int g = tid; g < n; g += TNT) {
+    // 6. Secular eigenvectors, four lanes per root: U(i, j) = z_i / (d_i -
+    //    lambda_j), normalised; U row-major within the merge's block.
+    for (int g = g4; g < n; g += TNT / 4) {
       const int b = g / (2 * s);
       int a, k1, k2;
       merge_geom(b, s, n, a, k1, k2);
@@ -443,20 +474,20 @@ __global__ __launch_bounds__(TNT) void k_dc(const double* __restrict__ W, int n,
       const double* dd = S.dh + a;
       const double dj = dd[S.org[g]], tj = S.tau[g];
       double nrm = 0.0;
-      for (int i = 0; i < nk; ++i) {
-        const double u = S.rc[a + i] / ((dd[i] - dj) - tj);
+      for (int i = q4; i < nk; i += 4) {
+        const double u = S.zg[a + i] * rcp_nr((dd[i] - dj) - tj);
         nrm = fma(u, u, nrm);
       }
-      const double inv = 1.0 / sqrt(nrm);
-      for (int i = 0; i < nk; ++i) {
-        const double u = S.rc[a + i] / ((dd[i] - dj) - tj);
+      const double inv = rsq_nr(quad_sum(nrm));
+      for (int i = q4; i < nk; i += 4) {
+        const double u = S.zg[a + i] * rcp_nr((dd[i] - dj) - tj);
         U[static_cast<int64_t>(a + i) * ldz + a + j] = u * inv;
       }
-      S.Ds[g] = dj + tj;                                // root value
+      if (q4 == 0) S.Ds[g] = dj + tj;                  // the root
     }
     __syncthreads();
-    // 7. Z block = Qc[:, 0:nk] U on matrix cores; deflated columns copied;
-    //    eigenvalues in compact order.
+    // 7. Z block = Qc[:, 0:nk] U on matrix cores (K unrolled by 4 so that
+    //    eight loads are in flight); deflated columns copied.
     const int ntile = S.tile0[nm];
     for (int t = w; t < ntile; t += TNT / 64) {
       int b = 0;
@@ -470,11 +501,18 @@ __global__ __launch_bounds__(TNT) void k_dc(const double* __restrict__ W, int n,
       const int li = lane & 15, lk = lane >> 4;
       f64x4 acc = {0.0, 0.0, 0.0, 0.0};
       const bool rok = (r0 + li) < k, cok = (c0 + li) < nk;
-      for (int i0 = 0; i0 < nk; i0 += 4) {
-        const int ii = i0 + lk;
-        const double av = (rok && ii < nk) ? Qc[static_cast<int64_t>(a + ii) * ldz + a + r0 + li] : 0.0;
-        const double bv = (cok && ii < nk) ? U[static_cast<int64_t>(a + ii) * ldz + a + c0 + li] : 0.0;
-        acc = mfma_f64(av, bv, acc);
+      const double* Ab = Qc + static_cast<int64_t>(a) * ldz + a + r0 + li;
+      const double* Bb = U + static_cast<int64_t>(a) * ldz + a + c0 + li;
+      for (int i0 = 0; i0 < nk; i0 += 16) {
+        double av[4], bv[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int ii = i0 + 4 * u + lk;
+          av[u] = (rok && ii < nk) ? Ab[static_cast<int64_t>(ii) * ldz] : 0.0;
+          bv[u] = (cok && ii < nk) ? Bb[static_cast<int64_t>(ii) * ldz] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) acc = mfma_f64(av[u], bv[u], acc);
       }
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
@@ -482,15 +520,17 @@ __global__ __launch_bounds__(TNT) void k_dc(const double* __restrict__ W, int n,
         if (row < k && cok) Z[static_cast<int64_t>(a + c0 + li) * ldz + a + row] = acc[v];
       }
     }
-    for (int b = 0; b < nm; ++b) {
-      int a, k1, k2;
-      merge_geom(b, s, n, a, k1, k2);
-      if (k2 == 0) continue;
-      const int k = k1 + k2, nk = S.kk[b];
-      const int nd = k - nk;
-      for (int e = tid; e < nd * k; e += TNT) {
-        const int c = nk + e / k, r = e % k;
-        Z[static_cast<int64_t>(a + c) * ldz + a + r] = Qc[static_cast<int64_t>(a + c) * ldz + a + r];
+    {
+      const int K2 = 2 * s;
+      const int64_t tot = static_cast<int64_t>(n) * K2;
+      for (int64_t e = tid; e < tot; e += TNT) {
+        const int g = static_cast<int>(e / K2), r = static_cast<int>(e % K2);
+        const int b = g / K2;
+        int a, k1, k2;
+        merge_geom(b, s, n, a, k1, k2);
+        const int k = k1 + k2, c = g - a;
+        if (k2 == 0 || r >= k || c < S.kk[b]) continue;
+        Z[static_cast<int64_t>(g) * ldz + a + r] = Qc[static_cast<int64_t>(g) * ldz + a + r];
       }
     }
     __syncthreads();
