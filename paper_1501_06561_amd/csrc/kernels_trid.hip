@@ -194,6 +194,8 @@ struct DcSmem {
   int kk[kDcMax / 2];    // non-deflated count per merge
   int nrot[kDcMax / 2];  // deflation rotations per merge
   int tile0[kDcMax / 2 + 1];
+  int rot_any[kDcMax / 2];  // the merge needs the sequential deflation scan
+  char zdef[kDcMax];        // 1 z-deflated, 2 rotation candidate, 0 otherwise
 };
 
 // Merge b of the level with half-size s: block [a, a+k1+k2).
@@ -317,17 +319,72 @@ __global__ __launch_bounds__(TNT) void k_dc(const double* __restrict__ W, int n,
       S.Zs[a + rank] = zj * 0.70710678118654752440;
     }
     __syncthreads();
-    // 2. Deflation scan, one thread per merge: negligible rho |z_j|, or a
-    //    Givens rotation of the pending entry into j when their d's are close.
-    for (int b = tid; b < nm; b += TNT) {
+    // 2. Deflation.  a) z-deflation flags (negligible rho |z_j|) and, for the
+    //    other entries, whether the previous such entry is close enough for a
+    //    Givens rotation (tested on the unrotated values).
+    for (int g = tid; g < n; g += TNT) {
+      const int b = g / (2 * s);
       int a, k1, k2;
       merge_geom(b, s, n, a, k1, k2);
       if (k2 == 0) continue;
+      const int k = k1 + k2, j = g - a;
+      const double rho = 2.0 * fabs(eG[a + k1 - 1]);
+      const double tol = 8.0 * eps * fmax(fmax(fabs(S.Ds[a]), fabs(S.Ds[a + k - 1])), rho);
+      const bool zd = rho * fabs(S.Zs[g]) <= tol;
+      S.zdef[g] = zd ? 1 : 0;
+      if (j == 0) S.rot_any[b] = 0;
+      if (zd) continue;
+      int p = j - 1;
+      while (p >= 0 && rho * fabs(S.Zs[a + p]) <= tol) --p;
+      if (p < 0) continue;
+      const double zl = S.Zs[a + p], zj = S.Zs[g];
+      const double th = hypot(zl, zj);
+      const double c = zj / th, sn = zl / th;
+      if (fabs((S.Ds[g] - S.Ds[a + p]) * c * sn) <= tol) S.zdef[g] = 2;
+    }
+    __syncthreads();
+    for (int g = tid; g < n; g += TNT) {
+      const int b = g / (2 * s);
+      if (S.zdef[g] == 2) S.rot_any[b] = 1;
+    }
+    __syncthreads();
+    //    b) Merges without a rotation: compact in parallel (non-deflated
+    //    first, in sorted order, then the deflated ones).  Merges with one:
+    //    the sequential scan below, where each rotation changes the pending
+    //    entry's d and z.
+    for (int g = tid; g < n; g += TNT) {
+      const int b = g / (2 * s);
+      int a, k1, k2;
+      merge_geom(b, s, n, a, k1, k2);
+      if (k2 == 0 || S.rot_any[b]) continue;
+      const int k = k1 + k2, j = g - a;
+      int before = 0, total = 0;
+      for (int i = 0; i < k; ++i) {
+        const int nd_i = (S.zdef[a + i] == 0) ? 1 : 0;
+        total += nd_i;
+        before += (i < j) ? nd_i : 0;
+      }
+      if (S.zdef[g] == 0) {
+        S.dest[g] = static_cast<short>(before);
+        S.dh[a + before] = S.Ds[g];
+        S.zh[a + before] = S.Zs[g];
+      } else {
+        const int di = j - before;
+        S.dest[g] = static_cast<short>(total + di);
+        S.ddf[a + di] = S.Ds[g];
+      }
+      if (j == 0) {
+        S.kk[b] = total;
+        S.nrot[b] = 0;
+      }
+    }
+    for (int b = tid; b < nm; b += TNT) {
+      int a, k1, k2;
+      merge_geom(b, s, n, a, k1, k2);
+      if (k2 == 0 || !S.rot_any[b]) continue;
       const int k = k1 + k2;
       const double rho = 2.0 * fabs(eG[a + k1 - 1]);
-      double dmax = 0.0;
-      for (int j = 0; j < k; ++j) dmax = fmax(dmax, fabs(S.Ds[a + j]));
-      const double tol = 8.0 * eps * fmax(dmax, rho);
+      const double tol = 8.0 * eps * fmax(fmax(fabs(S.Ds[a]), fabs(S.Ds[a + k - 1])), rho);
       int nk = 0, nd = 0, nr = 0, last = -1;
       for (int j = 0; j < k; ++j) {
         const int pj = a + j;
@@ -386,7 +443,7 @@ __global__ __launch_bounds__(TNT) void k_dc(const double* __restrict__ W, int n,
         int a, k1, k2;
         merge_geom(b, s, n, a, k1, k2);
         S.tile0[b] = acc;
-        if (k2 > 0) acc += ((k1 + k2 + 15) / 16) * ((S.kk[b] + 15) / 16);
+        if (k2 > 0) acc += ((k1 + k2 + 31) / 32) * ((S.kk[b] + 15) / 16);
       }
       S.tile0[nm] = acc;
     }
@@ -486,8 +543,10 @@ __global__ __launch_bounds__(TNT) void k_dc(const double* __restrict__ W, int n,
       if (q4 == 0) S.Ds[g] = dj + tj;                  // the root
     }
     __syncthreads();
-    // 7. Z block = Qc[:, 0:nk] U on matrix cores (K unrolled by 4 so that
-    //    eight loads are in flight); deflated columns copied.
+    // 7. Z block = Qc[:, 0:nk] U on matrix cores.  A wave computes two
+    //    vertically adjacent 16 x 16 tiles (sharing the U fragment); the
+    //    next 16-deep slice of both operands is loaded before the current
+    //    one is multiplied.
     const int ntile = S.tile0[nm];
     for (int t = w; t < ntile; t += TNT / 64) {
       int b = 0;
@@ -497,27 +556,51 @@ __global__ __launch_bounds__(TNT) void k_dc(const double* __restrict__ W, int n,
       const int k = k1 + k2, nk = S.kk[b];
       const int nct = (nk + 15) / 16;
       const int tl = t - S.tile0[b];
-      const int r0 = (tl / nct) * 16, c0 = (tl % nct) * 16;
+      const int r0 = (tl / nct) * 32, c0 = (tl % nct) * 16;
       const int li = lane & 15, lk = lane >> 4;
-      f64x4 acc = {0.0, 0.0, 0.0, 0.0};
-      const bool rok = (r0 + li) < k, cok = (c0 + li) < nk;
+      f64x4 acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = {0.0, 0.0, 0.0, 0.0};
+      const bool rok0 = (r0 + li) < k, rok1 = (r0 + 16 + li) < k, cok = (c0 + li) < nk;
       const double* Ab = Qc + static_cast<int64_t>(a) * ldz + a + r0 + li;
       const double* Bb = U + static_cast<int64_t>(a) * ldz + a + c0 + li;
+      double x0[4], x1[4], y[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int ii = 4 * u + lk;
+        const int64_t o = static_cast<int64_t>(ii) * ldz;
+        x0[u] = (rok0 && ii < nk) ? Ab[o] : 0.0;
+        x1[u] = (rok1 && ii < nk) ? Ab[o + 16] : 0.0;
+        y[u] = (cok && ii < nk) ? Bb[o] : 0.0;
+      }
       for (int i0 = 0; i0 < nk; i0 += 16) {
-        double av[4], bv[4];
+        double nx0[4], nx1[4], ny[4];
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
-          const int ii = i0 + 4 * u + lk;
-          av[u] = (rok && ii < nk) ? Ab[static_cast<int64_t>(ii) * ldz] : 0.0;
-          bv[u] = (cok && ii < nk) ? Bb[static_cast<int64_t>(ii) * ldz] : 0.0;
+          const int ii = i0 + 16 + 4 * u + lk;
+          const int64_t o = static_cast<int64_t>(ii) * ldz;
+          nx0[u] = (rok0 && ii < nk) ? Ab[o] : 0.0;
+          nx1[u] = (rok1 && ii < nk) ? Ab[o + 16] : 0.0;
+          ny[u] = (cok && ii < nk) ? Bb[o] : 0.0;
         }
 #pragma unroll
-        for (int u = 0; u < 4; ++u) acc = mfma_f64(av[u], bv[u], acc);
-      }
+        for (int u = 0; u < 4; ++u) {
+          acc0 = mfma_f64(x0[u], y[u], acc0);
+          acc1 = mfma_f64(x1[u], y[u], acc1);
+        }
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int row = r0 + lk + 4 * v;
-        if (row < k && cok) Z[static_cast<int64_t>(a + c0 + li) * ldz + a + row] = acc[v];
+        for (int u = 0; u < 4; ++u) {
+          x0[u] = nx0[u];
+          x1[u] = nx1[u];
+          y[u] = ny[u];
+        }
+      }
+      if (cok) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int row = r0 + lk + 4 * v;
+          double* zc = Z + static_cast<int64_t>(a + c0 + li) * ldz + a;
+          if (row < k) zc[row] = acc0[v];
+          if (row + 16 < k) zc[row + 16] = acc1[v];
+        }
       }
     }
     {
