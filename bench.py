@@ -73,6 +73,51 @@ def measured_traffic(stage, l, variant):
     return None
 
 
+def batched_leg(S, n_max, seed=(4, 0)):
+    """The many-sketch workload shape (d ~ U{64..2048}, l ~ U{16..100}, n ~
+    U{1000..n_max}, Random Noisy rows with k = l/2, zeta = 10, fp32 on the
+    device): all sketches through the lock-step batch, then the same sketches
+    one after another through the single-sketch path.  Rows/s of each."""
+    import torch
+    from paper_1501_06561_amd import fdsketch, synth
+    d, l, n = synth.batch_shapes(S, seed=seed, l_range=(16, 100), n_range=(1000, n_max))
+    mats = [synth.random_noisy_device(int(n[i]), int(d[i]), max(1, int(l[i]) // 2), 10.0,
+                                      (seed[0], seed[1], i)) for i in range(S)]
+    cfgs = [dict(d=int(d[i]), l=int(l[i])) for i in range(S)]
+    rows = int(n.sum())
+    # Warm both paths (first launches load the kernels).
+    w = fdsketch.FDSketchBatch(cfgs[:2])
+    w.append([m[:300] for m in mats[:2]])
+    w.finalize()
+    w.close()
+    torch.cuda.synchronize()
+    b = fdsketch.FDSketchBatch(cfgs)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b.append(mats)
+    b.finalize()
+    torch.cuda.synchronize()
+    t_batch = time.perf_counter() - t0
+    n_rr = sum(b.stats(i)["n_reduce"] for i in range(S))
+    b.close()
+    sks = [fdsketch.FDSketch(c["d"], c["l"]) for c in cfgs]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for sk, m in zip(sks, mats):
+        sk.append(m)
+        sk.finalize()
+    torch.cuda.synchronize()
+    t_seq = time.perf_counter() - t0
+    for sk in sks:
+        sk.close()
+    return {"workload": f"{S} sketches, d~U{{64..2048}}, l~U{{16..100}}, n~U{{1000..{n_max}}}, "
+                        "random noisy k=l/2 zeta=10, fp32 rows on device",
+            "rows": rows, "reduce_steps": n_rr,
+            "value": rows / t_batch, "unit": "rows/s", "ms": t_batch * 1e3,
+            "sequential_value": rows / t_seq, "sequential_ms": t_seq * 1e3,
+            "speedup_vs_sequential": t_seq / t_batch, "dtype": "f64"}
+
+
 def copy_calibration(nbytes, reps):
     """A plain device-to-device copy of `nbytes`, `reps` times (counter reference)."""
     import torch
@@ -122,6 +167,10 @@ def main():
                     help="eigensolver: tridiagonal divide and conquer (m <= 200) or Jacobi")
     ap.add_argument("--rows", type=int, default=100_000,
                     help="rows of the stream to sketch (profiling runs use a prefix)")
+    ap.add_argument("--batch-sketches", type=int, default=512,
+                    help="sketches in the many-sketch leg (0 skips it)")
+    ap.add_argument("--batch-nmax", type=int, default=5000,
+                    help="largest rows per sketch in the many-sketch leg")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run a plain device copy of BYTES (counter reference) and exit")
     args = ap.parse_args()
@@ -196,6 +245,9 @@ def main():
 
     # Covariance error of the GPU sketch on the device evaluator (untimed).
     ev = sk.error(At, k=10, method=0)
+    sk.close()
+    del At
+    batched = batched_leg(args.batch_sketches, args.batch_nmax) if args.batch_sketches > 0 else None
 
     cpu = None
     cov_oracle = None
@@ -239,6 +291,7 @@ def main():
         "roofline": roof,
         "cpu_baseline": cpu,
         "stages_ms_per_step": {s: prof[s][0] / args.steps for s in prof},
+        "batched": batched,
         "cov_err": ev["cov_err"],
         "cov_err_oracle": cov_oracle,
         "reduce_steps": st["n_reduce"],

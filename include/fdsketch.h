@@ -191,35 +191,38 @@ int fdsk_eigh(const double* G, int32_t m, int64_t ldg, double* lam, double* V, i
               int32_t method, void* hip_stream);
 
 /* ------------------------------------------------------------------------
- * Many independent sketches advanced by one persistent launch.
+ * Many independent sketches advanced together (Algorithm 1 for each).
  *
- * The batch owns S sketches (each with its own configuration; buffer rows
- * m <= 256, FP64 arithmetic).  Each append call gives every sketch its own
- * device rows; one kernel launch then runs every sketch's full schedule of
- * Algorithm 1 -- a workgroup claims a sketch from a device queue (longest
- * estimated work first), ingests its rows and performs each ReduceRank
- * (Gram, eigensolve, shrink, rebuild) by itself, then claims the next one.
- * Results are independent of how many workgroups run (grid_size 0 = one per
- * compute unit, 1 = a single workgroup processing the sketches in order).
+ * The batch owns S sketches, each with its own configuration (buffer rows
+ * m <= 256; any precision; the eigensolver is the tridiagonal route).  Because the schedule of Algorithm 1 does not
+ * depend on the data, an append call first lays out, on the host, every
+ * sketch's ingests and ReduceRanks for the call; round r then holds at most
+ * one ingest and one ReduceRank per sketch, and each stage of a round (ingest,
+ * Gram, tridiagonal reduction, divide and conquer, back-transformation,
+ * shrink, rebuild) is one launch over all sketches active in it.  Each
+ * sketch's arithmetic is exactly that of a single sketch with the same
+ * configuration, so results do not depend on how sketches are grouped.
+ * grid_size > 0 caps the sketches per launch (0: all active ones).
  * ------------------------------------------------------------------------ */
 typedef struct fdsk_batch fdsk_batch;
 
-/* Create S sketches from cfgs[0..S-1] (precision must be FDSK_P_FP64, flags 0,
- * buffer rows <= 256).  Errors: EINVAL, EUNSUPPORTED, ENOMEM, EDEVICE. */
+/* Create S sketches from cfgs[0..S-1] (flags 0, buffer rows <= 256).
+ * Errors: EINVAL, EUNSUPPORTED, ENOMEM, EDEVICE. */
 int sketch_batch_create(int32_t S, const fdsk_config* cfgs, void* hip_stream, fdsk_batch** out);
 
 /* Append rows[i] (n_rows[i] x d_i, leading dimension strides[i], device
- * pointers only, common dtype) to sketch i for every i, in one launch.
- * n_rows[i] may be 0.  grid_size as described above.  Returns when the
- * launch has completed (the rows may be overwritten afterwards).
- * Errors: EINVAL, ESTATE (after finalize), EUNSUPPORTED (host memory), EDEVICE. */
+ * pointers only, common dtype) to sketch i for every i.  n_rows[i] may be 0
+ * (rows[i] may then be NULL).  Returns when the work has completed (the rows
+ * may be overwritten afterwards).  Errors: EINVAL, ESTATE (after finalize),
+ * EUNSUPPORTED (host memory), ENOMEM, EDEVICE. */
 int sketch_batch_append(fdsk_batch* b, const void* const* rows, const int64_t* n_rows,
                         const int64_t* strides, fdsk_dtype dtype, fdsk_mem mem, int32_t grid_size);
 
 /* Finish every sketch (one more ReduceRank where more than l rows are
  * occupied) and write sketch i (l_i x d_i, leading dimension ldb[i], FDSK_F64 or
- * FDSK_F32) to the device pointer B_out[i]; rows_out[i] (host array) receives
- * the number of rows that may be nonzero.  Synchronises the stream. */
+ * FDSK_F32) to the device pointer B_out[i]; rows_out[i] (host array, may be
+ * NULL) receives the number of rows that may be nonzero.  Synchronises the
+ * stream.  Errors: EINVAL, ESTATE (twice), EUNSUPPORTED, EDEVICE, ENONFINITE. */
 int sketch_batch_finalize(fdsk_batch* b, void* const* B_out, const int64_t* ldb, fdsk_dtype out_dtype,
                           fdsk_mem mem, int32_t grid_size, int32_t* rows_out);
 

@@ -1,6 +1,6 @@
 // Host side of the many-sketch batch (see include/fdsketch.h and
-// kernels_batch.hip): workspace layout, descriptor upload, queue order and
-// the C ABI entry points.
+// fdsk_batch.hpp): per-sketch workspace, the round schedule of an append or
+// finalize call, and the C ABI entry points.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -8,7 +8,6 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
-#include <numeric>
 #include <string>
 #include <vector>
 
@@ -21,28 +20,21 @@ struct fdsk_batch {
   int S = 0;
   hipStream_t stream = nullptr;
   std::vector<fdsk_config> cfg;
-  std::vector<BatchDesc> desc;     // host copy; per-call fields are rewritten
-  void* arena = nullptr;
-  BatchDesc* d_desc = nullptr;
-  BatchState* d_state = nullptr;
-  int* d_order = nullptr;
-  int* d_counter = nullptr;
-  DevStats* d_stats = nullptr;
-  std::vector<int64_t> rows_in;    // rows appended so far per sketch
+  std::vector<GroupSketch> sk;     // host copy of the device descriptors
+  std::vector<int> occ, cur, new0; // schedule state per sketch
+  std::vector<int64_t> rows_in;
   std::vector<int32_t> rows_out;
+  void* arena = nullptr;
+  GroupSketch* d_sk = nullptr;
+  DevStats* d_stats = nullptr;
+  void* d_tasks = nullptr;         // task lists of the current call
+  size_t tasks_cap = 0;
   bool finalized = false;
-  int cus = 256;
   int err = 0;
   std::string msg;
 };
 
 namespace {
-
-// The persistent many-sketch launch is switched off: its first GPU run ended
-// in a device memory fault whose cause has not been shown (a CPU emulation of
-// the kernel under AddressSanitizer finds every access in bounds).  Creation
-// and stats work; append/finalize report FDSK_EUNSUPPORTED until then.
-constexpr bool kBatchLaunchEnabled = false;
 
 thread_local std::string g_batch_err;
 
@@ -63,6 +55,15 @@ int berr(fdsk_batch* b, int code, const char* fmt, ...) {
 
 int rup(int x, int a) { return (x + a - 1) / a * a; }
 
+size_t dtype_bytes(fdsk_dtype t) {
+  switch (t) {
+    case FDSK_F64: return 8;
+    case FDSK_F32: return 4;
+    case FDSK_BF16: return 2;
+  }
+  return 0;
+}
+
 RuleParams rule_for(const fdsk_config& c) {
   RuleParams rp{};
   rp.variant = static_cast<int>(c.variant);
@@ -80,31 +81,83 @@ RuleParams rule_for(const fdsk_config& c) {
   return rp;
 }
 
-// Launch with a queue order that starts with the most expensive sketches
-// (estimated ReduceRank count times the cost of one ReduceRank).
-int launch(fdsk_batch* b, const std::vector<int64_t>& n, int finalize, int grid_size) {
-  if (!kBatchLaunchEnabled)
-    return berr(b, FDSK_EUNSUPPORTED, "the persistent many-sketch launch is disabled in this build");
-  std::vector<double> cost(b->S);
-  for (int i = 0; i < b->S; ++i) {
-    const BatchDesc& D = b->desc[i];
-    double rr = static_cast<double>(n[i]) / std::max(1, D.m - D.rp.keep) + (finalize ? 1.0 : 0.0);
-    double per = 30.0 * D.m * D.m * static_cast<double>(D.m) + 3.0 * D.m * D.m * static_cast<double>(D.d);
-    cost[i] = rr * per;
+// The tasks of one call, grouped by round.
+struct Plan {
+  std::vector<std::vector<GroupIngest>> ing;
+  std::vector<std::vector<GroupRR>> rr;
+};
+
+// Upload a plan and launch it round by round, at most `cap` sketches per
+// launch.  The device task buffer is reused by the next call, so the stream
+// is synchronised before returning.
+int run_plan(fdsk_batch* b, const Plan& p, int dt, int cap) {
+  size_t ni = 0, nr = 0;
+  for (auto& v : p.ing) ni += v.size();
+  for (auto& v : p.rr) nr += v.size();
+  const size_t ing_bytes = (ni * sizeof(GroupIngest) + 255) / 256 * 256;
+  const size_t bytes = ing_bytes + nr * sizeof(GroupRR) + 256;
+  if (bytes > b->tasks_cap) {
+    if (b->d_tasks) {
+      hipError_t e = hipStreamSynchronize(b->stream);
+      if (e == hipSuccess) e = hipFree(b->d_tasks);
+      b->d_tasks = nullptr;
+      b->tasks_cap = 0;
+      if (e != hipSuccess) return berr(b, FDSK_EDEVICE, "batch tasks: %s", hipGetErrorString(e));
+    }
+    if (hipMalloc(&b->d_tasks, bytes) != hipSuccess)
+      return berr(b, FDSK_ENOMEM, "batch task lists of %zu bytes", bytes);
+    b->tasks_cap = bytes;
   }
-  std::vector<int> order(b->S);
-  std::iota(order.begin(), order.end(), 0);
-  std::stable_sort(order.begin(), order.end(), [&](int a, int c) { return cost[a] > cost[c]; });
-  hipError_t e = hipMemcpyAsync(b->d_desc, b->desc.data(), sizeof(BatchDesc) * b->S,
-                                hipMemcpyHostToDevice, b->stream);
-  if (e == hipSuccess)
-    e = hipMemcpyAsync(b->d_order, order.data(), sizeof(int) * b->S, hipMemcpyHostToDevice, b->stream);
-  int grid = grid_size > 0 ? grid_size : std::min(b->S, b->cus);
-  grid = std::max(1, std::min(grid, b->S));
-  if (e == hipSuccess)
-    e = launch_batch_run(b->d_desc, b->d_state, b->d_order, b->S, b->d_counter, finalize, grid, b->stream);
-  // The descriptor array is read by the kernel; keep the host copy stable
-  // until the launch has consumed it.
+  std::vector<GroupIngest> hi;
+  std::vector<GroupRR> hr;
+  hi.reserve(ni);
+  hr.reserve(nr);
+  for (auto& v : p.ing) hi.insert(hi.end(), v.begin(), v.end());
+  for (auto& v : p.rr) hr.insert(hr.end(), v.begin(), v.end());
+  GroupIngest* d_ing = static_cast<GroupIngest*>(b->d_tasks);
+  GroupRR* d_rr = reinterpret_cast<GroupRR*>(static_cast<char*>(b->d_tasks) + ing_bytes);
+  hipError_t e = hipSuccess;
+  if (ni) e = hipMemcpyAsync(d_ing, hi.data(), ni * sizeof(GroupIngest), hipMemcpyHostToDevice, b->stream);
+  if (e == hipSuccess && nr)
+    e = hipMemcpyAsync(d_rr, hr.data(), nr * sizeof(GroupRR), hipMemcpyHostToDevice, b->stream);
+  size_t oi = 0, orr = 0;
+  const size_t rounds = std::max(p.ing.size(), p.rr.size());
+  const std::vector<GroupIngest> empty_i;
+  const std::vector<GroupRR> empty_r;
+  for (size_t r = 0; r < rounds && e == hipSuccess; ++r) {
+    const auto& vi = r < p.ing.size() ? p.ing[r] : empty_i;
+    const auto& vr = r < p.rr.size() ? p.rr[r] : empty_r;
+    for (size_t c0 = 0; c0 < vi.size() && e == hipSuccess; c0 += cap) {
+      const int nt = static_cast<int>(std::min<size_t>(cap, vi.size() - c0));
+      int max_f = 0;
+      for (int t = 0; t < nt; ++t) max_f = std::max(max_f, vi[c0 + t].f);
+      e = launch_group_ingest(b->d_sk, d_ing + oi + c0, nt, max_f, dt, b->stream);
+    }
+    for (size_t c0 = 0; c0 < vr.size() && e == hipSuccess; c0 += cap) {
+      const int nt = static_cast<int>(std::min<size_t>(cap, vr.size() - c0));
+      int max_mp = 0, max_m = 0, max_ldc = 0, max_keep = 0;
+      bool p0 = false, p1 = false, p3 = false;   // precisions present in this launch
+      for (int t = 0; t < nt; ++t) {
+        const GroupSketch& s = b->sk[vr[c0 + t].sk];
+        max_mp = std::max(max_mp, s.mp);
+        max_m = std::max(max_m, s.m);
+        max_ldc = std::max(max_ldc, s.ldc);
+        max_keep = std::max(max_keep, s.rp.keep);
+        p0 |= s.npass == 0;
+        p1 |= s.npass == 1;
+        p3 |= s.npass == 3;
+      }
+      const GroupRR* tt = d_rr + orr + c0;
+      if (p1 || p3) e = launch_group_gram_lowp(b->d_sk, tt, nt, max_mp, p1, p3, b->stream);
+      if (e == hipSuccess) e = launch_group_gram(b->d_sk, tt, nt, max_mp, p0, b->stream);
+      if (e == hipSuccess) e = launch_group_eig(b->d_sk, tt, nt, max_m, b->stream);
+      if (e == hipSuccess) e = launch_group_shrink_rebuild(b->d_sk, tt, nt, max_ldc, max_keep, p0, b->stream);
+      if (e == hipSuccess && (p1 || p3))
+        e = launch_group_rebuild_lowp(b->d_sk, tt, nt, max_ldc, max_keep, p1, p3, b->stream);
+    }
+    oi += vi.size();
+    orr += vr.size();
+  }
   if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
   if (e != hipSuccess) return berr(b, FDSK_EDEVICE, "batch launch: %s", hipGetErrorString(e));
   return 0;
@@ -123,40 +176,40 @@ int sketch_batch_create(int32_t S, const fdsk_config* cfgs, void* hip_stream, fd
   *out = nullptr;
   for (int i = 0; i < S; ++i) {
     const fdsk_config& c = cfgs[i];
-    int m = c.buffer_rows == 0 ? 2 * c.l : c.buffer_rows;
+    const int m = c.buffer_rows == 0 ? 2 * c.l : c.buffer_rows;
     if (c.d < 1 || c.d > 65536 || c.l < 1 || m < c.l)
       return berr(nullptr, FDSK_EINVAL, "sketch %d: bad sizes", i);
-    if (m > kBatchMaxRows) return berr(nullptr, FDSK_EUNSUPPORTED, "sketch %d: m = %d > %d", i, m, kBatchMaxRows);
+    if (m > kTridGlobalMax)
+      return berr(nullptr, FDSK_EUNSUPPORTED, "sketch %d: buffer rows %d > %d", i, m, kTridGlobalMax);
     if (c.variant < FDSK_FD || c.variant > FDSK_FAST_ALPHA) return berr(nullptr, FDSK_EINVAL, "bad variant");
     if ((c.variant == FDSK_ALPHA || c.variant == FDSK_FAST_ALPHA) && !(c.alpha > 0.0 && c.alpha <= 1.0))
       return berr(nullptr, FDSK_EINVAL, "sketch %d: alpha must lie in (0, 1]", i);
-    if (c.precision != FDSK_P_FP64 || c.flags != 0)
-      return berr(nullptr, FDSK_EUNSUPPORTED, "sketch %d: batched sketches are FP64 without flags", i);
+    if (c.precision != FDSK_P_FP64 && c.precision != FDSK_P_BF16 && c.precision != FDSK_P_BF16X3)
+      return berr(nullptr, FDSK_EINVAL, "sketch %d: unknown precision", i);
+    if (c.flags != 0) return berr(nullptr, FDSK_EUNSUPPORTED, "sketch %d: batched sketches take no flags", i);
   }
   fdsk_batch* b = new fdsk_batch;
   b->S = S;
   b->stream = static_cast<hipStream_t>(hip_stream);
   b->cfg.assign(cfgs, cfgs + S);
-  b->desc.resize(S);
+  b->sk.resize(S);
+  b->occ.assign(S, 0);
+  b->cur.assign(S, 0);
+  b->new0.assign(S, 0);
   b->rows_in.assign(S, 0);
   b->rows_out.assign(S, 0);
-  int dev = 0;
-  if (hipGetDevice(&dev) == hipSuccess) {
-    int cus = 0;
-    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cus > 0)
-      b->cus = cus;
-  }
-  // One arena: per-sketch buffers, then descriptors, states, order, counter, stats.
+  // One arena: every sketch's buffers, then the descriptors and statistics.
   size_t off = 0;
   auto take = [&](size_t bytes) {
     size_t o = off;
     off += (bytes + 255) / 256 * 256;
     return o;
   };
-  std::vector<size_t> oC0(S), oC1(S), oG(S), oW(S), oV(S), oUt(S), oL(S), oR(S);
+  constexpr int NB = 11;   // C0 C1 Gp G W V Ut S1 S2 lam rownorm
+  std::vector<size_t> o(static_cast<size_t>(S) * NB);
   for (int i = 0; i < S; ++i) {
     const fdsk_config& c = cfgs[i];
-    BatchDesc& D = b->desc[i];
+    GroupSketch& D = b->sk[i];
     std::memset(&D, 0, sizeof D);
     D.d = static_cast<int>(c.d);
     D.l = c.l;
@@ -164,42 +217,36 @@ int sketch_batch_create(int32_t S, const fdsk_config* cfgs, void* hip_stream, fd
     D.mp = rup(D.m, 32);
     D.ldc = rup(D.d, 64);
     D.rp = rule_for(c);
+    D.npass = c.precision == FDSK_P_BF16 ? 1 : (c.precision == FDSK_P_BF16X3 ? 3 : 0);
     const size_t cb = static_cast<size_t>(D.mp) * D.ldc * 8, g = static_cast<size_t>(D.mp) * D.mp * 8;
-    oC0[i] = take(cb);
-    oC1[i] = take(cb);
-    oG[i] = take(g);
-    oW[i] = take(g);
-    oV[i] = take(g);
-    oUt[i] = take(g);
-    oL[i] = take(D.mp * 8);
-    oR[i] = take(D.mp * 8);
+    size_t* q = &o[static_cast<size_t>(i) * NB];
+    q[0] = take(cb);
+    q[1] = take(cb);
+    for (int k = 2; k < 9; ++k) q[k] = take(g);
+    q[9] = take(static_cast<size_t>(D.mp) * 8);
+    q[10] = take(static_cast<size_t>(D.mp) * 8);
   }
-  size_t oDesc = take(sizeof(BatchDesc) * S), oState = take(sizeof(BatchState) * S),
-         oOrder = take(sizeof(int) * S), oCnt = take(64), oStats = take(sizeof(DevStats) * S);
+  const size_t oDesc = take(sizeof(GroupSketch) * S), oStats = take(sizeof(DevStats) * S);
   hipError_t e = hipMalloc(&b->arena, off);
   if (e != hipSuccess) {
     delete b;
     return berr(nullptr, FDSK_ENOMEM, "batch workspace of %zu bytes: %s", off, hipGetErrorString(e));
   }
   char* a = static_cast<char*>(b->arena);
-  b->d_desc = reinterpret_cast<BatchDesc*>(a + oDesc);
-  b->d_state = reinterpret_cast<BatchState*>(a + oState);
-  b->d_order = reinterpret_cast<int*>(a + oOrder);
-  b->d_counter = reinterpret_cast<int*>(a + oCnt);
+  b->d_sk = reinterpret_cast<GroupSketch*>(a + oDesc);
   b->d_stats = reinterpret_cast<DevStats*>(a + oStats);
   for (int i = 0; i < S; ++i) {
-    BatchDesc& D = b->desc[i];
-    D.C0 = reinterpret_cast<double*>(a + oC0[i]);
-    D.C1 = reinterpret_cast<double*>(a + oC1[i]);
-    D.G = reinterpret_cast<double*>(a + oG[i]);
-    D.W = reinterpret_cast<double*>(a + oW[i]);
-    D.V = reinterpret_cast<double*>(a + oV[i]);
-    D.Ut = reinterpret_cast<double*>(a + oUt[i]);
-    D.lam = reinterpret_cast<double*>(a + oL[i]);
-    D.rownorm = reinterpret_cast<double*>(a + oR[i]);
+    GroupSketch& D = b->sk[i];
+    const size_t* q = &o[static_cast<size_t>(i) * NB];
+    double** f[9] = {&D.C0, &D.C1, &D.Gp, &D.G, &D.W, &D.V, &D.Ut, &D.S1, &D.S2};
+    for (int k = 0; k < 9; ++k) *f[k] = reinterpret_cast<double*>(a + q[k]);
+    D.lam = reinterpret_cast<double*>(a + q[9]);
+    D.rownorm = reinterpret_cast<double*>(a + q[10]);
     D.st = b->d_stats + i;
   }
   e = hipMemsetAsync(b->arena, 0, off, b->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(b->d_sk, b->sk.data(), sizeof(GroupSketch) * S, hipMemcpyHostToDevice, b->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
   if (e != hipSuccess) {
     (void)hipFree(b->arena);
@@ -217,24 +264,44 @@ int sketch_batch_append(fdsk_batch* b, const void* const* rows, const int64_t* n
   if (b->finalized) return berr(b, FDSK_ESTATE, "append after finalize");
   if (!rows || !n_rows || !strides) return berr(b, FDSK_EINVAL, "null argument");
   if (mem != FDSK_MEM_DEVICE) return berr(b, FDSK_EUNSUPPORTED, "batched rows must be on the device");
-  if (dtype != FDSK_F64 && dtype != FDSK_F32 && dtype != FDSK_BF16) return berr(b, FDSK_EINVAL, "bad dtype");
-  std::vector<int64_t> n(b->S);
+  const size_t es = dtype_bytes(dtype);
+  if (es == 0) return berr(b, FDSK_EINVAL, "bad dtype");
+  if (grid_size < 0) return berr(b, FDSK_EINVAL, "grid_size < 0");
   for (int i = 0; i < b->S; ++i) {
     if (n_rows[i] < 0) return berr(b, FDSK_EINVAL, "sketch %d: n_rows < 0", i);
-    if (n_rows[i] > 0 && (!rows[i] || strides[i] < b->desc[i].d))
+    if (n_rows[i] > 0 && (!rows[i] || strides[i] < b->sk[i].d))
       return berr(b, FDSK_EINVAL, "sketch %d: bad rows or stride", i);
-    BatchDesc& D = b->desc[i];
-    D.rows = rows[i];
-    D.stride = strides[i];
-    D.n = n_rows[i];
-    D.dt = static_cast<int>(dtype);
-    D.out = nullptr;
-    n[i] = n_rows[i];
   }
-  int rc = launch(b, n, 0, grid_size);
-  if (rc) return rc;
-  for (int i = 0; i < b->S; ++i) b->rows_in[i] += n[i];
-  return 0;
+  // Lay out every sketch's ingests and ReduceRanks of this call by round.
+  Plan p;
+  for (int i = 0; i < b->S; ++i) {
+    const GroupSketch& D = b->sk[i];
+    int64_t pos = 0;
+    size_t r = 0;
+    while (pos < n_rows[i]) {
+      const int f = static_cast<int>(std::min<int64_t>(D.m - b->occ[i], n_rows[i] - pos));
+      GroupIngest t;
+      t.src = static_cast<const char*>(rows[i]) + pos * strides[i] * static_cast<int64_t>(es);
+      t.stride = strides[i];
+      t.sk = i;
+      t.f = f;
+      t.row0 = b->occ[i];
+      t.cur = b->cur[i];
+      if (p.ing.size() <= r) p.ing.resize(r + 1);
+      p.ing[r].push_back(t);
+      b->occ[i] += f;
+      pos += f;
+      if (b->occ[i] < D.m) break;
+      if (p.rr.size() <= r) p.rr.resize(r + 1);
+      p.rr[r].push_back(GroupRR{i, b->cur[i], b->new0[i], D.m});
+      b->cur[i] ^= 1;
+      b->occ[i] = D.rp.keep;
+      b->new0[i] = D.rp.keep;
+      ++r;
+    }
+    b->rows_in[i] += n_rows[i];
+  }
+  return run_plan(b, p, static_cast<int>(dtype), grid_size > 0 ? grid_size : b->S);
 }
 
 int sketch_batch_finalize(fdsk_batch* b, void* const* B_out, const int64_t* ldb, fdsk_dtype out_dtype,
@@ -245,29 +312,66 @@ int sketch_batch_finalize(fdsk_batch* b, void* const* B_out, const int64_t* ldb,
   if (!B_out || !ldb) return berr(b, FDSK_EINVAL, "null argument");
   if (mem != FDSK_MEM_DEVICE) return berr(b, FDSK_EUNSUPPORTED, "batched outputs must be on the device");
   if (out_dtype != FDSK_F64 && out_dtype != FDSK_F32) return berr(b, FDSK_EINVAL, "output dtype");
-  std::vector<int64_t> n(b->S, 0);
+  if (grid_size < 0) return berr(b, FDSK_EINVAL, "grid_size < 0");
+  for (int i = 0; i < b->S; ++i)
+    if (!B_out[i] || ldb[i] < b->sk[i].d) return berr(b, FDSK_EINVAL, "sketch %d: bad output", i);
+  // Sketches holding more than l rows: zero the free rows and reduce once
+  // more; the others: account for the rows appended since their last
+  // ReduceRank.
+  std::vector<GroupSpan> spans;
+  int nzero = 0;
+  Plan p;
+  p.rr.resize(1);
   for (int i = 0; i < b->S; ++i) {
-    if (!B_out[i] || ldb[i] < b->desc[i].d) return berr(b, FDSK_EINVAL, "sketch %d: bad output", i);
-    BatchDesc& D = b->desc[i];
-    D.rows = nullptr;
-    D.n = 0;
-    D.out = B_out[i];
-    D.ldb = ldb[i];
-    D.out_dt = static_cast<int>(out_dtype);
+    const GroupSketch& D = b->sk[i];
+    if (b->occ[i] > D.l && b->occ[i] < D.m) {
+      spans.push_back(GroupSpan{i, b->cur[i], b->occ[i], D.m});
+      ++nzero;
+    }
   }
-  int rc = launch(b, n, 1, grid_size);
+  for (int i = 0; i < b->S; ++i) {
+    const GroupSketch& D = b->sk[i];
+    if (b->occ[i] > D.l) {
+      p.rr[0].push_back(GroupRR{i, b->cur[i], b->new0[i], b->occ[i]});
+      b->cur[i] ^= 1;
+      b->occ[i] = D.rp.keep;
+      b->new0[i] = D.rp.keep;
+    } else if (b->occ[i] > b->new0[i]) {
+      spans.push_back(GroupSpan{i, b->cur[i], b->new0[i], b->occ[i]});
+      b->new0[i] = b->occ[i];
+    }
+  }
+  void* d_span = nullptr;
+  hipError_t e = hipSuccess;
+  if (!spans.empty()) {
+    e = hipMalloc(&d_span, spans.size() * sizeof(GroupSpan));
+    if (e != hipSuccess) return berr(b, FDSK_ENOMEM, "batch finalize spans");
+    e = hipMemcpyAsync(d_span, spans.data(), spans.size() * sizeof(GroupSpan), hipMemcpyHostToDevice,
+                       b->stream);
+    GroupSpan* ds = static_cast<GroupSpan*>(d_span);
+    if (e == hipSuccess) e = launch_group_zero(b->d_sk, ds, nzero, b->stream);
+    if (e == hipSuccess)
+      e = launch_group_pending(b->d_sk, ds + nzero, static_cast<int>(spans.size()) - nzero, b->stream);
+  }
+  int rc = 0;
+  if (e == hipSuccess) rc = run_plan(b, p, FDSK_F64, grid_size > 0 ? grid_size : b->S);
+  if (d_span) (void)hipFree(d_span);
+  if (e != hipSuccess) return berr(b, FDSK_EDEVICE, "batch finalize: %s", hipGetErrorString(e));
   if (rc) return rc;
-  b->finalized = true;
-  std::vector<BatchState> st(b->S);
+  for (int i = 0; i < b->S && e == hipSuccess; ++i) {
+    const GroupSketch& D = b->sk[i];
+    b->rows_out[i] = std::min(b->occ[i], D.l);
+    e = launch_copy_out(b->cur[i] ? D.C1 : D.C0, D.ldc, b->rows_out[i], D.l, D.d, B_out[i], ldb[i],
+                        static_cast<int>(out_dtype), b->stream);
+  }
   std::vector<DevStats> ds(b->S);
-  hipError_t e = hipMemcpyAsync(st.data(), b->d_state, sizeof(BatchState) * b->S, hipMemcpyDeviceToHost, b->stream);
   if (e == hipSuccess)
     e = hipMemcpyAsync(ds.data(), b->d_stats, sizeof(DevStats) * b->S, hipMemcpyDeviceToHost, b->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
   if (e != hipSuccess) return berr(b, FDSK_EDEVICE, "batch finalize: %s", hipGetErrorString(e));
+  b->finalized = true;
   int bad = -1;
   for (int i = 0; i < b->S; ++i) {
-    b->rows_out[i] = std::min(st[i].occ, b->desc[i].l);
     if (rows_out) rows_out[i] = b->rows_out[i];
     if (ds[i].nonfinite && bad < 0) bad = i;
   }
@@ -299,6 +403,7 @@ int sketch_batch_stats(const fdsk_batch* cb, int32_t index, fdsk_report* out) {
 void sketch_batch_destroy(fdsk_batch* b) {
   if (!b) return;
   (void)hipStreamSynchronize(b->stream);
+  if (b->d_tasks) (void)hipFree(b->d_tasks);
   if (b->arena) (void)hipFree(b->arena);
   delete b;
 }

@@ -1,4 +1,13 @@
-// Descriptors of the many-sketch persistent kernel (kernels_batch.hip).
+// Many independent sketches advanced together in lock-step rounds.
+//
+// The schedule of Algorithm 1 does not depend on the data (after a
+// ReduceRank the surviving rows count as occupied, and a ReduceRank runs
+// whenever all m rows are occupied), so the host knows in advance, for every
+// sketch, which rows go into which buffer rows and when each ReduceRank runs.
+// Round r holds at most one ingest and one ReduceRank per sketch; each stage
+// of a round is one launch over all sketches active in it (the grid's last
+// dimension indexes the task).  A sketch's ReduceRank kernels are the same
+// device code as the single-sketch path.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -7,40 +16,55 @@
 
 namespace fdsk {
 
-constexpr int kBatchMaxRows = 256;    // buffer rows m supported by the batched kernel
-
-// Per sketch, per call: input rows and the sketch's device workspace.
-struct BatchDesc {
-  const void* rows;      // n x d input rows of this call (device)
-  int64_t stride;        // leading dimension of rows (elements)
-  int64_t n;             // rows in this call
-  int dt;                // input dtype
-  int d, ldc, l, m, mp;
-  RuleParams rp;
-  double* C0;            // mp x ldc buffers (double-buffered rebuild)
+// Device workspace of one sketch (fixed for the life of the batch).
+struct GroupSketch {
+  double* C0;        // mp x ldc buffers (the rebuild writes the other one)
   double* C1;
-  double* G;             // mp x mp
-  double* W;             // mp x mp (one-sided Jacobi)
-  double* V;             // mp x mp eigenvectors (column-major)
-  double* Ut;            // mp x mp rebuild operator
-  double* lam;           // mp
-  double* rownorm;       // mp
+  double* Gp;        // mp x mp Gram, lower tiles
+  double* G;         // mp x mp Gram, symmetric
+  double* W;         // mp x mp reflectors / tridiagonal
+  double* V;         // mp x mp eigenvectors (column-major)
+  double* Ut;        // mp x mp rebuild operator
+  double* S1;        // mp x mp scratch (divide and conquer)
+  double* S2;
+  double* lam;       // mp
+  double* rownorm;   // mp
   DevStats* st;
-  void* out;             // finalize: l x d output (device), leading dim ldb
-  int64_t ldb;
-  int out_dt;
-  int pad;
+  int d, ldc, l, m, mp;
+  int npass;         // Gram/rebuild products: 0 FP64, 1 BF16, 3 split-BF16 (compensated)
+  RuleParams rp;
 };
 
-// Per sketch state kept on the device between calls.
-struct BatchState {
-  int occ;    // occupied rows
-  int cur;    // which buffer holds the sketch
-  int new0;   // first row appended since the last ReduceRank
-  int pad;
+struct GroupIngest {      // f rows of src (leading dimension stride) into rows row0.. of C[cur]
+  const void* src;
+  int64_t stride;
+  int sk, f, row0, cur;
 };
 
-hipError_t launch_batch_run(const BatchDesc* descs, BatchState* states, const int* order, int nsk,
-                            int* counter, int finalize, int grid, hipStream_t s);
+struct GroupRR {          // a ReduceRank of sketch sk on C[cur]; rows [new0, new1) are new
+  int sk, cur, new0, new1;
+};
+
+struct GroupSpan {        // rows [r0, r1) of C[cur] (zeroing, pending norms)
+  int sk, cur, r0, r1;
+};
+
+// Launch shapes come from the host, which knows every task of the round.
+hipError_t launch_group_ingest(const GroupSketch* sk, const GroupIngest* t, int nt, int max_f, int dt,
+                               hipStream_t s);
+// FP64 Gram for tasks with npass 0, then the symmetric mirror for every task.
+hipError_t launch_group_gram(const GroupSketch* sk, const GroupRR* t, int nt, int max_mp, bool fp64,
+                             hipStream_t s);
+hipError_t launch_group_gram_lowp(const GroupSketch* sk, const GroupRR* t, int nt, int max_mp, bool one,
+                                  bool three, hipStream_t s);
+hipError_t launch_group_rebuild_lowp(const GroupSketch* sk, const GroupRR* t, int nt, int max_ldc,
+                                     int max_keep, bool one, bool three, hipStream_t s);
+hipError_t launch_group_eig(const GroupSketch* sk, const GroupRR* t, int nt, int max_m, hipStream_t s);
+// Shrink for every task; the FP64 rebuild only for tasks with npass 0 (when
+// fp64 is set).
+hipError_t launch_group_shrink_rebuild(const GroupSketch* sk, const GroupRR* t, int nt, int max_ldc,
+                                       int max_keep, bool fp64, hipStream_t s);
+hipError_t launch_group_zero(const GroupSketch* sk, const GroupSpan* t, int nt, hipStream_t s);
+hipError_t launch_group_pending(const GroupSketch* sk, const GroupSpan* t, int nt, hipStream_t s);
 
 }  // namespace fdsk

@@ -72,11 +72,12 @@ struct EigWork {
 enum { EIG_AUTO = 0, EIG_JACOBI = 1 };
 constexpr int kMaxSweeps = 40;
 constexpr int kLdsEigMax = 100;   // single-workgroup solver limit (G and V in LDS)
-constexpr int kTridMax = 200;     // tridiagonal route: packed lower triangle in LDS
+constexpr int kTridMax = 200;     // tridiagonal route with the packed lower triangle in LDS
+constexpr int kTridGlobalMax = 256;  // ... and with it in the (L2-resident) workspace
 constexpr int kDcMax = 256;       // divide and conquer: O(n) state in LDS
 // Eigen-decomposition of the symmetric m x m G (leading dimension mp): lam
 // (m values, any order) and V (column j = eigenvector of lam[j], leading
-// dimension mp).  m <= kTridMax goes through the tridiagonal route unless
+// dimension mp).  m <= kTridGlobalMax goes through the tridiagonal route unless
 // wk.method is EIG_JACOBI; larger m through the Jacobi solvers.
 hipError_t launch_eig(const double* G, int m, int mp, double* lam, double* V, EigWork wk,
                       hipStream_t s);
@@ -89,7 +90,7 @@ hipError_t launch_tridiag(const double* G, int m, int mp, EigWork wk, hipStream_
 hipError_t launch_dc(int m, int mp, double* lam, double* V, EigWork wk, hipStream_t s);
 hipError_t launch_backtr(int m, int mp, double* V, EigWork wk, hipStream_t s);
 inline bool eig_uses_trid(int m, const EigWork& wk) {
-  return wk.method != EIG_JACOBI && m <= kTridMax && wk.S1 && wk.S2;
+  return wk.method != EIG_JACOBI && m <= kTridGlobalMax && wk.S1 && wk.S2;
 }
 
 }  // namespace fdsk

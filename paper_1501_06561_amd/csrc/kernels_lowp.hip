@@ -6,6 +6,7 @@
 // FP32 accumulation error).  Eigensolve, shrink and accumulators stay FP64.
 #include "fdsk_device.hpp"
 #include "fdsk_kernels.hpp"
+#include "fdsk_batch.hpp"
 
 namespace fdsk {
 
@@ -38,14 +39,13 @@ __device__ __forceinline__ f32x4 mfma_split(const bf16x8_t& ah, const bf16x8_t& 
 
 // G partials on lower-triangular 32x32 tiles with split-K (see k_gram_f64).
 template <int NPASS>
-__global__ __launch_bounds__(256) void k_gram_bf16(const double* __restrict__ C, int ldc, int mp,
-                                                   int kchunk, double* __restrict__ Gpart) {
-  const int tile = blockIdx.x;
+__device__ __forceinline__ void gram_bf16_body(const double* __restrict__ C, int ldc, int mp, int kchunk,
+                                               double* __restrict__ Gpart, int tile, int ks) {
   int ti = static_cast<int>((sqrtf(8.0f * tile + 1.0f) - 1.0f) * 0.5f);
   while ((ti + 1) * (ti + 2) / 2 <= tile) ++ti;
   while (ti * (ti + 1) / 2 > tile) --ti;
   const int tj = tile - ti * (ti + 1) / 2;
-  const int k0 = blockIdx.y * kchunk;
+  const int k0 = ks * kchunk;
   const int k1 = min(ldc, k0 + kchunk);
   __shared__ double As[32][33];
   __shared__ double Bs[32][33];
@@ -78,7 +78,7 @@ __global__ __launch_bounds__(256) void k_gram_bf16(const double* __restrict__ C,
     acc = mfma_split<NPASS>(ah, al, bh, bl, acc);
     __syncthreads();
   }
-  double* out = Gpart + static_cast<int64_t>(blockIdx.y) * mp * mp;
+  double* out = Gpart + static_cast<int64_t>(ks) * mp * mp;
 #pragma unroll
   for (int v = 0; v < 4; ++v) {
     int row = ti * 32 + wi * 16 + 4 * lq + v;
@@ -87,12 +87,18 @@ __global__ __launch_bounds__(256) void k_gram_bf16(const double* __restrict__ C,
   }
 }
 
+template <int NPASS>
+__global__ __launch_bounds__(256) void k_gram_bf16(const double* __restrict__ C, int ldc, int mp,
+                                                   int kchunk, double* __restrict__ Gpart) {
+  gram_bf16_body<NPASS>(C, ldc, mp, kchunk, Gpart, blockIdx.x, blockIdx.y);
+}
+
 // out[0:keep, :] = Ut[0:keep, 0:mp] * C (see k_rebuild_f64), BF16 products.
 template <int NPASS>
-__global__ __launch_bounds__(256) void k_rebuild_bf16(const double* __restrict__ Ut,
-                                                      const double* __restrict__ C, int ldc, int mp,
-                                                      int keep, double* __restrict__ out) {
-  const int r0 = blockIdx.y * 32, c0 = blockIdx.x * 64;
+__device__ __forceinline__ void rebuild_bf16_body(const double* __restrict__ Ut, const double* __restrict__ C,
+                                                  int ldc, int mp, int keep, double* __restrict__ out, int bx,
+                                                  int by) {
+  const int r0 = by * 32, c0 = bx * 64;
   __shared__ double As[32][33];
   __shared__ double Bs[32][65];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -142,6 +148,13 @@ __global__ __launch_bounds__(256) void k_rebuild_bf16(const double* __restrict__
   }
 }
 
+template <int NPASS>
+__global__ __launch_bounds__(256) void k_rebuild_bf16(const double* __restrict__ Ut,
+                                                      const double* __restrict__ C, int ldc, int mp,
+                                                      int keep, double* __restrict__ out) {
+  rebuild_bf16_body<NPASS>(Ut, C, ldc, mp, keep, out, blockIdx.x, blockIdx.y);
+}
+
 hipError_t launch_gram_lowp(const double* C, int ldc, int mp, double* Gpart, int ksplit_max, double* G,
                             int npass, hipStream_t s) {
   const int T = mp / 32;
@@ -170,6 +183,58 @@ hipError_t launch_rebuild_lowp(const double* Ut, const double* C, int ldc, int m
   else
     hipLaunchKernelGGL(k_rebuild_bf16<1>, grid, dim3(256), 0, s, Ut, C, ldc, mp, keep, out);
   return hipGetLastError();
+}
+
+// ------------------------------------------------------ grouped (batches)
+// Tasks of sketches with another precision return at once (the FP64 kernels
+// of kernels_stream.hip take those).
+template <int NPASS>
+__global__ __launch_bounds__(256) void kg_gram_bf16(const GroupSketch* __restrict__ SK,
+                                                    const GroupRR* __restrict__ T) {
+  const GroupRR t = T[blockIdx.z];
+  const GroupSketch& s = SK[t.sk];
+  if (s.npass != NPASS) return;
+  const int nt = s.mp / 32;
+  if (static_cast<int>(blockIdx.x) >= nt * (nt + 1) / 2) return;
+  gram_bf16_body<NPASS>(t.cur ? s.C1 : s.C0, s.ldc, s.mp, s.ldc, s.Gp, blockIdx.x, 0);
+}
+
+template <int NPASS>
+__global__ __launch_bounds__(256) void kg_rebuild_bf16(const GroupSketch* __restrict__ SK,
+                                                       const GroupRR* __restrict__ T) {
+  const GroupRR t = T[blockIdx.z];
+  const GroupSketch& s = SK[t.sk];
+  if (s.npass != NPASS) return;
+  if (static_cast<int>(blockIdx.x) >= s.ldc / 64 || static_cast<int>(blockIdx.y) * 32 >= s.rp.keep) return;
+  rebuild_bf16_body<NPASS>(s.Ut, t.cur ? s.C1 : s.C0, s.ldc, s.mp, s.rp.keep, t.cur ? s.C0 : s.C1,
+                           blockIdx.x, blockIdx.y);
+}
+
+hipError_t launch_group_gram_lowp(const GroupSketch* sk, const GroupRR* t, int nt, int max_mp, bool one,
+                                  bool three, hipStream_t s) {
+  if (nt <= 0) return hipSuccess;
+  const int T = max_mp / 32;
+  const dim3 g(T * (T + 1) / 2, 1, nt);
+  if (one) hipLaunchKernelGGL(kg_gram_bf16<1>, g, dim3(256), 0, s, sk, t);
+  hipError_t e = hipGetLastError();
+  if (e == hipSuccess && three) {
+    hipLaunchKernelGGL(kg_gram_bf16<3>, g, dim3(256), 0, s, sk, t);
+    e = hipGetLastError();
+  }
+  return e;
+}
+
+hipError_t launch_group_rebuild_lowp(const GroupSketch* sk, const GroupRR* t, int nt, int max_ldc,
+                                     int max_keep, bool one, bool three, hipStream_t s) {
+  if (nt <= 0 || max_keep <= 0) return hipSuccess;
+  const dim3 g(max_ldc / 64, (max_keep + 31) / 32, nt);
+  if (one) hipLaunchKernelGGL(kg_rebuild_bf16<1>, g, dim3(256), 0, s, sk, t);
+  hipError_t e = hipGetLastError();
+  if (e == hipSuccess && three) {
+    hipLaunchKernelGGL(kg_rebuild_bf16<3>, g, dim3(256), 0, s, sk, t);
+    e = hipGetLastError();
+  }
+  return e;
 }
 
 }  // namespace fdsk

@@ -6,16 +6,16 @@
 // are zero).  Rows [0, occ) are occupied.
 #include "fdsk_device.hpp"
 #include "fdsk_kernels.hpp"
+#include "fdsk_batch.hpp"
 
 namespace fdsk {
 
 // ----------------------------------------------------------------- ingest
 // One workgroup per row: convert to FP64, zero the pad columns, and store the
 // row's squared norm (FP64) for the ||A||_F^2 accumulator.
-__global__ __launch_bounds__(256) void k_ingest(const void* __restrict__ src, int dt,
-                                                int64_t stride, int d, double* __restrict__ C,
-                                                int ldc, int row0, double* __restrict__ rownorm) {
-  const int i = blockIdx.x;
+__device__ __forceinline__ void ingest_body(const void* __restrict__ src, int dt, int64_t stride, int d,
+                                            double* __restrict__ C, int ldc, int row0,
+                                            double* __restrict__ rownorm, int i) {
   const int64_t base = static_cast<int64_t>(i) * stride;
   double* dst = C + static_cast<int64_t>(row0 + i) * ldc;
   double acc = 0.0;
@@ -31,20 +31,25 @@ __global__ __launch_bounds__(256) void k_ingest(const void* __restrict__ src, in
   if (threadIdx.x == 0) rownorm[row0 + i] = (red[0] + red[1]) + (red[2] + red[3]);
 }
 
+__global__ __launch_bounds__(256) void k_ingest(const void* __restrict__ src, int dt,
+                                                int64_t stride, int d, double* __restrict__ C,
+                                                int ldc, int row0, double* __restrict__ rownorm) {
+  ingest_body(src, dt, stride, d, C, ldc, row0, rownorm, blockIdx.x);
+}
+
 // ------------------------------------------------------------------- Gram
 // G = C C^T on lower-triangular 32x32 tiles with split-K.  Four waves per
 // workgroup, each owning a 16x16 sub-tile fed by 16x16x4 FP64 MFMA.
 constexpr int GT = 32;   // output tile
 constexpr int GK = 32;   // K chunk staged in LDS
 
-__global__ __launch_bounds__(256) void k_gram_f64(const double* __restrict__ C, int ldc,
-                                                  int mp, int kchunk, double* __restrict__ Gpart) {
-  const int tile = blockIdx.x;
+__device__ __forceinline__ void gram_body(const double* __restrict__ C, int ldc, int mp, int kchunk,
+                                          double* __restrict__ Gpart, int tile, int ks) {
   int ti = static_cast<int>((sqrtf(8.0f * tile + 1.0f) - 1.0f) * 0.5f);
   while ((ti + 1) * (ti + 2) / 2 <= tile) ++ti;
   while (ti * (ti + 1) / 2 > tile) --ti;
   const int tj = tile - ti * (ti + 1) / 2;
-  const int k0 = blockIdx.y * kchunk;
+  const int k0 = ks * kchunk;
   const int k1 = min(ldc, k0 + kchunk);
 
   __shared__ double As[GT][GK + 1];
@@ -74,7 +79,7 @@ __global__ __launch_bounds__(256) void k_gram_f64(const double* __restrict__ C, 
     }
     __syncthreads();
   }
-  double* out = Gpart + static_cast<int64_t>(blockIdx.y) * mp * mp;
+  double* out = Gpart + static_cast<int64_t>(ks) * mp * mp;
 #pragma unroll
   for (int v = 0; v < 4; ++v) {
     int row = ti * GT + wi * 16 + lk + 4 * v;
@@ -83,12 +88,17 @@ __global__ __launch_bounds__(256) void k_gram_f64(const double* __restrict__ C, 
   }
 }
 
+__global__ __launch_bounds__(256) void k_gram_f64(const double* __restrict__ C, int ldc,
+                                                  int mp, int kchunk, double* __restrict__ Gpart) {
+  gram_body(C, ldc, mp, kchunk, Gpart, blockIdx.x, blockIdx.y);
+}
+
 // Sum the split-K partials in a fixed order and mirror the lower triangle.
-__global__ void k_gram_reduce(const double* __restrict__ Gpart, int ksplit, int mp,
-                              double* __restrict__ G) {
+__device__ __forceinline__ void gram_reduce_body(const double* __restrict__ Gpart, int ksplit, int mp,
+                                                 double* __restrict__ G, int bx, int nbx) {
   const int64_t n = static_cast<int64_t>(mp) * mp;
-  for (int64_t e = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; e < n;
-       e += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+  for (int64_t e = bx * static_cast<int64_t>(blockDim.x) + threadIdx.x; e < n;
+       e += static_cast<int64_t>(nbx) * blockDim.x) {
     int r = static_cast<int>(e / mp), c = static_cast<int>(e % mp);
     if ((r >> 5) < (c >> 5)) continue;   // upper tiles are written by the mirror
     double v = 0.0;
@@ -100,15 +110,19 @@ __global__ void k_gram_reduce(const double* __restrict__ Gpart, int ksplit, int 
   }
 }
 
+__global__ void k_gram_reduce(const double* __restrict__ Gpart, int ksplit, int mp,
+                              double* __restrict__ G) {
+  gram_reduce_body(Gpart, ksplit, mp, G, blockIdx.x, gridDim.x);
+}
+
 // ----------------------------------------------------------------- shrink
 // One workgroup.  Ranks the eigenvalues (descending, ties by index), applies
 // the variant's ReduceRank rule in FP64, updates the accumulators and writes
 // Ut = diag(rho) * U^T for the keep surviving rows, rho_j = sigma'_j/sigma_j.
-__global__ __launch_bounds__(1024) void k_shrink(const double* __restrict__ lam_raw,
-                                                 const double* __restrict__ V, int m, int mp,
-                                                 RuleParams rp, const double* __restrict__ rownorm,
-                                                 int new0, int new1, double* __restrict__ Ut,
-                                                 DevStats* __restrict__ st) {
+__device__ __forceinline__ void shrink_body(const double* __restrict__ lam_raw,
+                                            const double* __restrict__ V, int m, int mp, RuleParams rp,
+                                            const double* __restrict__ rownorm, int new0, int new1,
+                                            double* __restrict__ Ut, DevStats* __restrict__ st) {
   __shared__ double lam[1024];
   __shared__ int perm[1024];
   __shared__ double rho[1024];
@@ -179,13 +193,21 @@ __global__ __launch_bounds__(1024) void k_shrink(const double* __restrict__ lam_
   }
 }
 
+__global__ __launch_bounds__(1024) void k_shrink(const double* __restrict__ lam_raw,
+                                                 const double* __restrict__ V, int m, int mp,
+                                                 RuleParams rp, const double* __restrict__ rownorm,
+                                                 int new0, int new1, double* __restrict__ Ut,
+                                                 DevStats* __restrict__ st) {
+  shrink_body(lam_raw, V, m, mp, rp, rownorm, new0, new1, Ut, st);
+}
+
 // ---------------------------------------------------------------- rebuild
 // out[0:keep, :] = Ut[0:keep, 0:mp] * C[0:mp, :].  Tile 32 rows x 64 cols;
 // wave w owns rows (w>>1)*16.. and cols (w&1)*32.. (two 16x16 MFMA tiles).
-__global__ __launch_bounds__(256) void k_rebuild_f64(const double* __restrict__ Ut,
-                                                     const double* __restrict__ C, int ldc,
-                                                     int mp, int keep, double* __restrict__ out) {
-  const int r0 = blockIdx.y * 32, c0 = blockIdx.x * 64;
+__device__ __forceinline__ void rebuild_body(const double* __restrict__ Ut, const double* __restrict__ C,
+                                             int ldc, int mp, int keep, double* __restrict__ out, int bx,
+                                             int by) {
+  const int r0 = by * 32, c0 = bx * 64;
   __shared__ double As[32][33];
   __shared__ double Bs[32][65];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -225,6 +247,12 @@ __global__ __launch_bounds__(256) void k_rebuild_f64(const double* __restrict__ 
       out[o + 16] = acc1[v];
     }
   }
+}
+
+__global__ __launch_bounds__(256) void k_rebuild_f64(const double* __restrict__ Ut,
+                                                     const double* __restrict__ C, int ldc,
+                                                     int mp, int keep, double* __restrict__ out) {
+  rebuild_body(Ut, C, ldc, mp, keep, out, blockIdx.x, blockIdx.y);
 }
 
 // --------------------------------------------------------------- helpers
@@ -364,6 +392,111 @@ hipError_t launch_copy_out(const double* C, int ldc, int valid_rows, int l, int 
   if (blocks <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_copy_out, dim3(blocks), dim3(256), 0, s, C, ldc, valid_rows, l, d, out, ldb,
                      out_dt);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------ grouped (batches)
+// One task per entry of the grid's last dimension; blocks past the task's
+// own extent return at once (before any barrier).
+__global__ __launch_bounds__(256) void kg_ingest(const GroupSketch* __restrict__ SK,
+                                                 const GroupIngest* __restrict__ T, int dt) {
+  const GroupIngest t = T[blockIdx.y];
+  if (static_cast<int>(blockIdx.x) >= t.f) return;
+  const GroupSketch& s = SK[t.sk];
+  ingest_body(t.src, dt, t.stride, s.d, t.cur ? s.C1 : s.C0, s.ldc, t.row0, s.rownorm, blockIdx.x);
+}
+
+__global__ __launch_bounds__(256) void kg_gram(const GroupSketch* __restrict__ SK,
+                                               const GroupRR* __restrict__ T) {
+  const GroupRR t = T[blockIdx.z];
+  const GroupSketch& s = SK[t.sk];
+  if (s.npass != 0) return;
+  const int nt = s.mp / GT;
+  if (static_cast<int>(blockIdx.x) >= nt * (nt + 1) / 2) return;
+  gram_body(t.cur ? s.C1 : s.C0, s.ldc, s.mp, s.ldc, s.Gp, blockIdx.x, 0);
+}
+
+__global__ __launch_bounds__(256) void kg_mirror(const GroupSketch* __restrict__ SK,
+                                                 const GroupRR* __restrict__ T) {
+  const GroupSketch& s = SK[T[blockIdx.y].sk];
+  gram_reduce_body(s.Gp, 1, s.mp, s.G, blockIdx.x, gridDim.x);
+}
+
+__global__ __launch_bounds__(1024) void kg_shrink(const GroupSketch* __restrict__ SK,
+                                                  const GroupRR* __restrict__ T) {
+  const GroupRR t = T[blockIdx.x];
+  const GroupSketch& s = SK[t.sk];
+  shrink_body(s.lam, s.V, s.m, s.mp, s.rp, s.rownorm, t.new0, t.new1, s.Ut, s.st);
+}
+
+__global__ __launch_bounds__(256) void kg_rebuild(const GroupSketch* __restrict__ SK,
+                                                  const GroupRR* __restrict__ T) {
+  const GroupRR t = T[blockIdx.z];
+  const GroupSketch& s = SK[t.sk];
+  if (s.npass != 0) return;
+  if (static_cast<int>(blockIdx.x) >= s.ldc / 64 || static_cast<int>(blockIdx.y) * 32 >= s.rp.keep) return;
+  rebuild_body(s.Ut, t.cur ? s.C1 : s.C0, s.ldc, s.mp, s.rp.keep, t.cur ? s.C0 : s.C1, blockIdx.x,
+               blockIdx.y);
+}
+
+__global__ __launch_bounds__(256) void kg_zero(const GroupSketch* __restrict__ SK,
+                                               const GroupSpan* __restrict__ T) {
+  const GroupSpan t = T[blockIdx.y];
+  const GroupSketch& s = SK[t.sk];
+  double* p = (t.cur ? s.C1 : s.C0) + static_cast<int64_t>(t.r0) * s.ldc;
+  const int64_t n = static_cast<int64_t>(t.r1 - t.r0) * s.ldc;
+  for (int64_t e = blockIdx.x * 256LL + threadIdx.x; e < n; e += 256LL * gridDim.x) p[e] = 0.0;
+}
+
+__global__ void kg_pending(const GroupSketch* __restrict__ SK, const GroupSpan* __restrict__ T, int nt) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nt) return;
+  const GroupSpan t = T[i];
+  const GroupSketch& s = SK[t.sk];
+  double nrm = 0.0;
+  for (int r = t.r0; r < t.r1; ++r) nrm += s.rownorm[r];
+  s.st->fro2A += nrm;
+  if (!(nrm == nrm) || isinf(nrm)) s.st->nonfinite = 1;
+}
+
+hipError_t launch_group_ingest(const GroupSketch* sk, const GroupIngest* t, int nt, int max_f, int dt,
+                               hipStream_t s) {
+  if (nt <= 0 || max_f <= 0) return hipSuccess;
+  hipLaunchKernelGGL(kg_ingest, dim3(max_f, nt), dim3(256), 0, s, sk, t, dt);
+  return hipGetLastError();
+}
+
+hipError_t launch_group_gram(const GroupSketch* sk, const GroupRR* t, int nt, int max_mp, bool fp64,
+                             hipStream_t s) {
+  if (nt <= 0) return hipSuccess;
+  const int T = max_mp / GT;
+  if (fp64) hipLaunchKernelGGL(kg_gram, dim3(T * (T + 1) / 2, 1, nt), dim3(256), 0, s, sk, t);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const int nb = std::max(1, std::min(64, (max_mp * max_mp + 255) / 256));
+  hipLaunchKernelGGL(kg_mirror, dim3(nb, nt), dim3(256), 0, s, sk, t);
+  return hipGetLastError();
+}
+
+hipError_t launch_group_shrink_rebuild(const GroupSketch* sk, const GroupRR* t, int nt, int max_ldc,
+                                       int max_keep, bool fp64, hipStream_t s) {
+  if (nt <= 0) return hipSuccess;
+  hipLaunchKernelGGL(kg_shrink, dim3(nt), dim3(1024), 0, s, sk, t);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || max_keep <= 0 || !fp64) return e;
+  hipLaunchKernelGGL(kg_rebuild, dim3(max_ldc / 64, (max_keep + 31) / 32, nt), dim3(256), 0, s, sk, t);
+  return hipGetLastError();
+}
+
+hipError_t launch_group_zero(const GroupSketch* sk, const GroupSpan* t, int nt, hipStream_t s) {
+  if (nt <= 0) return hipSuccess;
+  hipLaunchKernelGGL(kg_zero, dim3(16, nt), dim3(256), 0, s, sk, t);
+  return hipGetLastError();
+}
+
+hipError_t launch_group_pending(const GroupSketch* sk, const GroupSpan* t, int nt, hipStream_t s) {
+  if (nt <= 0) return hipSuccess;
+  hipLaunchKernelGGL(kg_pending, dim3((nt + 255) / 256), dim3(256), 0, s, sk, t, nt);
   return hipGetLastError();
 }
 

@@ -1,10 +1,11 @@
 // FP64 symmetric eigensolver by tridiagonal reduction and divide and conquer.
 //
-// The m x m Gram matrix G of a ReduceRank (m <= kTridMax) goes through three
-// kernels, all in FP64 and all in stream order:
+// The m x m Gram matrix G of a ReduceRank (m <= kTridGlobalMax) goes through
+// three kernels, all in FP64 and all in stream order:
 //
 // * k_tridiag: Householder reduction Q^T G Q = T (T tridiagonal) in one
-//   workgroup, the lower triangle of G packed by columns in LDS.  Reflector
+//   workgroup, the lower triangle of G packed by columns in LDS (m <=
+//   kTridMax) or, above that, in the workspace W itself (L2-resident).  Reflector
 //   H_k = I - tau_k u_k u_k^T with u_k = (0,..,0, 1, v_k) zeroes column k below
 //   the subdiagonal; the trailing block is updated by the symmetric rank-2
 //   form A <- A - v w^T - w v^T, w = p - (tau/2)(p.v) v, p = tau A v.
@@ -27,6 +28,7 @@
 //   column in registers and the reflectors staged in LDS.
 #include "fdsk_device.hpp"
 #include "fdsk_kernels.hpp"
+#include "fdsk_batch.hpp"
 
 namespace fdsk {
 
@@ -49,10 +51,12 @@ __device__ __forceinline__ double wave_max(double v) {
 // Output in W (doubles): [0, P) packed columns (column k holds v_k below the
 // subdiagonal, P = n(n+1)/2), then tau[n], d[n], e[n], scale.  d and e are of
 // G * 2^-s (an exact power-of-two scaling by the largest |g|); scale = 2^s.
-__global__ __launch_bounds__(TNT) void k_tridiag(const double* __restrict__ G, int n, int ldg,
-                                                 double* __restrict__ W) {
-  __shared__ double A[TRI_PACK];
-  __shared__ double p[kTridMax];
+template <bool GA>
+__device__ __forceinline__ void tridiag_body(const double* __restrict__ G, int n, int ldg,
+                                             double* __restrict__ W) {
+  __shared__ double A_lds[GA ? 1 : TRI_PACK];
+  __shared__ double p[kTridGlobalMax];
+  double* const A = GA ? W : A_lds;
   __shared__ double red[16];
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int P = n * (n + 1) / 2;
@@ -169,7 +173,14 @@ __global__ __launch_bounds__(TNT) void k_tridiag(const double* __restrict__ G, i
     eG[n - 1] = 0.0;
     W[P + 3 * n] = ldexp(1.0, sexp);
   }
-  for (int e = tid; e < P; e += TNT) W[e] = A[e];
+  if (!GA)
+    for (int e = tid; e < P; e += TNT) W[e] = A[e];
+}
+
+template <bool GA>
+__global__ __launch_bounds__(TNT) void k_tridiag(const double* __restrict__ G, int n, int ldg,
+                                                 double* __restrict__ W) {
+  tridiag_body<GA>(G, n, ldg, W);
 }
 
 // ------------------------------------------------------ divide and conquer
@@ -273,9 +284,9 @@ __device__ int secular_root(const double* dd, const double* zz, int kk, int i, d
 // T = Z diag(lambda) Z^T for the tridiagonal (d, e) written by k_tridiag in W.
 // Z (n x n, column-major, leading dimension ldz) and lambda are the outputs;
 // Qc, U (ldz) are scratch.
-__global__ __launch_bounds__(TNT) void k_dc(const double* __restrict__ W, int n, double* __restrict__ Z,
-                                            int ldz, double* __restrict__ Qc, double* __restrict__ U,
-                                            double* __restrict__ lam, DevStats* __restrict__ st) {
+__device__ __forceinline__ void dc_body(const double* __restrict__ W, int n, double* __restrict__ Z,
+                                        int ldz, double* __restrict__ Qc, double* __restrict__ U,
+                                        double* __restrict__ lam, DevStats* __restrict__ st) {
   __shared__ DcSmem S;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int P = n * (n + 1) / 2;
@@ -544,9 +555,7 @@ __global__ __launch_bounds__(TNT) void k_dc(const double* __restrict__ W, int n,
     }
     __syncthreads();
     // 7. Z block = Qc[:, 0:nk] U on matrix cores.  A wave computes two
-    //    vertically adjacent 16 x 16 tiles (sharing the U fragment); the
-    //    next 16-deep slice of both operands is loaded before the current
-    //    one is multiplied.
+    //    vertically adjacent 16 x 16 tiles (sharing the U fragment).
     const int ntile = S.tile0[nm];
     for (int t = w; t < ntile; t += TNT / 64) {
       int b = 0;
@@ -562,35 +571,20 @@ __global__ __launch_bounds__(TNT) void k_dc(const double* __restrict__ W, int n,
       const bool rok0 = (r0 + li) < k, rok1 = (r0 + 16 + li) < k, cok = (c0 + li) < nk;
       const double* Ab = Qc + static_cast<int64_t>(a) * ldz + a + r0 + li;
       const double* Bb = U + static_cast<int64_t>(a) * ldz + a + c0 + li;
-      double x0[4], x1[4], y[4];
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const int ii = 4 * u + lk;
-        const int64_t o = static_cast<int64_t>(ii) * ldz;
-        x0[u] = (rok0 && ii < nk) ? Ab[o] : 0.0;
-        x1[u] = (rok1 && ii < nk) ? Ab[o + 16] : 0.0;
-        y[u] = (cok && ii < nk) ? Bb[o] : 0.0;
-      }
       for (int i0 = 0; i0 < nk; i0 += 16) {
-        double nx0[4], nx1[4], ny[4];
+        double x0[4], x1[4], y[4];
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
-          const int ii = i0 + 16 + 4 * u + lk;
+          const int ii = i0 + 4 * u + lk;
           const int64_t o = static_cast<int64_t>(ii) * ldz;
-          nx0[u] = (rok0 && ii < nk) ? Ab[o] : 0.0;
-          nx1[u] = (rok1 && ii < nk) ? Ab[o + 16] : 0.0;
-          ny[u] = (cok && ii < nk) ? Bb[o] : 0.0;
+          x0[u] = (rok0 && ii < nk) ? Ab[o] : 0.0;
+          x1[u] = (rok1 && ii < nk) ? Ab[o + 16] : 0.0;
+          y[u] = (cok && ii < nk) ? Bb[o] : 0.0;
         }
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
           acc0 = mfma_f64(x0[u], y[u], acc0);
           acc1 = mfma_f64(x1[u], y[u], acc1);
-        }
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          x0[u] = nx0[u];
-          x1[u] = nx1[u];
-          y[u] = ny[u];
         }
       }
       if (cok) {
@@ -632,19 +626,28 @@ __global__ __launch_bounds__(TNT) void k_dc(const double* __restrict__ W, int n,
   if (tid == 0 && st) atomicAdd(&st->eig_sweeps, 1ull);
 }
 
+__global__ __launch_bounds__(TNT) void k_dc(const double* __restrict__ W, int n, double* __restrict__ Z,
+                                            int ldz, double* __restrict__ Qc, double* __restrict__ U,
+                                            double* __restrict__ lam, DevStats* __restrict__ st) {
+  dc_body(W, n, Z, ldz, Qc, U, lam, st);
+}
+
 // ---------------------------------------------------------- back-transform
 // Z <- H_0 H_1 ... H_{n-3} Z for every column (in place): one wave per
 // column, NPL elements per lane, the packed reflectors staged in LDS.
-template <int NPL>
-__global__ __launch_bounds__(TNT) void k_backtr(const double* __restrict__ W, int n,
-                                                double* __restrict__ Z, int ldz) {
-  __shared__ double R[TRI_PACK];
+template <int NPL, bool GA>
+__device__ __forceinline__ void backtr_body(const double* __restrict__ W, int n, double* __restrict__ Z,
+                                            int ldz, int cb) {
+  __shared__ double R_lds[GA ? 1 : TRI_PACK];
+  const double* const R = GA ? W : R_lds;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int P = n * (n + 1) / 2;
   const double* tauG = W + P;
-  for (int e = tid; e < P; e += TNT) R[e] = W[e];
-  __syncthreads();
-  const int col = blockIdx.x * (TNT / 64) + w;
+  if (!GA) {
+    for (int e = tid; e < P; e += TNT) R_lds[e] = W[e];
+    __syncthreads();
+  }
+  const int col = cb * (TNT / 64) + w;
   if (col >= n) return;
   double z[NPL];
   double* zc = Z + static_cast<int64_t>(col) * ldz;
@@ -676,27 +679,38 @@ __global__ __launch_bounds__(TNT) void k_backtr(const double* __restrict__ W, in
   }
 }
 
+template <int NPL, bool GA>
+__global__ __launch_bounds__(TNT) void k_backtr(const double* __restrict__ W, int n,
+                                                double* __restrict__ Z, int ldz) {
+  backtr_body<NPL, GA>(W, n, Z, ldz, blockIdx.x);
+}
+
 hipError_t launch_tridiag(const double* G, int m, int mp, EigWork wk, hipStream_t s) {
-  if (m < 1 || m > kTridMax || mp < m) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_tridiag, dim3(1), dim3(TNT), 0, s, G, m, mp, wk.W);
+  if (m < 1 || m > kTridGlobalMax || mp < m) return hipErrorInvalidValue;
+  if (m <= kTridMax)
+    hipLaunchKernelGGL(k_tridiag<false>, dim3(1), dim3(TNT), 0, s, G, m, mp, wk.W);
+  else
+    hipLaunchKernelGGL(k_tridiag<true>, dim3(1), dim3(TNT), 0, s, G, m, mp, wk.W);
   return hipGetLastError();
 }
 
 hipError_t launch_dc(int m, int mp, double* lam, double* V, EigWork wk, hipStream_t s) {
-  if (m < 1 || m > kTridMax || mp < m) return hipErrorInvalidValue;
+  if (m < 1 || m > kDcMax || mp < m) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_dc, dim3(1), dim3(TNT), 0, s, wk.W, m, V, mp, wk.S1, wk.S2, lam, wk.st);
   return hipGetLastError();
 }
 
 hipError_t launch_backtr(int m, int mp, double* V, EigWork wk, hipStream_t s) {
-  if (m < 1 || m > kTridMax || mp < m) return hipErrorInvalidValue;
+  if (m < 1 || m > kTridGlobalMax || mp < m) return hipErrorInvalidValue;
   const int grid = (m + TNT / 64 - 1) / (TNT / 64);
   if (m <= 64)
-    hipLaunchKernelGGL(k_backtr<1>, dim3(grid), dim3(TNT), 0, s, wk.W, m, V, mp);
+    hipLaunchKernelGGL((k_backtr<1, false>), dim3(grid), dim3(TNT), 0, s, wk.W, m, V, mp);
   else if (m <= 128)
-    hipLaunchKernelGGL(k_backtr<2>, dim3(grid), dim3(TNT), 0, s, wk.W, m, V, mp);
+    hipLaunchKernelGGL((k_backtr<2, false>), dim3(grid), dim3(TNT), 0, s, wk.W, m, V, mp);
+  else if (m <= kTridMax)
+    hipLaunchKernelGGL((k_backtr<4, false>), dim3(grid), dim3(TNT), 0, s, wk.W, m, V, mp);
   else
-    hipLaunchKernelGGL(k_backtr<4>, dim3(grid), dim3(TNT), 0, s, wk.W, m, V, mp);
+    hipLaunchKernelGGL((k_backtr<4, true>), dim3(grid), dim3(TNT), 0, s, wk.W, m, V, mp);
   return hipGetLastError();
 }
 
@@ -705,6 +719,54 @@ hipError_t launch_eig_trid(const double* G, int m, int mp, double* lam, double* 
   hipError_t e = launch_tridiag(G, m, mp, wk, s);
   if (e == hipSuccess) e = launch_dc(m, mp, lam, V, wk, s);
   if (e == hipSuccess) e = launch_backtr(m, mp, V, wk, s);
+  return e;
+}
+
+// ------------------------------------------------------ grouped (batches)
+template <bool GA>
+__global__ __launch_bounds__(TNT) void kg_tridiag(const GroupSketch* __restrict__ SK,
+                                                  const GroupRR* __restrict__ T) {
+  const GroupSketch& s = SK[T[blockIdx.x].sk];
+  if ((s.m > kTridMax) != GA) return;    // the other variant's task
+  tridiag_body<GA>(s.G, s.m, s.mp, s.W);
+}
+
+__global__ __launch_bounds__(TNT) void kg_dc(const GroupSketch* __restrict__ SK,
+                                             const GroupRR* __restrict__ T) {
+  const GroupSketch& s = SK[T[blockIdx.x].sk];
+  dc_body(s.W, s.m, s.V, s.mp, s.S1, s.S2, s.lam, s.st);
+}
+
+template <bool GA>
+__global__ __launch_bounds__(TNT) void kg_backtr(const GroupSketch* __restrict__ SK,
+                                                 const GroupRR* __restrict__ T) {
+  const GroupSketch& s = SK[T[blockIdx.y].sk];
+  if ((s.m > kTridMax) != GA) return;
+  if (static_cast<int>(blockIdx.x) * (TNT / 64) >= s.m) return;
+  backtr_body<4, GA>(s.W, s.m, s.V, s.mp, blockIdx.x);
+}
+
+hipError_t launch_group_eig(const GroupSketch* sk, const GroupRR* t, int nt, int max_m, hipStream_t s) {
+  if (nt <= 0) return hipSuccess;
+  if (max_m > kTridGlobalMax) return hipErrorInvalidValue;
+  const bool big = max_m > kTridMax;
+  hipLaunchKernelGGL(kg_tridiag<false>, dim3(nt), dim3(TNT), 0, s, sk, t);
+  hipError_t e = hipGetLastError();
+  if (e == hipSuccess && big) {
+    hipLaunchKernelGGL(kg_tridiag<true>, dim3(nt), dim3(TNT), 0, s, sk, t);
+    e = hipGetLastError();
+  }
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(kg_dc, dim3(nt), dim3(TNT), 0, s, sk, t);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const dim3 g((max_m + TNT / 64 - 1) / (TNT / 64), nt);
+  hipLaunchKernelGGL(kg_backtr<false>, g, dim3(TNT), 0, s, sk, t);
+  e = hipGetLastError();
+  if (e == hipSuccess && big) {
+    hipLaunchKernelGGL(kg_backtr<true>, g, dim3(TNT), 0, s, sk, t);
+    e = hipGetLastError();
+  }
   return e;
 }
 

@@ -280,16 +280,19 @@ def _check_batch(rc, handle=None):
 
 
 class FDSketchBatch:
-    """Many independent sketches advanced by one persistent launch per call."""
+    """Many independent sketches advanced together in lock-step rounds (one launch per
+    stage and round over all active sketches)."""
 
     def __init__(self, configs, stream=None):
-        """configs: list of dicts with keys d, l and optionally variant, alpha, buffer_rows."""
+        """configs: list of dicts with keys d, l and optionally variant, alpha, buffer_rows,
+        precision ("fp64", "bf16", "bf16x3")."""
         self.S = len(configs)
         arr = (FdskConfig * self.S)()
         self.shapes = []
         for i, c in enumerate(configs):
             arr[i] = FdskConfig(int(c["d"]), int(c["l"]), int(c.get("buffer_rows", 0)),
-                                VARIANTS[c.get("variant", "fd")], float(c.get("alpha", 0.2)), 0, 0)
+                                VARIANTS[c.get("variant", "fd")], float(c.get("alpha", 0.2)),
+                                PRECISIONS[c.get("precision", "fp64")], 0)
             self.shapes.append((int(c["l"]), int(c["d"])))
         h = ctypes.c_void_p()
         _check_batch(lib().sketch_batch_create(self.S, arr, _stream_handle(stream), ctypes.byref(h)))

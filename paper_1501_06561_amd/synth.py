@@ -23,6 +23,9 @@ Recipes
 * ``basis_rows`` -- rows that are scaled coordinate vectors (frequent-items
   special case used to test the sketch against a counter simulation).
 * ``batch_shapes`` -- per-sketch (d, l, n) draws for the many-sketch workload.
+* ``random_noisy_device`` -- the Random Noisy recipe drawn on a torch device
+  (S and N from a seeded ``torch.Generator`` there, U from NumPy as above),
+  for workloads too large to draw on the host quickly.
 
 All NumPy draws use ``numpy.random.Generator(PCG64)``; chunked streams derive
 one child seed per chunk so any chunk regenerates on its own.
@@ -35,7 +38,7 @@ __all__ = [
     "rng_for", "random_noisy", "random_noisy_chunk", "random_noisy_basis",
     "power_law", "power_law_basis", "power_law_chunk",
     "rotating_adversarial", "two_subspace_adversarial", "basis_rows",
-    "batch_shapes", "to_bf16", "bf16_bits", "WORKLOADS",
+    "batch_shapes", "random_noisy_device", "to_bf16", "bf16_bits", "WORKLOADS",
 ]
 
 
@@ -163,6 +166,23 @@ def batch_shapes(S: int = 512, seed=(4, 0), d_range=(64, 2048), l_range=(16, 128
     l = rng.integers(l_range[0], l_range[1] + 1, size=S)
     n = rng.integers(n_range[0], n_range[1] + 1, size=S)
     return d.astype(np.int64), l.astype(np.int64), n.astype(np.int64)
+
+
+def random_noisy_device(n: int, d: int, k: int, zeta: float, seed, device="cuda", dtype=None):
+    """Random Noisy rows (n x d) drawn on a torch device: the same recipe as
+    ``random_noisy`` (D_ii = 1 - (i-1)/k, U orthonormal rows), with S and N
+    from a torch.Generator on the device seeded by the key's first 64 bits."""
+    import torch
+    key = seed if isinstance(seed, (tuple, list)) else (seed,)
+    ss = np.random.SeedSequence(list(key))
+    g = torch.Generator(device=device)
+    g.manual_seed(int(ss.generate_state(1, dtype=np.uint64)[0] & 0x7FFFFFFFFFFFFFFF))
+    U = torch.from_numpy(_orthonormal_rows(rng_for(*key, 1), k, d)).to(device)
+    D = 1.0 - torch.arange(k, dtype=torch.float64, device=device) / k
+    S = torch.randn((n, k), generator=g, dtype=torch.float64, device=device)
+    A = (S * D) @ U
+    A += torch.randn((n, d), generator=g, dtype=torch.float64, device=device) / zeta
+    return A.to(dtype or torch.float32)
 
 
 def bf16_bits(x: np.ndarray) -> np.ndarray:

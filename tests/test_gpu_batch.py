@@ -1,5 +1,6 @@
-"""Many-sketch persistent launch: every sketch of a batch against the oracle,
-and results independent of how many workgroups run the batch."""
+"""Many sketches advanced together in lock-step rounds: every sketch of a
+batch against the oracle, and results independent of how the sketches are
+grouped into launches or how the rows are split into append calls."""
 import numpy as np
 import pytest
 
@@ -7,10 +8,7 @@ import oracle
 from paper_1501_06561_amd import synth
 
 torch = pytest.importorskip("torch")
-pytestmark = [pytest.mark.gpu, pytest.mark.skip(
-    reason="persistent many-sketch launch disabled: its first GPU run ended in a device memory "
-           "fault whose cause is not yet shown (CPU emulation under AddressSanitizer finds no "
-           "out-of-bounds access)")]
+pytestmark = pytest.mark.gpu
 
 from paper_1501_06561_amd import fdsketch as F  # noqa: E402
 
@@ -61,8 +59,10 @@ def _check(cfg, A, B, st, gram_tol):
 
 
 def test_batch_matches_oracle_mixed_shapes():
-    """Both in-workgroup eigensolvers (m <= 100 in LDS; 100 < m <= 256 blocked)."""
-    cfgs, mats = _make_batch(1, 24, (20, 300), (4, 128), (50, 2500))
+    """Buffer rows 8..256 (both storage forms of the tridiagonal reduction:
+    LDS up to 200 rows, workspace above), d ragged against the 64-column
+    padding, all four variants."""
+    cfgs, mats = _make_batch(1, 24, (20, 300), (4, 129), (50, 2500))
     outs, stats = _run(cfgs, mats)
     for cfg, A, B, st in zip(cfgs, mats, outs, stats):
         _check(cfg, A, B, st, 1e-9 if cfg["variant"] == "fd" else 1e-7)
@@ -111,5 +111,28 @@ def test_batch_many_sketch_workload_draws():
 
 def test_batch_rejects_large_buffers():
     with pytest.raises(F.FdskError) as e:
-        F.FDSketchBatch([dict(d=10, l=200)])
+        F.FDSketchBatch([dict(d=10, l=129)])
     assert e.value.code == -6
+
+
+def test_batch_reduced_precision_mixed():
+    """BF16 / split-BF16 Gram and rebuild inside a batch that also holds FP64
+    sketches: each sketch within its precision's bound of the FP64 oracle on
+    the same bf16 rows (1e-4 for split-BF16, 5e-3 for one BF16 pass)."""
+    precs = ["fp64", "bf16x3", "bf16", "bf16x3"]
+    cfgs, mats = [], []
+    for i, p in enumerate(precs):
+        A = synth.power_law(1500, 384, r=120, seed=(62, i), chunk=1500)
+        mats.append(synth.to_bf16(A).astype(np.float64))
+        cfgs.append(dict(d=384, l=24 + 8 * i, variant="fd", alpha=0.2, precision=p))
+    b = F.FDSketchBatch(cfgs)
+    b.append([torch.from_numpy(synth.bf16_bits(m.astype(np.float32)).view(np.int16)).view(torch.bfloat16).cuda()
+              for m in mats])
+    outs = [o.cpu().numpy() for o in b.finalize()]
+    for i, (cfg, A, B) in enumerate(zip(cfgs, mats, outs)):
+        Bo = oracle.fd_sketch(A, cfg["l"], "fd")
+        ce, co = oracle.cov_err(A, B), oracle.cov_err(A, Bo)
+        tol = {"fp64": 1e-6 * co + 1e-12, "bf16x3": 1e-4, "bf16": 5e-3}[cfg["precision"]]
+        assert abs(ce - co) <= tol, (cfg, ce, co)
+        assert b.stats(i)["n_reduce"] == oracle.fd_sketch(A, cfg["l"], "fd", return_state=True)[1].n_rr
+    b.close()
