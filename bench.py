@@ -73,49 +73,61 @@ def measured_traffic(stage, l, variant):
     return None
 
 
-def batched_leg(S, n_max, seed=(4, 0)):
-    """The many-sketch workload shape (d ~ U{64..2048}, l ~ U{16..100}, n ~
+def batched_leg(S, n_max, seq_sketches, seed=(4, 0)):
+    """The many-sketch workload (d ~ U{64..2048}, l ~ U{16..128}, n ~
     U{1000..n_max}, Random Noisy rows with k = l/2, zeta = 10, fp32 on the
-    device): all sketches through the lock-step batch, then the same sketches
-    one after another through the single-sketch path.  Rows/s of each."""
+    device): all sketches through the lock-step batch with FP64 and with
+    split-BF16 (x3) Gram/rebuild products, and the first `seq_sketches` of them
+    one after another through the single-sketch FP64 path.  Rows/s of each
+    (the sequential rate is measured on that prefix of the sketches)."""
     import torch
     from paper_1501_06561_amd import fdsketch, synth
-    d, l, n = synth.batch_shapes(S, seed=seed, l_range=(16, 100), n_range=(1000, n_max))
+    d, l, n = synth.batch_shapes(S, seed=seed, n_range=(1000, n_max))
     mats = [synth.random_noisy_device(int(n[i]), int(d[i]), max(1, int(l[i]) // 2), 10.0,
                                       (seed[0], seed[1], i)) for i in range(S)]
-    cfgs = [dict(d=int(d[i]), l=int(l[i])) for i in range(S)]
     rows = int(n.sum())
     # Warm both paths (first launches load the kernels).
-    w = fdsketch.FDSketchBatch(cfgs[:2])
+    w = fdsketch.FDSketchBatch([dict(d=int(d[i]), l=int(l[i])) for i in range(2)])
     w.append([m[:300] for m in mats[:2]])
     w.finalize()
     w.close()
     torch.cuda.synchronize()
-    b = fdsketch.FDSketchBatch(cfgs)
+    out = {"workload": f"{S} sketches, d~U{{64..2048}}, l~U{{16..128}}, n~U{{1000..{n_max}}}, "
+                       "random noisy k=l/2 zeta=10, fp32 rows on device",
+           "rows": rows, "unit": "rows/s"}
+    for prec in ("fp64", "bf16x3"):
+        b = fdsketch.FDSketchBatch([dict(d=int(d[i]), l=int(l[i]), precision=prec) for i in range(S)])
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        b.append(mats)
+        b.finalize()
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        if prec == "fp64":
+            out["reduce_steps"] = sum(b.stats(i)["n_reduce"] for i in range(S))
+            out["value"] = rows / dt
+            out["ms"] = dt * 1e3
+        else:
+            out["value_bf16x3"] = rows / dt
+            out["ms_bf16x3"] = dt * 1e3
+        b.close()
+    k = min(seq_sketches, S)
+    sks = [fdsketch.FDSketch(int(d[i]), int(l[i])) for i in range(k)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    b.append(mats)
-    b.finalize()
-    torch.cuda.synchronize()
-    t_batch = time.perf_counter() - t0
-    n_rr = sum(b.stats(i)["n_reduce"] for i in range(S))
-    b.close()
-    sks = [fdsketch.FDSketch(c["d"], c["l"]) for c in cfgs]
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for sk, m in zip(sks, mats):
+    for sk, m in zip(sks, mats[:k]):
         sk.append(m)
         sk.finalize()
     torch.cuda.synchronize()
     t_seq = time.perf_counter() - t0
     for sk in sks:
         sk.close()
-    return {"workload": f"{S} sketches, d~U{{64..2048}}, l~U{{16..100}}, n~U{{1000..{n_max}}}, "
-                        "random noisy k=l/2 zeta=10, fp32 rows on device",
-            "rows": rows, "reduce_steps": n_rr,
-            "value": rows / t_batch, "unit": "rows/s", "ms": t_batch * 1e3,
-            "sequential_value": rows / t_seq, "sequential_ms": t_seq * 1e3,
-            "speedup_vs_sequential": t_seq / t_batch, "dtype": "f64"}
+    out["sequential_value"] = int(n[:k].sum()) / t_seq
+    out["sequential_sample"] = f"first {k} sketches ({int(n[:k].sum())} rows), single-sketch FP64 path"
+    out["speedup_vs_sequential"] = out["value"] / out["sequential_value"]
+    out["speedup_bf16x3_vs_sequential"] = out["value_bf16x3"] / out["sequential_value"]
+    out["dtype"] = "f64 (bf16x3: split-bf16 Gram/rebuild, f64 eigensolve)"
+    return out
 
 
 def copy_calibration(nbytes, reps):
@@ -169,8 +181,10 @@ def main():
                     help="rows of the stream to sketch (profiling runs use a prefix)")
     ap.add_argument("--batch-sketches", type=int, default=512,
                     help="sketches in the many-sketch leg (0 skips it)")
-    ap.add_argument("--batch-nmax", type=int, default=5000,
+    ap.add_argument("--batch-nmax", type=int, default=50_000,
                     help="largest rows per sketch in the many-sketch leg")
+    ap.add_argument("--batch-seq", type=int, default=64,
+                    help="sketches of the many-sketch leg also run one after another")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run a plain device copy of BYTES (counter reference) and exit")
     args = ap.parse_args()
@@ -247,7 +261,8 @@ def main():
     ev = sk.error(At, k=10, method=0)
     sk.close()
     del At
-    batched = batched_leg(args.batch_sketches, args.batch_nmax) if args.batch_sketches > 0 else None
+    batched = (batched_leg(args.batch_sketches, args.batch_nmax, args.batch_seq)
+               if args.batch_sketches > 0 else None)
 
     cpu = None
     cov_oracle = None
