@@ -53,8 +53,12 @@ typedef enum { FDSK_F64 = 0, FDSK_F32 = 1, FDSK_BF16 = 2 } fdsk_dtype;  /* BF16 
  * subtraction and every accumulator are FP64 in all modes; the buffer stays
  * FP64.  BF16: each FP64 operand rounded to bfloat16, products on BF16
  * matrix cores with FP32 accumulation.  BF16X3: operands split as
- * hi = bf16(x), lo = bf16(x - hi) and hi*hi + hi*lo + lo*hi accumulated. */
-typedef enum { FDSK_P_FP64 = 0, FDSK_P_BF16 = 1, FDSK_P_BF16X3 = 2 } fdsk_precision;
+ * hi = bf16(x), lo = bf16(x - hi) and hi*hi + hi*lo + lo*hi accumulated.
+ * FP8X3 (Gram only; the rebuild is BF16X3): each buffer row split as
+ * hi = e4m3(x / s), lo = e4m3((x - s hi) / t) with per-row scales s, t (row
+ * maximum / 240), and hi*hi + hi*lo + lo*hi on FP8 matrix cores with FP32
+ * accumulation, the scales applied in FP64. */
+typedef enum { FDSK_P_FP64 = 0, FDSK_P_BF16 = 1, FDSK_P_BF16X3 = 2, FDSK_P_FP8X3 = 3 } fdsk_precision;
 typedef enum { FDSK_MEM_HOST = 0, FDSK_MEM_DEVICE = 1 } fdsk_mem;
 
 #define FDSK_FLAG_PROFILE 1u       /* record per-stage HIP events (see sketch_profile) */

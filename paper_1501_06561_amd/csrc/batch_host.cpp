@@ -184,6 +184,8 @@ int sketch_batch_create(int32_t S, const fdsk_config* cfgs, void* hip_stream, fd
     if (c.variant < FDSK_FD || c.variant > FDSK_FAST_ALPHA) return berr(nullptr, FDSK_EINVAL, "bad variant");
     if ((c.variant == FDSK_ALPHA || c.variant == FDSK_FAST_ALPHA) && !(c.alpha > 0.0 && c.alpha <= 1.0))
       return berr(nullptr, FDSK_EINVAL, "sketch %d: alpha must lie in (0, 1]", i);
+    if (c.precision == FDSK_P_FP8X3)
+      return berr(nullptr, FDSK_EUNSUPPORTED, "sketch %d: the FP8 Gram is single-sketch only", i);
     if (c.precision != FDSK_P_FP64 && c.precision != FDSK_P_BF16 && c.precision != FDSK_P_BF16X3)
       return berr(nullptr, FDSK_EINVAL, "sketch %d: unknown precision", i);
     if (c.flags != 0) return berr(nullptr, FDSK_EUNSUPPORTED, "sketch %d: batched sketches take no flags", i);

@@ -39,6 +39,11 @@ hipError_t launch_gram_reduce(const double* Gpart, int ksplit, int mp, double* G
 // 3 = hi*hi + hi*lo + lo*hi (split-bf16 compensation), FP32 accumulation.
 hipError_t launch_gram_lowp(const double* C, int ldc, int mp, double* Gpart, int ksplit_max, double* G,
                             int npass, hipStream_t s);
+// FP8 (e4m3) compensated Gram: per-row scaled hi/lo codes of C in q8
+// (fp8_workspace_bytes), then three FP8 products per tile.
+hipError_t launch_gram_fp8(const double* C, int ldc, int mp, void* q8, double* Gpart, int ksplit_max,
+                           double* G, hipStream_t s);
+size_t fp8_workspace_bytes(int mp, int ldc);
 hipError_t launch_rebuild_lowp(const double* Ut, const double* C, int ldc, int mp, int keep, double* out,
                                int npass, hipStream_t s);
 hipError_t launch_shrink(const double* lam, const double* V, int m, int mp, RuleParams rp,

@@ -34,6 +34,7 @@ struct fdsk_sketch {
   int cur = 0;
   double *G = nullptr, *Gpart = nullptr, *W = nullptr, *V = nullptr, *lam = nullptr,
          *Ut = nullptr, *rownorm = nullptr, *S1 = nullptr, *S2 = nullptr;
+  void* q8 = nullptr;   // FP8 codes and scales of the buffer (FDSK_P_FP8X3)
   int ksplit_max = 1;
   DevStats* st = nullptr;
   unsigned* bar = nullptr;
@@ -139,6 +140,8 @@ int reduce(fdsk_sketch* s) {
   const int npass = s->cfg.precision == FDSK_P_BF16 ? 1 : 3;
   if (s->cfg.precision == FDSK_P_FP64)
     HIPCHK(s, launch_gram(s->C[s->cur], s->ldc, s->mp, s->Gpart, s->ksplit_max, s->G, s->stream));
+  else if (s->cfg.precision == FDSK_P_FP8X3)
+    HIPCHK(s, launch_gram_fp8(s->C[s->cur], s->ldc, s->mp, s->q8, s->Gpart, s->ksplit_max, s->G, s->stream));
   else
     HIPCHK(s, launch_gram_lowp(s->C[s->cur], s->ldc, s->mp, s->Gpart, s->ksplit_max, s->G, npass,
                                s->stream));
@@ -234,7 +237,8 @@ int sketch_create(const fdsk_config* cfg, void* hip_stream, fdsk_sketch** out) {
     return set_err(nullptr, FDSK_EINVAL, "unknown variant");
   if ((c.variant == FDSK_ALPHA || c.variant == FDSK_FAST_ALPHA) && !(c.alpha > 0.0 && c.alpha <= 1.0))
     return set_err(nullptr, FDSK_EINVAL, "alpha must lie in (0, 1]");
-  if (c.precision != FDSK_P_FP64 && c.precision != FDSK_P_BF16 && c.precision != FDSK_P_BF16X3)
+  if (c.precision != FDSK_P_FP64 && c.precision != FDSK_P_BF16 && c.precision != FDSK_P_BF16X3 &&
+      c.precision != FDSK_P_FP8X3)
     return set_err(nullptr, FDSK_EINVAL, "unknown precision %d", (int)c.precision);
   if (c.flags & ~(FDSK_FLAG_PROFILE | FDSK_FLAG_EIG_JACOBI))
     return set_err(nullptr, FDSK_EINVAL, "unknown flags");
@@ -265,7 +269,8 @@ int sketch_create(const fdsk_config* cfg, void* hip_stream, fdsk_sketch** out) {
          oGp = take(mp2 * 8 * s->ksplit_max), oW = take(mp2 * 8), oV = take(mp2 * 8),
          oUt = take(mp2 * 8), oLam = take(s->mp * 8), oRn = take(s->mp * 8),
          oSt = take(sizeof(DevStats)), oBar = take(4 * sizeof(unsigned)),
-         oRot = take(kMaxSweeps * sizeof(int)), oS1 = take(mp2 * 8), oS2 = take(mp2 * 8);
+         oRot = take(kMaxSweeps * sizeof(int)), oS1 = take(mp2 * 8), oS2 = take(mp2 * 8),
+         oQ8 = take(c.precision == FDSK_P_FP8X3 ? fp8_workspace_bytes(s->mp, s->ldc) : 0);
   hipError_t e = hipMalloc(&s->arena, off);
   if (e != hipSuccess) {
     delete s;
@@ -286,6 +291,7 @@ int sketch_create(const fdsk_config* cfg, void* hip_stream, fdsk_sketch** out) {
   s->rot = reinterpret_cast<int*>(a + oRot);
   s->S1 = reinterpret_cast<double*>(a + oS1);
   s->S2 = reinterpret_cast<double*>(a + oS2);
+  s->q8 = (c.precision == FDSK_P_FP8X3) ? static_cast<void*>(a + oQ8) : nullptr;
   e = hipMemsetAsync(s->arena, 0, off, s->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
   if (e != hipSuccess) {
@@ -591,7 +597,7 @@ struct DevBuf {
 
 extern "C" int fdsk_gram(const double* C, int32_t rows, int64_t d, int64_t ldc, double* G,
                          int64_t ldg, fdsk_precision prec, void* hip_stream) {
-  if (prec != FDSK_P_FP64 && prec != FDSK_P_BF16 && prec != FDSK_P_BF16X3)
+  if (prec != FDSK_P_FP64 && prec != FDSK_P_BF16 && prec != FDSK_P_BF16X3 && prec != FDSK_P_FP8X3)
     return set_err(nullptr, FDSK_EINVAL, "fdsk_gram: unknown precision");
   if (!C || !G || rows < 1 || rows > 1024 || d < 1 || d > 65536 || ldc < d || ldg < rows)
     return set_err(nullptr, FDSK_EINVAL, "fdsk_gram: bad arguments");
@@ -601,15 +607,19 @@ extern "C" int fdsk_gram(const double* C, int32_t rows, int64_t d, int64_t ldc, 
   const int ks = std::max(1, std::min({(256 + ntiles - 1) / ntiles, ld / 256, 16}));
   DevBuf buf;
   const size_t nC = static_cast<size_t>(mp) * ld, nG = static_cast<size_t>(mp) * mp;
-  if (hipMalloc(&buf.p, (nC + nG * (1 + ks)) * 8) != hipSuccess)
+  const size_t q8b = (prec == FDSK_P_FP8X3) ? fp8_workspace_bytes(mp, ld) : 0;
+  if (hipMalloc(&buf.p, (nC + nG * (1 + ks)) * 8 + q8b) != hipSuccess)
     return set_err(nullptr, FDSK_ENOMEM, "fdsk_gram: workspace");
   double* Cp = static_cast<double*>(buf.p);
   double* Gp = Cp + nC;
   double* Gpart = Gp + nG;
+  void* q8 = Gpart + nG * ks;
   HIPCHK(nullptr, hipMemsetAsync(Cp, 0, nC * 8, st));
   HIPCHK(nullptr, hipMemcpy2DAsync(Cp, ld * 8, C, ldc * 8, d * 8, rows, hipMemcpyDeviceToDevice, st));
   if (prec == FDSK_P_FP64)
     HIPCHK(nullptr, launch_gram(Cp, ld, mp, Gpart, ks, Gp, st));
+  else if (prec == FDSK_P_FP8X3)
+    HIPCHK(nullptr, launch_gram_fp8(Cp, ld, mp, q8, Gpart, ks, Gp, st));
   else
     HIPCHK(nullptr, launch_gram_lowp(Cp, ld, mp, Gpart, ks, Gp, prec == FDSK_P_BF16 ? 1 : 3, st));
   HIPCHK(nullptr, hipMemcpy2DAsync(G, ldg * 8, Gp, mp * 8, rows * 8, rows, hipMemcpyDeviceToDevice, st));

@@ -185,6 +185,155 @@ hipError_t launch_rebuild_lowp(const double* Ut, const double* C, int ldc, int m
   return hipGetLastError();
 }
 
+// ------------------------------------------------------------------- FP8
+// Per-row e4m3 split of the FP64 buffer: hi = e4m3(x / s) with s = amax/240,
+// lo = e4m3((x - s hi) / t) with t the same for the residual (240 keeps every
+// value inside the e4m3 range whichever bias the hardware format uses).  The
+// Gram G_ij = s_i s_j (hi_i . hi_j) + s_i t_j (hi_i . lo_j) + t_i s_j (lo_i .
+// hi_j): three FP8 matrix-core products, FP32 accumulation, scales in FP64.
+constexpr double kFp8Range = 240.0;
+
+// Byte u (0..3) of a word of e4m3 codes as a float.
+__device__ __forceinline__ float fp8_byte(int w, int u) {
+  switch (u) {
+    case 0: return __builtin_amdgcn_cvt_f32_fp8(w, 0);
+    case 1: return __builtin_amdgcn_cvt_f32_fp8(w, 1);
+    case 2: return __builtin_amdgcn_cvt_f32_fp8(w, 2);
+    default: return __builtin_amdgcn_cvt_f32_fp8(w, 3);
+  }
+}
+
+__device__ __forceinline__ double block_max_256(double v, double* red) {
+  for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  const double m = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+  __syncthreads();
+  return m;
+}
+
+// One workgroup per buffer row; four consecutive elements per thread and
+// pass (packed into one 32-bit word of e4m3 codes).
+__global__ __launch_bounds__(256) void k_quant_fp8(const double* __restrict__ C, int ldc,
+                                                   uint32_t* __restrict__ Qh, uint32_t* __restrict__ Ql,
+                                                   double* __restrict__ sc, int mp) {
+  __shared__ double red[4];
+  const int r = blockIdx.x;
+  const double* x = C + static_cast<int64_t>(r) * ldc;
+  double amax = 0.0;
+  for (int c = threadIdx.x; c < ldc; c += 256) amax = fmax(amax, fabs(x[c]));
+  amax = block_max_256(amax, red);
+  const double s = (amax > 0.0) ? amax / kFp8Range : 1.0;
+  const double inv_s = 1.0 / s;
+  const int nw = ldc / 4;
+  double rmax = 0.0;
+  for (int q = threadIdx.x; q < nw; q += 256) {
+    double v[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) v[u] = x[4 * q + u];
+    int w = __builtin_amdgcn_cvt_pk_fp8_f32(static_cast<float>(v[0] * inv_s), static_cast<float>(v[1] * inv_s), 0, false);
+    w = __builtin_amdgcn_cvt_pk_fp8_f32(static_cast<float>(v[2] * inv_s), static_cast<float>(v[3] * inv_s), w, true);
+    Qh[static_cast<int64_t>(r) * nw + q] = static_cast<uint32_t>(w);
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const double hv = static_cast<double>(fp8_byte(w, u)) * s;
+      rmax = fmax(rmax, fabs(v[u] - hv));
+    }
+  }
+  rmax = block_max_256(rmax, red);
+  const double t = (rmax > 0.0) ? rmax / kFp8Range : 1.0;
+  const double inv_t = 1.0 / t;
+  for (int q = threadIdx.x; q < nw; q += 256) {
+    const int w = static_cast<int>(Qh[static_cast<int64_t>(r) * nw + q]);
+    float res[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      res[u] = static_cast<float>((x[4 * q + u] - static_cast<double>(fp8_byte(w, u)) * s) * inv_t);
+    int wl = __builtin_amdgcn_cvt_pk_fp8_f32(res[0], res[1], 0, false);
+    wl = __builtin_amdgcn_cvt_pk_fp8_f32(res[2], res[3], wl, true);
+    Ql[static_cast<int64_t>(r) * nw + q] = static_cast<uint32_t>(wl);
+  }
+  if (threadIdx.x == 0) {
+    sc[r] = s;
+    sc[mp + r] = t;
+  }
+}
+
+__device__ __forceinline__ f32x4 mfma_fp8(long a, long b, f32x4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(a, b, c, 0, 0, 0);
+}
+
+// G partials on lower-triangular 32x32 tiles with split-K (see k_gram_f64);
+// 16x16x32 FP8 steps: lane = i + 16 q holds A[i][8q..8q+7] and B[8q..8q+7][i]
+// (eight e4m3 codes in one 64-bit word); the result lane = j + 16 q holds
+// D[4q + v][j] in element v.
+__global__ __launch_bounds__(256) void k_gram_fp8(const uint8_t* __restrict__ Qh,
+                                                  const uint8_t* __restrict__ Ql,
+                                                  const double* __restrict__ sc, int ldc, int mp,
+                                                  int kchunk, double* __restrict__ Gpart) {
+  const int tile = blockIdx.x;
+  int ti = static_cast<int>((sqrtf(8.0f * tile + 1.0f) - 1.0f) * 0.5f);
+  while ((ti + 1) * (ti + 2) / 2 <= tile) ++ti;
+  while (ti * (ti + 1) / 2 > tile) --ti;
+  const int tj = tile - ti * (ti + 1) / 2;
+  const int k0 = blockIdx.y * kchunk;
+  const int k1 = min(ldc, k0 + kchunk);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int wi = w >> 1, wj = w & 1;
+  const int li = lane & 15, lq = lane >> 4;
+  const int ra = ti * 32 + wi * 16 + li, rb = tj * 32 + wj * 16 + li;
+  const long* ah_p = reinterpret_cast<const long*>(Qh + static_cast<int64_t>(ra) * ldc);
+  const long* al_p = reinterpret_cast<const long*>(Ql + static_cast<int64_t>(ra) * ldc);
+  const long* bh_p = reinterpret_cast<const long*>(Qh + static_cast<int64_t>(rb) * ldc);
+  const long* bl_p = reinterpret_cast<const long*>(Ql + static_cast<int64_t>(rb) * ldc);
+  f32x4 hh = {0.f, 0.f, 0.f, 0.f}, hl = hh, lh = hh;
+  for (int kk = k0; kk < k1; kk += 32) {
+    const int o = (kk >> 3) + lq;
+    const long ah = ah_p[o], al = al_p[o], bh = bh_p[o], bl = bl_p[o];
+    hh = mfma_fp8(ah, bh, hh);
+    hl = mfma_fp8(ah, bl, hl);
+    lh = mfma_fp8(al, bh, lh);
+  }
+  double* out = Gpart + static_cast<int64_t>(blockIdx.y) * mp * mp;
+  const int col = tj * 32 + wj * 16 + li;
+  const double scol = sc[col], tcol = sc[mp + col];
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int row = ti * 32 + wi * 16 + 4 * lq + v;
+    const double srow = sc[row], trow = sc[mp + row];
+    out[static_cast<int64_t>(row) * mp + col] =
+        srow * scol * static_cast<double>(hh[v]) + srow * tcol * static_cast<double>(hl[v]) +
+        trow * scol * static_cast<double>(lh[v]);
+  }
+}
+
+hipError_t launch_gram_fp8(const double* C, int ldc, int mp, void* q8, double* Gpart, int ksplit_max,
+                           double* G, hipStream_t s) {
+  uint8_t* Qh = static_cast<uint8_t*>(q8);
+  uint8_t* Ql = Qh + static_cast<size_t>(mp) * ldc;
+  double* sc = reinterpret_cast<double*>(Ql + static_cast<size_t>(mp) * ldc);
+  hipLaunchKernelGGL(k_quant_fp8, dim3(mp), dim3(256), 0, s, C, ldc, reinterpret_cast<uint32_t*>(Qh),
+                     reinterpret_cast<uint32_t*>(Ql), sc, mp);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const int T = mp / 32;
+  const int ntiles = T * (T + 1) / 2;
+  int ksplit = (256 + ntiles - 1) / ntiles;
+  ksplit = std::min(ksplit, std::max(1, ldc / 256));
+  ksplit = std::min(ksplit, ksplit_max);
+  int kchunk = (ldc + ksplit - 1) / ksplit;
+  kchunk = (kchunk + 31) / 32 * 32;
+  ksplit = (ldc + kchunk - 1) / kchunk;
+  hipLaunchKernelGGL(k_gram_fp8, dim3(ntiles, ksplit), dim3(256), 0, s, Qh, Ql, sc, ldc, mp, kchunk, Gpart);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  return launch_gram_reduce(Gpart, ksplit, mp, G, s);
+}
+
+size_t fp8_workspace_bytes(int mp, int ldc) {
+  return 2 * static_cast<size_t>(mp) * ldc + 2 * static_cast<size_t>(mp) * 8;
+}
+
 // ------------------------------------------------------ grouped (batches)
 // Tasks of sketches with another precision return at once (the FP64 kernels
 // of kernels_stream.hip take those).

@@ -36,6 +36,7 @@ def test_library_exports_every_declared_symbol():
     (dict(d=10, l=8, variant=2, alpha=0.0), -1),
     (dict(d=10, l=8, variant=3, alpha=1.5), -1),
     (dict(d=10, l=8, flags=6), -1),
+    (dict(d=10, l=8, precision=4), -1),
     (dict(d=70000, l=8), -1),
 ])
 def test_create_rejects_bad_config(cfg, code):

@@ -60,11 +60,13 @@ def test_eigh_special_matrices(m, method):
     _check_eigh(np.diag(np.r_[np.full(m // 2, 1e4), np.full(m - m // 2, 1e-6)]), method=method)  # two clusters
 
 
-@pytest.mark.parametrize("precision,tol", [("bf16x3", 5e-5), ("bf16", 2e-2)])
+@pytest.mark.parametrize("precision,tol", [("bf16x3", 5e-5), ("bf16", 2e-2), ("fp8x3", 1e-2)])
 @pytest.mark.parametrize("rows,d", [(40, 100), (130, 77), (512, 3072)])
 def test_gram_reduced_precision(precision, tol, rows, d):
-    """BF16 matrix-core Gram: error bounded by the operand rounding (one
-    bf16 rounding ~2^-8 relative, split-bf16 ~2^-16) times |c_i||c_j|."""
+    """Reduced-precision matrix-core Gram: error bounded by the operand
+    rounding times |c_i||c_j| -- one bf16 rounding ~2^-8 relative per
+    element, split-bf16 ~2^-16; the per-row scaled e4m3 hi/lo split keeps
+    each element to ~2^-8 of its row's largest magnitude."""
     rng = np.random.default_rng(rows + d)
     C = rng.standard_normal((rows, d)) * rng.uniform(0.5, 2.0, (rows, 1))
     G = F.gram(torch.from_numpy(C).cuda(), precision=precision).cpu().numpy()
