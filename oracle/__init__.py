@@ -8,18 +8,20 @@ path; both sides meet only at the seeded input generators.
 Modules
 -------
 fd        -- the streaming sketch (Algorithm 1 with the ReduceRank rules of
-             Sections 2.3 and 3.1), computed through LAPACK's SVD of the buffer;
+             Sections 2.3 and 3.1, SpaceSaving and Compensative FD included),
+             computed through LAPACK's SVD of the buffer;
              an independent covariance-form re-derivation; a frequent-items
              counter simulation for rows that are scaled basis vectors.
 evaluate  -- the error measures of Section 1.1 (covariance and projection error).
 """
-from .fd import (FD, ISVD, ALPHA, FAST_ALPHA, VARIANTS, rule_indices, alpha_eff,
+from .fd import (FD, ISVD, ALPHA, FAST_ALPHA, SSD, CFD, VARIANTS, ALL_VARIANTS, rule_indices, alpha_eff,
                  reduce_rank, SketchOracle, fd_sketch, fd_covariance_form,
                  counter_simulation)
 from .evaluate import cov_err, proj_err, proj_full, tail_mass, fro2
 
 __all__ = [
-    "FD", "ISVD", "ALPHA", "FAST_ALPHA", "VARIANTS", "rule_indices", "alpha_eff",
+    "FD", "ISVD", "ALPHA", "FAST_ALPHA", "SSD", "CFD", "VARIANTS", "ALL_VARIANTS", "rule_indices",
+    "alpha_eff",
     "reduce_rank", "SketchOracle", "fd_sketch", "fd_covariance_form",
     "counter_simulation", "cov_err", "proj_err", "proj_full", "tail_mass", "fro2",
 ]

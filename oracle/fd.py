@@ -13,6 +13,17 @@ the buffer becomes S' V^T.  The rules:
   leading l(1-alpha) values are untouched, the trailing alpha*l are shrunk.
 * fast alpha-FD (Section 3.1, "Fast Parameterized FD"): delta = sigma_t^2 with
   t = l - alpha*l/2, only the trailing alpha*l values are shrunk, clamped at 0.
+* SpaceSaving Directions (Section 3.1, Algorithm 3): delta = sigma_{l-1}^2;
+  sigma_{l-1} becomes 0 and sigma_l becomes sqrt(sigma_l^2 + delta), the
+  others are untouched.  Algorithm 3 returns exactly l values, so SSD runs on
+  the l-row buffer of Algorithm 1 (m = l).
+* Compensative FD (Section 3.1, "Compensative Frequent Directions"): FD
+  during the stream; at the end B = S' V^T of the latest reduction is
+  returned with each of the l output squared singular values raised by
+  Delta = sum of all delta_i (so the l-th direction, zeroed by that
+  reduction, carries sqrt(Delta)).  When rows arrived after the latest
+  reduction, the buffer's own SVD (after one more FD reduction if more than
+  l rows are occupied) plays that role.
 
 Readings taken where the text is silent or inexact (each is listed with its
 reason in the design notes):
@@ -27,6 +38,10 @@ reason in the design notes):
    and a ReduceRank runs whenever all m rows are occupied.
 4. At the end, if more than l rows are occupied one more ReduceRank runs; the
    sketch is the first l rows of the buffer.
+5. A direction with a zero singular value (at or below 1e-12 of the largest
+   squared one before the reduction) is not in the buffer's row space: SSD
+   then has nothing to move and leaves the values unchanged (delta = 0), and
+   CFD leaves that output row zero.
 
 The SVD route here (LAPACK gesdd on the m x d buffer) is deliberately a
 different algorithm from the GPU path's Gram matrix + Jacobi eigensolver.
@@ -38,7 +53,10 @@ import math
 import numpy as np
 
 FD, ISVD, ALPHA, FAST_ALPHA = "fd", "isvd", "alpha", "fast_alpha"
+SSD, CFD = "ssd", "cfd"
 VARIANTS = (FD, ISVD, ALPHA, FAST_ALPHA)
+ALL_VARIANTS = VARIANTS + (SSD, CFD)
+NULL_REL = 1e-12        # squared singular values at or below this times the largest are zero (reading 5)
 
 
 def _split(l: int, alpha: float):
@@ -55,7 +73,7 @@ def rule_indices(l: int, variant: str, alpha: float = 0.2):
 
     After a ReduceRank rows t, t+1, ... of S'V^T are zero, so t-1 rows survive.
     """
-    if variant == FD:
+    if variant in (FD, CFD, SSD):
         return l, 0
     if variant == ISVD:
         return l, l - 1
@@ -69,10 +87,12 @@ def rule_indices(l: int, variant: str, alpha: float = 0.2):
 
 def alpha_eff(l: int, variant: str, alpha: float = 0.2) -> float:
     """Constant of Property 3 (mass removed >= alpha_eff * l * Delta)."""
-    if variant == FD:
+    if variant in (FD, CFD):
         return 1.0
     if variant == ISVD:
         return 1.0 / l
+    if variant == SSD:
+        raise ValueError("SSD does not satisfy Property 3 as it stands (its mass is conserved)")
     r, s = _split(l, alpha)
     if variant == ALPHA:
         return s / l
@@ -88,6 +108,14 @@ def reduce_rank(sigma: np.ndarray, l: int, variant: str, alpha: float = 0.2):
     lam = np.asarray(sigma, dtype=np.float64) ** 2
     t, r = rule_indices(l, variant, alpha)
     delta = lam[t - 1]
+    if variant == SSD:
+        lam_new = lam.copy()
+        if lam[l - 1] <= NULL_REL * lam[0]:
+            return np.sqrt(lam_new), 0.0           # a free direction: nothing to move
+        delta = lam[l - 2]
+        lam_new[l - 2] = 0.0
+        lam_new[l - 1] = lam[l - 1] + delta
+        return np.sqrt(lam_new), float(delta)
     if variant == ISVD:
         lam_new = lam.copy()
         lam_new[l - 1:] = 0.0
@@ -108,6 +136,8 @@ class SketchOracle:
         self.m = 2 * l if m is None else int(m)
         if self.m < l:
             raise ValueError("buffer must have at least l rows")
+        if variant == SSD and (self.m != l or l < 2):
+            raise ValueError("SSD runs on an l-row buffer with l >= 2")
         self.t, self.r = rule_indices(l, variant, alpha)
         self.C = np.zeros((self.m, d))
         self.occ = 0
@@ -116,6 +146,8 @@ class SketchOracle:
         self.Stot = 0.0       # total squared mass removed by the rules
         self.n_rows = 0
         self.n_rr = 0
+        self._last = None         # (lambda, lambda', V^T) of the latest ReduceRank
+        self._since = 0           # rows appended since it
 
     def _reduce(self):
         _, sig, vt = np.linalg.svd(self.C[:self.occ], full_matrices=False)
@@ -124,13 +156,18 @@ class SketchOracle:
         sig_new, delta = reduce_rank(sig_full, self.l, self.variant, self.alpha)
         keep = self.t - 1
         C = np.zeros_like(self.C)
-        kk = min(keep, vt.shape[0])
-        C[:kk] = sig_new[:kk, None] * vt[:kk]
+        rows = list(range(keep))
+        if self.variant == SSD and delta > 0.0:
+            rows[self.l - 2] = self.l - 1           # the merged direction takes the freed slot
+        for q, j in enumerate(rows):
+            if j < vt.shape[0]:
+                C[q] = sig_new[j] * vt[j]
         self.Stot += float(np.sum(sig_full ** 2 - sig_new ** 2))
         self.Delta += delta
         self.n_rr += 1
         self.C = C
         self.occ = keep
+        self._last = (sig_full ** 2, sig_new ** 2, vt)   # for Compensative FD's last step
 
     def append(self, rows: np.ndarray):
         rows = np.atleast_2d(np.asarray(rows, dtype=np.float64))
@@ -142,14 +179,51 @@ class SketchOracle:
             self.fro2A += float(np.sum(block * block))
             self.occ += f
             self.n_rows += f
+            self._since += f
             i += f
             if self.occ == self.m:
                 self._reduce()
+                self._since = 0
 
     def finalize(self) -> np.ndarray:
+        if self.variant == CFD:
+            return self._finalize_cfd()
         if self.occ > self.l:
             self._reduce()
         return self.C[:self.l].copy()
+
+    def _finalize_cfd(self) -> np.ndarray:
+        """Compensative FD's last step: B = S' V^T of the latest reduction with
+        sigma_hat_j = sqrt(sigma'_j^2 + Delta) for the l output rows (Delta the
+        total subtracted).  When rows arrived after the latest reduction (or
+        none ran), the buffer's own SVD is that S' V^T, after one more FD
+        reduction if more than l rows are occupied."""
+        l = self.l
+        if self._last is not None and self._since == 0:
+            lam, lam_new, vt = self._last
+            kept = float(np.sum(lam_new))               # mass the buffer holds now
+        else:
+            _, sig, vt = np.linalg.svd(self.C[:self.occ], full_matrices=False)
+            lam = np.zeros(max(self.m, l))
+            lam[:sig.size] = sig ** 2
+            lam_new = lam.copy()
+            kept = float(np.sum(lam))
+            if self.occ > l:
+                delta = lam[l - 1]
+                lam_new = np.maximum(lam - delta, 0.0)
+                self.Delta += delta
+                self.n_rr += 1
+        out = np.zeros((l, self.d))
+        written = 0.0
+        for j in range(min(l, vt.shape[0])):
+            if lam[j] > NULL_REL * lam[0]:
+                out[j] = np.sqrt(lam_new[j] + self.Delta) * vt[j]
+                written += lam_new[j] + self.Delta
+        self.Stot += kept - written
+        self.C = np.zeros_like(self.C)
+        self.C[:l] = out
+        self.occ = l
+        return out.copy()
 
     def stats(self) -> dict:
         return dict(fro2A=self.fro2A, Delta=self.Delta, Stot=self.Stot,
@@ -227,6 +301,10 @@ def counter_simulation(j: np.ndarray, c: np.ndarray, d: int, l: int,
     Returns the diagonal of B^T B.
     """
     mm = 2 * l if m is None else m
+    if variant == SSD:
+        return _counter_ssd(j, c, d, l)
+    if variant == CFD:
+        return _counter_cfd(j, c, d, l, mm)
     counters = np.zeros(d)
     pending = np.zeros(d)
     occ = 0
@@ -266,3 +344,71 @@ def counter_simulation(j: np.ndarray, c: np.ndarray, d: int, l: int,
     else:
         counters = counters + pending
     return counters
+
+
+def _counter_ssd(j, c, d, l):
+    """SpaceSaving on squared-weight counters (l-row buffer): after l rows, the
+    two smallest of the l largest totals merge -- the second smallest is
+    emptied into the smallest -- unless the smallest is empty."""
+    counters = np.zeros(d)
+    occ = 0
+    for jj, cc in zip(j, c):
+        counters[jj] += cc * cc
+        occ += 1
+        if occ == l:
+            order = np.argsort(-counters, kind="stable")
+            top = counters[order[0]]
+            a, b = order[l - 2], order[l - 1]        # ranks l-1 and l (1-based)
+            if counters[b] > NULL_REL * top:
+                counters[b] += counters[a]
+                counters[a] = 0.0
+            else:
+                counters[b] = 0.0
+            occ = l - 1
+    return counters
+
+
+def _counter_cfd(j, c, d, l, mm):
+    """Compensative FD on counters: the FD simulation, then Delta added to each
+    of the (at most l) largest non-empty totals at the end."""
+    counters = np.zeros(d)
+    pending = np.zeros(d)
+    occ, Delta = 0, 0.0
+
+    def ranked_cut(totals):
+        r = np.sort(totals)[::-1]
+        r = np.concatenate([r, np.zeros(max(0, mm - r.size))])
+        return r[l - 1]
+
+    last = None
+    since = 0
+    for jj, cc in zip(j, c):
+        pending[jj] += cc * cc
+        occ += 1
+        since += 1
+        if occ == mm:
+            totals = counters + pending
+            cut = ranked_cut(totals)
+            counters = np.maximum(totals - cut, 0.0)
+            Delta += cut
+            last = (totals, counters.copy())
+            pending[:] = 0.0
+            occ = l - 1
+            since = 0
+    if last is not None and since == 0:
+        totals, shrunk = last
+    else:
+        totals = counters + pending
+        if occ > l:
+            cut = ranked_cut(totals)
+            shrunk = np.maximum(totals - cut, 0.0)
+            Delta += cut
+        else:
+            shrunk = totals
+    order = np.argsort(-totals, kind="stable")
+    out = np.zeros(d)
+    top = totals[order[0]] if d else 0.0
+    for idx in order[:l]:
+        if totals[idx] > NULL_REL * top:
+            out[idx] = shrunk[idx] + Delta
+    return out

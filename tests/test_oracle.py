@@ -274,3 +274,84 @@ def test_adversarial_stream_defeats_isvd_only():
     assert err[ALPHA, 30] <= err[ISVD, 30] / 5
     assert err[ALPHA, 30] <= err[ALPHA, 10] / 5
     assert gold["isvd_err_l100"] >= 0.5 * gold["isvd_err_l20"]
+
+
+# ------------------------------------------- SpaceSaving and Compensative FD
+# Section 3.1: Algorithm 3 (SSD) on the l-row buffer, and Compensative FD.
+from oracle import SSD, CFD  # noqa: E402
+
+
+@pytest.mark.parametrize("variant,mult", [(SSD, 1), (CFD, 1), (CFD, 2)])
+@pytest.mark.parametrize("l", [4, 7])
+def test_ssd_cfd_basis_rows_match_counters(variant, mult, l):
+    """Rows c*e_j: the SVD route's B^T B is diagonal and equals an independent
+    counter simulation (SpaceSaving merge of the two smallest counters; FD
+    counters with Delta added back to the l largest at the end)."""
+    d = 30
+    A, j, c = synth.basis_rows(900, d, seed=(71, l, mult))
+    B = oracle.fd_sketch(A, l, variant, m=mult * l)
+    G = B.T @ B
+    counters = oracle.counter_simulation(j, c, d, l, variant, m=mult * l)
+    tol = 1e-9 * oracle.fro2(A)
+    assert np.max(np.abs(G - np.diag(np.diag(G)))) <= tol
+    assert np.max(np.abs(np.diag(G) - counters)) <= tol
+
+
+def test_spacesaving_counters_textbook():
+    """The SSD counter rule on unit weights is the SpaceSaving summary when
+    every new item is lighter than all monitored ones: the new item takes
+    over the lightest counter and adds its count."""
+    l = 4
+    counters = oracle.counter_simulation(np.array([0, 0, 0, 1, 1, 2, 3]), np.ones(7), 5, l, SSD)
+    # rows 0,0,0,1 fill the buffer: counts {0:3, 1:1} + zeros -> rank 4 empty, nothing moves
+    # row 1 -> {0:3, 1:2}; row 2 -> {0:3, 1:2, 2:1}; row 3 fills the l-th slot:
+    # {0:3, 1:2, 2:1, 3:1} -> the 2nd smallest (item 2) is emptied into item 3.
+    assert np.allclose(counters, [3, 2, 0, 2, 0])
+
+
+@pytest.mark.parametrize("l", [6, 11])
+def test_ssd_theorem_bounds(l):
+    """Theorem of Section 3.1 for SSD: ||A||_F^2 = ||B||_F^2; for k < (l-1)/2
+    every direction's error is at most ||A - A_k||_F^2 / ((l-1)/2 - k); for
+    k < l/2 - 1 the rank-k projection error is within (l-1)/(l-1-2k)."""
+    A = synth.random_noisy(700, 40, 6, 4.0, seed=(72, l))
+    B, st = oracle.fd_sketch(A, l, SSD, m=l, return_state=True)
+    fa = oracle.fro2(A)
+    assert abs(fa - oracle.fro2(B)) <= 1e-10 * fa
+    assert abs(st.Stot) <= 1e-10 * fa
+    w = np.linalg.eigvalsh(A.T @ A - B.T @ B)
+    err = max(abs(w[0]), abs(w[-1]))
+    for k in range(int(math.ceil((l - 1) / 2)) ):
+        if k < (l - 1) / 2:
+            assert err <= oracle.tail_mass(A, k) / ((l - 1) / 2 - k) * (1 + 1e-9)
+    for k in range(1, l):
+        if k < l / 2 - 1:
+            assert oracle.proj_err(A, B, k) <= (l - 1) / (l - 1 - 2 * k) * (1 + 1e-9)
+
+
+@pytest.mark.parametrize("mult", [1, 2])
+def test_cfd_bounds_and_mass(mult):
+    """Compensative FD (Section 3.1): every direction's error at most Delta,
+    Delta <= ||A - A_k||_F^2 / (l - k), the projection bound l / (l - k); with
+    the l-row buffer of the paper also ||A||_F^2 = ||B||_F^2."""
+    l = 8
+    A = synth.random_noisy(800, 50, 6, 4.0, seed=(73, mult))
+    B, st = oracle.fd_sketch(A, l, CFD, m=mult * l, return_state=True)
+    fa = oracle.fro2(A)
+    w = np.linalg.eigvalsh(A.T @ A - B.T @ B)
+    assert max(abs(w[0]), abs(w[-1])) <= st.Delta * (1 + 1e-9)
+    for k in range(l):
+        assert st.Delta <= oracle.tail_mass(A, k) / (l - k) * (1 + 1e-9)
+        if k >= 1:
+            assert oracle.proj_err(A, B, k) <= l / (l - k) * (1 + 1e-9)
+    assert abs(fa - oracle.fro2(B) - st.Stot) <= 1e-10 * fa
+    if mult == 1:
+        assert abs(fa - oracle.fro2(B)) <= 1e-10 * fa
+
+
+@pytest.mark.parametrize("variant,m", [(SSD, 9), (CFD, 18)])
+def test_ssd_cfd_short_stream_exact(variant, m):
+    """Fewer rows than the buffer: SSD returns A, CFD its SVD form (Delta = 0)."""
+    A = synth.random_noisy(7, 20, 3, seed=(74, m))
+    B = oracle.fd_sketch(A, 9, variant, m=m)
+    assert np.allclose(B.T @ B, A.T @ A, atol=1e-10 * oracle.fro2(A))
