@@ -19,8 +19,23 @@
  *   FDSK_FAST_ALPHA  Section 3.1, fast parameterized FD: delta = sigma_t^2 with
  *                    t = r + ceil(s/2), s = ceil(alpha*l), r = l - s; the
  *                    trailing s values are shrunk, clamped at zero.
+ *   FDSK_SSD         SpaceSaving Directions (Section 3.1, Algorithm 3):
+ *                    delta = sigma_{l-1}^2, sigma_{l-1} becomes 0 and sigma_l
+ *                    becomes sqrt(sigma_l^2 + delta); the rest untouched.  Needs
+ *                    buffer_rows == l and l >= 2 (the rule returns l values).
+ *                    When sigma_l^2 <= 1e-12 sigma_1^2 (a direction outside
+ *                    the buffer's row space) nothing moves and delta = 0.
+ *   FDSK_CFD         Compensative FD (Section 3.1): FD during the stream; at
+ *                    finalize B = S^ V^T of the latest reduction, with
+ *                    sigma^_j^2 = sigma'_j^2 + Delta (Delta = sum of every
+ *                    delta) on the first l directions (rows l..: none); a
+ *                    direction with sigma_j^2 <= 1e-12 sigma_1^2 stays zero.
+ *                    When rows arrived after the latest reduction, the
+ *                    buffer's own factorization (after one more FD reduction
+ *                    if more than l rows are occupied) is compensated.
  * Shrunk values are clamped at 0; after a reduction the first t-1 rows are
- * kept (t = l except for the fast variant) and the next rows go after them.
+ * kept (t = l except for the fast variant) and the next rows go after them;
+ * SSD's merged direction is kept in row l-1 (1-based).
  *
  * Conventions for every entry point:
  *  - Return 0 on success or a negative FDSK_E* code.  Errors are sticky per
@@ -47,7 +62,14 @@ extern "C" {
 
 typedef struct fdsk_sketch fdsk_sketch;           /* opaque */
 
-typedef enum { FDSK_FD = 0, FDSK_ISVD = 1, FDSK_ALPHA = 2, FDSK_FAST_ALPHA = 3 } fdsk_variant;
+typedef enum {
+  FDSK_FD = 0,
+  FDSK_ISVD = 1,
+  FDSK_ALPHA = 2,
+  FDSK_FAST_ALPHA = 3,
+  FDSK_SSD = 4,
+  FDSK_CFD = 5
+} fdsk_variant;
 typedef enum { FDSK_F64 = 0, FDSK_F32 = 1, FDSK_BF16 = 2 } fdsk_dtype;  /* BF16 = raw uint16 bits */
 /* Arithmetic of the Gram and rebuild products.  The eigensolver, the shrink
  * subtraction and every accumulator are FP64 in all modes; the buffer stays
@@ -116,7 +138,8 @@ int sketch_create(const fdsk_config* cfg, void* hip_stream, fdsk_sketch** out);
 int sketch_append_rows(fdsk_sketch* s, const void* rows, int64_t n_rows, int64_t row_stride,
                        fdsk_dtype dtype, fdsk_mem mem);
 
-/* Finish the stream: if more than l rows are occupied, one more ReduceRank;
+/* Finish the stream: if more than l rows are occupied, one more ReduceRank
+ * (FDSK_CFD: then its compensation, see the rules above, *rows_out = l);
  * then write the l x d sketch B (rows beyond *rows_out are zero) to B_out
  * (leading dimension ldb >= d, dtype FDSK_F64 or FDSK_F32).  Synchronises the
  * stream and reports sticky device errors.  Afterwards only sketch_stats,
@@ -198,7 +221,8 @@ int fdsk_eigh(const double* G, int32_t m, int64_t ldg, double* lam, double* V, i
  * Many independent sketches advanced together (Algorithm 1 for each).
  *
  * The batch owns S sketches, each with its own configuration (buffer rows
- * m <= 256; any precision; the eigensolver is the tridiagonal route).  Because the schedule of Algorithm 1 does not
+ * m <= 256; variants FD, iSVD, alpha and fast alpha; FP64, BF16 or BF16x3; the
+ * eigensolver is the tridiagonal route).  Because the schedule of Algorithm 1 does not
  * depend on the data, an append call first lays out, on the host, every
  * sketch's ingests and ReduceRanks for the call; round r then holds at most
  * one ingest and one ReduceRank per sketch, and each stage of a round (ingest,

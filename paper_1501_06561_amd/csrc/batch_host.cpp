@@ -76,6 +76,7 @@ RuleParams rule_for(const fdsk_config& c) {
     case FDSK_ISVD: rp.t = c.l; rp.r = c.l - 1; break;
     case FDSK_ALPHA: rp.t = c.l; rp.r = r; break;
     case FDSK_FAST_ALPHA: rp.t = r + (s + 1) / 2; rp.r = r; break;
+    default: rp.t = c.l; rp.r = 0; break;   // SSD / CFD: refused by sketch_batch_create
   }
   rp.keep = rp.t - 1;
   return rp;
@@ -181,6 +182,8 @@ int sketch_batch_create(int32_t S, const fdsk_config* cfgs, void* hip_stream, fd
       return berr(nullptr, FDSK_EINVAL, "sketch %d: bad sizes", i);
     if (m > kTridGlobalMax)
       return berr(nullptr, FDSK_EUNSUPPORTED, "sketch %d: buffer rows %d > %d", i, m, kTridGlobalMax);
+    if (c.variant == FDSK_SSD || c.variant == FDSK_CFD)
+      return berr(nullptr, FDSK_EUNSUPPORTED, "SSD and CFD run on single sketches only");
     if (c.variant < FDSK_FD || c.variant > FDSK_FAST_ALPHA) return berr(nullptr, FDSK_EINVAL, "bad variant");
     if ((c.variant == FDSK_ALPHA || c.variant == FDSK_FAST_ALPHA) && !(c.alpha > 0.0 && c.alpha <= 1.0))
       return berr(nullptr, FDSK_EINVAL, "sketch %d: alpha must lie in (0, 1]", i);

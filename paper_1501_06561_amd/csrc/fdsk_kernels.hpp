@@ -21,14 +21,27 @@ struct DevStats {
 };
 
 // ReduceRank rule: delta = lambda_t (1-based t); indices < r are untouched;
-// variant 1 (iSVD) keeps the first l-1 and zeroes the rest; keep = t-1 rows survive.
+// variant 1 (iSVD) keeps the first l-1 and zeroes the rest; variant 4
+// (SpaceSaving Directions) moves lambda_{l-1} onto the l-th direction;
+// keep = t-1 rows survive.
+//
+// comp != 0 turns the stage into Compensative FD's last step (Section 3.1):
+// every one of the first l squared values is raised by the accumulated Delta
+// and keep = l rows are written; comp = 1 applies the FD rule first (the
+// reduction just run is re-evaluated from the same spectrum), comp = 2 takes
+// the spectrum as it is.  Only the shrink total and fro2A are updated.
 struct RuleParams {
   int variant;
   int l;
   int t;
   int r;
   int keep;
+  int comp;
 };
+
+// Squared singular values at or below this fraction of the largest are
+// treated as directions outside the buffer's row space.
+constexpr double kNullRel = 1e-12;
 
 hipError_t launch_ingest(const void* src, int dt, int64_t stride, int f, int d, double* C, int ldc,
                          int row0, double* rownorm, hipStream_t s);

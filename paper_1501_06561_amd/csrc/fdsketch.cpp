@@ -105,6 +105,8 @@ RuleParams make_rule(const fdsk_config& c) {
     case FDSK_ISVD: rp.t = c.l; rp.r = c.l - 1; break;
     case FDSK_ALPHA: rp.t = c.l; rp.r = r; break;
     case FDSK_FAST_ALPHA: rp.t = r + (s + 1) / 2; rp.r = r; break;
+    case FDSK_SSD: rp.t = c.l; rp.r = 0; break;
+    case FDSK_CFD: rp.t = c.l; rp.r = 0; break;
   }
   rp.keep = rp.t - 1;
   return rp;
@@ -133,7 +135,8 @@ void add_mark(fdsk_sketch* s, int stage, hipEvent_t a, hipEvent_t b) {
   if (a && b) s->marks.push_back({stage, a, b});
 }
 
-int reduce(fdsk_sketch* s) {
+// Gram and eigensolve of the current buffer: lam and V on the device.
+int spectrum(fdsk_sketch* s) {
   EigWork wk{s->W, s->bar, s->rot, s->st, s->S1, s->S2,
              (s->cfg.flags & FDSK_FLAG_EIG_JACOBI) ? EIG_JACOBI : EIG_AUTO};
   hipEvent_t e0 = mark(s);
@@ -160,20 +163,33 @@ int reduce(fdsk_sketch* s) {
     HIPCHK(s, launch_eig(s->G, s->m, s->mp, s->lam, s->V, wk, s->stream));
   }
   hipEvent_t e2 = mark(s);
-  HIPCHK(s, launch_shrink(s->lam, s->V, s->m, s->mp, s->rp, s->rownorm, s->new0, s->occ, s->Ut,
-                          s->st, s->stream));
-  hipEvent_t e3 = mark(s);
-  if (s->cfg.precision == FDSK_P_FP64)
-    HIPCHK(s, launch_rebuild(s->Ut, s->C[s->cur], s->ldc, s->mp, s->rp.keep, s->C[1 - s->cur],
-                             s->stream));
-  else
-    HIPCHK(s, launch_rebuild_lowp(s->Ut, s->C[s->cur], s->ldc, s->mp, s->rp.keep, s->C[1 - s->cur],
-                                  npass, s->stream));
-  hipEvent_t e4 = mark(s);
   add_mark(s, 1, e0, e1);
   add_mark(s, 2, e1, e2);
+  return 0;
+}
+
+// Shrink with rule rp and rebuild rp.keep rows of src into dst.
+int shrink_rebuild(fdsk_sketch* s, const RuleParams& rp, int new0, int new1, const double* src,
+                   double* dst) {
+  const int npass = s->cfg.precision == FDSK_P_BF16 ? 1 : 3;
+  hipEvent_t e2 = mark(s);
+  HIPCHK(s, launch_shrink(s->lam, s->V, s->m, s->mp, rp, s->rownorm, new0, new1, s->Ut, s->st,
+                          s->stream));
+  hipEvent_t e3 = mark(s);
+  if (s->cfg.precision == FDSK_P_FP64)
+    HIPCHK(s, launch_rebuild(s->Ut, src, s->ldc, s->mp, rp.keep, dst, s->stream));
+  else
+    HIPCHK(s, launch_rebuild_lowp(s->Ut, src, s->ldc, s->mp, rp.keep, dst, npass, s->stream));
   add_mark(s, 3, e2, e3);
-  add_mark(s, 4, e3, e4);
+  add_mark(s, 4, e3, mark(s));
+  return 0;
+}
+
+int reduce(fdsk_sketch* s) {
+  int rc = spectrum(s);
+  if (rc) return rc;
+  rc = shrink_rebuild(s, s->rp, s->new0, s->occ, s->C[s->cur], s->C[1 - s->cur]);
+  if (rc) return rc;
   s->cur = 1 - s->cur;
   s->occ = s->rp.keep;
   s->new0 = s->occ;
@@ -198,6 +214,40 @@ int ingest_device(fdsk_sketch* s, const char* src, int64_t n, int64_t stride, fd
       if (rc) return rc;
     }
   }
+  return 0;
+}
+
+// Compensative FD's last step (Section 3.1): B = S^ V^T of the latest
+// reduction with sigma^_j^2 = sigma'_j^2 + Delta on the first l directions.
+// When no row arrived after the latest reduction, its spectrum (lam, V) and the
+// buffer it factored (the other half of the double buffer) are still on the
+// device and the l output rows are rebuilt from them.  Otherwise the current
+// buffer is factored (after one more FD reduction when more than l rows are
+// occupied, which brings back the first case) and compensated as it is.
+int finalize_cfd(fdsk_sketch* s) {
+  if (s->n_rows == 0) return 0;
+  if (s->occ > s->l) {
+    HIPCHK(s, launch_zero_rows(s->C[s->cur], s->ldc, s->occ, s->m, s->stream));
+    int rc = reduce(s);
+    if (rc) return rc;
+  }
+  RuleParams rp = s->rp;
+  rp.keep = s->l;
+  int rc;
+  if (s->n_rr_host > 0 && s->occ == s->new0) {
+    rp.comp = 1;
+    rc = shrink_rebuild(s, rp, s->new0, s->new0, s->C[1 - s->cur], s->C[s->cur]);
+  } else {
+    HIPCHK(s, launch_zero_rows(s->C[s->cur], s->ldc, s->occ, s->m, s->stream));
+    rc = spectrum(s);
+    if (rc) return rc;
+    rp.comp = 2;
+    rc = shrink_rebuild(s, rp, s->new0, s->occ, s->C[s->cur], s->C[1 - s->cur]);
+    s->cur = 1 - s->cur;
+  }
+  if (rc) return rc;
+  s->occ = s->l;
+  s->new0 = s->occ;
   return 0;
 }
 
@@ -233,8 +283,10 @@ int sketch_create(const fdsk_config* cfg, void* hip_stream, fdsk_sketch** out) {
   int m = c.buffer_rows == 0 ? 2 * c.l : c.buffer_rows;
   if (m < c.l) return set_err(nullptr, FDSK_EINVAL, "buffer_rows must be 0 or >= l");
   if (m > 1024) return set_err(nullptr, FDSK_EUNSUPPORTED, "buffer rows %d > 1024", m);
-  if (c.variant < FDSK_FD || c.variant > FDSK_FAST_ALPHA)
+  if (c.variant < FDSK_FD || c.variant > FDSK_CFD)
     return set_err(nullptr, FDSK_EINVAL, "unknown variant");
+  if (c.variant == FDSK_SSD && (m != c.l || c.l < 2))
+    return set_err(nullptr, FDSK_EINVAL, "SSD needs buffer_rows == l and l >= 2");
   if ((c.variant == FDSK_ALPHA || c.variant == FDSK_FAST_ALPHA) && !(c.alpha > 0.0 && c.alpha <= 1.0))
     return set_err(nullptr, FDSK_EINVAL, "alpha must lie in (0, 1]");
   if (c.precision != FDSK_P_FP64 && c.precision != FDSK_P_BF16 && c.precision != FDSK_P_BF16X3 &&
@@ -351,7 +403,10 @@ int sketch_finalize(fdsk_sketch* s, void* B_out, int64_t ldb, fdsk_dtype out_dty
   if (ldb < s->d) return set_err(s, FDSK_EINVAL, "ldb < d");
   if (out_dtype != FDSK_F64 && out_dtype != FDSK_F32)
     return set_err(s, FDSK_EINVAL, "output dtype must be F64 or F32");
-  if (s->occ > s->l) {
+  if (s->cfg.variant == FDSK_CFD) {
+    int rc = finalize_cfd(s);
+    if (rc) return rc;
+  } else if (s->occ > s->l) {
     HIPCHK(s, launch_zero_rows(s->C[s->cur], s->ldc, s->occ, s->m, s->stream));
     int rc = reduce(s);
     if (rc) return rc;

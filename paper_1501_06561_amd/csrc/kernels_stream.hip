@@ -152,21 +152,48 @@ __device__ __forceinline__ void shrink_body(const double* __restrict__ lam_raw,
   __syncthreads();
   for (int q = tid; q < m; q += blockDim.x) lam[q] = fmax(raw[perm[q]], 0.0);
   __syncthreads();
-  const double delta = (rp.t - 1 < m) ? lam[rp.t - 1] : 0.0;
+  double delta = (rp.t - 1 < m) ? lam[rp.t - 1] : 0.0;
+  const double lnull = kNullRel * lam[0];
+  // SpaceSaving Directions: nothing moves when the l-th direction is outside
+  // the row space (then the buffer already has a free row).
+  const bool ssd_move = rp.variant == 4 && lam[rp.l - 1] > lnull;
+  if (rp.variant == 4) delta = ssd_move ? lam[rp.l - 2] : 0.0;
+  // Compensative FD: the accumulated Delta after the latest reduction.
+  const double Dtot = rp.comp ? st->Delta : 0.0;
   double removed = 0.0;
   for (int q = tid; q < m; q += blockDim.x) {
     double x = lam[q];
     double y;
     bool untouched;
-    if (rp.variant == 1) {            // iSVD: keep the first l-1, drop the rest
+    if (rp.comp == 2) {               // the spectrum as it is
+      untouched = false;
+      y = x;
+    } else if (rp.variant == 1) {     // iSVD: keep the first l-1, drop the rest
       untouched = q < rp.l - 1;
       y = untouched ? x : 0.0;
-    } else {                          // FD / alpha / fast alpha: shrink from index r on
+    } else if (rp.variant == 4) {     // SSD: lambda_{l-1} moves onto the l-th direction
+      untouched = !ssd_move || q < rp.l - 2;
+      y = untouched ? x : (q == rp.l - 2 ? 0.0 : x + delta);
+    } else {                          // FD / alpha / fast alpha / CFD: shrink from index r on
       untouched = q < rp.r;
       y = untouched ? x : fmax(x - delta, 0.0);
     }
-    removed += x - y;
-    rho[q] = untouched ? 1.0 : ((x > 0.0 && y > 0.0) ? sqrt(y / x) : 0.0);
+    if (rp.comp) {
+      // Output value y + Delta on the first l directions in the row space;
+      // the shrink total falls by what is added back.
+      double yh = (q < rp.l && x > lnull) ? y + Dtot : 0.0;
+      removed += y - yh;
+      rho[q] = yh > 0.0 ? sqrt(yh / x) : 0.0;
+    } else {
+      removed += x - y;
+      rho[q] = untouched ? 1.0 : ((x > 0.0 && y > 0.0) ? sqrt(y / x) : 0.0);
+    }
+  }
+  // SSD: the merged direction takes the freed slot l-2 of the kept rows.
+  __syncthreads();
+  if (ssd_move && tid == 0) {
+    perm[rp.l - 2] = perm[rp.l - 1];
+    rho[rp.l - 2] = rho[rp.l - 1];
   }
   red[tid] = removed;
   __syncthreads();
@@ -178,9 +205,11 @@ __device__ __forceinline__ void shrink_body(const double* __restrict__ lam_raw,
     double nrm = 0.0;
     for (int i = new0; i < new1; ++i) nrm += rownorm[i];
     st->fro2A += nrm;
-    st->Delta += delta;
     st->Stot += red[0];
-    st->n_rr += 1;
+    if (!rp.comp) {
+      st->Delta += delta;
+      st->n_rr += 1;
+    }
     if (bad || !(nrm == nrm)) st->nonfinite = 1;
   }
   // Ut rows [0, keep) ; rows up to the next multiple of 32 are zero.

@@ -15,7 +15,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libfdsketch.so")
 
-VARIANTS = {"fd": 0, "isvd": 1, "alpha": 2, "fast_alpha": 3}
+VARIANTS = {"fd": 0, "isvd": 1, "alpha": 2, "fast_alpha": 3, "ssd": 4, "cfd": 5}
 PRECISIONS = {"fp64": 0, "bf16": 1, "bf16x3": 2, "fp8x3": 3}
 F64, F32, BF16 = 0, 1, 2
 MEM_HOST, MEM_DEVICE = 0, 1

@@ -33,6 +33,10 @@ def test_library_exports_every_declared_symbol():
     (dict(d=10, l=8, buffer_rows=5), -1),
     (dict(d=10, l=600), -6),                 # 2l > 1024
     (dict(d=10, l=8, variant=7), -1),
+    (dict(d=10, l=8, variant=6), -1),
+    (dict(d=10, l=8, variant=4), -1),                  # SSD needs buffer_rows == l
+    (dict(d=10, l=8, variant=4, buffer_rows=12), -1),
+    (dict(d=10, l=1, variant=4, buffer_rows=1), -1),   # SSD needs l >= 2
     (dict(d=10, l=8, variant=2, alpha=0.0), -1),
     (dict(d=10, l=8, variant=3, alpha=1.5), -1),
     (dict(d=10, l=8, flags=6), -1),
@@ -48,6 +52,27 @@ def test_create_rejects_bad_config(cfg, code):
     assert rc == code
     assert not h.value
     assert F.lib().sketch_last_error(None)
+
+
+@pytest.mark.parametrize("cfg,code", [
+    (dict(variant=4, buffer_rows=8), -6),      # SSD: single sketches only
+    (dict(variant=5), -6),                     # CFD: single sketches only
+    (dict(variant=6), -1),
+    (dict(precision=3), -6),                   # FP8 Gram: single sketches only
+    (dict(l=200), -6),                         # 400 buffer rows > 256
+    (dict(flags=1), -6),
+])
+def test_batch_create_rejects_bad_config(cfg, code):
+    good = F.FdskConfig(64, 8, 0, 0, 0.2, 0, 0)
+    bad = F.FdskConfig(cfg.get("d", 64), cfg.get("l", 8), cfg.get("buffer_rows", 0),
+                       cfg.get("variant", 0), cfg.get("alpha", 0.2), cfg.get("precision", 0),
+                       cfg.get("flags", 0))
+    arr = (F.FdskConfig * 2)(good, bad)
+    h = ctypes.c_void_p()
+    rc = F.lib().sketch_batch_create(2, arr, None, ctypes.byref(h))
+    assert rc == code
+    assert not h.value
+    assert F.lib().sketch_batch_last_error(None)
 
 
 def test_null_handles_are_rejected():
