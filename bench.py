@@ -44,7 +44,14 @@ STAGE_SOURCES = {
 }
 KERNELS = {"eig": "k_eig_lds/k_eig_blk (Jacobi)", "gram": "k_gram_f64+k_gram_reduce",
            "rebuild": "k_rebuild_f64", "shrink": "k_shrink", "ingest": "k_ingest",
-           "tridiag": "k_tridiag", "dc": "k_dc", "backtr": "k_backtr"}
+           "tridiag": "k_tridiag_reg (m <= 208) / k_tridiag", "dc": "k_dc", "backtr": "k_backtr"}
+
+
+def kernel_name(stage, m):
+    """The kernel a stage runs at buffer size m."""
+    if stage == "tridiag":
+        return "k_tridiag_reg" if m <= 208 else "k_tridiag"
+    return KERNELS[stage]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_random_noisy_100k_x1000.json")
 
 
@@ -252,7 +259,7 @@ def main():
                 "unit": "TFLOP/s"}
     roof["frac"] = roof["achieved"] / roof["peak"]
     roof["traffic"] = measured_traffic(dom, l, args.variant)
-    roof["kernel"] = KERNELS[dom]
+    roof["kernel"] = kernel_name(dom, m)
     roof["stage"] = dom
     roof["avg_launch_us"] = avg_s * 1e6
     roof["work_per_launch"] = work

@@ -57,6 +57,16 @@ __device__ __forceinline__ double quad_prod(double v) {
   return v;
 }
 
+// Sum over each row of 16 lanes, returned in every lane of the row (a
+// butterfly: each step adds the same two operands on both partners, so the
+// 16 results are bitwise equal).
+__device__ __forceinline__ double row16_sum(double v) {
+  v = quad_sum(v);
+  v += dpp_f64<0x141>(v, 0.0);          // row_half_mirror
+  v += dpp_f64<0x140>(v, 0.0);          // row_mirror
+  return v;
+}
+
 // Wave-wide (64 lanes, all active) sum, returned in every lane: quad
 // butterflies and row mirrors give each row of 16 its total, two row
 // broadcasts accumulate the rows into lane 63, which is read back.

@@ -3,9 +3,10 @@
 // The m x m Gram matrix G of a ReduceRank (m <= kTridGlobalMax) goes through
 // three kernels, all in FP64 and all in stream order:
 //
-// * k_tridiag: Householder reduction Q^T G Q = T (T tridiagonal) in one
-//   workgroup, the lower triangle of G packed by columns in LDS (m <=
-//   kTridMax) or, above that, in the workspace W itself (L2-resident).  Reflector
+// * k_tridiag_reg / k_tridiag: Householder reduction Q^T G Q = T (T
+//   tridiagonal) in one workgroup, the matrix held in registers across the
+//   workgroup (m <= kTridRegMax) or, above that, its lower triangle packed by
+//   columns in the workspace W itself (L2-resident).  Reflector
 //   H_k = I - tau_k u_k u_k^T with u_k = (0,..,0, 1, v_k) zeroes column k below
 //   the subdiagonal; the trailing block is updated by the symmetric rank-2
 //   form A <- A - v w^T - w v^T, w = p - (tau/2)(p.v) v, p = tau A v.
@@ -51,12 +52,10 @@ __device__ __forceinline__ double wave_max(double v) {
 // Output in W (doubles): [0, P) packed columns (column k holds v_k below the
 // subdiagonal, P = n(n+1)/2), then tau[n], d[n], e[n], scale.  d and e are of
 // G * 2^-s (an exact power-of-two scaling by the largest |g|); scale = 2^s.
-template <bool GA>
 __device__ __forceinline__ void tridiag_body(const double* __restrict__ G, int n, int ldg,
                                              double* __restrict__ W) {
-  __shared__ double A_lds[GA ? 1 : TRI_PACK];
   __shared__ double p[kTridGlobalMax];
-  double* const A = GA ? W : A_lds;
+  double* const A = W;
   __shared__ double red[16];
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int P = n * (n + 1) / 2;
@@ -173,14 +172,243 @@ __device__ __forceinline__ void tridiag_body(const double* __restrict__ G, int n
     eG[n - 1] = 0.0;
     W[P + 3 * n] = ldexp(1.0, sexp);
   }
-  if (!GA)
-    for (int e = tid; e < P; e += TNT) W[e] = A[e];
 }
 
-template <bool GA>
 __global__ __launch_bounds__(TNT) void k_tridiag(const double* __restrict__ G, int n, int ldg,
                                                  double* __restrict__ W) {
-  tridiag_body<GA>(G, n, ldg, W);
+  tridiag_body(G, n, ldg, W);
+}
+
+// ------------------------------------------------- reduce, in registers
+// The same reduction with the matrix held in registers (n <= 32*RP and
+// n <= 16*CP).  512 threads; thread (ti, tk) with ti = 4*wave + lane/16 in
+// [0, 32) and tk = lane%16 keeps A(ti + 32a, tk + 16b), a < RP, b < CP, of
+// the full symmetric matrix.  Per column k:
+//  * every wave forms the reflector from column k (in LDS) itself, in the
+//    same order, so all waves hold bitwise-equal tau and scale;
+//  * p = tau A v: each thread sums its own columns, the 16 lanes of a row
+//    group finish the row by a DPP butterfly, and one lane stores p_i;
+//  * every wave forms c = (tau/2) p.v, then each thread applies
+//    A -= v w^T + w v^T to its own elements, w = p - c v, with no LDS
+//    traffic for A; the owners of column k+1 store it for the next step.
+// Two barriers per column.  Slots whose rows (per wave) or columns (for all
+// lanes) lie entirely in the finished part are skipped; v and w are zero
+// outside the trailing block, so partially finished slots need no masking.
+constexpr int RNT = 512;
+constexpr int kTridRegMax = 208;   // 32 * 7 rows, 16 * 13 columns
+
+template <int RP, int CP>
+__device__ __forceinline__ void tridiag_reg_body(const double* __restrict__ G, int n, int ldg,
+                                                 double* __restrict__ W) {
+  constexpr int NB = (32 * RP > 16 * CP) ? 32 * RP : 16 * CP;
+  constexpr int NL = (NB + 63) / 64;    // strided entries per lane
+  __shared__ double colb[2][64 * NL];
+  __shared__ double pv[64 * NL];
+  __shared__ double vwave[RNT / 64][64 * NL];   // each wave's copy of v
+  __shared__ double red[RNT / 64];
+  // The wave index is made a scalar so that the slot tests below are
+  // uniform branches.
+  const int tid = threadIdx.x, lane = tid & 63, wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int ti = 4 * wv + (lane >> 4), tk = lane & 15;
+  for (int e = tid; e < 64 * NL; e += RNT) {
+    colb[0][e] = 0.0;
+    colb[1][e] = 0.0;
+    pv[e] = 0.0;
+  }
+  double A[RP][CP];
+  double amax = 0.0;
+#pragma unroll
+  for (int a = 0; a < RP; ++a) {
+    const int i = ti + 32 * a;
+#pragma unroll
+    for (int b = 0; b < CP; ++b) {
+      const int k = tk + 16 * b;
+      double g = 0.0;
+      if (i < n && k < n)
+        g = (i >= k) ? G[static_cast<int64_t>(i) * ldg + k] : G[static_cast<int64_t>(k) * ldg + i];
+      A[a][b] = g;
+      amax = fmax(amax, fabs(g));
+    }
+  }
+  amax = wave_max(amax);
+  if (lane == 0) red[wv] = amax;
+  __syncthreads();
+  double gmax = 0.0;
+  for (int i = 0; i < RNT / 64; ++i) gmax = fmax(gmax, red[i]);
+  const int sexp = (gmax > 0.0 && gmax < INFINITY) ? ilogb(gmax) : 0;
+  const double sc = ldexp(1.0, -sexp);
+#pragma unroll
+  for (int a = 0; a < RP; ++a)
+#pragma unroll
+    for (int b = 0; b < CP; ++b) A[a][b] *= sc;
+  if (tk == 0) {
+#pragma unroll
+    for (int a = 0; a < RP; ++a) {
+      const int i = ti + 32 * a;
+      if (i < n) colb[0][i] = A[a][0];
+    }
+  }
+  __syncthreads();
+  const int P = n * (n + 1) / 2;
+  double* tauG = W + P;
+  double* dG = tauG + n;
+  double* eG = dG + n;
+  // Column slots b < bend hold a column < n.
+  const int bend = (n + 15) >> 4;
+  double* const vv = vwave[wv];
+  for (int k = 0; k + 2 < n; ++k) {
+    const double* cb = colb[k & 1];
+    double* nb = colb[(k + 1) & 1];
+    const int k1 = k + 1, b1 = k1 >> 4, tk1 = k1 & 15;
+    // Column slots b >= b0 hold a column > k.  Every row slot is processed
+    // (a per-slot row test would become a select per element).
+    const int b0 = k1 >> 4;
+    double xs[NL];
+#pragma unroll
+    for (int q = 0; q < NL; ++q) xs[q] = cb[lane + 64 * q];
+    const double alpha = cb[k1];
+    double s2 = 0.0;
+#pragma unroll
+    for (int q = 0; q < NL; ++q) {
+      const double x = (lane + 64 * q >= k + 2) ? xs[q] : 0.0;
+      s2 = fma(x, x, s2);
+    }
+    s2 = wave_sum(s2);
+    double tau = 0.0, beta = alpha, scale = 0.0;
+    if (s2 > 0.0) {
+      const double mu = sqrt(alpha * alpha + s2);
+      beta = (alpha >= 0.0) ? -mu : mu;
+      tau = (beta - alpha) / beta;
+      scale = 1.0 / (alpha - beta);
+    }
+    // This wave's copy of v: 0 up to k, 1 at k+1, x*scale below (0 beyond n,
+    // where x = 0).  LDS operations of one wave complete in order, so the
+    // wave reads its copy back after a wave barrier only (which keeps the
+    // compiler from moving the reads above the writes).
+#pragma unroll
+    for (int q = 0; q < NL; ++q) {
+      const int t = lane + 64 * q;
+      vv[t] = (t > k1) ? xs[q] * scale : ((t == k1) ? 1.0 : 0.0);
+    }
+    __builtin_amdgcn_wave_barrier();
+    if (wv == 0) {
+      const int ck = colstart(k, n);
+#pragma unroll
+      for (int q = 0; q < NL; ++q) {
+        const int t = lane + 64 * q;
+        if (t >= k + 2 && t < n) W[ck + t - k] = xs[q] * scale;
+      }
+      if (lane == 0) {
+        W[ck] = cb[k];
+        W[ck + 1] = 1.0;
+        tauG[k] = tau;
+        dG[k] = cb[k];
+        eG[k] = beta;
+      }
+    }
+    if (tau != 0.0) {                  // the same in every wave
+      // p = tau A v over the trailing block (v is zero on finished columns).
+      // Elements of finished rows and columns are updated below with
+      // meaningless values; they are never read again, as every later v is
+      // zero there.  The next slot's v is fetched before this slot's FMAs.
+      double sp[RP];
+#pragma unroll
+      for (int a = 0; a < RP; ++a) sp[a] = 0.0;
+      double nvk = vv[tk + 16 * b0];
+#pragma unroll
+      for (int b = 0; b < CP; ++b) {
+        if (b >= b0 && b < bend) {
+          const double vk = nvk;
+          if (b + 1 < CP) nvk = vv[tk + 16 * (b + 1)];
+#pragma unroll
+          for (int a = 0; a < RP; ++a) sp[a] = fma(A[a][b], vk, sp[a]);
+        }
+      }
+#pragma unroll
+      for (int a = 0; a < RP; ++a) {
+        const double t = row16_sum(sp[a]);
+        const int i = ti + 32 * a;
+        if (tk == 0 && i > k && i < n) pv[i] = tau * t;
+      }
+      __syncthreads();
+      // c = (tau/2) p.v (v is zero up to k; p is zero beyond n).
+      double dot = 0.0;
+#pragma unroll
+      for (int q = 0; q < NL; ++q) dot = fma(pv[lane + 64 * q], vv[lane + 64 * q], dot);
+      dot = wave_sum(dot);
+      const double c = 0.5 * tau * dot;
+      // A -= v w^T + w v^T with w = p - c v.
+      double vr[RP], wr[RP];
+#pragma unroll
+      for (int a = 0; a < RP; ++a) {
+        vr[a] = vv[ti + 32 * a];
+        wr[a] = pv[ti + 32 * a];
+      }
+#pragma unroll
+      for (int a = 0; a < RP; ++a) wr[a] = fma(-c, vr[a], wr[a]);
+      double nv = vv[tk + 16 * b0], np = pv[tk + 16 * b0];
+#pragma unroll
+      for (int b = 0; b < CP; ++b) {
+        if (b >= b0 && b < bend) {
+          const double vk = nv;
+          const double wk = fma(-c, vk, np);
+          if (b + 1 < CP) {
+            nv = vv[tk + 16 * (b + 1)];
+            np = pv[tk + 16 * (b + 1)];
+          }
+#pragma unroll
+          for (int a = 0; a < RP; ++a) A[a][b] = fma(-vr[a], wk, fma(-wr[a], vk, A[a][b]));
+          if (b == b1 && tk == tk1) {
+#pragma unroll
+            for (int a = 0; a < RP; ++a) {
+              const int i = ti + 32 * a;
+              if (i >= k1 && i < n) nb[i] = A[a][b];
+            }
+          }
+        }
+      }
+    } else {
+#pragma unroll
+      for (int b = 0; b < CP; ++b) {
+        if (b == b1 && tk == tk1) {
+#pragma unroll
+          for (int a = 0; a < RP; ++a) {
+            const int i = ti + 32 * a;
+            if (i >= k1 && i < n) nb[i] = A[a][b];
+          }
+        }
+      }
+    }
+    __syncthreads();
+  }
+  // Column n-2 is in colb[(n-2) & 1] (n >= 2); A(n-1, n-1) is with its owner.
+  if (tid == 0) {
+    if (n >= 2) {
+      const double* cb = colb[(n - 2) & 1];
+      dG[n - 2] = cb[n - 2];
+      eG[n - 2] = cb[n - 1];
+      tauG[n - 2] = 0.0;
+      W[colstart(n - 2, n)] = cb[n - 2];
+      W[colstart(n - 2, n) + 1] = cb[n - 1];
+    }
+    tauG[n - 1] = 0.0;
+    eG[n - 1] = 0.0;
+    W[P + 3 * n] = ldexp(1.0, sexp);
+  }
+#pragma unroll
+  for (int a = 0; a < RP; ++a)
+#pragma unroll
+    for (int b = 0; b < CP; ++b)
+      if (ti + 32 * a == n - 1 && tk + 16 * b == n - 1) {
+        dG[n - 1] = A[a][b];
+        W[colstart(n - 1, n)] = A[a][b];
+      }
+}
+
+template <int RP, int CP>
+__global__ __launch_bounds__(RNT) void k_tridiag_reg(const double* __restrict__ G, int n, int ldg,
+                                                     double* __restrict__ W) {
+  tridiag_reg_body<RP, CP>(G, n, ldg, W);
 }
 
 // ------------------------------------------------------ divide and conquer
@@ -687,10 +915,14 @@ __global__ __launch_bounds__(TNT) void k_backtr(const double* __restrict__ W, in
 
 hipError_t launch_tridiag(const double* G, int m, int mp, EigWork wk, hipStream_t s) {
   if (m < 1 || m > kTridGlobalMax || mp < m) return hipErrorInvalidValue;
-  if (m <= kTridMax)
-    hipLaunchKernelGGL(k_tridiag<false>, dim3(1), dim3(TNT), 0, s, G, m, mp, wk.W);
+  if (m <= 64)
+    hipLaunchKernelGGL((k_tridiag_reg<2, 4>), dim3(1), dim3(RNT), 0, s, G, m, mp, wk.W);
+  else if (m <= 128)
+    hipLaunchKernelGGL((k_tridiag_reg<4, 8>), dim3(1), dim3(RNT), 0, s, G, m, mp, wk.W);
+  else if (m <= kTridRegMax)
+    hipLaunchKernelGGL((k_tridiag_reg<7, 13>), dim3(1), dim3(RNT), 0, s, G, m, mp, wk.W);
   else
-    hipLaunchKernelGGL(k_tridiag<true>, dim3(1), dim3(TNT), 0, s, G, m, mp, wk.W);
+    hipLaunchKernelGGL(k_tridiag, dim3(1), dim3(TNT), 0, s, G, m, mp, wk.W);
   return hipGetLastError();
 }
 
@@ -723,12 +955,20 @@ hipError_t launch_eig_trid(const double* G, int m, int mp, double* lam, double* 
 }
 
 // ------------------------------------------------------ grouped (batches)
-template <bool GA>
+// Size class [LO, HI] of buffer rows; tasks of other classes return at once.
+template <int RP, int CP, int LO, int HI>
+__global__ __launch_bounds__(RNT) void kg_tridiag_reg(const GroupSketch* __restrict__ SK,
+                                                      const GroupRR* __restrict__ T) {
+  const GroupSketch& s = SK[T[blockIdx.x].sk];
+  if (s.m < LO || s.m > HI) return;
+  tridiag_reg_body<RP, CP>(s.G, s.m, s.mp, s.W);
+}
+
 __global__ __launch_bounds__(TNT) void kg_tridiag(const GroupSketch* __restrict__ SK,
                                                   const GroupRR* __restrict__ T) {
   const GroupSketch& s = SK[T[blockIdx.x].sk];
-  if ((s.m > kTridMax) != GA) return;    // the other variant's task
-  tridiag_body<GA>(s.G, s.m, s.mp, s.W);
+  if (s.m <= kTridRegMax) return;        // the register variant's task
+  tridiag_body(s.G, s.m, s.mp, s.W);
 }
 
 __global__ __launch_bounds__(TNT) void kg_dc(const GroupSketch* __restrict__ SK,
@@ -750,10 +990,18 @@ hipError_t launch_group_eig(const GroupSketch* sk, const GroupRR* t, int nt, int
   if (nt <= 0) return hipSuccess;
   if (max_m > kTridGlobalMax) return hipErrorInvalidValue;
   const bool big = max_m > kTridMax;
-  hipLaunchKernelGGL(kg_tridiag<false>, dim3(nt), dim3(TNT), 0, s, sk, t);
+  hipLaunchKernelGGL((kg_tridiag_reg<2, 4, 1, 64>), dim3(nt), dim3(RNT), 0, s, sk, t);
   hipError_t e = hipGetLastError();
-  if (e == hipSuccess && big) {
-    hipLaunchKernelGGL(kg_tridiag<true>, dim3(nt), dim3(TNT), 0, s, sk, t);
+  if (e == hipSuccess && max_m > 64) {
+    hipLaunchKernelGGL((kg_tridiag_reg<4, 8, 65, 128>), dim3(nt), dim3(RNT), 0, s, sk, t);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess && max_m > 128) {
+    hipLaunchKernelGGL((kg_tridiag_reg<7, 13, 129, kTridRegMax>), dim3(nt), dim3(RNT), 0, s, sk, t);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess && max_m > kTridRegMax) {
+    hipLaunchKernelGGL(kg_tridiag, dim3(nt), dim3(TNT), 0, s, sk, t);
     e = hipGetLastError();
   }
   if (e != hipSuccess) return e;
