@@ -105,7 +105,9 @@ hipError_t launch_eig_trid(const double* G, int m, int mp, double* lam, double* 
                            hipStream_t s);
 // The three kernels of the tridiagonal route on their own (same arguments).
 hipError_t launch_tridiag(const double* G, int m, int mp, EigWork wk, hipStream_t s);
-hipError_t launch_dc(int m, int mp, double* lam, double* V, EigWork wk, hipStream_t s);
+// nvec: eigenvectors wanted (those of the nvec largest eigenvalues; the
+// others are left undefined); m or less than 1 for all.
+hipError_t launch_dc(int m, int mp, double* lam, double* V, EigWork wk, hipStream_t s, int nvec);
 hipError_t launch_backtr(int m, int mp, double* V, EigWork wk, hipStream_t s);
 inline bool eig_uses_trid(int m, const EigWork& wk) {
   return wk.method != EIG_JACOBI && m <= kTridGlobalMax && wk.S1 && wk.S2;

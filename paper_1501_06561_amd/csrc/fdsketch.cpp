@@ -152,7 +152,8 @@ int spectrum(fdsk_sketch* s) {
   if (eig_uses_trid(s->m, wk)) {
     HIPCHK(s, launch_tridiag(s->G, s->m, s->mp, wk, s->stream));
     hipEvent_t t1 = mark(s);
-    HIPCHK(s, launch_dc(s->m, s->mp, s->lam, s->V, wk, s->stream));
+    // Every rule reads at most the eigenvectors of the l largest values.
+    HIPCHK(s, launch_dc(s->m, s->mp, s->lam, s->V, wk, s->stream, std::min(s->m, s->l)));
     hipEvent_t t2 = mark(s);
     HIPCHK(s, launch_backtr(s->m, s->mp, s->V, wk, s->stream));
     hipEvent_t t3 = mark(s);

@@ -430,11 +430,16 @@ struct DcSmem {
   short perm[kDcMax];    // sorted position -> local column
   short dest[kDcMax];    // sorted position -> compact column
   short org[kDcMax];     // root -> compact index of its pole
+  short src[kDcMax];     // compact column -> local column of the level's input
   int kk[kDcMax / 2];    // non-deflated count per merge
   int nrot[kDcMax / 2];  // deflation rotations per merge
   int tile0[kDcMax / 2 + 1];
   int rot_any[kDcMax / 2];  // the merge needs the sequential deflation scan
   char zdef[kDcMax];        // 1 z-deflated, 2 rotation candidate, 0 otherwise
+  double rv[kDcMax];        // last merge: final eigenvalue of each column (ranking)
+  char want[kDcMax];        // last merge: the column's eigenvector is wanted
+  int clo;                  // last merge: first wanted non-deflated column
+  int cfirst;               // last merge: first column tile of its products
 };
 
 // Merge b of the level with half-size s: block [a, a+k1+k2).
@@ -445,56 +450,107 @@ __device__ __forceinline__ void merge_geom(int b, int s, int n, int& a, int& k1,
 }
 
 // Root `i` of 1 + rho sum_j zz_j^2 / (dd_j - lambda) = 0 over the sorted,
-// distinct dd (kk of them), evaluated by the four lanes of a quad (each sums
-// every fourth term; the quad totals are identical in all four lanes, so the
-// lanes take the same decisions).  Returns the pole index o and tau with
-// lambda = dd_o + tau; every difference dd_j - lambda is (dd_j - dd_o) - tau.
-// Safeguarded Newton on tau inside the bracket that the pole and the
-// midpoint (or the bound rho |z|^2 for the last root) give, falling back to
-// bisection -- geometric when the bracket spans orders of magnitude.
+// non-deflated poles dd (kk of them, rho > 0): lambda_i lies in (dd_i,
+// dd_{i+1}), the last one in (dd_{kk-1}, dd_{kk-1} + rho |zz|^2).  The root
+// is kept as an offset tau from its nearer pole dd_o, so that every
+// dd_j - lambda = (dd_j - dd_o) - tau is formed without cancellation.  Each
+// step fits psi (poles up to i) and phi (poles above i) with one simple
+// pole each at dd_i and dd_{i+1}, matching value and slope, and solves the
+// resulting quadratic (the two-pole rational model of the secular-equation
+// literature); the first iterate comes from the same model at the midpoint,
+// where the origin is chosen.  Steps leaving the bracket fall back to
+// geometric or plain bisection; the loop stops when g is at the rounding
+// level of its own evaluation or the step is below 2 eps |tau|.  Four lanes
+// (q = 0..3) share a root; returns o and writes tau.
 __device__ int secular_root(const double* dd, const double* zz, int kk, int i, double rho, int q,
                             double& tau_out) {
+  const double eps = 1.1102230246251565e-16;
+  const double irho = 1.0 / rho;
+  // Split sums at offset t from d0: p1 = sum_{j<=i} z_j^2/delta_j and its
+  // slope dp1 = sum z_j^2/delta_j^2, p2 and dp2 over j > i.
+  auto sums = [&](double d0, double t, double& p1, double& dp1, double& p2, double& dp2) {
+    double a1 = 0.0, b1 = 0.0, a2 = 0.0, b2 = 0.0;
+    for (int j = q; j <= i; j += 4) {
+      const double r = zz[j] * rcp_nr((dd[j] - d0) - t);
+      a1 = fma(zz[j], r, a1);
+      b1 = fma(r, r, b1);
+    }
+    for (int j = i + 1 + ((q - i - 1) & 3); j < kk; j += 4) {
+      const double r = zz[j] * rcp_nr((dd[j] - d0) - t);
+      a2 = fma(zz[j], r, a2);
+      b2 = fma(r, r, b2);
+    }
+    p1 = quad_sum(a1);
+    dp1 = quad_sum(b1);
+    p2 = quad_sum(a2);
+    dp2 = quad_sum(b2);
+  };
+  // Step eta of the two-pole model from offset t (g = 1 + rho (p1 + p2)).
+  auto model = [&](double d0, double t, double g, double p1, double dp1, double p2, double dp2,
+                   double& eta) -> bool {
+    const double Di = (dd[i] - d0) - t;
+    if (i < kk - 1) {
+      const double Di1 = (dd[i + 1] - d0) - t;
+      const double C = irho + (p1 - dp1 * Di) + (p2 - dp2 * Di1);
+      const double b = C * (Di + Di1) + dp1 * Di * Di + dp2 * Di1 * Di1;
+      const double c0 = Di * Di1 * g * irho;
+      const double disc = b * b - 4.0 * C * c0;
+      if (!(disc >= 0.0)) return false;
+      double e1, e2;
+      if (C == 0.0) {
+        if (b == 0.0) return false;
+        e1 = e2 = c0 / b;
+      } else {
+        const double qq = 0.5 * (b + copysign(sqrt(disc), b));
+        if (qq == 0.0) {
+          e1 = e2 = 0.5 * b / C;
+        } else {
+          e1 = qq / C;
+          e2 = c0 / qq;
+        }
+      }
+      if (e1 > Di && e1 < Di1) { eta = e1; return true; }
+      if (e2 > Di && e2 < Di1) { eta = e2; return true; }
+      return false;
+    }
+    const double C = irho + (p1 - dp1 * Di);
+    if (!(C > 0.0)) return false;
+    eta = Di + dp1 * Di * Di / C;
+    return true;
+  };
   int o;
-  double lo, hi;
+  double lo, hi, t, d0;
   if (i < kk - 1) {
     const double h = 0.5 * (dd[i + 1] - dd[i]);
-    double f = 0.0;
-    for (int j = q; j < kk; j += 4) f += zz[j] * zz[j] * rcp_nr((dd[j] - dd[i]) - h);
-    f = 1.0 + rho * quad_sum(f);
-    if (f >= 0.0) {
-      o = i; lo = 0.0; hi = h;
+    double p1, dp1, p2, dp2;
+    sums(dd[i], h, p1, dp1, p2, dp2);
+    const double g = 1.0 + rho * (p1 + p2);
+    if (g >= 0.0) {
+      o = i; lo = 0.0; hi = h; t = h;
     } else {
-      o = i + 1; lo = -h; hi = 0.0;
+      o = i + 1; lo = -h; hi = 0.0; t = -h;
     }
+    d0 = dd[o];
+    double eta;
+    double tn = model(d0, t, g, p1, dp1, p2, dp2, eta) ? t + eta : 0.5 * (lo + hi);
+    if (!(tn > lo && tn < hi)) tn = 0.5 * (lo + hi);
+    t = tn;
   } else {
     double z2 = 0.0;
-    for (int j = q; j < kk; j += 4) z2 += zz[j] * zz[j];
-    o = kk - 1; lo = 0.0; hi = rho * quad_sum(z2);
+    for (int j = q; j < kk; j += 4) z2 = fma(zz[j], zz[j], z2);
+    o = kk - 1; lo = 0.0; hi = rho * quad_sum(z2); t = 0.5 * hi;
+    d0 = dd[o];
   }
-  const double d0 = dd[o];
-  // Start from the one-pole model: the other terms frozen at tau = 0.
-  double rest = 0.0;
-  for (int j = q; j < kk; j += 4)
-    if (j != o) rest += zz[j] * zz[j] * rcp_nr(dd[j] - d0);
-  rest = quad_sum(rest);
-  double t = rho * zz[o] * zz[o] / (1.0 + rho * rest);
-  if (!(t > lo && t < hi)) t = 0.5 * (lo + hi);
-  const double eps = 1.1102230246251565e-16;
   for (int it = 0; it < 100; ++it) {
-    double psi = 0.0, dpsi = 0.0;
-    for (int j = q; j < kk; j += 4) {
-      const double r = zz[j] * rcp_nr((dd[j] - d0) - t);
-      psi = fma(zz[j], r, psi);
-      dpsi = fma(r, r, dpsi);
-    }
-    psi = quad_sum(psi);
-    dpsi = quad_sum(dpsi);
-    const double g = 1.0 + rho * psi;
-    if (g == 0.0) break;
+    double p1, dp1, p2, dp2;
+    sums(d0, t, p1, dp1, p2, dp2);
+    const double g = 1.0 + rho * (p1 + p2);
+    if (fabs(g) <= 8.0 * eps * (1.0 + rho * (fabs(p1) + fabs(p2)))) break;
     if (g > 0.0) hi = t; else lo = t;
-    const double step = g / (rho * dpsi);
-    double tn = t - step;
-    if (fabs(step) <= 2.0 * eps * fabs(t)) { t = tn; break; }
+    double eta;
+    if (!model(d0, t, g, p1, dp1, p2, dp2, eta)) eta = -g / (rho * (dp1 + dp2));
+    double tn = t + eta;
+    if (fabs(eta) <= 2.0 * eps * fabs(t)) { t = tn; break; }
     if (!(tn > lo && tn < hi)) {
       if (lo > 0.0 && hi > 16.0 * lo) tn = sqrt(lo * hi);
       else if (hi < 0.0 && lo < 16.0 * hi) tn = -sqrt(lo * hi);
@@ -511,21 +567,35 @@ __device__ int secular_root(const double* dd, const double* zz, int kk, int i, d
 
 // T = Z diag(lambda) Z^T for the tridiagonal (d, e) written by k_tridiag in W.
 // Z (n x n, column-major, leading dimension ldz) and lambda are the outputs;
-// Qc, U (ldz) are scratch.
-__device__ __forceinline__ void dc_body(const double* __restrict__ W, int n, double* __restrict__ Z,
-                                        int ldz, double* __restrict__ Qc, double* __restrict__ U,
-                                        double* __restrict__ lam, DevStats* __restrict__ st) {
+// Qc, U (ldz) are scratch.  Only the eigenvectors of the nvec largest
+// eigenvalues (descending, ties to the lower index, NaN last: the order the
+// shrink ranks them in) are wanted; the last merge forms only those of its
+// non-deflated roots (they are a suffix: the roots ascend), and the wanted
+// columns are flagged (1.0 / 0.0) at W[P + 3n + 1 + j] for the
+// back-transformation.  Other columns of Z are left undefined.
+__device__ __forceinline__ void dc_body(double* __restrict__ W, int n, double* __restrict__ Z, int ldz,
+                                        double* __restrict__ Qc, double* __restrict__ U,
+                                        double* __restrict__ lam, DevStats* __restrict__ st, int nvec) {
   __shared__ DcSmem S;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int P = n * (n + 1) / 2;
   const double* dG = W + P + n;
   const double* eG = dG + n;
   const double scale = W[P + 3 * n];
-  // Z = I; torn diagonal.
-  for (int64_t e = tid; e < static_cast<int64_t>(n) * n; e += TNT) {
-    const int c = static_cast<int>(e / n), r = static_cast<int>(e % n);
-    Z[static_cast<int64_t>(c) * ldz + r] = (r == c) ? 1.0 : 0.0;
-  }
+  // The eigenvectors of the current blocks alternate between Z and Qc from
+  // level to level (each level reads one and writes the other), starting in
+  // the one that makes the last level write Z.  Both start as I: a level
+  // reads, within its merge blocks, entries that no earlier level wrote
+  // (between two blocks of the level before), and those must be zero.
+  int levels = 0;
+  for (int s = 1; s < n; s *= 2) ++levels;
+  double* buf[2] = {Z, Qc};
+  int cur = levels & 1;
+  for (int c = w; c < n; c += TNT / 64)
+    for (int r = lane; r < n; r += 64) {
+      Z[static_cast<int64_t>(c) * ldz + r] = (r == c) ? 1.0 : 0.0;
+      Qc[static_cast<int64_t>(c) * ldz + r] = (r == c) ? 1.0 : 0.0;
+    }
   for (int i = tid; i < n; i += TNT) {
     const double el = (i > 0) ? fabs(eG[i - 1]) : 0.0;
     const double er = (i < n - 1) ? fabs(eG[i]) : 0.0;
@@ -535,7 +605,9 @@ __device__ __forceinline__ void dc_body(const double* __restrict__ W, int n, dou
   const double eps = 1.1102230246251565e-16;
   // Four lanes per root in the per-root steps.
   const int g4 = tid >> 2, q4 = tid & 3;
-  for (int s = 1; s < n; s *= 2) {
+  for (int s = 1; s < n; s *= 2, cur ^= 1) {
+    const double* In = buf[cur];
+    double* Out = buf[cur ^ 1];
     const int nm = (n + 2 * s - 1) / (2 * s);
     // 1. z from the boundary rows, sorted by eigenvalue within each merge.
     for (int g = tid; g < n; g += TNT) {
@@ -545,8 +617,8 @@ __device__ __forceinline__ void dc_body(const double* __restrict__ W, int n, dou
       if (k2 == 0) continue;
       const int k = k1 + k2, j = g - a;
       const double beta = eG[a + k1 - 1];
-      const double zj = (j < k1) ? Z[static_cast<int64_t>(a + j) * ldz + a + k1 - 1]
-                                 : ((beta >= 0.0) ? 1.0 : -1.0) * Z[static_cast<int64_t>(a + j) * ldz + a + k1];
+      const double zj = (j < k1) ? In[static_cast<int64_t>(a + j) * ldz + a + k1 - 1]
+                                 : ((beta >= 0.0) ? 1.0 : -1.0) * In[static_cast<int64_t>(a + j) * ldz + a + k1];
       const double dj = S.D[g];
       int rank = 0;
       for (int i = 0; i < k; ++i) {
@@ -676,6 +748,9 @@ __device__ __forceinline__ void dc_body(const double* __restrict__ W, int n, dou
       S.nrot[b] = nr;
     }
     __syncthreads();
+    // The last merge covers the whole matrix; with nvec < n it forms only
+    // the wanted eigenvectors.
+    const bool part = (2 * s >= n) && nvec < n;
     if (tid == 0) {
       int acc = 0;
       for (int b = 0; b < nm; ++b) {
@@ -685,20 +760,17 @@ __device__ __forceinline__ void dc_body(const double* __restrict__ W, int n, dou
         if (k2 > 0) acc += ((k1 + k2 + 31) / 32) * ((S.kk[b] + 15) / 16);
       }
       S.tile0[nm] = acc;
+      S.clo = n;
+      S.cfirst = 0;
     }
-    // 3. Qc = the block's eigenvectors in compact column order (column
-    //    dest[j] <- old column perm[j]), rows of the merge only.
-    {
-      const int K2 = 2 * s;
-      const int64_t tot = static_cast<int64_t>(n) * K2;
-      for (int64_t e = tid; e < tot; e += TNT) {
-        const int g = static_cast<int>(e / K2), r = static_cast<int>(e % K2);
-        const int b = g / K2;
-        int a, k1, k2;
-        merge_geom(b, s, n, a, k1, k2);
-        if (k2 == 0 || r >= k1 + k2) continue;
-        Qc[static_cast<int64_t>(a + S.dest[g]) * ldz + a + r] = Z[static_cast<int64_t>(a + S.perm[g]) * ldz + a + r];
-      }
+    // 3. Compact column dest[j] of the merge is the input's local column
+    //    perm[j]; the products below read the input through this map.
+    for (int g = tid; g < n; g += TNT) {
+      const int b = g / (2 * s);
+      int a, k1, k2;
+      merge_geom(b, s, n, a, k1, k2);
+      if (k2 == 0) continue;
+      S.src[a + S.dest[g]] = S.perm[g];
     }
     // 4. Secular roots, four lanes per root.
     for (int g = g4; g < n; g += TNT / 4) {
@@ -718,16 +790,47 @@ __device__ __forceinline__ void dc_body(const double* __restrict__ W, int n, dou
       }
     }
     __syncthreads();
-    // 3b. Deflation rotations on the copied columns, one thread per row.
+    if (part) {
+      // Rank every final eigenvalue (the same expressions as below, so the
+      // same doubles) and mark the nvec largest.
+      const int nk0 = S.kk[0];
+      for (int c = tid; c < n; c += TNT) {
+        const double v = (c < nk0) ? S.dh[S.org[c]] + S.tau[c] : S.ddf[c - nk0];
+        S.rv[c] = (v == v) ? v : -INFINITY;
+      }
+      __syncthreads();
+      for (int c = tid; c < n; c += TNT) {
+        const double vc = S.rv[c];
+        int rank = 0;
+        for (int j = 0; j < n; ++j) {
+          const double vj = S.rv[j];
+          rank += (vj > vc) || (vj == vc && j < c);
+        }
+        const bool wt = rank < nvec;
+        S.want[c] = wt ? 1 : 0;
+        if (wt && c < nk0) atomicMin(&S.clo, c);
+      }
+      __syncthreads();
+      if (tid == 0) {
+        int a, k1, k2;
+        merge_geom(0, s, n, a, k1, k2);
+        const int nct = (nk0 + 15) / 16, cf = min(S.clo, nk0) / 16;
+        S.cfirst = cf;
+        S.tile0[1] = ((k1 + k2 + 31) / 32) * max(0, nct - cf);
+      }
+    }
+    // 3b. Deflation rotations, in place on the input's columns (read only
+    //    by the products and copies below), one thread per row.
     for (int g = tid; g < n; g += TNT) {
       const int b = g / (2 * s);
       int a, k1, k2;
       merge_geom(b, s, n, a, k1, k2);
       if (k2 == 0) continue;
       const int nr = S.nrot[b];
+      double* InW = buf[cur];
       for (int t = 0; t < nr; ++t) {
-        double* xp = Qc + static_cast<int64_t>(a + S.dest[S.rp[a + t]]) * ldz + g;
-        double* xj = Qc + static_cast<int64_t>(a + S.dest[S.rj[a + t]]) * ldz + g;
+        double* xp = InW + static_cast<int64_t>(a + S.perm[S.rp[a + t]]) * ldz + g;
+        double* xj = InW + static_cast<int64_t>(a + S.perm[S.rj[a + t]]) * ldz + g;
         const double c = S.rc[a + t], sn = S.rs[a + t];
         const double x = *xp, y = *xj;
         *xp = c * x - sn * y;
@@ -769,6 +872,8 @@ __device__ __forceinline__ void dc_body(const double* __restrict__ W, int n, dou
       if (j >= nk) continue;
       const double* dd = S.dh + a;
       const double dj = dd[S.org[g]], tj = S.tau[g];
+      if (q4 == 0) S.Ds[g] = dj + tj;                  // the root
+      if (part && j < S.clo) continue;                 // eigenvector not wanted
       double nrm = 0.0;
       for (int i = q4; i < nk; i += 4) {
         const double u = S.zg[a + i] * rcp_nr((dd[i] - dj) - tj);
@@ -779,11 +884,11 @@ __device__ __forceinline__ void dc_body(const double* __restrict__ W, int n, dou
         const double u = S.zg[a + i] * rcp_nr((dd[i] - dj) - tj);
         U[static_cast<int64_t>(a + i) * ldz + a + j] = u * inv;
       }
-      if (q4 == 0) S.Ds[g] = dj + tj;                  // the root
     }
     __syncthreads();
-    // 7. Z block = Qc[:, 0:nk] U on matrix cores.  A wave computes two
-    //    vertically adjacent 16 x 16 tiles (sharing the U fragment).
+    // 7. Output block = (input columns src[0:nk]) U on matrix cores.  A wave
+    //    computes two vertically adjacent 16 x 16 tiles (sharing the U
+    //    fragment).
     const int ntile = S.tile0[nm];
     for (int t = w; t < ntile; t += TNT / 64) {
       int b = 0;
@@ -791,22 +896,24 @@ __device__ __forceinline__ void dc_body(const double* __restrict__ W, int n, dou
       int a, k1, k2;
       merge_geom(b, s, n, a, k1, k2);
       const int k = k1 + k2, nk = S.kk[b];
-      const int nct = (nk + 15) / 16;
+      const int cf = part ? S.cfirst : 0;
+      const int nct = (nk + 15) / 16 - cf;
       const int tl = t - S.tile0[b];
-      const int r0 = (tl / nct) * 32, c0 = (tl % nct) * 16;
+      const int r0 = (tl / nct) * 32, c0 = (cf + tl % nct) * 16;
       const int li = lane & 15, lk = lane >> 4;
       f64x4 acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = {0.0, 0.0, 0.0, 0.0};
       const bool rok0 = (r0 + li) < k, rok1 = (r0 + 16 + li) < k, cok = (c0 + li) < nk;
-      const double* Ab = Qc + static_cast<int64_t>(a) * ldz + a + r0 + li;
+      const double* Ab = In + static_cast<int64_t>(a) * ldz + a + r0 + li;
       const double* Bb = U + static_cast<int64_t>(a) * ldz + a + c0 + li;
       for (int i0 = 0; i0 < nk; i0 += 16) {
         double x0[4], x1[4], y[4];
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
           const int ii = i0 + 4 * u + lk;
+          const int64_t oa = static_cast<int64_t>(S.src[a + min(ii, nk - 1)]) * ldz;
           const int64_t o = static_cast<int64_t>(ii) * ldz;
-          x0[u] = (rok0 && ii < nk) ? Ab[o] : 0.0;
-          x1[u] = (rok1 && ii < nk) ? Ab[o + 16] : 0.0;
+          x0[u] = (rok0 && ii < nk) ? Ab[oa] : 0.0;
+          x1[u] = (rok1 && ii < nk) ? Ab[oa + 16] : 0.0;
           y[u] = (cok && ii < nk) ? Bb[o] : 0.0;
         }
 #pragma unroll
@@ -819,24 +926,30 @@ __device__ __forceinline__ void dc_body(const double* __restrict__ W, int n, dou
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
           const int row = r0 + lk + 4 * v;
-          double* zc = Z + static_cast<int64_t>(a + c0 + li) * ldz + a;
+          double* zc = Out + static_cast<int64_t>(a + c0 + li) * ldz + a;
           if (row < k) zc[row] = acc0[v];
           if (row + 16 < k) zc[row + 16] = acc1[v];
         }
       }
     }
-    {
-      const int K2 = 2 * s;
-      const int64_t tot = static_cast<int64_t>(n) * K2;
-      for (int64_t e = tid; e < tot; e += TNT) {
-        const int g = static_cast<int>(e / K2), r = static_cast<int>(e % K2);
-        const int b = g / K2;
-        int a, k1, k2;
-        merge_geom(b, s, n, a, k1, k2);
-        const int k = k1 + k2, c = g - a;
-        if (k2 == 0 || r >= k || c < S.kk[b]) continue;
-        Z[static_cast<int64_t>(g) * ldz + a + r] = Qc[static_cast<int64_t>(g) * ldz + a + r];
+    // Deflated columns (compact index >= kk) are copied unchanged, and so
+    // are the columns of a block with no partner at this level.
+    for (int g = w; g < n; g += TNT / 64) {
+      const int b = g / (2 * s);
+      int a, k1, k2;
+      merge_geom(b, s, n, a, k1, k2);
+      int k, from;
+      if (k2 == 0) {
+        k = k1;
+        from = g;
+      } else {
+        if (g - a < S.kk[b]) continue;
+        k = k1 + k2;
+        from = a + S.src[g];
       }
+      const double* src = In + static_cast<int64_t>(from) * ldz + a;
+      double* dst = Out + static_cast<int64_t>(g) * ldz + a;
+      for (int r = lane; r < k; r += 64) dst[r] = src[r];
     }
     __syncthreads();
     for (int g = tid; g < n; g += TNT) {
@@ -851,18 +964,21 @@ __device__ __forceinline__ void dc_body(const double* __restrict__ W, int n, dou
     __syncthreads();
   }
   for (int i = tid; i < n; i += TNT) lam[i] = S.D[i] * scale;
+  const bool flagged = n >= 2 && nvec < n;
+  for (int i = tid; i < n; i += TNT) W[P + 3 * n + 1 + i] = (!flagged || S.want[i]) ? 1.0 : 0.0;
   if (tid == 0 && st) atomicAdd(&st->eig_sweeps, 1ull);
 }
 
-__global__ __launch_bounds__(TNT) void k_dc(const double* __restrict__ W, int n, double* __restrict__ Z,
-                                            int ldz, double* __restrict__ Qc, double* __restrict__ U,
-                                            double* __restrict__ lam, DevStats* __restrict__ st) {
-  dc_body(W, n, Z, ldz, Qc, U, lam, st);
+__global__ __launch_bounds__(TNT) void k_dc(double* __restrict__ W, int n, double* __restrict__ Z, int ldz,
+                                            double* __restrict__ Qc, double* __restrict__ U,
+                                            double* __restrict__ lam, DevStats* __restrict__ st, int nvec) {
+  dc_body(W, n, Z, ldz, Qc, U, lam, st, nvec);
 }
 
 // ---------------------------------------------------------- back-transform
-// Z <- H_0 H_1 ... H_{n-3} Z for every column (in place): one wave per
-// column, NPL elements per lane, the packed reflectors staged in LDS.
+// Z <- H_0 H_1 ... H_{n-3} Z for every wanted column (flagged by the divide
+// and conquer), in place: one wave per column, NPL elements per lane, the
+// packed reflectors staged in LDS.
 template <int NPL, bool GA>
 __device__ __forceinline__ void backtr_body(const double* __restrict__ W, int n, double* __restrict__ Z,
                                             int ldz, int cb) {
@@ -876,7 +992,7 @@ __device__ __forceinline__ void backtr_body(const double* __restrict__ W, int n,
     __syncthreads();
   }
   const int col = cb * (TNT / 64) + w;
-  if (col >= n) return;
+  if (col >= n || W[P + 3 * n + 1 + col] == 0.0) return;
   double z[NPL];
   double* zc = Z + static_cast<int64_t>(col) * ldz;
 #pragma unroll
@@ -926,9 +1042,10 @@ hipError_t launch_tridiag(const double* G, int m, int mp, EigWork wk, hipStream_
   return hipGetLastError();
 }
 
-hipError_t launch_dc(int m, int mp, double* lam, double* V, EigWork wk, hipStream_t s) {
+hipError_t launch_dc(int m, int mp, double* lam, double* V, EigWork wk, hipStream_t s, int nvec) {
   if (m < 1 || m > kDcMax || mp < m) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_dc, dim3(1), dim3(TNT), 0, s, wk.W, m, V, mp, wk.S1, wk.S2, lam, wk.st);
+  hipLaunchKernelGGL(k_dc, dim3(1), dim3(TNT), 0, s, wk.W, m, V, mp, wk.S1, wk.S2, lam, wk.st,
+                     nvec < 1 ? m : nvec);
   return hipGetLastError();
 }
 
@@ -949,7 +1066,7 @@ hipError_t launch_backtr(int m, int mp, double* V, EigWork wk, hipStream_t s) {
 hipError_t launch_eig_trid(const double* G, int m, int mp, double* lam, double* V, EigWork wk,
                            hipStream_t s) {
   hipError_t e = launch_tridiag(G, m, mp, wk, s);
-  if (e == hipSuccess) e = launch_dc(m, mp, lam, V, wk, s);
+  if (e == hipSuccess) e = launch_dc(m, mp, lam, V, wk, s, m);
   if (e == hipSuccess) e = launch_backtr(m, mp, V, wk, s);
   return e;
 }
@@ -974,7 +1091,7 @@ __global__ __launch_bounds__(TNT) void kg_tridiag(const GroupSketch* __restrict_
 __global__ __launch_bounds__(TNT) void kg_dc(const GroupSketch* __restrict__ SK,
                                              const GroupRR* __restrict__ T) {
   const GroupSketch& s = SK[T[blockIdx.x].sk];
-  dc_body(s.W, s.m, s.V, s.mp, s.S1, s.S2, s.lam, s.st);
+  dc_body(s.W, s.m, s.V, s.mp, s.S1, s.S2, s.lam, s.st, min(s.m, s.l));
 }
 
 template <bool GA>
