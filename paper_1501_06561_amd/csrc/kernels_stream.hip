@@ -127,6 +127,7 @@ __device__ __forceinline__ void shrink_body(const double* __restrict__ lam_raw,
   __shared__ int perm[1024];
   __shared__ double rho[1024];
   __shared__ double red[1024];
+  __shared__ double red2[1024];
   __shared__ double raw[1024];
   __shared__ int bad;
   const int tid = threadIdx.x;
@@ -195,15 +196,22 @@ __device__ __forceinline__ void shrink_body(const double* __restrict__ lam_raw,
     perm[rp.l - 2] = perm[rp.l - 1];
     rho[rp.l - 2] = rho[rp.l - 1];
   }
+  // Squared norms of the rows appended since the last reduction, summed by
+  // the block alongside the removed mass.
+  double nrm_part = 0.0;
+  for (int i = new0 + tid; i < new1; i += blockDim.x) nrm_part += rownorm[i];
   red[tid] = removed;
+  red2[tid] = nrm_part;
   __syncthreads();
   for (int s = blockDim.x >> 1; s > 0; s >>= 1) {
-    if (tid < s) red[tid] += red[tid + s];
+    if (tid < s) {
+      red[tid] += red[tid + s];
+      red2[tid] += red2[tid + s];
+    }
     __syncthreads();
   }
   if (tid == 0) {
-    double nrm = 0.0;
-    for (int i = new0; i < new1; ++i) nrm += rownorm[i];
+    const double nrm = red2[0];
     st->fro2A += nrm;
     st->Stot += red[0];
     if (!rp.comp) {
@@ -212,13 +220,16 @@ __device__ __forceinline__ void shrink_body(const double* __restrict__ lam_raw,
     }
     if (bad || !(nrm == nrm)) st->nonfinite = 1;
   }
-  // Ut rows [0, keep) ; rows up to the next multiple of 32 are zero.
+  // Ut rows [0, keep) ; rows up to the next multiple of 32 are zero.  A
+  // wave per row, lanes across it.
   const int rows = (rp.keep + 31) & ~31;
-  for (int64_t e = tid; e < static_cast<int64_t>(rows) * mp; e += blockDim.x) {
-    int q = static_cast<int>(e / mp), i = static_cast<int>(e % mp);
-    double v = 0.0;
-    if (q < rp.keep && q < m && i < m) v = rho[q] * V[static_cast<int64_t>(perm[q]) * mp + i];
-    Ut[e] = v;
+  const int lane = tid & 63, nwave = blockDim.x >> 6;
+  for (int q = tid >> 6; q < rows; q += nwave) {
+    const bool live = q < rp.keep && q < m;
+    const double r = live ? rho[q] : 0.0;
+    const double* src = V + static_cast<int64_t>(live ? perm[q] : 0) * mp;
+    double* dst = Ut + static_cast<int64_t>(q) * mp;
+    for (int i = lane; i < mp; i += 64) dst[i] = (live && i < m) ? r * src[i] : 0.0;
   }
 }
 

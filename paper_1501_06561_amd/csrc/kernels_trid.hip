@@ -978,21 +978,46 @@ __global__ __launch_bounds__(TNT) void k_dc(double* __restrict__ W, int n, doubl
 // ---------------------------------------------------------- back-transform
 // Z <- H_0 H_1 ... H_{n-3} Z for every wanted column (flagged by the divide
 // and conquer), in place: one wave per column, NPL elements per lane, the
-// packed reflectors staged in LDS.
+// packed reflectors staged in LDS.  A column's reflectors are a sequential
+// chain, so the time is that of one wave's chain: blocks have one wave per
+// SIMD, and wave w of block cb takes the (4 cb + w)-th wanted column.
+constexpr int BNT = 256;
+
+// The t-th (0-based) column flagged in W[F .. F+n), or -1; also the count.
+__device__ __forceinline__ int nth_flagged(const double* __restrict__ flags, int n, int t, int& count) {
+  const int lane = threadIdx.x & 63;
+  int col = -1, seen = 0;
+  for (int c0 = 0; c0 < n; c0 += 64) {
+    const bool f = (c0 + lane < n) && flags[c0 + lane] != 0.0;
+    const unsigned long long m = __ballot(f);
+    const int cnt = __popcll(m);
+    if (col < 0 && t >= seen && t < seen + cnt) {
+      const int before = __popcll(m & ((1ull << lane) - 1ull));
+      const unsigned long long hit = __ballot(f && (seen + before == t));
+      col = c0 + __ffsll(static_cast<long long>(hit)) - 1;
+    }
+    seen += cnt;
+  }
+  count = seen;
+  return col;
+}
+
 template <int NPL, bool GA>
 __device__ __forceinline__ void backtr_body(const double* __restrict__ W, int n, double* __restrict__ Z,
                                             int ldz, int cb) {
   __shared__ double R_lds[GA ? 1 : TRI_PACK];
+  __shared__ double tau_lds[kTridGlobalMax];
   const double* const R = GA ? W : R_lds;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int P = n * (n + 1) / 2;
-  const double* tauG = W + P;
-  if (!GA) {
-    for (int e = tid; e < P; e += TNT) R_lds[e] = W[e];
-    __syncthreads();
-  }
-  const int col = cb * (TNT / 64) + w;
-  if (col >= n || W[P + 3 * n + 1 + col] == 0.0) return;
+  int nw;
+  const int col = nth_flagged(W + P + 3 * n + 1, n, cb * (BNT / 64) + w, nw);
+  if (cb * (BNT / 64) >= nw) return;     // the whole block: no wanted column left
+  if (!GA)
+    for (int e = tid; e < P; e += BNT) R_lds[e] = W[e];
+  for (int e = tid; e < n; e += BNT) tau_lds[e] = W[P + e];
+  __syncthreads();
+  if (col < 0) return;
   double z[NPL];
   double* zc = Z + static_cast<int64_t>(col) * ldz;
 #pragma unroll
@@ -1000,21 +1025,31 @@ __device__ __forceinline__ void backtr_body(const double* __restrict__ W, int n,
     const int i = lane + 64 * t;
     z[t] = (i < n) ? zc[i] : 0.0;
   }
-  for (int k = n - 3; k >= 0; --k) {
-    const double tk = tauG[k];
-    if (tk == 0.0) continue;
+  // Reflector k's v (and tau) are fetched while reflector k+1 is applied.
+  auto fetch = [&](int k, double* v) {
     const int ck = colstart(k, n);
-    double v[NPL];
-    double dot = 0.0;
 #pragma unroll
     for (int t = 0; t < NPL; ++t) {
       const int i = lane + 64 * t;
-      v[t] = (i == k + 1) ? 1.0 : ((i > k + 1 && i < n) ? R[ck + i - k] : 0.0);
-      dot = fma(v[t], z[t], dot);
+      const double x = R[ck + min(max(i - k, 0), n - 1 - k)];
+      v[t] = (i == k + 1) ? 1.0 : ((i > k + 1 && i < n) ? x : 0.0);
     }
+  };
+  double v[NPL];
+  if (n >= 3) fetch(n - 3, v);
+  for (int k = n - 3; k >= 0; --k) {
+    const double tk = tau_lds[k];
+    double cv[NPL];
+#pragma unroll
+    for (int t = 0; t < NPL; ++t) cv[t] = v[t];
+    if (k > 0) fetch(k - 1, v);
+    if (tk == 0.0) continue;
+    double dot = 0.0;
+#pragma unroll
+    for (int t = 0; t < NPL; ++t) dot = fma(cv[t], z[t], dot);
     dot = wave_sum(dot) * tk;
 #pragma unroll
-    for (int t = 0; t < NPL; ++t) z[t] = fma(-dot, v[t], z[t]);
+    for (int t = 0; t < NPL; ++t) z[t] = fma(-dot, cv[t], z[t]);
   }
 #pragma unroll
   for (int t = 0; t < NPL; ++t) {
@@ -1024,7 +1059,7 @@ __device__ __forceinline__ void backtr_body(const double* __restrict__ W, int n,
 }
 
 template <int NPL, bool GA>
-__global__ __launch_bounds__(TNT) void k_backtr(const double* __restrict__ W, int n,
+__global__ __launch_bounds__(BNT) void k_backtr(const double* __restrict__ W, int n,
                                                 double* __restrict__ Z, int ldz) {
   backtr_body<NPL, GA>(W, n, Z, ldz, blockIdx.x);
 }
@@ -1051,15 +1086,15 @@ hipError_t launch_dc(int m, int mp, double* lam, double* V, EigWork wk, hipStrea
 
 hipError_t launch_backtr(int m, int mp, double* V, EigWork wk, hipStream_t s) {
   if (m < 1 || m > kTridGlobalMax || mp < m) return hipErrorInvalidValue;
-  const int grid = (m + TNT / 64 - 1) / (TNT / 64);
+  const int grid = (m + BNT / 64 - 1) / (BNT / 64);
   if (m <= 64)
-    hipLaunchKernelGGL((k_backtr<1, false>), dim3(grid), dim3(TNT), 0, s, wk.W, m, V, mp);
+    hipLaunchKernelGGL((k_backtr<1, false>), dim3(grid), dim3(BNT), 0, s, wk.W, m, V, mp);
   else if (m <= 128)
-    hipLaunchKernelGGL((k_backtr<2, false>), dim3(grid), dim3(TNT), 0, s, wk.W, m, V, mp);
+    hipLaunchKernelGGL((k_backtr<2, false>), dim3(grid), dim3(BNT), 0, s, wk.W, m, V, mp);
   else if (m <= kTridMax)
-    hipLaunchKernelGGL((k_backtr<4, false>), dim3(grid), dim3(TNT), 0, s, wk.W, m, V, mp);
+    hipLaunchKernelGGL((k_backtr<4, false>), dim3(grid), dim3(BNT), 0, s, wk.W, m, V, mp);
   else
-    hipLaunchKernelGGL((k_backtr<4, true>), dim3(grid), dim3(TNT), 0, s, wk.W, m, V, mp);
+    hipLaunchKernelGGL((k_backtr<4, true>), dim3(grid), dim3(BNT), 0, s, wk.W, m, V, mp);
   return hipGetLastError();
 }
 
@@ -1095,11 +1130,11 @@ __global__ __launch_bounds__(TNT) void kg_dc(const GroupSketch* __restrict__ SK,
 }
 
 template <bool GA>
-__global__ __launch_bounds__(TNT) void kg_backtr(const GroupSketch* __restrict__ SK,
+__global__ __launch_bounds__(BNT) void kg_backtr(const GroupSketch* __restrict__ SK,
                                                  const GroupRR* __restrict__ T) {
   const GroupSketch& s = SK[T[blockIdx.y].sk];
   if ((s.m > kTridMax) != GA) return;
-  if (static_cast<int>(blockIdx.x) * (TNT / 64) >= s.m) return;
+  if (static_cast<int>(blockIdx.x) * (BNT / 64) >= s.m) return;
   backtr_body<4, GA>(s.W, s.m, s.V, s.mp, blockIdx.x);
 }
 
@@ -1125,11 +1160,11 @@ hipError_t launch_group_eig(const GroupSketch* sk, const GroupRR* t, int nt, int
   hipLaunchKernelGGL(kg_dc, dim3(nt), dim3(TNT), 0, s, sk, t);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
-  const dim3 g((max_m + TNT / 64 - 1) / (TNT / 64), nt);
-  hipLaunchKernelGGL(kg_backtr<false>, g, dim3(TNT), 0, s, sk, t);
+  const dim3 g((max_m + BNT / 64 - 1) / (BNT / 64), nt);
+  hipLaunchKernelGGL(kg_backtr<false>, g, dim3(BNT), 0, s, sk, t);
   e = hipGetLastError();
   if (e == hipSuccess && big) {
-    hipLaunchKernelGGL(kg_backtr<true>, g, dim3(TNT), 0, s, sk, t);
+    hipLaunchKernelGGL(kg_backtr<true>, g, dim3(BNT), 0, s, sk, t);
     e = hipGetLastError();
   }
   return e;
