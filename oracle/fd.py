@@ -42,6 +42,9 @@ reason in the design notes):
    squared one before the reduction) is not in the buffer's row space: SSD
    then has nothing to move and leaves the values unchanged (delta = 0), and
    CFD leaves that output row zero.
+6. Merge: another sketch's occupied buffer rows are inserted
+   like stream rows without counting into ||A||_F^2, and its accumulators
+   (||A||_F^2, Delta, S_tot, rows, reductions) are added.
 
 The SVD route here (LAPACK gesdd on the m x d buffer) is deliberately a
 different algorithm from the GPU path's Gram matrix + Jacobi eigensolver.
@@ -170,20 +173,47 @@ class SketchOracle:
         self._last = (sig_full ** 2, sig_new ** 2, vt)   # for Compensative FD's last step
 
     def append(self, rows: np.ndarray):
+        self._insert(rows, count=True)
+
+    def _insert(self, rows, count):
+        """Algorithm 1's insertion; `count` adds the rows to ||A||_F^2 and the
+        row count (they are stream rows rather than another sketch's)."""
         rows = np.atleast_2d(np.asarray(rows, dtype=np.float64))
         i = 0
         while i < rows.shape[0]:
             f = min(self.m - self.occ, rows.shape[0] - i)
             block = rows[i:i + f]
             self.C[self.occ:self.occ + f] = block
-            self.fro2A += float(np.sum(block * block))
+            if count:
+                self.fro2A += float(np.sum(block * block))
+                self.n_rows += f
             self.occ += f
-            self.n_rows += f
             self._since += f
             i += f
             if self.occ == self.m:
                 self._reduce()
                 self._since = 0
+
+    def merge(self, other: "SketchOracle"):
+        """Absorb another sketch of the same configuration (reading 6): its
+        occupied buffer rows are inserted like stream rows, without counting
+        them into ||A||_F^2, and its accumulators are added.  By the argument
+        of the three-property framework (Section 3.1), the result sketches
+        the union of the two streams with Delta = Delta_1 + Delta_2 + the
+        merge's own."""
+        if (other.d, other.l, other.variant, other.m) != (self.d, self.l, self.variant, self.m):
+            raise ValueError("merge needs sketches of the same configuration")
+        if self.variant in (ALPHA, FAST_ALPHA) and other.alpha != self.alpha:
+            raise ValueError("merge needs the same alpha")
+        rows = other.C[:other.occ].copy()
+        fro2A, Delta, Stot = other.fro2A, other.Delta, other.Stot
+        n_rows, n_rr = other.n_rows, other.n_rr
+        self._insert(rows, count=False)
+        self.fro2A += fro2A
+        self.Delta += Delta
+        self.Stot += Stot
+        self.n_rows += n_rows
+        self.n_rr += n_rr
 
     def finalize(self) -> np.ndarray:
         if self.variant == CFD:

@@ -355,3 +355,79 @@ def test_ssd_cfd_short_stream_exact(variant, m):
     A = synth.random_noisy(7, 20, 3, seed=(74, m))
     B = oracle.fd_sketch(A, 9, variant, m=m)
     assert np.allclose(B.T @ B, A.T @ A, atol=1e-10 * oracle.fro2(A))
+
+
+# ---------------------------------------------------------------------------
+# Merge (reading 6; the three-property framework of Section 3.1).
+
+def _merged(parts, l, variant, alpha=0.2, m=None):
+    sks = []
+    for P in parts:
+        sk = oracle.SketchOracle(P.shape[1], l, variant, alpha, m)
+        sk.append(P)
+        sks.append(sk)
+    root = sks[0]
+    for other in sks[1:]:
+        root.merge(other)
+    return root
+
+
+@pytest.mark.parametrize("variant", oracle.VARIANTS)
+def test_merge_of_unreduced_sketches_is_the_stacked_stream(variant):
+    """Sketches that never reduced hold their raw rows: merging them is
+    exactly sketching the stacked stream (same rows, same order)."""
+    A = synth.random_noisy(60, 30, 5, 4.0, seed=(80, 0))
+    l = 20                                            # buffer 40 rows
+    sk = _merged([A[:25], A[25:55], A[55:]], l, variant)
+    B = sk.finalize()
+    Bo, so = oracle.fd_sketch(A, l, variant, return_state=True)
+    assert np.allclose(B.T @ B, Bo.T @ Bo, rtol=0, atol=1e-12 * oracle.fro2(A))
+    assert sk.n_rr == so.n_rr and sk.n_rows == so.n_rows == 60
+    assert abs(sk.fro2A - so.fro2A) <= 1e-12 * so.fro2A
+
+
+@pytest.mark.parametrize("variant", oracle.VARIANTS)
+def test_merge_with_empty_sketch(variant):
+    A = synth.random_noisy(300, 25, 4, 4.0, seed=(81, 0))
+    Bo = oracle.fd_sketch(A, 8, variant)
+    for parts in ([A, A[:0]], [A[:0], A]):
+        sk = _merged(parts, 8, variant)
+        B = sk.finalize()
+        assert np.allclose(B.T @ B, Bo.T @ Bo, rtol=0, atol=1e-10 * oracle.fro2(A))
+
+
+@pytest.mark.parametrize("variant", oracle.VARIANTS)
+@pytest.mark.parametrize("shards", [2, 4, 7])
+def test_merged_sketch_keeps_the_three_properties(variant, shards):
+    """Properties 1-3 of Section 3.1 for the union of the shards with the
+    summed Delta, hence the error bound of the lemma that follows them; the
+    mass identity ||A||^2 - ||B||^2 = S_tot."""
+    A = synth.random_noisy(1200, 40, 6, 4.0, seed=(82, shards))
+    l = 10
+    cuts = np.linspace(0, A.shape[0], shards + 1).astype(int)
+    sk = _merged([A[cuts[i]:cuts[i + 1]] for i in range(shards)], l, variant)
+    B = sk.finalize()
+    fa = oracle.fro2(A)
+    w = np.linalg.eigvalsh(A.T @ A - B.T @ B)
+    assert w[0] >= -1e-10 * fa                                    # Property 1
+    assert w[-1] <= sk.Delta * (1 + 1e-9) + 1e-10 * fa            # Property 2
+    ae = oracle.alpha_eff(l, variant)
+    assert fa - oracle.fro2(B) >= ae * l * sk.Delta * (1 - 1e-9)  # Property 3
+    assert abs(fa - oracle.fro2(B) - sk.Stot) <= 1e-9 * fa
+    assert abs(sk.fro2A - fa) <= 1e-12 * fa
+    cov = oracle.cov_err(A, B)
+    for k in range(int(ae * l)):
+        if ae * l - k > 0:
+            assert cov * fa <= oracle.tail_mass(A, k) / (ae * l - k) * (1 + 1e-9)
+
+
+def test_merge_rejects_mismatched_sketches():
+    a = oracle.SketchOracle(10, 4)
+    with pytest.raises(ValueError):
+        a.merge(oracle.SketchOracle(11, 4))
+    with pytest.raises(ValueError):
+        a.merge(oracle.SketchOracle(10, 5))
+    with pytest.raises(ValueError):
+        a.merge(oracle.SketchOracle(10, 4, oracle.ISVD))
+    with pytest.raises(ValueError):
+        oracle.SketchOracle(10, 4, oracle.ALPHA, 0.2).merge(oracle.SketchOracle(10, 4, oracle.ALPHA, 0.5))
