@@ -138,6 +138,22 @@ int sketch_create(const fdsk_config* cfg, void* hip_stream, fdsk_sketch** out);
 int sketch_append_rows(fdsk_sketch* s, const void* rows, int64_t n_rows, int64_t row_stride,
                        fdsk_dtype dtype, fdsk_mem mem);
 
+/* Merge: dst absorbs src, so that dst then sketches the concatenation of both
+ * streams (dst's rows, then src's).  src's occupied buffer rows are inserted
+ * into dst like stream rows (running every ReduceRank dst's schedule calls
+ * for) without counting into ||A||_F^2, and src's accumulators (||A||_F^2,
+ * delta sum, shrink total, rows, reductions) are added to dst's.  Because
+ * each ReduceRank rule satisfies Properties 1-3 of Section 3.1, the merged
+ * sketch keeps them for the union with the delta sums added; merges compose
+ * into trees (the building block of a sharded stream).  Both sketches must
+ * have the same d, l, buffer rows, variant, precision (and alpha for the
+ * alpha variants) and must not be finalized; src is left unchanged and stays
+ * usable.  Stream-ordered: dst's stream waits for src's stream before reading
+ * src, and src's stream waits for dst's reads before any later work on src.
+ * Errors: EINVAL (null, dst == src, different configurations, src in an error
+ * state), ESTATE (either finalized), EDEVICE. */
+int sketch_merge(fdsk_sketch* dst, fdsk_sketch* src);
+
 /* Finish the stream: if more than l rows are occupied, one more ReduceRank
  * (FDSK_CFD: then its compensation, see the rules above, *rows_out = l);
  * then write the l x d sketch B (rows beyond *rows_out are zero) to B_out

@@ -67,6 +67,8 @@ hipError_t launch_rebuild(const double* Ut, const double* C, int ldc, int mp, in
 hipError_t launch_zero_rows(double* C, int ldc, int r0, int r1, hipStream_t s);
 hipError_t launch_add_pending_norms(const double* rownorm, int new0, int new1, DevStats* st,
                                     hipStream_t s);
+hipError_t launch_merge_stats(DevStats* dst, const DevStats* src, const double* src_rownorm, int new0,
+                              int new1, hipStream_t s);
 // out (mp x mp) = in^T for the leading n x n block of an mp x mp matrix.
 hipError_t launch_transpose(const double* in, int mp, int n, double* out, hipStream_t s);
 // out (rows x d, ld d, FP64) = X converted from dtype dt (ld ldx).

@@ -198,7 +198,11 @@ int reduce(fdsk_sketch* s) {
   return 0;
 }
 
-int ingest_device(fdsk_sketch* s, const char* src, int64_t n, int64_t stride, fdsk_dtype dt) {
+// Algorithm 1's insertion of n rows.  count = false inserts another
+// sketch's rows (a merge): their squared norms are zeroed so that they do not
+// enter ||A||_F^2, and they are not counted as stream rows.
+int ingest_device(fdsk_sketch* s, const char* src, int64_t n, int64_t stride, fdsk_dtype dt,
+                  bool count = true) {
   const size_t es = dtype_size(dt);
   int64_t i = 0;
   while (i < n) {
@@ -206,10 +210,11 @@ int ingest_device(fdsk_sketch* s, const char* src, int64_t n, int64_t stride, fd
     hipEvent_t a = mark(s);
     HIPCHK(s, launch_ingest(src + i * stride * es, static_cast<int>(dt), stride, f, s->d,
                             s->C[s->cur], s->ldc, s->occ, s->rownorm, s->stream));
+    if (!count) HIPCHK(s, launch_zero_rows(s->rownorm, 1, s->occ, s->occ + f, s->stream));
     add_mark(s, 0, a, mark(s));
     s->occ += f;
     i += f;
-    s->n_rows += f;
+    if (count) s->n_rows += f;
     if (s->occ == s->m) {
       int rc = reduce(s);
       if (rc) return rc;
@@ -392,6 +397,42 @@ int sketch_append_rows(fdsk_sketch* s, const void* rows, int64_t n_rows, int64_t
     if (rc) return rc;
   }
   HIPCHK(s, hipStreamSynchronize(s->stream));
+  return 0;
+}
+
+int sketch_merge(fdsk_sketch* dst, fdsk_sketch* src) {
+  if (!dst || !src) return set_err(dst, FDSK_EINVAL, "null sketch");
+  if (dst == src) return set_err(dst, FDSK_EINVAL, "a sketch cannot absorb itself");
+  if (dst->err) return dst->err;
+  if (src->err) return set_err(dst, FDSK_EINVAL, "the source sketch is in an error state");
+  if (dst->finalized || src->finalized) return set_err(dst, FDSK_ESTATE, "merge after finalize");
+  const fdsk_config& a = dst->cfg;
+  const fdsk_config& b = src->cfg;
+  const bool uses_alpha = a.variant == FDSK_ALPHA || a.variant == FDSK_FAST_ALPHA;
+  if (a.d != b.d || a.l != b.l || dst->m != src->m || a.variant != b.variant ||
+      a.precision != b.precision || (uses_alpha && a.alpha != b.alpha))
+    return set_err(dst, FDSK_EINVAL, "merge needs sketches of the same configuration");
+  // dst's stream waits for src's work; src's stream then waits for dst's
+  // reads of src's buffer.
+  hipEvent_t ev = nullptr;
+  HIPCHK(dst, hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+  hipError_t e = hipEventRecord(ev, src->stream);
+  if (e == hipSuccess) e = hipStreamWaitEvent(dst->stream, ev, 0);
+  if (e == hipSuccess) e = launch_merge_stats(dst->st, src->st, src->rownorm, src->new0, src->occ, dst->stream);
+  if (e != hipSuccess) {
+    (void)hipEventDestroy(ev);
+    return set_err(dst, FDSK_EDEVICE, "merge: %s", hipGetErrorString(e));
+  }
+  int rc = ingest_device(dst, reinterpret_cast<const char*>(src->C[src->cur]), src->occ, src->ldc,
+                         FDSK_F64, false);
+  if (rc == 0) {
+    e = hipEventRecord(ev, dst->stream);
+    if (e == hipSuccess) e = hipStreamWaitEvent(src->stream, ev, 0);
+    if (e != hipSuccess) rc = set_err(dst, FDSK_EDEVICE, "merge: %s", hipGetErrorString(e));
+  }
+  (void)hipEventDestroy(ev);
+  if (rc) return rc;
+  dst->n_rows += src->n_rows;
   return 0;
 }
 

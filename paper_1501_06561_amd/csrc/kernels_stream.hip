@@ -425,6 +425,30 @@ hipError_t launch_add_pending_norms(const double* rownorm, int new0, int new1, D
   return hipGetLastError();
 }
 
+// Merge: dst's accumulators absorb src's, including the squared norms of
+// src's rows appended since its last reduction (not yet in src's fro2A).
+__global__ void k_merge_stats(DevStats* __restrict__ dst, const DevStats* __restrict__ src,
+                              const double* __restrict__ src_rownorm, int new0, int new1) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    double nrm = 0.0;
+    for (int i = new0; i < new1; ++i) nrm += src_rownorm[i];
+    dst->fro2A += src->fro2A + nrm;
+    dst->Delta += src->Delta;
+    dst->Stot += src->Stot;
+    dst->n_rr += src->n_rr;
+    dst->eig_unconv += src->eig_unconv;
+    dst->eig_sweeps += src->eig_sweeps;
+    if (src->nonfinite || !(nrm == nrm) || isinf(nrm)) dst->nonfinite = 1;
+    if (src->bar_err) dst->bar_err = 1;
+  }
+}
+
+hipError_t launch_merge_stats(DevStats* dst, const DevStats* src, const double* src_rownorm, int new0,
+                              int new1, hipStream_t s) {
+  hipLaunchKernelGGL(k_merge_stats, dim3(1), dim3(64), 0, s, dst, src, src_rownorm, new0, new1);
+  return hipGetLastError();
+}
+
 hipError_t launch_copy_out(const double* C, int ldc, int valid_rows, int l, int d, void* out,
                            int64_t ldb, int out_dt, hipStream_t s) {
   int64_t n = static_cast<int64_t>(l) * d;

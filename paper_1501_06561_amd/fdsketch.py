@@ -23,7 +23,7 @@ ERRORS = {0: "OK", -1: "EINVAL", -2: "ESTATE", -3: "ENOMEM", -4: "EDEVICE", -5: 
           -6: "EUNSUPPORTED"}
 
 # Every symbol the header declares (checked by the CPU test-suite).
-EXPORTS = ("sketch_create", "sketch_append_rows", "sketch_finalize", "sketch_error",
+EXPORTS = ("sketch_create", "sketch_append_rows", "sketch_merge", "sketch_finalize", "sketch_error",
            "fdsk_evaluate", "sketch_stats", "sketch_destroy", "sketch_last_error", "fdsk_version",
            "fdsk_gram", "fdsk_eigh", "sketch_reset", "sketch_profile", "sketch_batch_create",
            "sketch_batch_append", "sketch_batch_finalize", "sketch_batch_stats",
@@ -93,6 +93,7 @@ def lib():
     L.sketch_create.argtypes = [ctypes.POINTER(FdskConfig), vp, ctypes.POINTER(vp)]
     L.sketch_append_rows.argtypes = [vp, vp, i64, i64, cint, cint]
     L.sketch_finalize.argtypes = [vp, vp, i64, cint, cint, ctypes.POINTER(i32)]
+    L.sketch_merge.argtypes = [vp, vp]
     L.sketch_error.argtypes = [vp, vp, i64, i64, cint, cint, i32, i32, ctypes.POINTER(FdskReport)]
     L.fdsk_evaluate.argtypes = [vp, i64, i64, cint, vp, i64, i64, cint, i64, cint, i32, i32, vp,
                                 ctypes.POINTER(FdskReport)]
@@ -116,7 +117,7 @@ def lib():
     L.sketch_batch_last_error.restype = ctypes.c_char_p
     L.sketch_profile.argtypes = [vp, ctypes.POINTER(FdskProfile)]
     L.fdsk_eigh.argtypes = [vp, i32, i64, vp, vp, i64, i32, vp]
-    for f in ("sketch_create", "sketch_append_rows", "sketch_finalize", "sketch_error",
+    for f in ("sketch_create", "sketch_append_rows", "sketch_merge", "sketch_finalize", "sketch_error",
               "fdsk_evaluate", "sketch_stats", "fdsk_gram", "fdsk_eigh", "sketch_reset",
               "sketch_profile", "sketch_batch_create", "sketch_batch_append",
               "sketch_batch_finalize", "sketch_batch_stats"):
@@ -182,9 +183,28 @@ class FDSketch:
         _check(lib().sketch_create(ctypes.byref(cfg), _stream_handle(stream), ctypes.byref(h)))
         self._h = h
 
+    def _on_stream(self, t):
+        """A device tensor made on the current stream and read by the library
+        on the sketch's own stream: that stream waits for the current one, and
+        the tensor's memory is kept from reuse until the sketch's stream is
+        past it."""
+        if self._stream is None or not getattr(t, "is_cuda", False):
+            return
+        cur = _torch().cuda.current_stream()
+        if self._stream != cur:
+            self._stream.wait_stream(cur)
+            t.record_stream(self._stream)
+
     def append(self, rows):
         ptr, n, stride, dt, mem, keep = _rows_arg(rows)
+        self._on_stream(keep)
         _check(lib().sketch_append_rows(self._h, ctypes.c_void_p(ptr), n, stride, dt, mem), self._h)
+        return self
+
+    def merge(self, other):
+        """Absorb `other` (same configuration): afterwards this sketch covers
+        both streams; `other` is unchanged."""
+        _check(lib().sketch_merge(self._h, other._h), self._h)
         return self
 
     def finalize(self, dtype=None, device="cuda"):
@@ -215,6 +235,7 @@ class FDSketch:
 
     def error(self, A, k=10, method=0):
         ptr, n, stride, dt, mem, keep = _rows_arg(A)
+        self._on_stream(keep)
         rep = FdskReport()
         _check(lib().sketch_error(self._h, ctypes.c_void_p(ptr), n, stride, dt, mem, k, method,
                                   ctypes.byref(rep)), self._h)
@@ -297,6 +318,7 @@ class FDSketchBatch:
         h = ctypes.c_void_p()
         _check_batch(lib().sketch_batch_create(self.S, arr, _stream_handle(stream), ctypes.byref(h)))
         self._h = h
+        self._stream = stream
 
     def append(self, rows_list, grid_size=0):
         """rows_list[i]: 2-D cuda tensor for sketch i (or None for no rows)."""
@@ -319,6 +341,13 @@ class FDSketchBatch:
             elif dt != code:
                 raise ValueError("all sketches of one append call share a dtype")
             ptrs[i], ns[i], strides[i] = t.data_ptr(), t.shape[0], t.stride(0)
+        if self._stream is not None and keep:
+            # Inputs made on the current stream, read on the batch's stream.
+            cur = torch.cuda.current_stream()
+            if self._stream != cur:
+                self._stream.wait_stream(cur)
+                for t in keep:
+                    t.record_stream(self._stream)
         _check_batch(lib().sketch_batch_append(self._h, ptrs, ns, strides, F64 if dt is None else dt,
                                                MEM_DEVICE, int(grid_size)), self._h)
         return self

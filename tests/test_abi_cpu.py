@@ -80,6 +80,7 @@ def test_null_handles_are_rejected():
     rep = F.FdskReport()
     assert L.sketch_append_rows(None, None, 1, 1, 0, 0) == -1
     assert L.sketch_finalize(None, None, 1, 0, 0, None) == -1
+    assert L.sketch_merge(None, None) == -1
     assert L.sketch_stats(None, ctypes.byref(rep)) == -1
     L.sketch_destroy(None)
 
