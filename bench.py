@@ -27,6 +27,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_FP64 = 78.6e12      # MI355X FP64 vector and matrix peak, FLOP/s
+PEAK_BF16 = 2.5e15       # dense BF16 MFMA, FLOP/s
+PEAK_FP8 = 5.0e15        # dense FP8 MFMA, FLOP/s
 PEAK_HBM = 8.0e12        # bytes/s
 METRIC = "rows/sec sketched at fixed cov-err/||A||_F^2; batched+bf16 vs plain FD, 1 GPU"
 CSRC = os.path.join(ROOT, "paper_1501_06561_amd", "csrc")
@@ -137,6 +139,76 @@ def batched_leg(S, n_max, seq_sketches, seed=(4, 0)):
     return out
 
 
+def precision_leg(rows, l=256, d=3072, seed=(3, 0)):
+    """The power-law workload's shape (d = 3,072, bf16 rows, l = 256, buffer
+    512 rows): a prefix of `rows` rows sketched with FP64, BF16, split-BF16
+    (x3) and FP8 (x3, Gram only) products.  Per precision: rows/s, the Gram
+    and rebuild launches' matrix-core utilisation (their multiply-adds, all
+    passes, over the launch time, against the dtype's dense peak) and the
+    covariance error's distance from the FP64 sketch's."""
+    import numpy as np
+    import torch
+    from paper_1501_06561_amd import fdsketch, synth
+    A = synth.power_law(rows, d, r=300, seed=seed, chunk=rows)
+    bits = torch.from_numpy(synth.bf16_bits(A).view(np.int16)).view(torch.bfloat16).cuda()
+    m = 2 * l
+    keep = l - 1
+    npass = {"fp64": 1, "bf16": 1, "bf16x3": 3, "fp8x3": 3}
+    peak_gram = {"fp64": PEAK_FP64, "bf16": PEAK_BF16, "bf16x3": PEAK_BF16, "fp8x3": PEAK_FP8}
+    peak_rebuild = {"fp64": PEAK_FP64, "bf16": PEAK_BF16, "bf16x3": PEAK_BF16, "fp8x3": PEAK_BF16}
+    out = {"workload": f"power-law sigma_i = i^-0.8 over 300 directions + N(0,1e-2), {rows} x {d} "
+                       f"bf16 rows, FD l = {l} (buffer {m} rows), block Jacobi eigensolver",
+           "rows": rows}
+    cov64 = None
+    for prec in ("fp64", "bf16", "bf16x3", "fp8x3"):
+        sk = fdsketch.FDSketch(d, l, "fd", precision=prec, profile=True)
+        sk.append(bits[:m + 1])                      # warm the kernels
+        sk.finalize()
+        sk.reset()
+        sk.profile()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sk.append(bits)
+        sk.finalize()
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        prof = sk.profile()
+        ev = sk.error(bits, k=10, method=0)
+        sk.close()
+        g_ms, g_n = prof["gram"]
+        r_ms, r_n = prof["rebuild"]
+        g_flop = npass[prec] * float(m * (m + 1) * d)
+        r_flop = npass[prec] * 2.0 * keep * m * d
+        g_tf = g_flop / (g_ms / max(g_n, 1) / 1e3) / 1e12 if g_n else None
+        r_tf = r_flop / (r_ms / max(r_n, 1) / 1e3) / 1e12 if r_n else None
+        if prec == "fp64":
+            cov64 = ev["cov_err"]
+        out[prec] = {
+            "rows_per_s": rows / dt,
+            "gram_us": g_ms / max(g_n, 1) * 1e3, "gram_TFLOPs": g_tf,
+            "gram_frac_of_peak": g_tf * 1e12 / peak_gram[prec] if g_tf else None,
+            "rebuild_us": r_ms / max(r_n, 1) * 1e3, "rebuild_TFLOPs": r_tf,
+            "rebuild_frac_of_peak": r_tf * 1e12 / peak_rebuild[prec] if r_tf else None,
+            "eig_ms_per_reduce": prof["eig"][0] / max(prof["eig"][1], 1),
+            "cov_err": ev["cov_err"], "abs_diff_vs_fp64": abs(ev["cov_err"] - cov64),
+        }
+    return out
+
+
+def host_cpu():
+    """The host CPU's model name and logical core count."""
+    name = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    name = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"model": name, "logical_cores": os.cpu_count()}
+
+
 def copy_calibration(nbytes, reps):
     """A plain device-to-device copy of `nbytes`, `reps` times (counter reference)."""
     import torch
@@ -192,6 +264,10 @@ def main():
                     help="largest rows per sketch in the many-sketch leg")
     ap.add_argument("--batch-seq", type=int, default=64,
                     help="sketches of the many-sketch leg also run one after another")
+    ap.add_argument("--prec-rows", type=int, default=8_000,
+                    help="rows of the d = 3,072 precision leg (0 skips it)")
+    ap.add_argument("--cpu-1thread-rows", type=int, default=20_000,
+                    help="prefix the oracle also sketches with one BLAS thread (0 skips it)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run a plain device copy of BYTES (counter reference) and exit")
     args = ap.parse_args()
@@ -229,8 +305,11 @@ def main():
     sk.profile()                      # drop warmup marks
     torch.cuda.synchronize()
     t0 = time.perf_counter()
+    per_step = []
     for _ in range(args.steps):
-        B = step()
+        ts = time.perf_counter()
+        B = step()                    # finalize synchronises the stream
+        per_step.append((time.perf_counter() - ts) * 1e3)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     prof = sk.profile()
@@ -264,12 +343,38 @@ def main():
     roof["avg_launch_us"] = avg_s * 1e6
     roof["work_per_launch"] = work
 
+    # Every stage against its own roof.
+    kernels = {}
+    for s_ in kernel_stages:
+        t_ms, nl = prof[s_]
+        a_s = t_ms / max(nl, 1) / 1e3
+        w, kd, bd = stage_work(s_, m, keep, d, m - keep)
+        if kd == "byte":
+            kernels[s_] = {"avg_launch_us": a_s * 1e6, "achieved": w / a_s / 1e9, "unit": "GB/s",
+                           "peak": PEAK_HBM / 1e9, "frac": w / a_s / PEAK_HBM, "bound": "hbm"}
+        else:
+            kernels[s_] = {"avg_launch_us": a_s * 1e6, "achieved": w / a_s / 1e12, "unit": "TFLOP/s",
+                           "peak": PEAK_FP64 / 1e12, "frac": w / a_s / PEAK_FP64,
+                           "bound": "fp64 mfma" if bd == "mfma" else "fp64 alu"}
+    # End to end: the time the roofs allow (input bytes at HBM rate, the GEMMs
+    # and a 9 m^3 eigendecomposition per ReduceRank at the FP64 peak) over the
+    # measured time.
+    nrr = st["n_reduce"]              # stats restart with every step (sketch_reset)
+    t_bytes = n * d * 4 / PEAK_HBM
+    t_gemm = nrr * (m * (m + 1) * d + 2.0 * keep * m * d) / PEAK_FP64
+    t_eig = nrr * 9.0 * m ** 3 / PEAK_FP64
+    t_min = max(t_bytes, t_gemm, t_eig)
+    alg_roof = {"t_min_ms": t_min * 1e3, "t_meas_ms": ms_per_step, "frac": t_min * 1e3 / ms_per_step,
+                "terms_ms": {"input_bytes_at_hbm": t_bytes * 1e3, "gemm_at_fp64_peak": t_gemm * 1e3,
+                             "eig_9m3_at_fp64_peak": t_eig * 1e3}}
+
     # Covariance error of the GPU sketch on the device evaluator (untimed).
     ev = sk.error(At, k=10, method=0)
     sk.close()
     del At
     batched = (batched_leg(args.batch_sketches, args.batch_nmax, args.batch_seq)
                if args.batch_sketches > 0 else None)
+    prec = precision_leg(args.prec_rows) if args.prec_rows > 0 else None
 
     cpu = None
     cov_oracle = None
@@ -290,7 +395,21 @@ def main():
         cpu = {"value": rows / dt, "unit": "rows/s", "cores": cores, "kind": "oracle",
                "sample": (f"first {rows} of the {n} rows of the same stream" if rows < n
                           else f"the whole {n}-row stream") +
-                         f", same variant and l (NumPy FP64, LAPACK SVD of the buffer), {dt:.1f} s"}
+                         f", same variant and l (NumPy FP64, LAPACK SVD of the buffer), {dt:.1f} s",
+               "host": host_cpu()}
+        r1 = min(args.cpu_1thread_rows, n)
+        if r1 > 0:
+            try:
+                from threadpoolctl import threadpool_limits
+                with threadpool_limits(limits=1):
+                    t = time.perf_counter()
+                    oracle.fd_sketch(A[:r1].astype(np.float64), l, args.variant, args.alpha)
+                    dt1 = time.perf_counter() - t
+                cpu["value_1_thread"] = r1 / dt1
+                cpu["sample_1_thread"] = f"first {r1} rows, one BLAS thread, {dt1:.1f} s"
+            except Exception as e:      # threadpoolctl missing: report without it
+                cpu["value_1_thread"] = None
+                cpu["sample_1_thread"] = f"not measured ({type(e).__name__})"
 
     out = {
         "metric": METRIC,
@@ -300,6 +419,7 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": ms_per_step,
+        "ms_per_step_median": float(np.median(per_step)),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -311,9 +431,12 @@ def main():
                    "alpha": args.alpha if args.variant in ("alpha", "fast_alpha") else None,
                    "eigensolver": "tridiagonal divide and conquer" if split else "Jacobi"},
         "roofline": roof,
+        "kernels": kernels,
+        "algorithmic_roofline": alg_roof,
         "cpu_baseline": cpu,
         "stages_ms_per_step": {s: prof[s][0] / args.steps for s in prof},
         "batched": batched,
+        "precision_leg": prec,
         "cov_err": ev["cov_err"],
         "cov_err_oracle": cov_oracle,
         "reduce_steps": st["n_reduce"],
