@@ -50,15 +50,19 @@ hipError_t launch_gram(const double* C, int ldc, int mp, double* Gpart, int kspl
 hipError_t launch_gram_reduce(const double* Gpart, int ksplit, int mp, double* G, hipStream_t s);
 // BF16 matrix-core Gram / rebuild on the FP64 buffer; npass 1 = hi*hi,
 // 3 = hi*hi + hi*lo + lo*hi (split-bf16 compensation), FP32 accumulation.
+// bfw: workspace of bf16_workspace_bytes(mp, ldc) for the buffer's pre-split
+// hi/lo halves (written by the Gram, read by the rebuild of the same
+// ReduceRank), or null to split inside the products.
 hipError_t launch_gram_lowp(const double* C, int ldc, int mp, double* Gpart, int ksplit_max, double* G,
-                            int npass, hipStream_t s);
+                            int npass, void* bfw, hipStream_t s);
+size_t bf16_workspace_bytes(int mp, int ldc);
 // FP8 (e4m3) compensated Gram: per-row scaled hi/lo codes of C in q8
 // (fp8_workspace_bytes), then three FP8 products per tile.
 hipError_t launch_gram_fp8(const double* C, int ldc, int mp, void* q8, double* Gpart, int ksplit_max,
                            double* G, hipStream_t s);
 size_t fp8_workspace_bytes(int mp, int ldc);
 hipError_t launch_rebuild_lowp(const double* Ut, const double* C, int ldc, int mp, int keep, double* out,
-                               int npass, hipStream_t s);
+                               int npass, const void* bfw, hipStream_t s);
 hipError_t launch_shrink(const double* lam, const double* V, int m, int mp, RuleParams rp,
                          const double* rownorm, int new0, int new1, double* Ut, DevStats* st,
                          hipStream_t s);

@@ -35,6 +35,7 @@ struct fdsk_sketch {
   double *G = nullptr, *Gpart = nullptr, *W = nullptr, *V = nullptr, *lam = nullptr,
          *Ut = nullptr, *rownorm = nullptr, *S1 = nullptr, *S2 = nullptr;
   void* q8 = nullptr;   // FP8 codes and scales of the buffer (FDSK_P_FP8X3)
+  void* bfw = nullptr;  // the buffer's bf16 hi/lo halves (FDSK_P_BF16, FDSK_P_BF16X3)
   int ksplit_max = 1;
   DevStats* st = nullptr;
   unsigned* bar = nullptr;
@@ -146,7 +147,7 @@ int spectrum(fdsk_sketch* s) {
   else if (s->cfg.precision == FDSK_P_FP8X3)
     HIPCHK(s, launch_gram_fp8(s->C[s->cur], s->ldc, s->mp, s->q8, s->Gpart, s->ksplit_max, s->G, s->stream));
   else
-    HIPCHK(s, launch_gram_lowp(s->C[s->cur], s->ldc, s->mp, s->Gpart, s->ksplit_max, s->G, npass,
+    HIPCHK(s, launch_gram_lowp(s->C[s->cur], s->ldc, s->mp, s->Gpart, s->ksplit_max, s->G, npass, s->bfw,
                                s->stream));
   hipEvent_t e1 = mark(s);
   if (eig_uses_trid(s->m, wk)) {
@@ -180,7 +181,9 @@ int shrink_rebuild(fdsk_sketch* s, const RuleParams& rp, int new0, int new1, con
   if (s->cfg.precision == FDSK_P_FP64)
     HIPCHK(s, launch_rebuild(s->Ut, src, s->ldc, s->mp, rp.keep, dst, s->stream));
   else
-    HIPCHK(s, launch_rebuild_lowp(s->Ut, src, s->ldc, s->mp, rp.keep, dst, npass, s->stream));
+    // The bf16 path reads the halves the Gram of the same buffer wrote (src
+    // is that buffer for every caller); FP8X3 splits in the product.
+    HIPCHK(s, launch_rebuild_lowp(s->Ut, src, s->ldc, s->mp, rp.keep, dst, npass, s->bfw, s->stream));
   add_mark(s, 3, e2, e3);
   add_mark(s, 4, e3, mark(s));
   return 0;
@@ -328,7 +331,9 @@ int sketch_create(const fdsk_config* cfg, void* hip_stream, fdsk_sketch** out) {
          oUt = take(mp2 * 8), oLam = take(s->mp * 8), oRn = take(s->mp * 8),
          oSt = take(sizeof(DevStats)), oBar = take(4 * sizeof(unsigned)),
          oRot = take(kMaxSweeps * sizeof(int)), oS1 = take(mp2 * 8), oS2 = take(mp2 * 8),
-         oQ8 = take(c.precision == FDSK_P_FP8X3 ? fp8_workspace_bytes(s->mp, s->ldc) : 0);
+         oQ8 = take(c.precision == FDSK_P_FP8X3 ? fp8_workspace_bytes(s->mp, s->ldc) : 0),
+         oBf = take((c.precision == FDSK_P_BF16 || c.precision == FDSK_P_BF16X3)
+                        ? bf16_workspace_bytes(s->mp, s->ldc) : 0);
   hipError_t e = hipMalloc(&s->arena, off);
   if (e != hipSuccess) {
     delete s;
@@ -350,6 +355,7 @@ int sketch_create(const fdsk_config* cfg, void* hip_stream, fdsk_sketch** out) {
   s->S1 = reinterpret_cast<double*>(a + oS1);
   s->S2 = reinterpret_cast<double*>(a + oS2);
   s->q8 = (c.precision == FDSK_P_FP8X3) ? static_cast<void*>(a + oQ8) : nullptr;
+  s->bfw = (c.precision == FDSK_P_BF16 || c.precision == FDSK_P_BF16X3) ? static_cast<void*>(a + oBf) : nullptr;
   e = hipMemsetAsync(s->arena, 0, off, s->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
   if (e != hipSuccess) {
@@ -704,7 +710,8 @@ extern "C" int fdsk_gram(const double* C, int32_t rows, int64_t d, int64_t ldc, 
   const int ks = std::max(1, std::min({(256 + ntiles - 1) / ntiles, ld / 256, 16}));
   DevBuf buf;
   const size_t nC = static_cast<size_t>(mp) * ld, nG = static_cast<size_t>(mp) * mp;
-  const size_t q8b = (prec == FDSK_P_FP8X3) ? fp8_workspace_bytes(mp, ld) : 0;
+  const size_t q8b = (prec == FDSK_P_FP8X3) ? fp8_workspace_bytes(mp, ld)
+                     : (prec != FDSK_P_FP64) ? bf16_workspace_bytes(mp, ld) : 0;
   if (hipMalloc(&buf.p, (nC + nG * (1 + ks)) * 8 + q8b) != hipSuccess)
     return set_err(nullptr, FDSK_ENOMEM, "fdsk_gram: workspace");
   double* Cp = static_cast<double*>(buf.p);
@@ -718,7 +725,7 @@ extern "C" int fdsk_gram(const double* C, int32_t rows, int64_t d, int64_t ldc, 
   else if (prec == FDSK_P_FP8X3)
     HIPCHK(nullptr, launch_gram_fp8(Cp, ld, mp, q8, Gpart, ks, Gp, st));
   else
-    HIPCHK(nullptr, launch_gram_lowp(Cp, ld, mp, Gpart, ks, Gp, prec == FDSK_P_BF16 ? 1 : 3, st));
+    HIPCHK(nullptr, launch_gram_lowp(Cp, ld, mp, Gpart, ks, Gp, prec == FDSK_P_BF16 ? 1 : 3, q8, st));
   HIPCHK(nullptr, hipMemcpy2DAsync(G, ldg * 8, Gp, mp * 8, rows * 8, rows, hipMemcpyDeviceToDevice, st));
   HIPCHK(nullptr, hipStreamSynchronize(st));
   return 0;

@@ -155,8 +155,198 @@ __global__ __launch_bounds__(256) void k_rebuild_bf16(const double* __restrict__
   rebuild_bf16_body<NPASS>(Ut, C, ldc, mp, keep, out, blockIdx.x, blockIdx.y);
 }
 
+// ------------------------------------------------ pre-split BF16 operands
+// The buffer's hi and lo halves, H = bf16(C) and L = bf16(C - H), written
+// once per ReduceRank (rows64 = mp rounded up to 64; rows >= mp are zero)
+// and read by the Gram and the rebuild below instead of splitting FP64
+// operands inside their loops.
+size_t bf16_workspace_bytes(int mp, int ldc) {
+  const size_t rows64 = static_cast<size_t>((mp + 63) / 64 * 64);
+  return 2 * rows64 * static_cast<size_t>(ldc) * sizeof(uint16_t);
+}
+
+__global__ __launch_bounds__(256) void k_split_bf16(const double* __restrict__ C, int ldc, int mp,
+                                                    uint16_t* __restrict__ H, uint16_t* __restrict__ L) {
+  const int r = blockIdx.y;
+  for (int c = blockIdx.x * 256 + threadIdx.x; c < ldc; c += gridDim.x * 256) {
+    uint16_t hb = 0, lb = 0;
+    if (r < mp) {
+      const double x = C[static_cast<int64_t>(r) * ldc + c];
+      hb = f32_to_bf16_bits(static_cast<float>(x));
+      lb = f32_to_bf16_bits(static_cast<float>(x - static_cast<double>(bf16_bits_to_f32(hb))));
+    }
+    H[static_cast<int64_t>(r) * ldc + c] = hb;
+    L[static_cast<int64_t>(r) * ldc + c] = lb;
+  }
+}
+
+// G partials on lower-triangular 64x64 tiles of the pre-split buffer, split-K
+// in chunks of kchunk (a multiple of 64).  Four waves; wave (wi, wj) owns the
+// 32x32 block at (32 wi, 32 wj) as 2x2 16x16 tiles.  A 64-column K slab of
+// the hi (and lo) rows of both tile rows is staged in LDS per step.
+constexpr int kBt = 64, kBk = 64, kBpad = 8;
+
+template <int NPASS>
+__global__ __launch_bounds__(256) void k_gram_bf16t(const uint16_t* __restrict__ H, const uint16_t* __restrict__ L,
+                                                    int ldc, int mp, int kchunk, double* __restrict__ Gpart) {
+  const int tile = blockIdx.x, ks = blockIdx.y;
+  int ti = static_cast<int>((sqrtf(8.0f * tile + 1.0f) - 1.0f) * 0.5f);
+  while ((ti + 1) * (ti + 2) / 2 <= tile) ++ti;
+  while (ti * (ti + 1) / 2 > tile) --ti;
+  const int tj = tile - ti * (ti + 1) / 2;
+  const int k0 = ks * kchunk;
+  const int k1 = min(ldc, k0 + kchunk);
+  __shared__ __attribute__((aligned(16))) uint16_t Ah[kBt][kBk + kBpad], Bh[kBt][kBk + kBpad];
+  __shared__ __attribute__((aligned(16))) uint16_t Al[NPASS == 3 ? kBt : 1][kBk + kBpad];
+  __shared__ __attribute__((aligned(16))) uint16_t Bl[NPASS == 3 ? kBt : 1][kBk + kBpad];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int wi = w >> 1, wj = w & 1, li = lane & 15, lq = lane >> 4;
+  f32x4 acc[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) acc[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
+  const int64_t ra = static_cast<int64_t>(ti * kBt) * ldc, rb = static_cast<int64_t>(tj * kBt) * ldc;
+  for (int kk = k0; kk < k1; kk += kBk) {
+#pragma unroll
+    for (int p = 0; p < 2; ++p) {
+      const int idx = tid + 256 * p, r = idx >> 3, c = (idx & 7) * 8;
+      const int64_t o = static_cast<int64_t>(r) * ldc + kk + c;
+      *reinterpret_cast<uint4*>(&Ah[r][c]) = *reinterpret_cast<const uint4*>(H + ra + o);
+      *reinterpret_cast<uint4*>(&Bh[r][c]) = *reinterpret_cast<const uint4*>(H + rb + o);
+      if (NPASS == 3) {
+        *reinterpret_cast<uint4*>(&Al[r][c]) = *reinterpret_cast<const uint4*>(L + ra + o);
+        *reinterpret_cast<uint4*>(&Bl[r][c]) = *reinterpret_cast<const uint4*>(L + rb + o);
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k2 = 0; k2 < kBk; k2 += 32) {
+      bf16x8_t ah[2], al[2], bh[2], bl[2];
+#pragma unroll
+      for (int a = 0; a < 2; ++a) {
+        const int r = wi * 32 + a * 16 + li;
+        ah[a] = *reinterpret_cast<const bf16x8_t*>(&Ah[r][k2 + 8 * lq]);
+        if (NPASS == 3) al[a] = *reinterpret_cast<const bf16x8_t*>(&Al[r][k2 + 8 * lq]);
+      }
+#pragma unroll
+      for (int b = 0; b < 2; ++b) {
+        const int r = wj * 32 + b * 16 + li;
+        bh[b] = *reinterpret_cast<const bf16x8_t*>(&Bh[r][k2 + 8 * lq]);
+        if (NPASS == 3) bl[b] = *reinterpret_cast<const bf16x8_t*>(&Bl[r][k2 + 8 * lq]);
+      }
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) acc[a][b] = mfma_split<NPASS>(ah[a], al[a], bh[b], bl[b], acc[a][b]);
+    }
+    __syncthreads();
+  }
+  double* out = Gpart + static_cast<int64_t>(ks) * mp * mp;
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int row = ti * kBt + wi * 32 + a * 16 + 4 * lq + v;
+        const int col = tj * kBt + wj * 32 + b * 16 + li;
+        if (row < mp && col < mp) out[static_cast<int64_t>(row) * mp + col] = static_cast<double>(acc[a][b][v]);
+      }
+}
+
+// out[0:keep, :] = Ut[0:keep, 0:mp] * C with C's hi/lo from the pre-split
+// arrays (Ut is split in the loop: it is small).  Tile 32 rows x 64 columns;
+// C's 32x64 slab is staged transposed in LDS so that each B fragment is one
+// 16-byte read.
+template <int NPASS>
+__global__ __launch_bounds__(256) void k_rebuild_bf16t(const double* __restrict__ Ut, const uint16_t* __restrict__ H,
+                                                       const uint16_t* __restrict__ L, int ldc, int mp, int keep,
+                                                       double* __restrict__ out) {
+  const int r0 = blockIdx.y * 32, c0 = blockIdx.x * 64;
+  __shared__ double As[32][33];
+  __shared__ __attribute__((aligned(16))) uint16_t BhT[64][32 + kBpad];
+  __shared__ __attribute__((aligned(16))) uint16_t BlT[NPASS == 3 ? 64 : 1][32 + kBpad];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int wi = w >> 1, wj = w & 1, li = lane & 15, lq = lane >> 4;
+  f32x4 acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = {0.f, 0.f, 0.f, 0.f};
+  for (int k0 = 0; k0 < mp; k0 += 32) {
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int idx = tid + e * 256, r = idx >> 5, c = idx & 31;
+      As[r][c] = Ut[static_cast<int64_t>(r0 + r) * mp + k0 + c];
+    }
+    {
+      const int kr = tid >> 3, nc = (tid & 7) * 8;
+      const int64_t o = static_cast<int64_t>(k0 + kr) * ldc + c0 + nc;
+      const uint4 hv = *reinterpret_cast<const uint4*>(H + o);
+      const uint16_t* hs = reinterpret_cast<const uint16_t*>(&hv);
+#pragma unroll
+      for (int t = 0; t < 8; ++t) BhT[nc + t][kr] = hs[t];
+      if (NPASS == 3) {
+        const uint4 lv = *reinterpret_cast<const uint4*>(L + o);
+        const uint16_t* ls = reinterpret_cast<const uint16_t*>(&lv);
+#pragma unroll
+        for (int t = 0; t < 8; ++t) BlT[nc + t][kr] = ls[t];
+      }
+    }
+    __syncthreads();
+    bf16x8_t ah, al;
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+      __bf16 h, l;
+      split_bf16(As[wi * 16 + li][8 * lq + t], h, l);
+      ah[t] = h;
+      al[t] = l;
+    }
+    const int n0 = wj * 32 + li, n1 = n0 + 16;
+    const bf16x8_t b0h = *reinterpret_cast<const bf16x8_t*>(&BhT[n0][8 * lq]);
+    const bf16x8_t b1h = *reinterpret_cast<const bf16x8_t*>(&BhT[n1][8 * lq]);
+    bf16x8_t b0l = b0h, b1l = b1h;
+    if (NPASS == 3) {
+      b0l = *reinterpret_cast<const bf16x8_t*>(&BlT[n0][8 * lq]);
+      b1l = *reinterpret_cast<const bf16x8_t*>(&BlT[n1][8 * lq]);
+    }
+    acc0 = mfma_split<NPASS>(ah, al, b0h, b0l, acc0);
+    acc1 = mfma_split<NPASS>(ah, al, b1h, b1l, acc1);
+    __syncthreads();
+  }
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int row = r0 + wi * 16 + 4 * lq + v;
+    if (row < keep) {
+      const int64_t o = static_cast<int64_t>(row) * ldc + c0 + wj * 32 + li;
+      out[o] = static_cast<double>(acc0[v]);
+      out[o + 16] = static_cast<double>(acc1[v]);
+    }
+  }
+}
+
 hipError_t launch_gram_lowp(const double* C, int ldc, int mp, double* Gpart, int ksplit_max, double* G,
-                            int npass, hipStream_t s) {
+                            int npass, void* bfw, hipStream_t s) {
+  if (bfw) {
+    const int rows64 = (mp + 63) / 64 * 64;
+    uint16_t* H = static_cast<uint16_t*>(bfw);
+    uint16_t* L = H + static_cast<size_t>(rows64) * ldc;
+    hipLaunchKernelGGL(k_split_bf16, dim3((ldc + 255) / 256, rows64), dim3(256), 0, s, C, ldc, mp, H, L);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const int T = rows64 / kBt;
+    const int ntiles = T * (T + 1) / 2;
+    int ksplit = (256 + ntiles - 1) / ntiles;
+    ksplit = std::min(ksplit, std::max(1, ldc / 256));
+    ksplit = std::min(ksplit, ksplit_max);
+    int kchunk = (ldc + ksplit - 1) / ksplit;
+    kchunk = (kchunk + kBk - 1) / kBk * kBk;
+    ksplit = (ldc + kchunk - 1) / kchunk;
+    if (npass == 3)
+      hipLaunchKernelGGL(k_gram_bf16t<3>, dim3(ntiles, ksplit), dim3(256), 0, s, H, L, ldc, mp, kchunk, Gpart);
+    else
+      hipLaunchKernelGGL(k_gram_bf16t<1>, dim3(ntiles, ksplit), dim3(256), 0, s, H, L, ldc, mp, kchunk, Gpart);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return launch_gram_reduce(Gpart, ksplit, mp, G, s);
+  }
   const int T = mp / 32;
   const int ntiles = T * (T + 1) / 2;
   int ksplit = (256 + ntiles - 1) / ntiles;
@@ -175,9 +365,19 @@ hipError_t launch_gram_lowp(const double* C, int ldc, int mp, double* Gpart, int
 }
 
 hipError_t launch_rebuild_lowp(const double* Ut, const double* C, int ldc, int mp, int keep, double* out,
-                               int npass, hipStream_t s) {
+                               int npass, const void* bfw, hipStream_t s) {
   if (keep <= 0) return hipSuccess;
   dim3 grid(ldc / 64, (keep + 31) / 32);
+  if (bfw) {
+    const int rows64 = (mp + 63) / 64 * 64;
+    const uint16_t* H = static_cast<const uint16_t*>(bfw);
+    const uint16_t* L = H + static_cast<size_t>(rows64) * ldc;
+    if (npass == 3)
+      hipLaunchKernelGGL(k_rebuild_bf16t<3>, grid, dim3(256), 0, s, Ut, H, L, ldc, mp, keep, out);
+    else
+      hipLaunchKernelGGL(k_rebuild_bf16t<1>, grid, dim3(256), 0, s, Ut, H, L, ldc, mp, keep, out);
+    return hipGetLastError();
+  }
   if (npass == 3)
     hipLaunchKernelGGL(k_rebuild_bf16<3>, grid, dim3(256), 0, s, Ut, C, ldc, mp, keep, out);
   else
