@@ -89,9 +89,15 @@ struct Plan {
 };
 
 // Upload a plan and launch it round by round, at most `cap` sketches per
-// launch.  The device task buffer is reused by the next call, so the stream
-// is synchronised before returning.
-int run_plan(fdsk_batch* b, const Plan& p, int dt, int cap) {
+// launch.  A round's ReduceRanks are put in descending order of buffer rows,
+// so that the longest workgroups are dispatched first (the order changes no
+// result: every task works on its own sketch).  The device task buffer is
+// reused by the next call, so the stream is synchronised before returning.
+int run_plan(fdsk_batch* b, Plan& p, int dt, int cap) {
+  for (auto& v : p.rr)
+    std::stable_sort(v.begin(), v.end(), [b](const GroupRR& x, const GroupRR& y) {
+      return b->sk[x.sk].m > b->sk[y.sk].m;
+    });
   size_t ni = 0, nr = 0;
   for (auto& v : p.ing) ni += v.size();
   for (auto& v : p.rr) nr += v.size();

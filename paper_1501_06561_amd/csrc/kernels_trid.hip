@@ -5,8 +5,9 @@
 //
 // * k_tridiag_reg / k_tridiag: Householder reduction Q^T G Q = T (T
 //   tridiagonal) in one workgroup, the matrix held in registers across the
-//   workgroup (m <= kTridRegMax) or, above that, its lower triangle packed by
-//   columns in the workspace W itself (L2-resident).  Reflector
+//   workgroup (m <= kTridRegMax).  Above that, k_tridiag takes the first
+//   m - kTridRegMax columns with the lower triangle packed by columns in the
+//   workspace W itself (L2-resident), and the register kernel the rest.  Reflector
 //   H_k = I - tau_k u_k u_k^T with u_k = (0,..,0, 1, v_k) zeroes column k below
 //   the subdiagonal; the trailing block is updated by the symmetric rank-2
 //   form A <- A - v w^T - w v^T, w = p - (tau/2)(p.v) v, p = tau A v.
@@ -52,8 +53,12 @@ __device__ __forceinline__ double wave_max(double v) {
 // Output in W (doubles): [0, P) packed columns (column k holds v_k below the
 // subdiagonal, P = n(n+1)/2), then tau[n], d[n], e[n], scale.  d and e are of
 // G * 2^-s (an exact power-of-two scaling by the largest |g|); scale = 2^s.
+// With kend < n - 2 only columns [0, kend) are reduced: W then holds their
+// reflectors, d, e and tau, the scale, and the updated trailing block
+// (columns >= kend of the packed triangle), which the register kernel
+// finishes (its argument h = kend).
 __device__ __forceinline__ void tridiag_body(const double* __restrict__ G, int n, int ldg,
-                                             double* __restrict__ W) {
+                                             double* __restrict__ W, int kend) {
   __shared__ double p[kTridGlobalMax];
   double* const A = W;
   __shared__ double red[16];
@@ -80,7 +85,7 @@ __device__ __forceinline__ void tridiag_body(const double* __restrict__ G, int n
   double* tauG = W + P;
   double* dG = tauG + n;
   double* eG = dG + n;
-  for (int k = 0; k + 2 < n; ++k) {
+  for (int k = 0; k + 2 < n && k < kend; ++k) {
     const int L = n - k - 1;            // length of the column below the diagonal
     const int ck = colstart(k, n);      // A(k,k); A(k+1+t, k) at ck + 1 + t
     if (w == 0) {
@@ -161,22 +166,24 @@ __device__ __forceinline__ void tridiag_body(const double* __restrict__ G, int n
     }
   }
   if (tid == 0) {
-    if (n >= 2) {
-      const int c2 = colstart(n - 2, n);
-      dG[n - 2] = A[c2];
-      eG[n - 2] = A[c2 + 1];
-      tauG[n - 2] = 0.0;
+    if (kend >= n - 2) {
+      if (n >= 2) {
+        const int c2 = colstart(n - 2, n);
+        dG[n - 2] = A[c2];
+        eG[n - 2] = A[c2 + 1];
+        tauG[n - 2] = 0.0;
+      }
+      dG[n - 1] = A[colstart(n - 1, n)];
+      tauG[n - 1] = 0.0;
+      eG[n - 1] = 0.0;
     }
-    dG[n - 1] = A[colstart(n - 1, n)];
-    tauG[n - 1] = 0.0;
-    eG[n - 1] = 0.0;
     W[P + 3 * n] = ldexp(1.0, sexp);
   }
 }
 
 __global__ __launch_bounds__(TNT) void k_tridiag(const double* __restrict__ G, int n, int ldg,
-                                                 double* __restrict__ W) {
-  tridiag_body(G, n, ldg, W);
+                                                 double* __restrict__ W, int kend) {
+  tridiag_body(G, n, ldg, W, kend);
 }
 
 // ------------------------------------------------- reduce, in registers
@@ -194,12 +201,16 @@ __global__ __launch_bounds__(TNT) void k_tridiag(const double* __restrict__ G, i
 // Two barriers per column.  Slots whose rows (per wave) or columns (for all
 // lanes) lie entirely in the finished part are skipped; v and w are zero
 // outside the trailing block, so partially finished slots need no masking.
+// With h > 0 the kernel continues a reduction that k_tridiag took through
+// columns [0, h): it loads the trailing (ng-h) x (ng-h) block, already
+// scaled, from W's packed triangle and writes reflectors h.. in place.
 constexpr int RNT = 512;
 constexpr int kTridRegMax = 208;   // 32 * 7 rows, 16 * 13 columns
 
 template <int RP, int CP>
-__device__ __forceinline__ void tridiag_reg_body(const double* __restrict__ G, int n, int ldg,
-                                                 double* __restrict__ W) {
+__device__ __forceinline__ void tridiag_reg_body(const double* __restrict__ G, int ng, int ldg,
+                                                 double* __restrict__ W, int h) {
+  const int n = ng - h;                 // order of the block reduced here
   constexpr int NB = (32 * RP > 16 * CP) ? 32 * RP : 16 * CP;
   constexpr int NL = (NB + 63) / 64;    // strided entries per lane
   __shared__ double colb[2][64 * NL];
@@ -224,8 +235,12 @@ __device__ __forceinline__ void tridiag_reg_body(const double* __restrict__ G, i
     for (int b = 0; b < CP; ++b) {
       const int k = tk + 16 * b;
       double g = 0.0;
-      if (i < n && k < n)
-        g = (i >= k) ? G[static_cast<int64_t>(i) * ldg + k] : G[static_cast<int64_t>(k) * ldg + i];
+      if (i < n && k < n) {
+        if (h == 0)
+          g = (i >= k) ? G[static_cast<int64_t>(i) * ldg + k] : G[static_cast<int64_t>(k) * ldg + i];
+        else
+          g = (i >= k) ? W[colstart(h + k, ng) + i - k] : W[colstart(h + i, ng) + k - i];
+      }
       A[a][b] = g;
       amax = fmax(amax, fabs(g));
     }
@@ -236,7 +251,7 @@ __device__ __forceinline__ void tridiag_reg_body(const double* __restrict__ G, i
   double gmax = 0.0;
   for (int i = 0; i < RNT / 64; ++i) gmax = fmax(gmax, red[i]);
   const int sexp = (gmax > 0.0 && gmax < INFINITY) ? ilogb(gmax) : 0;
-  const double sc = ldexp(1.0, -sexp);
+  const double sc = (h == 0) ? ldexp(1.0, -sexp) : 1.0;
 #pragma unroll
   for (int a = 0; a < RP; ++a)
 #pragma unroll
@@ -249,10 +264,10 @@ __device__ __forceinline__ void tridiag_reg_body(const double* __restrict__ G, i
     }
   }
   __syncthreads();
-  const int P = n * (n + 1) / 2;
+  const int P = ng * (ng + 1) / 2;
   double* tauG = W + P;
-  double* dG = tauG + n;
-  double* eG = dG + n;
+  double* dG = tauG + ng;
+  double* eG = dG + ng;
   // Column slots b < bend hold a column < n.
   const int bend = (n + 15) >> 4;
   double* const vv = vwave[wv];
@@ -292,7 +307,7 @@ __device__ __forceinline__ void tridiag_reg_body(const double* __restrict__ G, i
     }
     __builtin_amdgcn_wave_barrier();
     if (wv == 0) {
-      const int ck = colstart(k, n);
+      const int ck = colstart(h + k, ng);
 #pragma unroll
       for (int q = 0; q < NL; ++q) {
         const int t = lane + 64 * q;
@@ -301,9 +316,9 @@ __device__ __forceinline__ void tridiag_reg_body(const double* __restrict__ G, i
       if (lane == 0) {
         W[ck] = cb[k];
         W[ck + 1] = 1.0;
-        tauG[k] = tau;
-        dG[k] = cb[k];
-        eG[k] = beta;
+        tauG[h + k] = tau;
+        dG[h + k] = cb[k];
+        eG[h + k] = beta;
       }
     }
     if (tau != 0.0) {                  // the same in every wave
@@ -385,30 +400,30 @@ __device__ __forceinline__ void tridiag_reg_body(const double* __restrict__ G, i
   if (tid == 0) {
     if (n >= 2) {
       const double* cb = colb[(n - 2) & 1];
-      dG[n - 2] = cb[n - 2];
-      eG[n - 2] = cb[n - 1];
-      tauG[n - 2] = 0.0;
-      W[colstart(n - 2, n)] = cb[n - 2];
-      W[colstart(n - 2, n) + 1] = cb[n - 1];
+      dG[ng - 2] = cb[n - 2];
+      eG[ng - 2] = cb[n - 1];
+      tauG[ng - 2] = 0.0;
+      W[colstart(ng - 2, ng)] = cb[n - 2];
+      W[colstart(ng - 2, ng) + 1] = cb[n - 1];
     }
-    tauG[n - 1] = 0.0;
-    eG[n - 1] = 0.0;
-    W[P + 3 * n] = ldexp(1.0, sexp);
+    tauG[ng - 1] = 0.0;
+    eG[ng - 1] = 0.0;
+    if (h == 0) W[P + 3 * ng] = ldexp(1.0, sexp);
   }
 #pragma unroll
   for (int a = 0; a < RP; ++a)
 #pragma unroll
     for (int b = 0; b < CP; ++b)
       if (ti + 32 * a == n - 1 && tk + 16 * b == n - 1) {
-        dG[n - 1] = A[a][b];
-        W[colstart(n - 1, n)] = A[a][b];
+        dG[ng - 1] = A[a][b];
+        W[colstart(ng - 1, ng)] = A[a][b];
       }
 }
 
 template <int RP, int CP>
 __global__ __launch_bounds__(RNT) void k_tridiag_reg(const double* __restrict__ G, int n, int ldg,
-                                                     double* __restrict__ W) {
-  tridiag_reg_body<RP, CP>(G, n, ldg, W);
+                                                     double* __restrict__ W, int h) {
+  tridiag_reg_body<RP, CP>(G, n, ldg, W, h);
 }
 
 // ------------------------------------------------------ divide and conquer
@@ -1002,10 +1017,15 @@ __device__ __forceinline__ int nth_flagged(const double* __restrict__ flags, int
   return col;
 }
 
+// Packed reflectors of an order up to 64*NPL, staged in LDS (n <= kTridMax).
+constexpr int bt_pack(int npl) {
+  return (64 * npl) * (64 * npl + 1) / 2 < TRI_PACK ? (64 * npl) * (64 * npl + 1) / 2 : TRI_PACK;
+}
+
 template <int NPL, bool GA>
 __device__ __forceinline__ void backtr_body(const double* __restrict__ W, int n, double* __restrict__ Z,
                                             int ldz, int cb) {
-  __shared__ double R_lds[GA ? 1 : TRI_PACK];
+  __shared__ double R_lds[GA ? 1 : bt_pack(NPL)];
   __shared__ double tau_lds[kTridGlobalMax];
   const double* const R = GA ? W : R_lds;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
@@ -1067,13 +1087,20 @@ __global__ __launch_bounds__(BNT) void k_backtr(const double* __restrict__ W, in
 hipError_t launch_tridiag(const double* G, int m, int mp, EigWork wk, hipStream_t s) {
   if (m < 1 || m > kTridGlobalMax || mp < m) return hipErrorInvalidValue;
   if (m <= 64)
-    hipLaunchKernelGGL((k_tridiag_reg<2, 4>), dim3(1), dim3(RNT), 0, s, G, m, mp, wk.W);
+    hipLaunchKernelGGL((k_tridiag_reg<2, 4>), dim3(1), dim3(RNT), 0, s, G, m, mp, wk.W, 0);
   else if (m <= 128)
-    hipLaunchKernelGGL((k_tridiag_reg<4, 8>), dim3(1), dim3(RNT), 0, s, G, m, mp, wk.W);
+    hipLaunchKernelGGL((k_tridiag_reg<4, 8>), dim3(1), dim3(RNT), 0, s, G, m, mp, wk.W, 0);
   else if (m <= kTridRegMax)
-    hipLaunchKernelGGL((k_tridiag_reg<7, 13>), dim3(1), dim3(RNT), 0, s, G, m, mp, wk.W);
-  else
-    hipLaunchKernelGGL(k_tridiag, dim3(1), dim3(TNT), 0, s, G, m, mp, wk.W);
+    hipLaunchKernelGGL((k_tridiag_reg<7, 13>), dim3(1), dim3(RNT), 0, s, G, m, mp, wk.W, 0);
+  else {
+    // The first m - kTridRegMax columns on the packed triangle in W, the
+    // rest in registers.
+    const int h = m - kTridRegMax;
+    hipLaunchKernelGGL(k_tridiag, dim3(1), dim3(TNT), 0, s, G, m, mp, wk.W, h);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_tridiag_reg<7, 13>), dim3(1), dim3(RNT), 0, s, G, m, mp, wk.W, h);
+  }
   return hipGetLastError();
 }
 
@@ -1107,20 +1134,26 @@ hipError_t launch_eig_trid(const double* G, int m, int mp, double* lam, double* 
 }
 
 // ------------------------------------------------------ grouped (batches)
-// Size class [LO, HI] of buffer rows; tasks of other classes return at once.
-template <int RP, int CP, int LO, int HI>
+// Every size class in one launch, so that a round's reductions of different
+// sizes share the machine instead of running one class after another.
+// Buffers above the register capacity continue the packed-triangle head.
 __global__ __launch_bounds__(RNT) void kg_tridiag_reg(const GroupSketch* __restrict__ SK,
                                                       const GroupRR* __restrict__ T) {
   const GroupSketch& s = SK[T[blockIdx.x].sk];
-  if (s.m < LO || s.m > HI) return;
-  tridiag_reg_body<RP, CP>(s.G, s.m, s.mp, s.W);
+  if (s.m <= 64)
+    tridiag_reg_body<2, 4>(s.G, s.m, s.mp, s.W, 0);
+  else if (s.m <= 128)
+    tridiag_reg_body<4, 8>(s.G, s.m, s.mp, s.W, 0);
+  else
+    tridiag_reg_body<7, 13>(s.G, s.m, s.mp, s.W, max(0, s.m - kTridRegMax));
 }
 
+// The head of the reduction of buffers above the register capacity.
 __global__ __launch_bounds__(TNT) void kg_tridiag(const GroupSketch* __restrict__ SK,
                                                   const GroupRR* __restrict__ T) {
   const GroupSketch& s = SK[T[blockIdx.x].sk];
   if (s.m <= kTridRegMax) return;        // the register variant's task
-  tridiag_body(s.G, s.m, s.mp, s.W);
+  tridiag_body(s.G, s.m, s.mp, s.W, s.m - kTridRegMax);
 }
 
 __global__ __launch_bounds__(TNT) void kg_dc(const GroupSketch* __restrict__ SK,
@@ -1129,44 +1162,45 @@ __global__ __launch_bounds__(TNT) void kg_dc(const GroupSketch* __restrict__ SK,
   dc_body(s.W, s.m, s.V, s.mp, s.S1, s.S2, s.lam, s.st, min(s.m, s.l));
 }
 
-template <bool GA>
+// Size class [LO, HI] of buffer rows, with the LDS staging sized for it;
+// tasks of other classes return at once.
+template <int NPL, bool GA, int LO, int HI>
 __global__ __launch_bounds__(BNT) void kg_backtr(const GroupSketch* __restrict__ SK,
                                                  const GroupRR* __restrict__ T) {
   const GroupSketch& s = SK[T[blockIdx.y].sk];
-  if ((s.m > kTridMax) != GA) return;
+  if (s.m < LO || s.m > HI) return;
   if (static_cast<int>(blockIdx.x) * (BNT / 64) >= s.m) return;
-  backtr_body<4, GA>(s.W, s.m, s.V, s.mp, blockIdx.x);
+  backtr_body<NPL, GA>(s.W, s.m, s.V, s.mp, blockIdx.x);
+}
+
+template <int NPL, bool GA, int LO, int HI>
+hipError_t launch_group_backtr(const GroupSketch* sk, const GroupRR* t, int nt, int max_m, hipStream_t s) {
+  if (max_m < LO) return hipSuccess;
+  const int top = min(max_m, HI);
+  const dim3 g((top + BNT / 64 - 1) / (BNT / 64), nt);
+  hipLaunchKernelGGL((kg_backtr<NPL, GA, LO, HI>), g, dim3(BNT), 0, s, sk, t);
+  return hipGetLastError();
 }
 
 hipError_t launch_group_eig(const GroupSketch* sk, const GroupRR* t, int nt, int max_m, hipStream_t s) {
   if (nt <= 0) return hipSuccess;
   if (max_m > kTridGlobalMax) return hipErrorInvalidValue;
-  const bool big = max_m > kTridMax;
-  hipLaunchKernelGGL((kg_tridiag_reg<2, 4, 1, 64>), dim3(nt), dim3(RNT), 0, s, sk, t);
-  hipError_t e = hipGetLastError();
-  if (e == hipSuccess && max_m > 64) {
-    hipLaunchKernelGGL((kg_tridiag_reg<4, 8, 65, 128>), dim3(nt), dim3(RNT), 0, s, sk, t);
-    e = hipGetLastError();
-  }
-  if (e == hipSuccess && max_m > 128) {
-    hipLaunchKernelGGL((kg_tridiag_reg<7, 13, 129, kTridRegMax>), dim3(nt), dim3(RNT), 0, s, sk, t);
-    e = hipGetLastError();
-  }
-  if (e == hipSuccess && max_m > kTridRegMax) {
+  hipError_t e = hipSuccess;
+  if (max_m > kTridRegMax) {
     hipLaunchKernelGGL(kg_tridiag, dim3(nt), dim3(TNT), 0, s, sk, t);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) {
+    hipLaunchKernelGGL(kg_tridiag_reg, dim3(nt), dim3(RNT), 0, s, sk, t);
     e = hipGetLastError();
   }
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(kg_dc, dim3(nt), dim3(TNT), 0, s, sk, t);
   e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  const dim3 g((max_m + BNT / 64 - 1) / (BNT / 64), nt);
-  hipLaunchKernelGGL(kg_backtr<false>, g, dim3(BNT), 0, s, sk, t);
-  e = hipGetLastError();
-  if (e == hipSuccess && big) {
-    hipLaunchKernelGGL(kg_backtr<true>, g, dim3(BNT), 0, s, sk, t);
-    e = hipGetLastError();
-  }
+  if (e == hipSuccess) e = launch_group_backtr<1, false, 1, 64>(sk, t, nt, max_m, s);
+  if (e == hipSuccess) e = launch_group_backtr<2, false, 65, 128>(sk, t, nt, max_m, s);
+  if (e == hipSuccess) e = launch_group_backtr<4, false, 129, kTridMax>(sk, t, nt, max_m, s);
+  if (e == hipSuccess) e = launch_group_backtr<4, true, kTridMax + 1, kTridGlobalMax>(sk, t, nt, max_m, s);
   return e;
 }
 

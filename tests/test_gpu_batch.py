@@ -59,9 +59,9 @@ def _check(cfg, A, B, st, gram_tol):
 
 
 def test_batch_matches_oracle_mixed_shapes():
-    """Buffer rows 8..256 (both storage forms of the tridiagonal reduction:
-    LDS up to 200 rows, workspace above), d ragged against the 64-column
-    padding, all four variants."""
+    """Buffer rows 8..256 (every size class of the tridiagonal reduction:
+    registers only up to 208 rows, a packed-triangle head then registers
+    above), d ragged against the 64-column padding, all four variants."""
     cfgs, mats = _make_batch(1, 24, (20, 300), (4, 129), (50, 2500))
     outs, stats = _run(cfgs, mats)
     for cfg, A, B, st in zip(cfgs, mats, outs, stats):

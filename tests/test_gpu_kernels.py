@@ -33,11 +33,13 @@ def _check_eigh(Gm, tol=1e-11, method="auto"):
 
 
 @pytest.mark.parametrize("method", ["auto", "jacobi"])
-@pytest.mark.parametrize("m", [1, 2, 3, 7, 33, 40, 64, 99, 100, 101, 128, 199, 200, 201, 230, 256, 333, 513, 1024])
+@pytest.mark.parametrize("m", [1, 2, 3, 7, 33, 40, 64, 99, 100, 101, 128, 199, 200, 201, 208, 209, 230, 256, 333,
+                               513, 1024])
 def test_eigh_random_psd(m, method):
-    """"auto" is the tridiagonal divide-and-conquer route up to m = 256 (packed
-    matrix in LDS up to 200, in the workspace above)."""
-    if method == "jacobi" and m in (3, 33, 64, 199, 201, 230):
+    """"auto" is the tridiagonal divide-and-conquer route up to m = 256 (the
+    matrix in registers up to 208; above, the first m - 208 columns on the
+    packed triangle in the workspace, the rest in registers)."""
+    if method == "jacobi" and m in (3, 33, 64, 199, 201, 208, 209, 230):
         pytest.skip("sizes added for the divide-and-conquer route")
     rng = np.random.default_rng(m)
     X = rng.standard_normal((m, 2 * m + 3)) * np.geomspace(1, 1e-3, 2 * m + 3)
