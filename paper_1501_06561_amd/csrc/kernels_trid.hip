@@ -57,112 +57,299 @@ __device__ __forceinline__ double wave_max(double v) {
 // reflectors, d, e and tau, the scale, and the updated trailing block
 // (columns >= kend of the packed triangle), which the register kernel
 // finishes (its argument h = kend).
+//
+// Blocked by panels of HNB columns (the blocked form of the Householder
+// tridiagonal reduction): within a panel the packed triangle keeps its
+// values from the panel's start, A_0, and the reflectors' v and
+// w = p - (tau/2)(p.v) v are collected in LDS; column k of the current matrix
+// is A_0(:,k) - sum_q (v_q w_q(k) + w_q v_q(k)), and p = tau (A_0 v -
+// sum_q (v_q (w_q.v) + w_q (v_q.v))).  The trailing block is written once
+// per panel (A -= V W^T + W V^T).  Per column the triangle is only read, one
+// wave per column (every HW-th), with each lane keeping the rows
+// lane + 64 t.  512 threads, two barriers per column.
+constexpr int HNT = 512;                        // threads of the packed-triangle reduction
+constexpr int HW = HNT / 64;                    // its waves
+constexpr int HNB = 8;                          // panel width (<= HW)
+constexpr int HT = kTridGlobalMax / 64;         // rows per lane
+
+template <int N>
+__device__ __forceinline__ double pick(const double (&x)[N], int t) {
+  double r = x[0];
+#pragma unroll
+  for (int q = 1; q < N; ++q) r = (t == q) ? x[q] : r;
+  return r;
+}
+
 __device__ __forceinline__ void tridiag_body(const double* __restrict__ G, int n, int ldg,
                                              double* __restrict__ W, int kend) {
-  __shared__ double p[kTridGlobalMax];
+  __shared__ double Vp[HNB][kTridGlobalMax];     // the panel's v
+  __shared__ double Wq[HNB][kTridGlobalMax];     // the panel's w
+  __shared__ double ys[HW][kTridGlobalMax];      // per-wave partial A_0 v
+  __shared__ double colw[HW][kTridGlobalMax];    // each wave's copy of the current column
+  __shared__ double vw[HW][kTridGlobalMax];      // each wave's copy of v
+  __shared__ double pl[kTridGlobalMax];
+  __shared__ double ac[kTridGlobalMax];          // next column: A_0 minus the older corrections
+  __shared__ double sdp[4][kTridGlobalMax];      // row-group partials of sum_{i >= jc} A_0(i,jc) v_i
+  __shared__ double dg0[kTridGlobalMax];         // diagonal of A_0
+  __shared__ double cs[2][HNB];                  // w_q.v and v_q.v
+  __shared__ double pd[HT];
+  __shared__ double red[HW];
+  static_assert(HNB <= HW, "one wave per panel column in the corrections");
   double* const A = W;
-  __shared__ double red[16];
-  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int tid = threadIdx.x, lane = tid & 63, wv = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int P = n * (n + 1) / 2;
+  // The lower triangle, read by rows (coalesced): its largest magnitude,
+  // then scaled into the packed columns.
   double amax = 0.0;
-  for (int j = w; j < n; j += TNT / 64) {
-    const int cj = colstart(j, n);
-    for (int i = j + lane; i < n; i += 64) {
-      const double g = G[static_cast<int64_t>(i) * ldg + j];
-      A[cj + i - j] = g;
-      amax = fmax(amax, fabs(g));
-    }
+  for (int i = wv; i < n; i += HW) {
+    const double* gi = G + static_cast<int64_t>(i) * ldg;
+    for (int j = lane; j <= i; j += 64) amax = fmax(amax, fabs(gi[j]));
   }
   amax = wave_max(amax);
-  if (lane == 0) red[w] = amax;
+  if (lane == 0) red[wv] = amax;
+  for (int e = tid; e < HNB * kTridGlobalMax; e += HNT) {
+    (&Vp[0][0])[e] = 0.0;
+    (&Wq[0][0])[e] = 0.0;
+  }
   __syncthreads();
   double gmax = 0.0;
-  for (int i = 0; i < TNT / 64; ++i) gmax = fmax(gmax, red[i]);
+  for (int i = 0; i < HW; ++i) gmax = fmax(gmax, red[i]);
   const int sexp = (gmax > 0.0 && gmax < INFINITY) ? ilogb(gmax) : 0;
   const double sc = ldexp(1.0, -sexp);
-  for (int e = tid; e < P; e += TNT) A[e] *= sc;
+  for (int i = wv; i < n; i += HW) {
+    const double* gi = G + static_cast<int64_t>(i) * ldg;
+    for (int j = lane; j <= i; j += 64) A[colstart(j, n) + i - j] = gi[j] * sc;
+    if (lane == 0) dg0[i] = gi[i] * sc;
+  }
   __syncthreads();
   double* tauG = W + P;
   double* dG = tauG + n;
   double* eG = dG + n;
-  for (int k = 0; k + 2 < n && k < kend; ++k) {
-    const int L = n - k - 1;            // length of the column below the diagonal
-    const int ck = colstart(k, n);      // A(k,k); A(k+1+t, k) at ck + 1 + t
-    if (w == 0) {
-      const double alpha = A[ck + 1];   // read by every lane before lane 0 overwrites it
+  const int kstop = min(kend, n - 2);
+  double* const cw = colw[wv];
+  double* const vv = vw[wv];
+  // a: column k of the current matrix (rows lane + 64 t, zero above k and
+  // at n and beyond); vprev/wprev: this wave's v and w of the previous step.
+  double a[HT], vprev[HT], wprev[HT];
+#pragma unroll
+  for (int t = 0; t < HT; ++t) {
+    const int i = lane + 64 * t;
+    const double x = A[min(i, n - 1)];
+    a[t] = (i < n) ? x : 0.0;
+    vprev[t] = 0.0;
+    wprev[t] = 0.0;
+  }
+  for (int k0 = 0; k0 < kstop; k0 += HNB) {
+    const int nb = min(HNB, kstop - k0);
+    for (int j = 0; j < nb; ++j) {
+      const int k = k0 + j, k1 = k + 1;
+      // Reflector, formed by every wave in the same order.
+#pragma unroll
+      for (int t = 0; t < HT; ++t) cw[lane + 64 * t] = a[t];
+      __builtin_amdgcn_wave_barrier();
+      const double alpha = cw[k1], dk = cw[k];
       double s2 = 0.0;
-      for (int t = 1 + lane; t < L; t += 64) {
-        const double x = A[ck + 1 + t];
-        s2 += x * x;
+#pragma unroll
+      for (int t = 0; t < HT; ++t) {
+        const double x = (lane + 64 * t >= k + 2) ? a[t] : 0.0;
+        s2 = fma(x, x, s2);
       }
       s2 = wave_sum(s2);
-      double tau = 0.0, beta = alpha;
+      double tau = 0.0, beta = alpha, scale = 0.0;
       if (s2 > 0.0) {
         const double mu = sqrt(alpha * alpha + s2);
         beta = (alpha >= 0.0) ? -mu : mu;
         tau = (beta - alpha) / beta;
-        const double scale = 1.0 / (alpha - beta);
-        for (int t = 1 + lane; t < L; t += 64) A[ck + 1 + t] *= scale;
+        scale = 1.0 / (alpha - beta);
       }
-      if (lane == 0) {
-        dG[k] = A[ck];
-        eG[k] = beta;
-        tauG[k] = tau;
-        red[k & 1] = tau;     // two slots: a step without reflection has no later barrier
-        A[ck + 1] = 1.0;
+      double v[HT];
+#pragma unroll
+      for (int t = 0; t < HT; ++t) {
+        const int i = lane + 64 * t;
+        v[t] = (i > k1) ? a[t] * scale : ((i == k1) ? 1.0 : 0.0);
+        vv[i] = v[t];
+      }
+      __builtin_amdgcn_wave_barrier();
+      if (wv == 0) {
+#pragma unroll
+        for (int t = 0; t < HT; ++t) Vp[j][lane + 64 * t] = v[t];
+      }
+      // Partial A_0 v over this wave's columns jc = k+1+wv, k+1+wv+HW, ...:
+      // A_0(i, jc) v_jc into row i, and sum_{i > jc} A_0(i, jc) v_i into
+      // row jc (the upper part, by symmetry).
+      // Four columns per pass, their loads issued together.  Column jc's
+      // entries sit at a uniform base plus the row, so the loads need no
+      // per-lane clamping: rows above jc or at n and beyond read other
+      // entries of the workspace (in bounds for n > 64), which the select
+      // discards.  The transposed sums (diagonal included, removed when p is
+      // assembled) leave as row-group partials through LDS.
+      double acc[HT];
+#pragma unroll
+      for (int t = 0; t < HT; ++t) acc[t] = 0.0;
+      for (int jc0 = k1 + wv; jc0 < n; jc0 += 4 * HW) {
+        double x[4][HT];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int jcc = min(jc0 + u * HW, n - 1);
+          const double* col = A + (colstart(jcc, n) - jcc);
+#pragma unroll
+          for (int t = 0; t < HT; ++t) x[u][t] = col[lane + 64 * t];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int jc = jc0 + u * HW;
+          const double vj = vv[min(jc, n - 1)];
+          double sd = 0.0;
+#pragma unroll
+          for (int t = 0; t < HT; ++t) {
+            const int i = lane + 64 * t;
+            const double xm = (i >= jc && i < n) ? x[u][t] : 0.0;
+            acc[t] = fma(xm, vj, acc[t]);
+            sd = fma(xm, v[t], sd);
+          }
+          sd = row16_sum(sd);
+          if ((lane & 15) == 0 && jc < n) sdp[lane >> 4][jc] = sd;
+        }
+      }
+#pragma unroll
+      for (int t = 0; t < HT; ++t) ys[wv][lane + 64 * t] = acc[t];
+      // w_q.v and v_q.v for the panel's earlier columns, one wave each; the
+      // previous step's pair is this wave's own registers.
+      if (wv < j) {
+        double s1 = 0.0, sv = 0.0;
+        if (wv == j - 1) {
+#pragma unroll
+          for (int t = 0; t < HT; ++t) {
+            s1 = fma(wprev[t], v[t], s1);
+            sv = fma(vprev[t], v[t], sv);
+          }
+        } else {
+#pragma unroll
+          for (int t = 0; t < HT; ++t) {
+            const int i = lane + 64 * t;
+            s1 = fma(Wq[wv][i], v[t], s1);
+            sv = fma(Vp[wv][i], v[t], sv);
+          }
+        }
+        s1 = wave_sum(s1);
+        sv = wave_sum(sv);
+        if (lane == 0) {
+          cs[0][wv] = s1;
+          cs[1][wv] = sv;
+        }
+      }
+      __syncthreads();
+      // p for rows 64 wv + lane (waves below HT), its part of p.v, and the
+      // next column of the panel less the corrections known so far.
+      if (wv < HT) {
+        const int i = 64 * wv + lane;
+        double y = -dg0[i] * vv[i];
+        for (int q = 0; q < HW; ++q) y += ys[q][i];
+        for (int g = 0; g < 4; ++g) y += sdp[g][i];
+        for (int q = 0; q < j; ++q) y -= fma(Vp[q][i], cs[0][q], Wq[q][i] * cs[1][q]);
+        const double pi = (i > k && i < n) ? tau * y : 0.0;
+        pl[i] = pi;
+        const double d = wave_sum(pi * vv[i]);
+        if (lane == 0) pd[wv] = d;
+        if (j + 1 < nb) {
+          const double raw = A[colstart(k1, n) + min(max(i, k1), n - 1) - k1];
+          double x = (i >= k1 && i < n) ? raw : 0.0;
+          for (int q = 0; q < j; ++q) x -= fma(Vp[q][i], Wq[q][k1], Wq[q][i] * Vp[q][k1]);
+          ac[i] = (i >= k1) ? x : 0.0;
+        }
+      }
+      // The reflector into column k (no wave reads column k any more).
+      if (wv == 0) {
+        const int ck = colstart(k, n);
+#pragma unroll
+        for (int t = 0; t < HT; ++t) {
+          const int i = lane + 64 * t;
+          if (i >= k + 2 && i < n) A[ck + i - k] = v[t];
+        }
+        if (lane == 0) {
+          A[ck] = dk;
+          A[ck + 1] = 1.0;
+          dG[k] = dk;
+          eG[k] = beta;
+          tauG[k] = tau;
+        }
+      }
+      __syncthreads();
+      double dot = 0.0;
+#pragma unroll
+      for (int t = 0; t < HT; ++t) dot += pd[t];
+      const double c = 0.5 * tau * dot;
+      double w[HT];
+#pragma unroll
+      for (int t = 0; t < HT; ++t) w[t] = fma(-c, v[t], pl[lane + 64 * t]);
+      if (wv == 0) {
+#pragma unroll
+        for (int t = 0; t < HT; ++t) Wq[j][lane + 64 * t] = w[t];
+      }
+      if (j + 1 < nb) {
+        // Column k+1 of the current matrix: the q = j term is v w(k1) + w
+        // (v(k1) = 1).
+        const double wk1 = pl[k1] - c;
+#pragma unroll
+        for (int t = 0; t < HT; ++t) {
+          const int i = lane + 64 * t;
+          a[t] = (i >= k1 && i < n) ? ac[i] - fma(v[t], wk1, w[t]) : 0.0;
+        }
+      }
+#pragma unroll
+      for (int t = 0; t < HT; ++t) {
+        vprev[t] = v[t];
+        wprev[t] = w[t];
+      }
+    }
+    // The panel's update of the trailing block: columns >= kt, one wave per
+    // column, A -= V W^T + W V^T.  Each lane keeps its rows of V and W; a
+    // column's coefficients are read once.  Loads are unconditional as in
+    // the product above; only rows jc..n-1 are stored.
+    __syncthreads();
+    const int kt = k0 + nb;
+    {
+      double vq[HT][HNB], wq[HT][HNB];
+#pragma unroll
+      for (int t = 0; t < HT; ++t)
+#pragma unroll
+        for (int q = 0; q < HNB; ++q) {
+          vq[t][q] = (q < nb) ? Vp[q][lane + 64 * t] : 0.0;
+          wq[t][q] = (q < nb) ? Wq[q][lane + 64 * t] : 0.0;
+        }
+      for (int jc = kt + wv; jc < n; jc += HW) {
+        double cwq[HNB], cvq[HNB];
+#pragma unroll
+        for (int q = 0; q < HNB; ++q) {
+          cwq[q] = Wq[q][jc];
+          cvq[q] = Vp[q][jc];
+        }
+        double* col = A + (colstart(jc, n) - jc);
+        double x[HT];
+#pragma unroll
+        for (int t = 0; t < HT; ++t) x[t] = col[lane + 64 * t];
+#pragma unroll
+        for (int t = 0; t < HT; ++t) {
+          const int i = lane + 64 * t;
+          double y = x[t];
+#pragma unroll
+          for (int q = 0; q < HNB; ++q) y -= fma(vq[t][q], cwq[q], wq[t][q] * cvq[q]);
+          if (i >= jc && i < n) col[i] = y;
+        }
       }
     }
     __syncthreads();
-    const double tau = red[k & 1];
-    if (tau != 0.0) {
-      // p = tau * A22 v: four threads per row, each on every fourth column;
-      // the lower part of the row (A(i, j), j <= i) and the upper part read
-      // from column i (A(j, i), j > i, contiguous) in two loops.
-      {
-        const int r = tid >> 2, q = tid & 3;
-        double acc0 = 0.0, acc1 = 0.0;
-        if (r < L) {
-          const int i = k + 1 + r;
-          int jj = q;
-          int cj = colstart(k + 1 + jj, n);
-#pragma unroll 4
-          for (; jj <= r; jj += 4) {
-            acc0 = fma(A[cj + r - jj], A[ck + 1 + jj], acc0);
-            const int j = k + 1 + jj;
-            cj += 4 * n - 4 * j - 6;              // colstart(j + 4) - colstart(j)
-          }
-          const int ci = colstart(i, n) - r;
-#pragma unroll 4
-          for (; jj < L; jj += 4) acc1 = fma(A[ci + jj], A[ck + 1 + jj], acc1);
-        }
-        double acc = acc0 + acc1;
-        acc += __shfl_xor(acc, 1, 64);
-        acc += __shfl_xor(acc, 2, 64);
-        if (r < L && q == 0) p[r] = tau * acc;
-      }
-      __syncthreads();
-      // c = (tau/2) p.v, w = p - c v, A22 -= v w^T + w v^T (lower part).  A
-      // wave owns every 16th column; its lanes take up to four row chunks
-      // of the column at once.
-      double dot = 0.0;
-      for (int t = lane; t < L; t += 64) dot = fma(p[t], A[ck + 1 + t], dot);
-      dot = wave_sum(dot);
-      const double c = 0.5 * tau * dot;
-      for (int jj = w; jj < L; jj += TNT / 64) {
-        const int cj = colstart(k + 1 + jj, n) - jj;
-        const double vj = A[ck + 1 + jj];
-        const double wj = fma(-c, vj, p[jj]);
+    for (int i = kt + tid; i < n; i += HNT) dg0[i] = A[colstart(i, n)];
+    if (kt < kstop) {
+      const int ct = colstart(kt, n);
 #pragma unroll
-        for (int t = 0; t < 4; ++t) {
-          const int ii = jj + lane + 64 * t;
-          if (ii < L) {
-            const double vi = A[ck + 1 + ii];
-            const double wi = fma(-c, vi, p[ii]);
-            A[cj + ii] -= fma(vi, wj, wi * vj);
-          }
-        }
+      for (int t = 0; t < HT; ++t) {
+        const int i = lane + 64 * t;
+        const double x = A[ct + min(max(i, kt), n - 1) - kt];
+        a[t] = (i >= kt && i < n) ? x : 0.0;
+        vprev[t] = 0.0;
+        wprev[t] = 0.0;
       }
-      __syncthreads();
     }
   }
   if (tid == 0) {
@@ -181,7 +368,7 @@ __device__ __forceinline__ void tridiag_body(const double* __restrict__ G, int n
   }
 }
 
-__global__ __launch_bounds__(TNT) void k_tridiag(const double* __restrict__ G, int n, int ldg,
+__global__ __launch_bounds__(HNT) void k_tridiag(const double* __restrict__ G, int n, int ldg,
                                                  double* __restrict__ W, int kend) {
   tridiag_body(G, n, ldg, W, kend);
 }
@@ -1096,7 +1283,7 @@ hipError_t launch_tridiag(const double* G, int m, int mp, EigWork wk, hipStream_
     // The first m - kTridRegMax columns on the packed triangle in W, the
     // rest in registers.
     const int h = m - kTridRegMax;
-    hipLaunchKernelGGL(k_tridiag, dim3(1), dim3(TNT), 0, s, G, m, mp, wk.W, h);
+    hipLaunchKernelGGL(k_tridiag, dim3(1), dim3(HNT), 0, s, G, m, mp, wk.W, h);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL((k_tridiag_reg<7, 13>), dim3(1), dim3(RNT), 0, s, G, m, mp, wk.W, h);
@@ -1149,7 +1336,7 @@ __global__ __launch_bounds__(RNT) void kg_tridiag_reg(const GroupSketch* __restr
 }
 
 // The head of the reduction of buffers above the register capacity.
-__global__ __launch_bounds__(TNT) void kg_tridiag(const GroupSketch* __restrict__ SK,
+__global__ __launch_bounds__(HNT) void kg_tridiag(const GroupSketch* __restrict__ SK,
                                                   const GroupRR* __restrict__ T) {
   const GroupSketch& s = SK[T[blockIdx.x].sk];
   if (s.m <= kTridRegMax) return;        // the register variant's task
@@ -1187,7 +1374,7 @@ hipError_t launch_group_eig(const GroupSketch* sk, const GroupRR* t, int nt, int
   if (max_m > kTridGlobalMax) return hipErrorInvalidValue;
   hipError_t e = hipSuccess;
   if (max_m > kTridRegMax) {
-    hipLaunchKernelGGL(kg_tridiag, dim3(nt), dim3(TNT), 0, s, sk, t);
+    hipLaunchKernelGGL(kg_tridiag, dim3(nt), dim3(HNT), 0, s, sk, t);
     e = hipGetLastError();
   }
   if (e == hipSuccess) {
