@@ -791,7 +791,6 @@ __device__ __forceinline__ void dc_body(double* __restrict__ W, int n, double* _
   // (between two blocks of the level before), and those must be zero.
   int levels = 0;
   for (int s = 1; s < n; s *= 2) ++levels;
-  double* buf[2] = {Z, Qc};
   int cur = levels & 1;
   for (int c = w; c < n; c += TNT / 64)
     for (int r = lane; r < n; r += 64) {
@@ -808,8 +807,10 @@ __device__ __forceinline__ void dc_body(double* __restrict__ W, int n, double* _
   // Four lanes per root in the per-root steps.
   const int g4 = tid >> 2, q4 = tid & 3;
   for (int s = 1; s < n; s *= 2, cur ^= 1) {
-    const double* In = buf[cur];
-    double* Out = buf[cur ^ 1];
+    // Selected, not indexed from a local array, so that the loads below
+    // stay global (flat loads would also count against the LDS counter).
+    const double* In = cur ? Qc : Z;
+    double* Out = cur ? Z : Qc;
     const int nm = (n + 2 * s - 1) / (2 * s);
     // 1. z from the boundary rows, sorted by eigenvalue within each merge.
     for (int g = tid; g < n; g += TNT) {
@@ -1029,7 +1030,7 @@ __device__ __forceinline__ void dc_body(double* __restrict__ W, int n, double* _
       merge_geom(b, s, n, a, k1, k2);
       if (k2 == 0) continue;
       const int nr = S.nrot[b];
-      double* InW = buf[cur];
+      double* InW = cur ? Qc : Z;
       for (int t = 0; t < nr; ++t) {
         double* xp = InW + static_cast<int64_t>(a + S.perm[S.rp[a + t]]) * ldz + g;
         double* xj = InW + static_cast<int64_t>(a + S.perm[S.rj[a + t]]) * ldz + g;
@@ -1105,23 +1106,42 @@ __device__ __forceinline__ void dc_body(double* __restrict__ W, int n, double* _
       const int li = lane & 15, lk = lane >> 4;
       f64x4 acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = {0.0, 0.0, 0.0, 0.0};
       const bool rok0 = (r0 + li) < k, rok1 = (r0 + 16 + li) < k, cok = (c0 + li) < nk;
-      const double* Ab = In + static_cast<int64_t>(a) * ldz + a + r0 + li;
-      const double* Bb = U + static_cast<int64_t>(a) * ldz + a + c0 + li;
-      for (int i0 = 0; i0 < nk; i0 += 16) {
-        double x0[4], x1[4], y[4];
+      // Row and column indices are clamped into the block, so every load is
+      // unconditional and reads a finite entry of the block; the padding is
+      // zeroed by multiplying with 0/1 at the product, which lets the next
+      // 16-deep slab stay in flight while the current one goes through the
+      // matrix cores.
+      const double* Ab0 = In + static_cast<int64_t>(a) * ldz + a + min(r0 + li, k - 1);
+      const double* Ab1 = In + static_cast<int64_t>(a) * ldz + a + min(r0 + 16 + li, k - 1);
+      const double* Bb = U + static_cast<int64_t>(a) * ldz + a + min(c0 + li, nk - 1);
+      const double m0 = rok0 ? 1.0 : 0.0, m1 = rok1 ? 1.0 : 0.0, mc = cok ? 1.0 : 0.0;
+      auto slab = [&](int i0, double (&x0)[4], double (&x1)[4], double (&y)[4]) {
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
-          const int ii = i0 + 4 * u + lk;
-          const int64_t oa = static_cast<int64_t>(S.src[a + min(ii, nk - 1)]) * ldz;
-          const int64_t o = static_cast<int64_t>(ii) * ldz;
-          x0[u] = (rok0 && ii < nk) ? Ab[oa] : 0.0;
-          x1[u] = (rok1 && ii < nk) ? Ab[oa + 16] : 0.0;
-          y[u] = (cok && ii < nk) ? Bb[o] : 0.0;
+          const int ic = min(i0 + 4 * u + lk, nk - 1);
+          const int64_t oa = static_cast<int64_t>(S.src[a + ic]) * ldz;
+          x0[u] = Ab0[oa];
+          x1[u] = Ab1[oa];
+          y[u] = Bb[static_cast<int64_t>(ic) * ldz];
+        }
+      };
+      double x0[4], x1[4], y[4];
+      slab(0, x0, x1, y);
+      for (int i0 = 0; i0 < nk; i0 += 16) {
+        double n0[4], n1[4], ny[4];
+        slab(i0 + 16, n0, n1, ny);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const double mk = (i0 + 4 * u + lk < nk) ? 1.0 : 0.0;
+          const double yu = y[u] * (mc * mk);
+          acc0 = mfma_f64(x0[u] * m0, yu, acc0);
+          acc1 = mfma_f64(x1[u] * m1, yu, acc1);
         }
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
-          acc0 = mfma_f64(x0[u], y[u], acc0);
-          acc1 = mfma_f64(x1[u], y[u], acc1);
+          x0[u] = n0[u];
+          x1[u] = n1[u];
+          y[u] = ny[u];
         }
       }
       if (cok) {
