@@ -157,7 +157,8 @@ def precision_leg(rows, l=256, d=3072, seed=(3, 0)):
     peak_gram = {"fp64": PEAK_FP64, "bf16": PEAK_BF16, "bf16x3": PEAK_BF16, "fp8x3": PEAK_FP8}
     peak_rebuild = {"fp64": PEAK_FP64, "bf16": PEAK_BF16, "bf16x3": PEAK_BF16, "fp8x3": PEAK_BF16}
     out = {"workload": f"power-law sigma_i = i^-0.8 over 300 directions + N(0,1e-2), {rows} x {d} "
-                       f"bf16 rows, FD l = {l} (buffer {m} rows), block Jacobi eigensolver",
+                       f"bf16 rows, FD l = {l} (buffer {m} rows), "
+                       + ("tridiagonal divide-and-conquer" if m <= 512 else "block Jacobi") + " eigensolver",
            "rows": rows}
     cov64 = None
     for prec in ("fp64", "bf16", "bf16x3", "fp8x3"):
@@ -255,7 +256,7 @@ def main():
                     help="prefix of the stream the CPU oracle sketches for the baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--eig", default="auto", choices=["auto", "jacobi"],
-                    help="eigensolver: tridiagonal divide and conquer (m <= 200) or Jacobi")
+                    help="eigensolver: tridiagonal divide and conquer (m <= 512) or Jacobi")
     ap.add_argument("--rows", type=int, default=100_000,
                     help="rows of the stream to sketch (profiling runs use a prefix)")
     ap.add_argument("--batch-sketches", type=int, default=512,

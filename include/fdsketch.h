@@ -222,7 +222,7 @@ const char* sketch_last_error(const fdsk_sketch* s);
  * fdsk_eigh: eigen-decomposition G = V diag(lam) V^T of a symmetric m x m
  *   matrix (m <= 1024); lam unsorted, V's column j (V[i*ldv + j]) belongs to
  *   lam[j].  method FDSK_EIG_AUTO: Householder tridiagonalisation, divide and
- *   conquer and back-transformation for m <= 200, one-sided block Jacobi
+ *   conquer and back-transformation for m <= 512, one-sided block Jacobi
  *   above; FDSK_EIG_JACOBI: the Jacobi solvers at every m (cyclic two-sided in
  *   LDS for m <= 100).  Errors: EINVAL, EUNSUPPORTED (m > 1024), ENOMEM,
  *   EDEVICE. */

@@ -186,8 +186,8 @@ int sketch_batch_create(int32_t S, const fdsk_config* cfgs, void* hip_stream, fd
     const int m = c.buffer_rows == 0 ? 2 * c.l : c.buffer_rows;
     if (c.d < 1 || c.d > 65536 || c.l < 1 || m < c.l)
       return berr(nullptr, FDSK_EINVAL, "sketch %d: bad sizes", i);
-    if (m > kTridGlobalMax)
-      return berr(nullptr, FDSK_EUNSUPPORTED, "sketch %d: buffer rows %d > %d", i, m, kTridGlobalMax);
+    if (m > kBatchMax)
+      return berr(nullptr, FDSK_EUNSUPPORTED, "sketch %d: buffer rows %d > %d", i, m, kBatchMax);
     if (c.variant == FDSK_SSD || c.variant == FDSK_CFD)
       return berr(nullptr, FDSK_EUNSUPPORTED, "SSD and CFD run on single sketches only");
     if (c.variant < FDSK_FD || c.variant > FDSK_FAST_ALPHA) return berr(nullptr, FDSK_EINVAL, "bad variant");

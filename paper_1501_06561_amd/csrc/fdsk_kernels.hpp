@@ -96,9 +96,10 @@ struct EigWork {
 enum { EIG_AUTO = 0, EIG_JACOBI = 1 };
 constexpr int kMaxSweeps = 40;
 constexpr int kLdsEigMax = 100;   // single-workgroup solver limit (G and V in LDS)
-constexpr int kTridMax = 200;     // tridiagonal route with the packed lower triangle in LDS
-constexpr int kTridGlobalMax = 256;  // ... and with it in the (L2-resident) workspace
-constexpr int kDcMax = 256;       // divide and conquer: O(n) state in LDS
+constexpr int kTridMax = 200;     // back-transformation with the reflectors staged in LDS
+constexpr int kTridGlobalMax = 512;  // tridiagonal route (packed triangle in the workspace above 208)
+constexpr int kBatchMax = 256;    // buffer rows of a batched sketch
+constexpr int kDcMax = 512;       // divide and conquer: O(n) state in LDS
 // Eigen-decomposition of the symmetric m x m G (leading dimension mp): lam
 // (m values, any order) and V (column j = eigenvector of lam[j], leading
 // dimension mp).  m <= kTridGlobalMax goes through the tridiagonal route unless

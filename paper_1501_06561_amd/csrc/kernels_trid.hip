@@ -66,31 +66,30 @@ __device__ __forceinline__ double wave_max(double v) {
 // sum_q (v_q (w_q.v) + w_q (v_q.v))).  The trailing block is written once
 // per panel (A -= V W^T + W V^T).  Per column the triangle is only read, one
 // wave per column (every HW-th), with each lane keeping the rows
-// lane + 64 t.  512 threads, two barriers per column.
+// lane + 64 t (t < HT, so n <= 64 HT).  512 threads, two barriers per
+// column.  Requires n > 64 (the unclamped loads below stay inside W).
 constexpr int HNT = 512;                        // threads of the packed-triangle reduction
 constexpr int HW = HNT / 64;                    // its waves
 constexpr int HNB = 8;                          // panel width (<= HW)
-constexpr int HT = kTridGlobalMax / 64;         // rows per lane
 
-template <int N>
-__device__ __forceinline__ double pick(const double (&x)[N], int t) {
-  double r = x[0];
-#pragma unroll
-  for (int q = 1; q < N; ++q) r = (t == q) ? x[q] : r;
-  return r;
-}
-
+template <int HT>
 __device__ __forceinline__ void tridiag_body(const double* __restrict__ G, int n, int ldg,
                                              double* __restrict__ W, int kend) {
-  __shared__ double Vp[HNB][kTridGlobalMax];     // the panel's v
-  __shared__ double Wq[HNB][kTridGlobalMax];     // the panel's w
-  __shared__ double ys[HW][kTridGlobalMax];      // per-wave partial A_0 v
-  __shared__ double colw[HW][kTridGlobalMax];    // each wave's copy of the current column
-  __shared__ double vw[HW][kTridGlobalMax];      // each wave's copy of v
-  __shared__ double pl[kTridGlobalMax];
-  __shared__ double ac[kTridGlobalMax];          // next column: A_0 minus the older corrections
-  __shared__ double sdp[4][kTridGlobalMax];      // row-group partials of sum_{i >= jc} A_0(i,jc) v_i
-  __shared__ double dg0[kTridGlobalMax];         // diagonal of A_0
+  constexpr int NM = 64 * HT;
+  constexpr int UNR = HT <= 4 ? 4 : 2;          // columns per pass of the product
+  constexpr int TG = HT <= 4 ? 4 : 2;           // row chunks per pass of the panel update
+  __shared__ double Vp[HNB][NM];     // the panel's v
+  __shared__ double Wq[HNB][NM];     // the panel's w
+  __shared__ double ys[HW][NM];      // per-wave partial A_0 v
+  // The current column and v are bitwise equal in every wave (each forms
+  // them the same way), so the waves share one copy: every wave writes all
+  // of it before reading, and any value it reads is its own or an equal one.
+  __shared__ double colw[NM];
+  __shared__ double vw[NM];
+  __shared__ double pl[NM];
+  __shared__ double ac[NM];          // next column: A_0 minus the older corrections
+  __shared__ double sdp[4][NM];      // row-group partials of sum_{i >= jc} A_0(i,jc) v_i
+  __shared__ double dg0[NM];         // diagonal of A_0
   __shared__ double cs[2][HNB];                  // w_q.v and v_q.v
   __shared__ double pd[HT];
   __shared__ double red[HW];
@@ -107,7 +106,7 @@ __device__ __forceinline__ void tridiag_body(const double* __restrict__ G, int n
   }
   amax = wave_max(amax);
   if (lane == 0) red[wv] = amax;
-  for (int e = tid; e < HNB * kTridGlobalMax; e += HNT) {
+  for (int e = tid; e < HNB * NM; e += HNT) {
     (&Vp[0][0])[e] = 0.0;
     (&Wq[0][0])[e] = 0.0;
   }
@@ -126,8 +125,8 @@ __device__ __forceinline__ void tridiag_body(const double* __restrict__ G, int n
   double* dG = tauG + n;
   double* eG = dG + n;
   const int kstop = min(kend, n - 2);
-  double* const cw = colw[wv];
-  double* const vv = vw[wv];
+  double* const cw = colw;
+  double* const vv = vw;
   // a: column k of the current matrix (rows lane + 64 t, zero above k and
   // at n and beyond); vprev/wprev: this wave's v and w of the previous step.
   double a[HT], vprev[HT], wprev[HT];
@@ -186,17 +185,17 @@ __device__ __forceinline__ void tridiag_body(const double* __restrict__ G, int n
       double acc[HT];
 #pragma unroll
       for (int t = 0; t < HT; ++t) acc[t] = 0.0;
-      for (int jc0 = k1 + wv; jc0 < n; jc0 += 4 * HW) {
-        double x[4][HT];
+      for (int jc0 = k1 + wv; jc0 < n; jc0 += UNR * HW) {
+        double x[UNR][HT];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
+        for (int u = 0; u < UNR; ++u) {
           const int jcc = min(jc0 + u * HW, n - 1);
           const double* col = A + (colstart(jcc, n) - jcc);
 #pragma unroll
           for (int t = 0; t < HT; ++t) x[u][t] = col[lane + 64 * t];
         }
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
+        for (int u = 0; u < UNR; ++u) {
           const int jc = jc0 + u * HW;
           const double vj = vv[min(jc, n - 1)];
           double sd = 0.0;
@@ -308,16 +307,20 @@ __device__ __forceinline__ void tridiag_body(const double* __restrict__ G, int n
     // the product above; only rows jc..n-1 are stored.
     __syncthreads();
     const int kt = k0 + nb;
-    {
-      double vq[HT][HNB], wq[HT][HNB];
 #pragma unroll
-      for (int t = 0; t < HT; ++t)
+    for (int tg = 0; tg < HT; tg += TG) {
+      // Row chunks tg .. tg+TG-1.
+      if (64 * (tg + TG) <= kt || 64 * tg >= n) continue;
+      double vq[TG][HNB], wq[TG][HNB];
+#pragma unroll
+      for (int t = 0; t < TG; ++t)
 #pragma unroll
         for (int q = 0; q < HNB; ++q) {
-          vq[t][q] = (q < nb) ? Vp[q][lane + 64 * t] : 0.0;
-          wq[t][q] = (q < nb) ? Wq[q][lane + 64 * t] : 0.0;
+          vq[t][q] = (q < nb) ? Vp[q][lane + 64 * (tg + t)] : 0.0;
+          wq[t][q] = (q < nb) ? Wq[q][lane + 64 * (tg + t)] : 0.0;
         }
-      for (int jc = kt + wv; jc < n; jc += HW) {
+      const int jend = min(n, 64 * (tg + TG));
+      for (int jc = kt + wv; jc < jend; jc += HW) {
         double cwq[HNB], cvq[HNB];
 #pragma unroll
         for (int q = 0; q < HNB; ++q) {
@@ -325,12 +328,12 @@ __device__ __forceinline__ void tridiag_body(const double* __restrict__ G, int n
           cvq[q] = Vp[q][jc];
         }
         double* col = A + (colstart(jc, n) - jc);
-        double x[HT];
+        double x[TG];
 #pragma unroll
-        for (int t = 0; t < HT; ++t) x[t] = col[lane + 64 * t];
+        for (int t = 0; t < TG; ++t) x[t] = col[lane + 64 * (tg + t)];
 #pragma unroll
-        for (int t = 0; t < HT; ++t) {
-          const int i = lane + 64 * t;
+        for (int t = 0; t < TG; ++t) {
+          const int i = lane + 64 * (tg + t);
           double y = x[t];
 #pragma unroll
           for (int q = 0; q < HNB; ++q) y -= fma(vq[t][q], cwq[q], wq[t][q] * cvq[q]);
@@ -368,9 +371,10 @@ __device__ __forceinline__ void tridiag_body(const double* __restrict__ G, int n
   }
 }
 
+template <int HT>
 __global__ __launch_bounds__(HNT) void k_tridiag(const double* __restrict__ G, int n, int ldg,
                                                  double* __restrict__ W, int kend) {
-  tridiag_body(G, n, ldg, W, kend);
+  tridiag_body<HT>(G, n, ldg, W, kend);
 }
 
 // ------------------------------------------------- reduce, in registers
@@ -1233,7 +1237,7 @@ template <int NPL, bool GA>
 __device__ __forceinline__ void backtr_body(const double* __restrict__ W, int n, double* __restrict__ Z,
                                             int ldz, int cb) {
   __shared__ double R_lds[GA ? 1 : bt_pack(NPL)];
-  __shared__ double tau_lds[kTridGlobalMax];
+  __shared__ double tau_lds[64 * NPL];
   const double* const R = GA ? W : R_lds;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int P = n * (n + 1) / 2;
@@ -1303,7 +1307,10 @@ hipError_t launch_tridiag(const double* G, int m, int mp, EigWork wk, hipStream_
     // The first m - kTridRegMax columns on the packed triangle in W, the
     // rest in registers.
     const int h = m - kTridRegMax;
-    hipLaunchKernelGGL(k_tridiag, dim3(1), dim3(HNT), 0, s, G, m, mp, wk.W, h);
+    if (m <= 256)
+      hipLaunchKernelGGL(k_tridiag<4>, dim3(1), dim3(HNT), 0, s, G, m, mp, wk.W, h);
+    else
+      hipLaunchKernelGGL(k_tridiag<8>, dim3(1), dim3(HNT), 0, s, G, m, mp, wk.W, h);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL((k_tridiag_reg<7, 13>), dim3(1), dim3(RNT), 0, s, G, m, mp, wk.W, h);
@@ -1327,8 +1334,10 @@ hipError_t launch_backtr(int m, int mp, double* V, EigWork wk, hipStream_t s) {
     hipLaunchKernelGGL((k_backtr<2, false>), dim3(grid), dim3(BNT), 0, s, wk.W, m, V, mp);
   else if (m <= kTridMax)
     hipLaunchKernelGGL((k_backtr<4, false>), dim3(grid), dim3(BNT), 0, s, wk.W, m, V, mp);
-  else
+  else if (m <= 256)
     hipLaunchKernelGGL((k_backtr<4, true>), dim3(grid), dim3(BNT), 0, s, wk.W, m, V, mp);
+  else
+    hipLaunchKernelGGL((k_backtr<8, true>), dim3(grid), dim3(BNT), 0, s, wk.W, m, V, mp);
   return hipGetLastError();
 }
 
@@ -1360,7 +1369,7 @@ __global__ __launch_bounds__(HNT) void kg_tridiag(const GroupSketch* __restrict_
                                                   const GroupRR* __restrict__ T) {
   const GroupSketch& s = SK[T[blockIdx.x].sk];
   if (s.m <= kTridRegMax) return;        // the register variant's task
-  tridiag_body(s.G, s.m, s.mp, s.W, s.m - kTridRegMax);
+  tridiag_body<4>(s.G, s.m, s.mp, s.W, s.m - kTridRegMax);
 }
 
 __global__ __launch_bounds__(TNT) void kg_dc(const GroupSketch* __restrict__ SK,
@@ -1391,7 +1400,7 @@ hipError_t launch_group_backtr(const GroupSketch* sk, const GroupRR* t, int nt, 
 
 hipError_t launch_group_eig(const GroupSketch* sk, const GroupRR* t, int nt, int max_m, hipStream_t s) {
   if (nt <= 0) return hipSuccess;
-  if (max_m > kTridGlobalMax) return hipErrorInvalidValue;
+  if (max_m > kBatchMax) return hipErrorInvalidValue;
   hipError_t e = hipSuccess;
   if (max_m > kTridRegMax) {
     hipLaunchKernelGGL(kg_tridiag, dim3(nt), dim3(HNT), 0, s, sk, t);
@@ -1407,7 +1416,7 @@ hipError_t launch_group_eig(const GroupSketch* sk, const GroupRR* t, int nt, int
   if (e == hipSuccess) e = launch_group_backtr<1, false, 1, 64>(sk, t, nt, max_m, s);
   if (e == hipSuccess) e = launch_group_backtr<2, false, 65, 128>(sk, t, nt, max_m, s);
   if (e == hipSuccess) e = launch_group_backtr<4, false, 129, kTridMax>(sk, t, nt, max_m, s);
-  if (e == hipSuccess) e = launch_group_backtr<4, true, kTridMax + 1, kTridGlobalMax>(sk, t, nt, max_m, s);
+  if (e == hipSuccess) e = launch_group_backtr<4, true, kTridMax + 1, kBatchMax>(sk, t, nt, max_m, s);
   return e;
 }
 

@@ -75,15 +75,16 @@ def test_config1_random_noisy_fd_l20():
 
 @pytest.mark.parametrize("eig", ["auto", "jacobi"])
 @pytest.mark.parametrize("variant", oracle.VARIANTS)
-@pytest.mark.parametrize("l", [6, 24, 50, 64, 100, 128])
+@pytest.mark.parametrize("l", [6, 24, 50, 64, 100, 128, 200])
 def test_variants_across_solver_sizes(variant, l, eig):
-    """Both eigensolvers end to end.  "auto": tridiagonal divide and conquer
-    up to m = 200 (l <= 100), block Jacobi at l = 128.  "jacobi": the LDS
-    two-sided solver for m <= 100, the multi-workgroup block solver above.
-    d = 300 (ragged against the 64-column padding), n ragged against the
-    schedule."""
-    if eig == "jacobi" and l == 128:
-        pytest.skip("same path as auto at this size")
+    """Both eigensolvers end to end.  "auto": tridiagonal divide and conquer,
+    the reduction in registers up to m = 208 (l <= 104) and with a
+    packed-triangle head above (l = 128, 200).  "jacobi": the LDS two-sided
+    solver for m <= 100, the multi-workgroup block solver above.  d = 300
+    (ragged against the 64-column padding; below m at l = 200), n ragged
+    against the schedule."""
+    if eig == "jacobi" and l == 200:
+        pytest.skip("block Jacobi at this size is covered by l = 128")
     A = synth.random_noisy(2_345, 300, 12, 10.0, seed=(21, l))
     gram = 1e-9 if variant == "fd" else 1e-7
     compare(A, l, variant, 0.2, gram_tol=gram, cov_rtol=1e-6, eig=eig)
