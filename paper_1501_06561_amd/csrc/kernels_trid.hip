@@ -1233,7 +1233,9 @@ constexpr int bt_pack(int npl) {
   return (64 * npl) * (64 * npl + 1) / 2 < TRI_PACK ? (64 * npl) * (64 * npl + 1) / 2 : TRI_PACK;
 }
 
-template <int NPL, bool GA>
+// NT threads per block, one wave per wanted column: block cb takes wanted
+// columns cb*NT/64 .. cb*NT/64 + NT/64 - 1.
+template <int NPL, bool GA, int NT = BNT>
 __device__ __forceinline__ void backtr_body(const double* __restrict__ W, int n, double* __restrict__ Z,
                                             int ldz, int cb) {
   __shared__ double R_lds[GA ? 1 : bt_pack(NPL)];
@@ -1242,11 +1244,11 @@ __device__ __forceinline__ void backtr_body(const double* __restrict__ W, int n,
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int P = n * (n + 1) / 2;
   int nw;
-  const int col = nth_flagged(W + P + 3 * n + 1, n, cb * (BNT / 64) + w, nw);
-  if (cb * (BNT / 64) >= nw) return;     // the whole block: no wanted column left
+  const int col = nth_flagged(W + P + 3 * n + 1, n, cb * (NT / 64) + w, nw);
+  if (cb * (NT / 64) >= nw) return;      // the whole block: no wanted column left
   if (!GA)
-    for (int e = tid; e < P; e += BNT) R_lds[e] = W[e];
-  for (int e = tid; e < n; e += BNT) tau_lds[e] = W[P + e];
+    for (int e = tid; e < P; e += NT) R_lds[e] = W[e];
+  for (int e = tid; e < n; e += NT) tau_lds[e] = W[P + e];
   __syncthreads();
   if (col < 0) return;
   double z[NPL];
@@ -1379,22 +1381,25 @@ __global__ __launch_bounds__(TNT) void kg_dc(const GroupSketch* __restrict__ SK,
 }
 
 // Size class [LO, HI] of buffer rows, with the LDS staging sized for it;
-// tasks of other classes return at once.
-template <int NPL, bool GA, int LO, int HI>
-__global__ __launch_bounds__(BNT) void kg_backtr(const GroupSketch* __restrict__ SK,
-                                                 const GroupRR* __restrict__ T) {
+// tasks of other classes return at once.  Classes that stage the reflectors
+// in LDS run 16 waves per block (NT = 1024), so one staging serves 16
+// columns and a CU holds enough waves to hide each column's chain.
+template <int NPL, bool GA, int LO, int HI, int NT>
+__global__ __launch_bounds__(NT) void kg_backtr(const GroupSketch* __restrict__ SK,
+                                                const GroupRR* __restrict__ T) {
   const GroupSketch& s = SK[T[blockIdx.y].sk];
   if (s.m < LO || s.m > HI) return;
-  if (static_cast<int>(blockIdx.x) * (BNT / 64) >= s.m) return;
-  backtr_body<NPL, GA>(s.W, s.m, s.V, s.mp, blockIdx.x);
+  if (static_cast<int>(blockIdx.x) * (NT / 64) >= s.m) return;
+  backtr_body<NPL, GA, NT>(s.W, s.m, s.V, s.mp, blockIdx.x);
 }
 
 template <int NPL, bool GA, int LO, int HI>
 hipError_t launch_group_backtr(const GroupSketch* sk, const GroupRR* t, int nt, int max_m, hipStream_t s) {
+  constexpr int NT = GA ? BNT : 1024;
   if (max_m < LO) return hipSuccess;
   const int top = min(max_m, HI);
-  const dim3 g((top + BNT / 64 - 1) / (BNT / 64), nt);
-  hipLaunchKernelGGL((kg_backtr<NPL, GA, LO, HI>), g, dim3(BNT), 0, s, sk, t);
+  const dim3 g((top + NT / 64 - 1) / (NT / 64), nt);
+  hipLaunchKernelGGL((kg_backtr<NPL, GA, LO, HI, NT>), g, dim3(NT), 0, s, sk, t);
   return hipGetLastError();
 }
 
