@@ -29,6 +29,13 @@ struct fdsk_batch {
   DevStats* d_stats = nullptr;
   void* d_tasks = nullptr;         // task lists of the current call
   size_t tasks_cap = 0;
+  // Appends run each size class of buffer rows as its own lock-step schedule
+  // on its own stream, ordered after the caller's stream by events.
+  static constexpr int kClasses = 4;
+  hipStream_t lane[kClasses] = {};
+  hipEvent_t ev_in = nullptr, ev_out[kClasses] = {};
+  void* d_tasks_c[kClasses] = {};
+  size_t tasks_cap_c[kClasses] = {};
   bool finalized = false;
   int err = 0;
   std::string msg;
@@ -88,12 +95,25 @@ struct Plan {
   std::vector<std::vector<GroupRR>> rr;
 };
 
-// Upload a plan and launch it round by round, at most `cap` sketches per
-// launch.  A round's ReduceRanks are put in descending order of buffer rows,
-// so that the longest workgroups are dispatched first (the order changes no
-// result: every task works on its own sketch).  The device task buffer is
-// reused by the next call, so the stream is synchronised before returning.
-int run_plan(fdsk_batch* b, Plan& p, int dt, int cap) {
+// Size class of a buffer (the register reduction's classes; above 208
+// rows the packed-triangle head runs first).
+int size_class(int m) { return m <= 64 ? 0 : (m <= 128 ? 1 : (m <= 208 ? 2 : 3)); }
+
+// A plan's task lists flattened for upload, with each round's offsets.  The
+// host vectors stay alive until the stream that copies them is synchronised.
+struct Staged {
+  std::vector<GroupIngest> hi;
+  std::vector<GroupRR> hr;
+  std::vector<size_t> oi, orr;
+  GroupIngest* d_ing = nullptr;
+  GroupRR* d_rr = nullptr;
+};
+
+// Sort each round's ReduceRanks in descending order of buffer rows, so that
+// the longest workgroups are dispatched first (the order changes no result:
+// every task works on its own sketch), flatten, and upload on stream st into
+// the task buffer (grown if needed; callers synchronise before reusing it).
+int stage_plan(fdsk_batch* b, Plan& p, hipStream_t st, void*& d_tasks, size_t& tasks_cap, Staged& sg) {
   for (auto& v : p.rr)
     std::stable_sort(v.begin(), v.end(), [b](const GroupRR& x, const GroupRR& y) {
       return b->sk[x.sk].m > b->sk[y.sk].m;
@@ -103,68 +123,137 @@ int run_plan(fdsk_batch* b, Plan& p, int dt, int cap) {
   for (auto& v : p.rr) nr += v.size();
   const size_t ing_bytes = (ni * sizeof(GroupIngest) + 255) / 256 * 256;
   const size_t bytes = ing_bytes + nr * sizeof(GroupRR) + 256;
-  if (bytes > b->tasks_cap) {
-    if (b->d_tasks) {
-      hipError_t e = hipStreamSynchronize(b->stream);
-      if (e == hipSuccess) e = hipFree(b->d_tasks);
-      b->d_tasks = nullptr;
-      b->tasks_cap = 0;
+  if (bytes > tasks_cap) {
+    if (d_tasks) {
+      hipError_t e = hipStreamSynchronize(st);
+      if (e == hipSuccess) e = hipFree(d_tasks);
+      d_tasks = nullptr;
+      tasks_cap = 0;
       if (e != hipSuccess) return berr(b, FDSK_EDEVICE, "batch tasks: %s", hipGetErrorString(e));
     }
-    if (hipMalloc(&b->d_tasks, bytes) != hipSuccess)
+    if (hipMalloc(&d_tasks, bytes) != hipSuccess)
       return berr(b, FDSK_ENOMEM, "batch task lists of %zu bytes", bytes);
-    b->tasks_cap = bytes;
+    tasks_cap = bytes;
   }
-  std::vector<GroupIngest> hi;
-  std::vector<GroupRR> hr;
-  hi.reserve(ni);
-  hr.reserve(nr);
-  for (auto& v : p.ing) hi.insert(hi.end(), v.begin(), v.end());
-  for (auto& v : p.rr) hr.insert(hr.end(), v.begin(), v.end());
-  GroupIngest* d_ing = static_cast<GroupIngest*>(b->d_tasks);
-  GroupRR* d_rr = reinterpret_cast<GroupRR*>(static_cast<char*>(b->d_tasks) + ing_bytes);
-  hipError_t e = hipSuccess;
-  if (ni) e = hipMemcpyAsync(d_ing, hi.data(), ni * sizeof(GroupIngest), hipMemcpyHostToDevice, b->stream);
-  if (e == hipSuccess && nr)
-    e = hipMemcpyAsync(d_rr, hr.data(), nr * sizeof(GroupRR), hipMemcpyHostToDevice, b->stream);
-  size_t oi = 0, orr = 0;
+  sg.hi.reserve(ni);
+  sg.hr.reserve(nr);
   const size_t rounds = std::max(p.ing.size(), p.rr.size());
-  const std::vector<GroupIngest> empty_i;
-  const std::vector<GroupRR> empty_r;
-  for (size_t r = 0; r < rounds && e == hipSuccess; ++r) {
-    const auto& vi = r < p.ing.size() ? p.ing[r] : empty_i;
-    const auto& vr = r < p.rr.size() ? p.rr[r] : empty_r;
-    for (size_t c0 = 0; c0 < vi.size() && e == hipSuccess; c0 += cap) {
-      const int nt = static_cast<int>(std::min<size_t>(cap, vi.size() - c0));
-      int max_f = 0;
-      for (int t = 0; t < nt; ++t) max_f = std::max(max_f, vi[c0 + t].f);
-      e = launch_group_ingest(b->d_sk, d_ing + oi + c0, nt, max_f, dt, b->stream);
-    }
-    for (size_t c0 = 0; c0 < vr.size() && e == hipSuccess; c0 += cap) {
-      const int nt = static_cast<int>(std::min<size_t>(cap, vr.size() - c0));
-      int max_mp = 0, max_m = 0, max_ldc = 0, max_keep = 0;
-      bool p0 = false, p1 = false, p3 = false;   // precisions present in this launch
-      for (int t = 0; t < nt; ++t) {
-        const GroupSketch& s = b->sk[vr[c0 + t].sk];
-        max_mp = std::max(max_mp, s.mp);
-        max_m = std::max(max_m, s.m);
-        max_ldc = std::max(max_ldc, s.ldc);
-        max_keep = std::max(max_keep, s.rp.keep);
-        p0 |= s.npass == 0;
-        p1 |= s.npass == 1;
-        p3 |= s.npass == 3;
-      }
-      const GroupRR* tt = d_rr + orr + c0;
-      if (p1 || p3) e = launch_group_gram_lowp(b->d_sk, tt, nt, max_mp, p1, p3, b->stream);
-      if (e == hipSuccess) e = launch_group_gram(b->d_sk, tt, nt, max_mp, p0, b->stream);
-      if (e == hipSuccess) e = launch_group_eig(b->d_sk, tt, nt, max_m, b->stream);
-      if (e == hipSuccess) e = launch_group_shrink_rebuild(b->d_sk, tt, nt, max_ldc, max_keep, p0, b->stream);
-      if (e == hipSuccess && (p1 || p3))
-        e = launch_group_rebuild_lowp(b->d_sk, tt, nt, max_ldc, max_keep, p1, p3, b->stream);
-    }
-    oi += vi.size();
-    orr += vr.size();
+  sg.oi.assign(rounds + 1, 0);
+  sg.orr.assign(rounds + 1, 0);
+  for (size_t r = 0; r < rounds; ++r) {
+    sg.oi[r] = sg.hi.size();
+    sg.orr[r] = sg.hr.size();
+    if (r < p.ing.size()) sg.hi.insert(sg.hi.end(), p.ing[r].begin(), p.ing[r].end());
+    if (r < p.rr.size()) sg.hr.insert(sg.hr.end(), p.rr[r].begin(), p.rr[r].end());
   }
+  sg.oi[rounds] = sg.hi.size();
+  sg.orr[rounds] = sg.hr.size();
+  sg.d_ing = static_cast<GroupIngest*>(d_tasks);
+  sg.d_rr = reinterpret_cast<GroupRR*>(static_cast<char*>(d_tasks) + ing_bytes);
+  hipError_t e = hipSuccess;
+  if (ni) e = hipMemcpyAsync(sg.d_ing, sg.hi.data(), ni * sizeof(GroupIngest), hipMemcpyHostToDevice, st);
+  if (e == hipSuccess && nr)
+    e = hipMemcpyAsync(sg.d_rr, sg.hr.data(), nr * sizeof(GroupRR), hipMemcpyHostToDevice, st);
+  if (e != hipSuccess) return berr(b, FDSK_EDEVICE, "batch task upload: %s", hipGetErrorString(e));
+  return 0;
+}
+
+// Launch round r of a staged plan on stream st, at most `cap` sketches per
+// launch.
+hipError_t launch_round(fdsk_batch* b, const Plan& p, const Staged& sg, size_t r, int dt, int cap,
+                        hipStream_t st) {
+  hipError_t e = hipSuccess;
+  static const std::vector<GroupIngest> empty_i;
+  static const std::vector<GroupRR> empty_r;
+  const auto& vi = r < p.ing.size() ? p.ing[r] : empty_i;
+  const auto& vr = r < p.rr.size() ? p.rr[r] : empty_r;
+  for (size_t c0 = 0; c0 < vi.size() && e == hipSuccess; c0 += cap) {
+    const int nt = static_cast<int>(std::min<size_t>(cap, vi.size() - c0));
+    int max_f = 0;
+    for (int t = 0; t < nt; ++t) max_f = std::max(max_f, vi[c0 + t].f);
+    e = launch_group_ingest(b->d_sk, sg.d_ing + sg.oi[r] + c0, nt, max_f, dt, st);
+  }
+  for (size_t c0 = 0; c0 < vr.size() && e == hipSuccess; c0 += cap) {
+    const int nt = static_cast<int>(std::min<size_t>(cap, vr.size() - c0));
+    int max_mp = 0, max_m = 0, max_ldc = 0, max_keep = 0;
+    bool p0 = false, p1 = false, p3 = false;   // precisions present in this launch
+    for (int t = 0; t < nt; ++t) {
+      const GroupSketch& s = b->sk[vr[c0 + t].sk];
+      max_mp = std::max(max_mp, s.mp);
+      max_m = std::max(max_m, s.m);
+      max_ldc = std::max(max_ldc, s.ldc);
+      max_keep = std::max(max_keep, s.rp.keep);
+      p0 |= s.npass == 0;
+      p1 |= s.npass == 1;
+      p3 |= s.npass == 3;
+    }
+    const GroupRR* tt = sg.d_rr + sg.orr[r] + c0;
+    if (p1 || p3) e = launch_group_gram_lowp(b->d_sk, tt, nt, max_mp, p1, p3, st);
+    if (e == hipSuccess) e = launch_group_gram(b->d_sk, tt, nt, max_mp, p0, st);
+    if (e == hipSuccess) e = launch_group_eig(b->d_sk, tt, nt, max_m, st);
+    if (e == hipSuccess) e = launch_group_shrink_rebuild(b->d_sk, tt, nt, max_ldc, max_keep, p0, st);
+    if (e == hipSuccess && (p1 || p3))
+      e = launch_group_rebuild_lowp(b->d_sk, tt, nt, max_ldc, max_keep, p1, p3, st);
+  }
+  return e;
+}
+
+// Upload a plan and launch it round by round on the batch's stream, then
+// synchronise it (the task buffer is reused by the next call).
+int run_plan(fdsk_batch* b, Plan& p, int dt, int cap) {
+  Staged sg;
+  int rc = stage_plan(b, p, b->stream, b->d_tasks, b->tasks_cap, sg);
+  if (rc) return rc;
+  hipError_t e = hipSuccess;
+  const size_t rounds = std::max(p.ing.size(), p.rr.size());
+  for (size_t r = 0; r < rounds && e == hipSuccess; ++r) e = launch_round(b, p, sg, r, dt, cap, b->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+  if (e != hipSuccess) return berr(b, FDSK_EDEVICE, "batch launch: %s", hipGetErrorString(e));
+  return 0;
+}
+
+// The same for one plan per size class, each on its own stream after the
+// caller's stream, rounds interleaved across the classes as they are
+// enqueued; the caller's stream waits for all of them and is synchronised.
+int run_class_plans(fdsk_batch* b, Plan* plans, int dt, int cap) {
+  constexpr int K = fdsk_batch::kClasses;
+  hipError_t e = hipSuccess;
+  if (!b->ev_in) {
+    e = hipEventCreateWithFlags(&b->ev_in, hipEventDisableTiming);
+    for (int g = 0; g < K && e == hipSuccess; ++g) {
+      e = hipStreamCreateWithFlags(&b->lane[g], hipStreamNonBlocking);
+      if (e == hipSuccess) e = hipEventCreateWithFlags(&b->ev_out[g], hipEventDisableTiming);
+    }
+    if (e != hipSuccess) return berr(b, FDSK_EDEVICE, "batch streams: %s", hipGetErrorString(e));
+  }
+  Staged sg[K];
+  size_t rounds = 0;
+  bool used[K] = {};
+  for (int g = 0; g < K; ++g) {
+    used[g] = !plans[g].ing.empty() || !plans[g].rr.empty();
+    if (!used[g]) continue;
+    int rc = stage_plan(b, plans[g], b->lane[g], b->d_tasks_c[g], b->tasks_cap_c[g], sg[g]);
+    if (rc) return rc;
+    rounds = std::max(rounds, std::max(plans[g].ing.size(), plans[g].rr.size()));
+  }
+  e = hipEventRecord(b->ev_in, b->stream);
+  for (int g = 0; g < K && e == hipSuccess; ++g)
+    if (used[g]) e = hipStreamWaitEvent(b->lane[g], b->ev_in, 0);
+  for (size_t r = 0; r < rounds && e == hipSuccess; ++r)
+    for (int g = 0; g < K && e == hipSuccess; ++g)
+      if (used[g]) e = launch_round(b, plans[g], sg[g], r, dt, cap, b->lane[g]);
+  for (int g = 0; g < K && e == hipSuccess; ++g)
+    if (used[g]) {
+      e = hipEventRecord(b->ev_out[g], b->lane[g]);
+      if (e == hipSuccess) e = hipStreamWaitEvent(b->stream, b->ev_out[g], 0);
+    }
+  // Synchronise every class stream (the host copies above and the task
+  // buffers are reused), then the caller's.
+  for (int g = 0; g < K; ++g)
+    if (used[g]) {
+      const hipError_t es = hipStreamSynchronize(b->lane[g]);
+      if (e == hipSuccess) e = es;
+    }
   if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
   if (e != hipSuccess) return berr(b, FDSK_EDEVICE, "batch launch: %s", hipGetErrorString(e));
   return 0;
@@ -283,10 +372,12 @@ int sketch_batch_append(fdsk_batch* b, const void* const* rows, const int64_t* n
     if (n_rows[i] > 0 && (!rows[i] || strides[i] < b->sk[i].d))
       return berr(b, FDSK_EINVAL, "sketch %d: bad rows or stride", i);
   }
-  // Lay out every sketch's ingests and ReduceRanks of this call by round.
-  Plan p;
+  // Lay out every sketch's ingests and ReduceRanks of this call by round,
+  // one plan per size class.
+  Plan plans[fdsk_batch::kClasses];
   for (int i = 0; i < b->S; ++i) {
     const GroupSketch& D = b->sk[i];
+    Plan& p = plans[size_class(D.m)];
     int64_t pos = 0;
     size_t r = 0;
     while (pos < n_rows[i]) {
@@ -312,7 +403,7 @@ int sketch_batch_append(fdsk_batch* b, const void* const* rows, const int64_t* n
     }
     b->rows_in[i] += n_rows[i];
   }
-  return run_plan(b, p, static_cast<int>(dtype), grid_size > 0 ? grid_size : b->S);
+  return run_class_plans(b, plans, static_cast<int>(dtype), grid_size > 0 ? grid_size : b->S);
 }
 
 int sketch_batch_finalize(fdsk_batch* b, void* const* B_out, const int64_t* ldb, fdsk_dtype out_dtype,
@@ -414,6 +505,15 @@ int sketch_batch_stats(const fdsk_batch* cb, int32_t index, fdsk_report* out) {
 void sketch_batch_destroy(fdsk_batch* b) {
   if (!b) return;
   (void)hipStreamSynchronize(b->stream);
+  for (int g = 0; g < fdsk_batch::kClasses; ++g) {
+    if (b->lane[g]) {
+      (void)hipStreamSynchronize(b->lane[g]);
+      (void)hipStreamDestroy(b->lane[g]);
+    }
+    if (b->ev_out[g]) (void)hipEventDestroy(b->ev_out[g]);
+    if (b->d_tasks_c[g]) (void)hipFree(b->d_tasks_c[g]);
+  }
+  if (b->ev_in) (void)hipEventDestroy(b->ev_in);
   if (b->d_tasks) (void)hipFree(b->d_tasks);
   if (b->arena) (void)hipFree(b->arena);
   delete b;
