@@ -301,8 +301,9 @@ def _check_batch(rc, handle=None):
 
 
 class FDSketchBatch:
-    """Many independent sketches advanced together in lock-step rounds (one launch per
-    stage and round over all active sketches)."""
+    """Many independent sketches advanced together in lock-step rounds: one schedule per
+    class of buffer rows, each class on its own library stream ordered after the batch's
+    stream, and one launch per stage and round over the class's active sketches."""
 
     def __init__(self, configs, stream=None):
         """configs: list of dicts with keys d, l and optionally variant, alpha, buffer_rows,

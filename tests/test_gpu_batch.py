@@ -78,6 +78,27 @@ def test_batch_is_independent_of_grid_and_chunking():
         assert np.array_equal(a, c)
 
 
+def test_batch_on_a_side_stream_waits_for_its_rows():
+    """The batch created on a side stream, its rows produced on the current
+    stream just before the append (a real dependency): the per-class streams
+    start after the rows are ready, and the sketches equal those of a batch
+    on the current stream, bit for bit.  Buffers in all four size classes."""
+    cfgs = [dict(d=90, l=l, variant="fd", alpha=0.2) for l in (20, 50, 90, 120)]
+    mats = [synth.random_noisy(900, 90, 5, 10.0, seed=(62, i)) for i in range(4)]
+    ref, _ = _run(cfgs, mats)
+    side = torch.cuda.Stream()
+    b = F.FDSketchBatch(cfgs, stream=side)
+    src = [torch.from_numpy(A).cuda() for A in mats]
+    torch.cuda.synchronize()
+    rows = [(t * 2.0) * 0.5 for t in src]          # made on the current stream
+    b.append(rows)
+    with torch.cuda.stream(side):
+        outs = [o.cpu().numpy() for o in b.finalize()]
+    b.close()
+    for a, o in zip(ref, outs):
+        assert np.array_equal(a, o)
+
+
 def test_batch_edge_cases():
     cfgs = [dict(d=15, l=8, variant="fd", alpha=0.2),      # no rows
             dict(d=40, l=10, variant="alpha", alpha=0.2),  # fewer rows than l
