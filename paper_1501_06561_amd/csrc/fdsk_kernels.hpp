@@ -56,6 +56,9 @@ hipError_t launch_gram_reduce(const double* Gpart, int ksplit, int mp, double* G
 hipError_t launch_gram_lowp(const double* C, int ldc, int mp, double* Gpart, int ksplit_max, double* G,
                             int npass, void* bfw, hipStream_t s);
 size_t bf16_workspace_bytes(int mp, int ldc);
+// The buffer's hi/lo bf16 halves into bfw (for a rebuild whose Gram did not
+// write them: the FP8 path).
+hipError_t launch_split_bf16(const double* C, int ldc, int mp, void* bfw, hipStream_t s);
 // FP8 (e4m3) compensated Gram: per-row scaled hi/lo codes of C in q8
 // (fp8_workspace_bytes), then three FP8 products per tile.
 hipError_t launch_gram_fp8(const double* C, int ldc, int mp, void* q8, double* Gpart, int ksplit_max,

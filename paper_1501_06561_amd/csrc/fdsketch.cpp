@@ -35,7 +35,7 @@ struct fdsk_sketch {
   double *G = nullptr, *Gpart = nullptr, *W = nullptr, *V = nullptr, *lam = nullptr,
          *Ut = nullptr, *rownorm = nullptr, *S1 = nullptr, *S2 = nullptr;
   void* q8 = nullptr;   // FP8 codes and scales of the buffer (FDSK_P_FP8X3)
-  void* bfw = nullptr;  // the buffer's bf16 hi/lo halves (FDSK_P_BF16, FDSK_P_BF16X3)
+  void* bfw = nullptr;  // the buffer's bf16 hi/lo halves (every reduced precision)
   int ksplit_max = 1;
   DevStats* st = nullptr;
   unsigned* bar = nullptr;
@@ -180,10 +180,13 @@ int shrink_rebuild(fdsk_sketch* s, const RuleParams& rp, int new0, int new1, con
   hipEvent_t e3 = mark(s);
   if (s->cfg.precision == FDSK_P_FP64)
     HIPCHK(s, launch_rebuild(s->Ut, src, s->ldc, s->mp, rp.keep, dst, s->stream));
-  else
-    // The bf16 path reads the halves the Gram of the same buffer wrote (src
-    // is that buffer for every caller); FP8X3 splits in the product.
+  else {
+    // The bf16 paths read the halves the Gram of the same buffer wrote (src
+    // is that buffer for every caller); the FP8 Gram wrote none, so FP8X3
+    // splits the buffer first and rebuilds with split-BF16 x3.
+    if (s->cfg.precision == FDSK_P_FP8X3) HIPCHK(s, launch_split_bf16(src, s->ldc, s->mp, s->bfw, s->stream));
     HIPCHK(s, launch_rebuild_lowp(s->Ut, src, s->ldc, s->mp, rp.keep, dst, npass, s->bfw, s->stream));
+  }
   add_mark(s, 3, e2, e3);
   add_mark(s, 4, e3, mark(s));
   return 0;
@@ -332,8 +335,7 @@ int sketch_create(const fdsk_config* cfg, void* hip_stream, fdsk_sketch** out) {
          oSt = take(sizeof(DevStats)), oBar = take(4 * sizeof(unsigned)),
          oRot = take(kMaxSweeps * sizeof(int)), oS1 = take(mp2 * 8), oS2 = take(mp2 * 8),
          oQ8 = take(c.precision == FDSK_P_FP8X3 ? fp8_workspace_bytes(s->mp, s->ldc) : 0),
-         oBf = take((c.precision == FDSK_P_BF16 || c.precision == FDSK_P_BF16X3)
-                        ? bf16_workspace_bytes(s->mp, s->ldc) : 0);
+         oBf = take(c.precision != FDSK_P_FP64 ? bf16_workspace_bytes(s->mp, s->ldc) : 0);
   hipError_t e = hipMalloc(&s->arena, off);
   if (e != hipSuccess) {
     delete s;
@@ -355,7 +357,7 @@ int sketch_create(const fdsk_config* cfg, void* hip_stream, fdsk_sketch** out) {
   s->S1 = reinterpret_cast<double*>(a + oS1);
   s->S2 = reinterpret_cast<double*>(a + oS2);
   s->q8 = (c.precision == FDSK_P_FP8X3) ? static_cast<void*>(a + oQ8) : nullptr;
-  s->bfw = (c.precision == FDSK_P_BF16 || c.precision == FDSK_P_BF16X3) ? static_cast<void*>(a + oBf) : nullptr;
+  s->bfw = (c.precision != FDSK_P_FP64) ? static_cast<void*>(a + oBf) : nullptr;
   e = hipMemsetAsync(s->arena, 0, off, s->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
   if (e != hipSuccess) {

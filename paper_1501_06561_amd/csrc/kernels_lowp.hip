@@ -322,6 +322,14 @@ __global__ __launch_bounds__(256) void k_rebuild_bf16t(const double* __restrict_
   }
 }
 
+hipError_t launch_split_bf16(const double* C, int ldc, int mp, void* bfw, hipStream_t s) {
+  const int rows64 = (mp + 63) / 64 * 64;
+  uint16_t* H = static_cast<uint16_t*>(bfw);
+  uint16_t* L = H + static_cast<size_t>(rows64) * ldc;
+  hipLaunchKernelGGL(k_split_bf16, dim3((ldc + 255) / 256, rows64), dim3(256), 0, s, C, ldc, mp, H, L);
+  return hipGetLastError();
+}
+
 hipError_t launch_gram_lowp(const double* C, int ldc, int mp, double* Gpart, int ksplit_max, double* G,
                             int npass, void* bfw, hipStream_t s) {
   if (bfw) {
