@@ -188,7 +188,7 @@ hipError_t launch_round(fdsk_batch* b, const Plan& p, const Staged& sg, size_t r
       p3 |= s.npass == 3;
     }
     const GroupRR* tt = sg.d_rr + sg.orr[r] + c0;
-    if (p1 || p3) e = launch_group_gram_lowp(b->d_sk, tt, nt, max_mp, p1, p3, st);
+    if (p1 || p3) e = launch_group_gram_lowp(b->d_sk, tt, nt, max_mp, max_ldc, p1, p3, st);
     if (e == hipSuccess) e = launch_group_gram(b->d_sk, tt, nt, max_mp, p0, st);
     if (e == hipSuccess) e = launch_group_eig(b->d_sk, tt, nt, max_m, st);
     if (e == hipSuccess) e = launch_group_shrink_rebuild(b->d_sk, tt, nt, max_ldc, max_keep, p0, st);
@@ -305,7 +305,7 @@ int sketch_batch_create(int32_t S, const fdsk_config* cfgs, void* hip_stream, fd
     off += (bytes + 255) / 256 * 256;
     return o;
   };
-  constexpr int NB = 11;   // C0 C1 Gp G W V Ut S1 S2 lam rownorm
+  constexpr int NB = 12;   // C0 C1 Gp G W V Ut S1 S2 lam rownorm bf16-halves
   std::vector<size_t> o(static_cast<size_t>(S) * NB);
   for (int i = 0; i < S; ++i) {
     const fdsk_config& c = cfgs[i];
@@ -325,6 +325,7 @@ int sketch_batch_create(int32_t S, const fdsk_config* cfgs, void* hip_stream, fd
     for (int k = 2; k < 9; ++k) q[k] = take(g);
     q[9] = take(static_cast<size_t>(D.mp) * 8);
     q[10] = take(static_cast<size_t>(D.mp) * 8);
+    q[11] = take(D.npass > 0 ? bf16_workspace_bytes(D.mp, D.ldc) : 0);
   }
   const size_t oDesc = take(sizeof(GroupSketch) * S), oStats = take(sizeof(DevStats) * S);
   hipError_t e = hipMalloc(&b->arena, off);
@@ -342,6 +343,7 @@ int sketch_batch_create(int32_t S, const fdsk_config* cfgs, void* hip_stream, fd
     for (int k = 0; k < 9; ++k) *f[k] = reinterpret_cast<double*>(a + q[k]);
     D.lam = reinterpret_cast<double*>(a + q[9]);
     D.rownorm = reinterpret_cast<double*>(a + q[10]);
+    D.bh = D.npass > 0 ? reinterpret_cast<uint16_t*>(a + q[11]) : nullptr;
     D.st = b->d_stats + i;
   }
   e = hipMemsetAsync(b->arena, 0, off, b->stream);

@@ -29,6 +29,7 @@ struct GroupSketch {
   double* S2;
   double* lam;       // mp
   double* rownorm;   // mp
+  uint16_t* bh;      // bf16 halves of the buffer (npass > 0): hi then lo, rows64 x ldc each
   DevStats* st;
   int d, ldc, l, m, mp;
   int npass;         // Gram/rebuild products: 0 FP64, 1 BF16, 3 split-BF16 (compensated)
@@ -55,8 +56,8 @@ hipError_t launch_group_ingest(const GroupSketch* sk, const GroupIngest* t, int 
 // FP64 Gram for tasks with npass 0, then the symmetric mirror for every task.
 hipError_t launch_group_gram(const GroupSketch* sk, const GroupRR* t, int nt, int max_mp, bool fp64,
                              hipStream_t s);
-hipError_t launch_group_gram_lowp(const GroupSketch* sk, const GroupRR* t, int nt, int max_mp, bool one,
-                                  bool three, hipStream_t s);
+hipError_t launch_group_gram_lowp(const GroupSketch* sk, const GroupRR* t, int nt, int max_mp, int max_ldc,
+                                  bool one, bool three, hipStream_t s);
 hipError_t launch_group_rebuild_lowp(const GroupSketch* sk, const GroupRR* t, int nt, int max_ldc,
                                      int max_keep, bool one, bool three, hipStream_t s);
 hipError_t launch_group_eig(const GroupSketch* sk, const GroupRR* t, int nt, int max_m, hipStream_t s);

@@ -165,10 +165,11 @@ size_t bf16_workspace_bytes(int mp, int ldc) {
   return 2 * rows64 * static_cast<size_t>(ldc) * sizeof(uint16_t);
 }
 
-__global__ __launch_bounds__(256) void k_split_bf16(const double* __restrict__ C, int ldc, int mp,
-                                                    uint16_t* __restrict__ H, uint16_t* __restrict__ L) {
-  const int r = blockIdx.y;
-  for (int c = blockIdx.x * 256 + threadIdx.x; c < ldc; c += gridDim.x * 256) {
+// Row r, columns bx*256 + tid (+ nbx*256 ...).
+__device__ __forceinline__ void split_bf16_body(const double* __restrict__ C, int ldc, int mp,
+                                                uint16_t* __restrict__ H, uint16_t* __restrict__ L,
+                                                int bx, int r, int nbx) {
+  for (int c = bx * 256 + threadIdx.x; c < ldc; c += nbx * 256) {
     uint16_t hb = 0, lb = 0;
     if (r < mp) {
       const double x = C[static_cast<int64_t>(r) * ldc + c];
@@ -180,6 +181,11 @@ __global__ __launch_bounds__(256) void k_split_bf16(const double* __restrict__ C
   }
 }
 
+__global__ __launch_bounds__(256) void k_split_bf16(const double* __restrict__ C, int ldc, int mp,
+                                                    uint16_t* __restrict__ H, uint16_t* __restrict__ L) {
+  split_bf16_body(C, ldc, mp, H, L, blockIdx.x, blockIdx.y, gridDim.x);
+}
+
 // G partials on lower-triangular 64x64 tiles of the pre-split buffer, split-K
 // in chunks of kchunk (a multiple of 64).  Four waves; wave (wi, wj) owns the
 // 32x32 block at (32 wi, 32 wj) as 2x2 16x16 tiles.  A 64-column K slab of
@@ -187,9 +193,9 @@ __global__ __launch_bounds__(256) void k_split_bf16(const double* __restrict__ C
 constexpr int kBt = 64, kBk = 64, kBpad = 8;
 
 template <int NPASS>
-__global__ __launch_bounds__(256) void k_gram_bf16t(const uint16_t* __restrict__ H, const uint16_t* __restrict__ L,
-                                                    int ldc, int mp, int kchunk, double* __restrict__ Gpart) {
-  const int tile = blockIdx.x, ks = blockIdx.y;
+__device__ __forceinline__ void gram_bf16t_body(const uint16_t* __restrict__ H, const uint16_t* __restrict__ L,
+                                                int ldc, int mp, int kchunk, double* __restrict__ Gpart,
+                                                int tile, int ks) {
   int ti = static_cast<int>((sqrtf(8.0f * tile + 1.0f) - 1.0f) * 0.5f);
   while ((ti + 1) * (ti + 2) / 2 <= tile) ++ti;
   while (ti * (ti + 1) / 2 > tile) --ti;
@@ -255,15 +261,21 @@ __global__ __launch_bounds__(256) void k_gram_bf16t(const uint16_t* __restrict__
       }
 }
 
+template <int NPASS>
+__global__ __launch_bounds__(256) void k_gram_bf16t(const uint16_t* __restrict__ H, const uint16_t* __restrict__ L,
+                                                    int ldc, int mp, int kchunk, double* __restrict__ Gpart) {
+  gram_bf16t_body<NPASS>(H, L, ldc, mp, kchunk, Gpart, blockIdx.x, blockIdx.y);
+}
+
 // out[0:keep, :] = Ut[0:keep, 0:mp] * C with C's hi/lo from the pre-split
 // arrays (Ut is split in the loop: it is small).  Tile 32 rows x 64 columns;
 // C's 32x64 slab is staged transposed in LDS so that each B fragment is one
 // 16-byte read.
 template <int NPASS>
-__global__ __launch_bounds__(256) void k_rebuild_bf16t(const double* __restrict__ Ut, const uint16_t* __restrict__ H,
-                                                       const uint16_t* __restrict__ L, int ldc, int mp, int keep,
-                                                       double* __restrict__ out) {
-  const int r0 = blockIdx.y * 32, c0 = blockIdx.x * 64;
+__device__ __forceinline__ void rebuild_bf16t_body(const double* __restrict__ Ut, const uint16_t* __restrict__ H,
+                                                   const uint16_t* __restrict__ L, int ldc, int mp, int keep,
+                                                   double* __restrict__ out, int bx, int by) {
+  const int r0 = by * 32, c0 = bx * 64;
   __shared__ double As[32][33];
   __shared__ __attribute__((aligned(16))) uint16_t BhT[64][32 + kBpad];
   __shared__ __attribute__((aligned(16))) uint16_t BlT[NPASS == 3 ? 64 : 1][32 + kBpad];
@@ -320,6 +332,13 @@ __global__ __launch_bounds__(256) void k_rebuild_bf16t(const double* __restrict_
       out[o + 16] = static_cast<double>(acc1[v]);
     }
   }
+}
+
+template <int NPASS>
+__global__ __launch_bounds__(256) void k_rebuild_bf16t(const double* __restrict__ Ut, const uint16_t* __restrict__ H,
+                                                       const uint16_t* __restrict__ L, int ldc, int mp, int keep,
+                                                       double* __restrict__ out) {
+  rebuild_bf16t_body<NPASS>(Ut, H, L, ldc, mp, keep, out, blockIdx.x, blockIdx.y);
 }
 
 hipError_t launch_split_bf16(const double* C, int ldc, int mp, void* bfw, hipStream_t s) {
@@ -544,16 +563,31 @@ size_t fp8_workspace_bytes(int mp, int ldc) {
 
 // ------------------------------------------------------ grouped (batches)
 // Tasks of sketches with another precision return at once (the FP64 kernels
-// of kernels_stream.hip take those).
+// of kernels_stream.hip take those).  As for a single sketch, the buffer is
+// split into its bf16 halves once per ReduceRank (s.bh: hi rows then lo
+// rows, rows64 x ldc each), read by the Gram (one K pass per tile, lower
+// 64 x 64 tiles into Gp) and by the rebuild of the same task.
+__global__ __launch_bounds__(256) void kg_split_bf16(const GroupSketch* __restrict__ SK,
+                                                     const GroupRR* __restrict__ T) {
+  const GroupRR t = T[blockIdx.z];
+  const GroupSketch& s = SK[t.sk];
+  if (s.npass == 0) return;
+  const int rows64 = (s.mp + 63) / 64 * 64;
+  if (static_cast<int>(blockIdx.y) >= rows64 || static_cast<int>(blockIdx.x) * 256 >= s.ldc) return;
+  split_bf16_body(t.cur ? s.C1 : s.C0, s.ldc, s.mp, s.bh, s.bh + static_cast<int64_t>(rows64) * s.ldc,
+                  blockIdx.x, blockIdx.y, gridDim.x);
+}
+
 template <int NPASS>
 __global__ __launch_bounds__(256) void kg_gram_bf16(const GroupSketch* __restrict__ SK,
                                                     const GroupRR* __restrict__ T) {
   const GroupRR t = T[blockIdx.z];
   const GroupSketch& s = SK[t.sk];
   if (s.npass != NPASS) return;
-  const int nt = s.mp / 32;
+  const int rows64 = (s.mp + 63) / 64 * 64, nt = rows64 / kBt;
   if (static_cast<int>(blockIdx.x) >= nt * (nt + 1) / 2) return;
-  gram_bf16_body<NPASS>(t.cur ? s.C1 : s.C0, s.ldc, s.mp, s.ldc, s.Gp, blockIdx.x, 0);
+  gram_bf16t_body<NPASS>(s.bh, s.bh + static_cast<int64_t>(rows64) * s.ldc, s.ldc, s.mp, s.ldc, s.Gp,
+                         blockIdx.x, 0);
 }
 
 template <int NPASS>
@@ -563,17 +597,22 @@ __global__ __launch_bounds__(256) void kg_rebuild_bf16(const GroupSketch* __rest
   const GroupSketch& s = SK[t.sk];
   if (s.npass != NPASS) return;
   if (static_cast<int>(blockIdx.x) >= s.ldc / 64 || static_cast<int>(blockIdx.y) * 32 >= s.rp.keep) return;
-  rebuild_bf16_body<NPASS>(s.Ut, t.cur ? s.C1 : s.C0, s.ldc, s.mp, s.rp.keep, t.cur ? s.C0 : s.C1,
-                           blockIdx.x, blockIdx.y);
+  const int rows64 = (s.mp + 63) / 64 * 64;
+  rebuild_bf16t_body<NPASS>(s.Ut, s.bh, s.bh + static_cast<int64_t>(rows64) * s.ldc, s.ldc, s.mp, s.rp.keep,
+                            t.cur ? s.C0 : s.C1, blockIdx.x, blockIdx.y);
 }
 
-hipError_t launch_group_gram_lowp(const GroupSketch* sk, const GroupRR* t, int nt, int max_mp, bool one,
-                                  bool three, hipStream_t s) {
+hipError_t launch_group_gram_lowp(const GroupSketch* sk, const GroupRR* t, int nt, int max_mp, int max_ldc,
+                                  bool one, bool three, hipStream_t s) {
   if (nt <= 0) return hipSuccess;
-  const int T = max_mp / 32;
-  const dim3 g(T * (T + 1) / 2, 1, nt);
-  if (one) hipLaunchKernelGGL(kg_gram_bf16<1>, g, dim3(256), 0, s, sk, t);
+  const int rows64 = (max_mp + 63) / 64 * 64, T = rows64 / kBt;
+  hipLaunchKernelGGL(kg_split_bf16, dim3((max_ldc + 255) / 256, rows64, nt), dim3(256), 0, s, sk, t);
   hipError_t e = hipGetLastError();
+  const dim3 g(T * (T + 1) / 2, 1, nt);
+  if (e == hipSuccess && one) {
+    hipLaunchKernelGGL(kg_gram_bf16<1>, g, dim3(256), 0, s, sk, t);
+    e = hipGetLastError();
+  }
   if (e == hipSuccess && three) {
     hipLaunchKernelGGL(kg_gram_bf16<3>, g, dim3(256), 0, s, sk, t);
     e = hipGetLastError();
