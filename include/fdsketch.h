@@ -73,8 +73,11 @@ typedef enum {
 typedef enum { FDSK_F64 = 0, FDSK_F32 = 1, FDSK_BF16 = 2 } fdsk_dtype;  /* BF16 = raw uint16 bits */
 /* Arithmetic of the Gram and rebuild products.  The eigensolver, the shrink
  * subtraction and every accumulator are FP64 in all modes; the buffer stays
- * FP64.  BF16: each FP64 operand rounded to bfloat16, products on BF16
- * matrix cores with FP32 accumulation.  BF16X3: operands split as
+ * FP64.  BF16 (fdsk_gram only; sketch_create and sketch_batch_create return
+ * FDSK_EUNSUPPORTED, because one uncompensated pass misses the 1e-3 of
+ * ||A||_F^2 covariance-error bar of the reduced-precision sketches): each
+ * FP64 operand rounded to bfloat16, products on BF16 matrix cores with FP32
+ * accumulation.  BF16X3: operands split as
  * hi = bf16(x), lo = bf16(x - hi) and hi*hi + hi*lo + lo*hi accumulated.
  * FP8X3 (Gram only; the rebuild is BF16X3): each buffer row split as
  * hi = e4m3(x / s), lo = e4m3((x - s hi) / t) with per-row scales s, t (row
@@ -103,7 +106,7 @@ typedef struct {
   fdsk_variant variant;
   double alpha;           /* (0, 1]; used by FDSK_ALPHA and FDSK_FAST_ALPHA */
   fdsk_precision precision;
-  uint32_t flags;         /* 0 or FDSK_FLAG_PROFILE */
+  uint32_t flags;         /* 0, or FDSK_FLAG_PROFILE and/or FDSK_FLAG_EIG_JACOBI */
 } fdsk_config;
 
 typedef struct {
@@ -154,7 +157,8 @@ int sketch_append_rows(fdsk_sketch* s, const void* rows, int64_t n_rows, int64_t
  * state), ESTATE (either finalized), EDEVICE. */
 int sketch_merge(fdsk_sketch* dst, fdsk_sketch* src);
 
-/* Finish the stream: if more than l rows are occupied, one more ReduceRank
+/* Finish the stream (Algorithm 1, Section 2.3: the sketch returned after the
+ * last row): if more than l rows are occupied, one more ReduceRank
  * (FDSK_CFD: then its compensation, see the rules above, *rows_out = l);
  * then write the l x d sketch B (rows beyond *rows_out are zero) to B_out
  * (leading dimension ldb >= d, dtype FDSK_F64 or FDSK_F32).  Synchronises the
@@ -181,8 +185,9 @@ int fdsk_evaluate(const void* A, int64_t n, int64_t lda, fdsk_dtype a_dtype,
                   int64_t d, fdsk_mem mem, int32_t k, int32_t method, void* hip_stream,
                   fdsk_report* out);
 
-/* Accumulators so far (||A||_F^2, Delta, shrink total, rows, reductions).
- * Synchronises the stream. */
+/* Accumulators so far: ||A||_F^2 (Section 1.1), Delta = sum of the delta_i
+ * and the total squared mass removed (the quantities of Properties 1-3,
+ * Section 3.1), rows and reductions.  Synchronises the stream. */
 int sketch_stats(const fdsk_sketch* s, fdsk_report* out);
 
 /* Return the sketch to its empty state (all rows free, accumulators zero,
@@ -203,7 +208,8 @@ typedef struct {
 } fdsk_profile;
 int sketch_profile(fdsk_sketch* s, fdsk_profile* out);
 
-/* Free everything the sketch owns (waits for its stream first). NULL is ok. */
+/* Free everything the sketch owns (waits for its stream first). NULL is ok.
+ * Resource management only: no step of the method. */
 void sketch_destroy(fdsk_sketch* s);
 
 /* Message of the last error on this sketch ("" if none); valid until the

@@ -17,11 +17,12 @@ evaluate  -- the error measures of Section 1.1 (covariance and projection error)
 from .fd import (FD, ISVD, ALPHA, FAST_ALPHA, SSD, CFD, VARIANTS, ALL_VARIANTS, rule_indices, alpha_eff,
                  reduce_rank, SketchOracle, fd_sketch, fd_covariance_form,
                  counter_simulation)
-from .evaluate import cov_err, proj_err, proj_full, tail_mass, fro2
+from .evaluate import cov_err, proj_err, proj_full, tail_mass, fro2, gram, cov_err_gram
 
 __all__ = [
     "FD", "ISVD", "ALPHA", "FAST_ALPHA", "SSD", "CFD", "VARIANTS", "ALL_VARIANTS", "rule_indices",
     "alpha_eff",
     "reduce_rank", "SketchOracle", "fd_sketch", "fd_covariance_form",
-    "counter_simulation", "cov_err", "proj_err", "proj_full", "tail_mass", "fro2",
+    "counter_simulation", "cov_err", "proj_err", "proj_full", "tail_mass", "fro2", "gram",
+    "cov_err_gram",
 ]

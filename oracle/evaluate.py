@@ -58,3 +58,21 @@ def proj_full(A: np.ndarray, B: np.ndarray) -> float:
     A = np.asarray(A, dtype=np.float64)
     V = _row_basis(B)
     return float((fro2(A) - fro2(A @ V.T)) / fro2(A))
+
+
+# Streams too long to hold as one matrix are scored from their column Gram
+# A^T A, accumulated chunk by chunk.  The measure is the same definition
+# (Section 1.1): the spectral norm of A^T A - B^T B over ||A||_F^2.
+
+def gram(A: np.ndarray) -> np.ndarray:
+    """A^T A in FP64."""
+    A = np.asarray(A, dtype=np.float64)
+    return A.T @ A
+
+
+def cov_err_gram(AtA: np.ndarray, fro2A: float, B: np.ndarray) -> float:
+    """||A^T A - B^T B||_2 / ||A||_F^2 from A's column Gram (dense eigvalsh)."""
+    B = np.asarray(B, dtype=np.float64)
+    M = np.asarray(AtA, dtype=np.float64) - B.T @ B
+    w = np.linalg.eigvalsh(M)
+    return float(max(abs(w[0]), abs(w[-1])) / fro2A)

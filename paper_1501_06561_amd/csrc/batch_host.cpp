@@ -284,7 +284,10 @@ int sketch_batch_create(int32_t S, const fdsk_config* cfgs, void* hip_stream, fd
       return berr(nullptr, FDSK_EINVAL, "sketch %d: alpha must lie in (0, 1]", i);
     if (c.precision == FDSK_P_FP8X3)
       return berr(nullptr, FDSK_EUNSUPPORTED, "sketch %d: the FP8 Gram is single-sketch only", i);
-    if (c.precision != FDSK_P_FP64 && c.precision != FDSK_P_BF16 && c.precision != FDSK_P_BF16X3)
+    if (c.precision == FDSK_P_BF16)
+      return berr(nullptr, FDSK_EUNSUPPORTED,
+                  "sketch %d: single-pass BF16 is not a sketching precision (use FDSK_P_BF16X3)", i);
+    if (c.precision != FDSK_P_FP64 && c.precision != FDSK_P_BF16X3)
       return berr(nullptr, FDSK_EINVAL, "sketch %d: unknown precision", i);
     if (c.flags != 0) return berr(nullptr, FDSK_EUNSUPPORTED, "sketch %d: batched sketches take no flags", i);
   }

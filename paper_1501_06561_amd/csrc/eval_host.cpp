@@ -94,11 +94,11 @@ hipError_t evaluate_device(const void* A, int a_dt, int64_t n, int64_t lda, cons
   need += dense ? al(dd * 8) * (1 + nsplit_max) : 0;                // M, partials
   need += al(static_cast<size_t>(K + 1) * d * 8) + 3 * al(d * 8);    // Q, y, (tmp)
   need += 4 * al(static_cast<size_t>(K + 1) * 8);                    // h1 h2 alpha beta
-  need += 4 * al(static_cast<size_t>(mpT) * mpT * 8) + al(mpT * 8);  // T, VT, W, spare, lamT
+  need += 5 * al(static_cast<size_t>(mpT) * mpT * 8) + al(mpT * 8);  // T, VT, W, S1, S2, lamT
   need += dense ? 0 : al(static_cast<size_t>(std::max<int64_t>(n, rows_b)) * 8) +
                           al(static_cast<size_t>(nz_max) * d * 8);
   need += 2 * al(static_cast<size_t>(mpB) * ldcB * 8);               // padded B, unused
-  need += 4 * al(static_cast<size_t>(mpB) * mpB * 8) + al(mpB * 8) + al(mpB * 4);  // GB, part, VB, WB, lamB, perm
+  need += 6 * al(static_cast<size_t>(mpB) * mpB * 8) + al(mpB * 8) + al(mpB * 4);  // GB, part, VB, WB, S1, S2, lamB, perm
   need += al(static_cast<size_t>(mpB) * d * 8);                      // Vt
   need += al(4096 * 2 * 8) + al(64 * 8) + 4 * al(sizeof(DevStats)) + al(64) + al(64 * 4) + al(16 * 8);
   need += al(static_cast<size_t>(2 + std::max(kk, 1)) * 8) * 2;
@@ -120,7 +120,8 @@ hipError_t evaluate_device(const void* A, int a_dt, int64_t n, int64_t lda, cons
   double* T = ar.take<double>(static_cast<size_t>(mpT) * mpT);
   double* VT = ar.take<double>(static_cast<size_t>(mpT) * mpT);
   double* WT = ar.take<double>(static_cast<size_t>(mpT) * mpT);
-  ar.take<double>(static_cast<size_t>(mpT) * mpT);
+  double* S1T = ar.take<double>(static_cast<size_t>(mpT) * mpT);
+  double* S2T = ar.take<double>(static_cast<size_t>(mpT) * mpT);
   double* lamT = ar.take<double>(mpT);
   double* tvec = dense ? nullptr : ar.take<double>(std::max<int64_t>(n, rows_b));
   double* part = dense ? nullptr : ar.take<double>(static_cast<size_t>(nz_max) * d);
@@ -130,6 +131,8 @@ hipError_t evaluate_device(const void* A, int a_dt, int64_t n, int64_t lda, cons
   double* GBpart = ar.take<double>(static_cast<size_t>(mpB) * mpB);
   double* VB = ar.take<double>(static_cast<size_t>(mpB) * mpB);
   double* WB = ar.take<double>(static_cast<size_t>(mpB) * mpB);
+  double* S1B = ar.take<double>(static_cast<size_t>(mpB) * mpB);
+  double* S2B = ar.take<double>(static_cast<size_t>(mpB) * mpB);
   double* lamB = ar.take<double>(mpB);
   int* perm = ar.take<int>(mpB);
   double* Vt = ar.take<double>(static_cast<size_t>(mpB) * d);
@@ -144,7 +147,8 @@ hipError_t evaluate_device(const void* A, int a_dt, int64_t n, int64_t lda, cons
   int* nrank = reinterpret_cast<int*>(scal + 32);
   EVCHK(hipMemsetAsync(ar.base, 0, ar.off, s));
 
-  EigWork wkT{WT, bar, rot, ds};
+  // Both eigensolves take the tridiagonal route (ordinary launches only).
+  EigWork wkT{WT, bar, rot, ds, S1T, S2T, EIG_AUTO};
 
   // 1. ||A||_F^2
   EVCHK(eval_fro2(A, a_dt, lda, n, d, mpart, scal + 0, s));
@@ -179,7 +183,7 @@ hipError_t evaluate_device(const void* A, int a_dt, int64_t n, int64_t lda, cons
     EVCHK(hipMemcpy2DAsync(Bp, ldcB * 8, B, ldb * 8, static_cast<size_t>(d) * 8, rows_b,
                            hipMemcpyDeviceToDevice, s));
     EVCHK(launch_gram(Bp, ldcB, mpB, GBpart, 1, GB, s));
-    EigWork wkB{WB, bar, rot, ds};
+    EigWork wkB{WB, bar, rot, ds, S1B, S2B, EIG_AUTO};
     EVCHK(launch_eig(GB, lb, mpB, lamB, VB, wkB, s));
     EVCHK(eval_rowspace(lamB, VB, lb, mpB, B, ldb, d, 1e-12, perm, nrank, Vt, s));
     EVCHK(eval_proj_mass(A, a_dt, lda, n, d, Vt, nrank, kk, mpart, scal + 8, s));

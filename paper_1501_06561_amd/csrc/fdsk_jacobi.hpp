@@ -1,5 +1,4 @@
-// Jacobi building blocks shared by the single-sketch eigensolvers and the
-// many-sketch persistent kernel (device code only).
+// Jacobi building blocks of the Jacobi eigensolvers (device code only).
 //
 // The buffer's SVD (Algorithm 1) is reached through G = C C^T = U diag(lambda) U^T:
 // sigma_j^2 = lambda_j and the rebuilt rows are diag(sigma'/sigma) U^T C.

@@ -304,6 +304,12 @@ int sketch_create(const fdsk_config* cfg, void* hip_stream, fdsk_sketch** out) {
   if (c.precision != FDSK_P_FP64 && c.precision != FDSK_P_BF16 && c.precision != FDSK_P_BF16X3 &&
       c.precision != FDSK_P_FP8X3)
     return set_err(nullptr, FDSK_EINVAL, "unknown precision %d", (int)c.precision);
+  // One uncompensated BF16 pass keeps ~8 significant bits per operand; the
+  // covariance error it reaches misses the 1e-3 (of ||A||_F^2) bar set for
+  // reduced-precision sketches, so it is offered by fdsk_gram only.
+  if (c.precision == FDSK_P_BF16)
+    return set_err(nullptr, FDSK_EUNSUPPORTED,
+                   "single-pass BF16 is not a sketching precision (use FDSK_P_BF16X3)");
   if (c.flags & ~(FDSK_FLAG_PROFILE | FDSK_FLAG_EIG_JACOBI))
     return set_err(nullptr, FDSK_EINVAL, "unknown flags");
 

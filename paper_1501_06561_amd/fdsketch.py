@@ -151,6 +151,29 @@ def _stream_handle(stream):
     return ctypes.c_void_p(stream.cuda_stream)
 
 
+def _bound_stream(stream):
+    """The torch stream a library object is bound to: the given one, else the
+    one current at creation (None without a GPU runtime)."""
+    if stream is not None:
+        return stream
+    torch = _torch()
+    return torch.cuda.current_stream() if torch.cuda.is_available() else None
+
+
+def _order_after_current(stream, *tensors):
+    """Make `stream` wait for the current stream and keep the device tensors'
+    memory from reuse until `stream` has passed them (no-op when they are
+    the same stream or nothing is on the device)."""
+    dev = [t for t in tensors if getattr(t, "is_cuda", False)]
+    if stream is None or not dev:
+        return
+    cur = _torch().cuda.current_stream()
+    if stream != cur:
+        stream.wait_stream(cur)
+        for t in dev:
+            t.record_stream(stream)
+
+
 def _rows_arg(rows):
     """(pointer, n, stride, dtype code, mem kind, keepalive) for a 2-D matrix."""
     if isinstance(rows, np.ndarray):
@@ -178,9 +201,11 @@ class FDSketch:
             raise ValueError(f"eig must be one of {sorted(EIG_METHODS)}")
         cfg = FdskConfig(self.d, self.l, int(buffer_rows), VARIANTS[variant], float(alpha),
                          PRECISIONS[precision], flags)
-        self._stream = stream
+        # The library keeps the stream it is created with; remember it as a
+        # torch stream object so later calls can order themselves after it.
+        self._stream = _bound_stream(stream)
         h = ctypes.c_void_p()
-        _check(lib().sketch_create(ctypes.byref(cfg), _stream_handle(stream), ctypes.byref(h)))
+        _check(lib().sketch_create(ctypes.byref(cfg), _stream_handle(self._stream), ctypes.byref(h)))
         self._h = h
 
     def _on_stream(self, t):
@@ -188,12 +213,7 @@ class FDSketch:
         on the sketch's own stream: that stream waits for the current one, and
         the tensor's memory is kept from reuse until the sketch's stream is
         past it."""
-        if self._stream is None or not getattr(t, "is_cuda", False):
-            return
-        cur = _torch().cuda.current_stream()
-        if self._stream != cur:
-            self._stream.wait_stream(cur)
-            t.record_stream(self._stream)
+        _order_after_current(self._stream, t)
 
     def append(self, rows):
         ptr, n, stride, dt, mem, keep = _rows_arg(rows)
@@ -280,7 +300,8 @@ def gram(C, precision="fp64", stream=None):
 
 def eigh(G, method="auto", stream=None):
     """(lam, V) with G = V diag(lam) V^T, unsorted, from the device solver
-    ("auto": tridiagonal divide and conquer for m <= 200, else Jacobi;
+    ("auto": Householder tridiagonalization, divide and conquer and
+    back-transformation at every m the library takes;
     "jacobi": the Jacobi solvers at every size)."""
     torch = _torch()
     if G.dtype != torch.float64 or not G.is_cuda or G.stride(1) != 1:
@@ -316,10 +337,10 @@ class FDSketchBatch:
                                 VARIANTS[c.get("variant", "fd")], float(c.get("alpha", 0.2)),
                                 PRECISIONS[c.get("precision", "fp64")], 0)
             self.shapes.append((int(c["l"]), int(c["d"])))
+        self._stream = _bound_stream(stream)
         h = ctypes.c_void_p()
-        _check_batch(lib().sketch_batch_create(self.S, arr, _stream_handle(stream), ctypes.byref(h)))
+        _check_batch(lib().sketch_batch_create(self.S, arr, _stream_handle(self._stream), ctypes.byref(h)))
         self._h = h
-        self._stream = stream
 
     def append(self, rows_list, grid_size=0):
         """rows_list[i]: 2-D cuda tensor for sketch i (or None for no rows)."""
@@ -342,13 +363,8 @@ class FDSketchBatch:
             elif dt != code:
                 raise ValueError("all sketches of one append call share a dtype")
             ptrs[i], ns[i], strides[i] = t.data_ptr(), t.shape[0], t.stride(0)
-        if self._stream is not None and keep:
-            # Inputs made on the current stream, read on the batch's stream.
-            cur = torch.cuda.current_stream()
-            if self._stream != cur:
-                self._stream.wait_stream(cur)
-                for t in keep:
-                    t.record_stream(self._stream)
+        # Inputs made on the current stream, read on the batch's stream.
+        _order_after_current(self._stream, *keep)
         _check_batch(lib().sketch_batch_append(self._h, ptrs, ns, strides, F64 if dt is None else dt,
                                                MEM_DEVICE, int(grid_size)), self._h)
         return self

@@ -22,7 +22,8 @@ Recipes
   come first.
 * ``basis_rows`` -- rows that are scaled coordinate vectors (frequent-items
   special case used to test the sketch against a counter simulation).
-* ``batch_shapes`` -- per-sketch (d, l, n) draws for the many-sketch workload.
+* ``batch_shapes`` -- per-sketch (d, l, n) draws for the many-sketch workload;
+  ``batch_sketch_rows`` -- the rows of one of its sketches.
 * ``random_noisy_device`` -- the Random Noisy recipe drawn on a torch device
   (S and N from a seeded ``torch.Generator`` there, U from NumPy as above),
   for workloads too large to draw on the host quickly.
@@ -38,7 +39,8 @@ __all__ = [
     "rng_for", "random_noisy", "random_noisy_chunk", "random_noisy_basis",
     "power_law", "power_law_basis", "power_law_chunk",
     "rotating_adversarial", "two_subspace_adversarial", "basis_rows",
-    "batch_shapes", "random_noisy_device", "to_bf16", "bf16_bits", "WORKLOADS",
+    "batch_shapes", "batch_sketch_rows", "chunk_sizes", "parallel_map", "random_noisy_device",
+    "to_bf16", "bf16_bits", "WORKLOADS",
 ]
 
 
@@ -168,6 +170,27 @@ def batch_shapes(S: int = 512, seed=(4, 0), d_range=(64, 2048), l_range=(16, 128
     return d.astype(np.int64), l.astype(np.int64), n.astype(np.int64)
 
 
+def batch_sketch_rows(i: int, n: int, d: int, l: int, seed=(4, 0), zeta: float = 10.0,
+                      dtype=np.float32) -> np.ndarray:
+    """Rows of sketch i of the many-sketch workload: Random Noisy with signal
+    rank k = max(1, l // 2), drawn from SeedSequence(seed + (i,))."""
+    return random_noisy(n, d, max(1, l // 2), zeta, seed=tuple(seed) + (i,), dtype=dtype)
+
+
+def chunk_sizes(n: int, chunk: int):
+    """Row counts of the chunks of an n-row stream (the last one ragged)."""
+    return [min(chunk, n - r0) for r0 in range(0, n, chunk)]
+
+
+def parallel_map(fn, items, workers: int = 16):
+    """[fn(x) for x in items] on a thread pool, in order.  NumPy's generators
+    and BLAS release the GIL, so independent chunks draw in parallel; every
+    chunk has its own seed, so the values do not depend on the pool."""
+    import concurrent.futures as cf
+    with cf.ThreadPoolExecutor(max_workers=max(1, workers)) as ex:
+        return list(ex.map(fn, items))
+
+
 def random_noisy_device(n: int, d: int, k: int, zeta: float, seed, device="cuda", dtype=None):
     """Random Noisy rows (n x d) drawn on a torch device: the same recipe as
     ``random_noisy`` (D_ii = 1 - (i-1)/k, U orthonormal rows), with S and N
@@ -211,10 +234,12 @@ WORKLOADS = {
                                        dtype="f32", l=(50, 100, 200),
                                        variants=("fd", "alpha", "fast_alpha", "isvd"),
                                        alpha=0.2),
-    "c2_rotating_adversarial_100k_x1000": dict(n=100_000, d=1000, theta=0.05, zeta=10.0,
-                                               seed=(2, 1), dtype="f32", l=(50, 100, 200)),
+    "c2_rotating_adversarial_100k_x1000": dict(n=100_000, d=1000, blocks=200, block_rows=500,
+                                               theta=0.05, zeta=10.0, seed=(2, 1), dtype="f32",
+                                               l=(50, 100, 200)),
     "c3_power_law_200k_x3072": dict(n=200_000, d=3072, r=300, exponent=0.8,
-                                    noise_var=1e-2, seed=(3, 0), dtype="bf16", l=256),
+                                    noise_var=1e-2, seed=(3, 0), chunk=50_000, dtype="bf16",
+                                    l=256),
     "c4_batch_512": dict(S=512, seed=(4, 0), zeta=10.0, dtype="f32"),
     "c5_random_noisy_1m_x8192": dict(n=1_000_000, d=8192, k=512, zeta=20.0, seed=(5, 0),
                                      chunk=4096, dtype="f32", l=512, alpha=0.2),

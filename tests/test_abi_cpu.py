@@ -41,6 +41,7 @@ def test_library_exports_every_declared_symbol():
     (dict(d=10, l=8, variant=3, alpha=1.5), -1),
     (dict(d=10, l=8, flags=6), -1),
     (dict(d=10, l=8, precision=4), -1),
+    (dict(d=10, l=8, precision=1), -6),      # one BF16 pass: fdsk_gram only
     (dict(d=70000, l=8), -1),
 ])
 def test_create_rejects_bad_config(cfg, code):
@@ -59,6 +60,7 @@ def test_create_rejects_bad_config(cfg, code):
     (dict(variant=5), -6),                     # CFD: single sketches only
     (dict(variant=6), -1),
     (dict(precision=3), -6),                   # FP8 Gram: single sketches only
+    (dict(precision=1), -6),                   # one BF16 pass: fdsk_gram only
     (dict(l=200), -6),                         # 400 buffer rows > 256
     (dict(flags=1), -6),
 ])

@@ -170,6 +170,17 @@ def test_nonfinite_rows_are_reported():
     assert e.value.code == -5
 
 
+def test_single_pass_bf16_is_not_a_sketching_precision():
+    """One uncompensated BF16 pass misses the 1e-3 bar, so the library offers
+    it in fdsk_gram only and refuses it as a sketch's precision."""
+    with pytest.raises(F.FdskError) as e:
+        F.FDSketch(64, 8, precision="bf16")
+    assert e.value.code == -6
+    with pytest.raises(F.FdskError) as e:
+        F.FDSketchBatch([dict(d=64, l=8, precision="bf16")])
+    assert e.value.code == -6
+
+
 def test_append_after_finalize_is_rejected():
     sk = F.FDSketch(10, 4)
     sk.append(torch.ones(3, 10, dtype=torch.float64, device="cuda"))
@@ -179,15 +190,14 @@ def test_append_after_finalize_is_rejected():
     assert e.value.code == -2
 
 
-@pytest.mark.parametrize("precision,tol", [("bf16x3", 1e-4), ("bf16", 5e-3), ("fp8x3", 1e-3)])
+@pytest.mark.parametrize("precision,tol", [("bf16x3", 1e-4), ("fp8x3", 1e-3)])
 @pytest.mark.parametrize("variant", ["fd", "alpha"])
 def test_reduced_precision_power_law(precision, tol, variant):
     """Power-law workload (sigma_i = i^-0.8 over 300 directions plus N(0,1e-2)
-    noise) stored as bf16, sketched with BF16 / split-BF16 Gram and rebuild;
-    the covariance error is within `tol` (absolute, it is already divided by
-    ||A||_F^2) of the FP64 oracle on the same bf16 rows.  The compensated form
-    meets the 1e-3 bar with a wide margin; a single BF16 pass does not always
-    (measured 1.7e-3 for FD here), which is what the compensation is for."""
+    noise) stored as bf16, sketched with split-BF16 or FP8 (x3) products; the
+    covariance error is within `tol` (absolute, it is already divided by
+    ||A||_F^2) of the FP64 oracle on the same bf16 rows.  The bar for the
+    reduced-precision sketches is 1e-3; split-BF16 is held to 1e-4."""
     A = synth.power_law(6000, 768, r=300, seed=(3, 7), chunk=6000)
     Ab = synth.to_bf16(A).astype(np.float64)
     sk = F.FDSketch(768, 64, variant, 0.2, precision=precision)
