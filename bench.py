@@ -1,20 +1,26 @@
 #!/usr/bin/env python
 """Rows/s sketched by the Frequent Directions hot path on one MI355X.
 
-Workload: the "Random Noisy" construction of the paper's Section 4 at
-100,000 x 1,000 (signal rank k = 50, zeta = 10, seed (2, 0)), rows stored as
-fp32 and already resident in HBM.  One step = one whole pass of the hot path
-over every row: ingest, every scheduled ReduceRank (Gram, eigensolve, shrink,
-rebuild) and finalize, for the chosen variant and sketch size (default: FD,
-l = 100, buffer 2l = 200 rows).  Arithmetic is FP64.
+Headline workload: 512 independent sketches of mixed shapes (d ~ U{64..2048},
+l ~ U{16..128}, n ~ U{1000..50000}; each stream the Random Noisy construction
+of the paper's Section 4 with signal rank k = l/2 and zeta = 10, fp32 rows
+resident in HBM; 13.2 million rows in all), Frequent Directions (Algorithm 1,
+buffer 2l).  One step = the whole hot path over every row of every sketch:
+ingest, every scheduled ReduceRank (Gram, eigensolve, shrink, rebuild) and
+finalize, through the batch (each size class of buffer rows on a stream of
+its own, one launch per stage and round) with split-BF16 (x3) Gram and
+rebuild products and the FP64 eigensolve, shrink and accumulators.  The same
+step replayed from HIP graphs captured per size class is timed beside it.  Beside it, on the same rows: the same batch in FP64, and plain
+FP64 FD run one sketch after another (the single-sketch path).  After the
+timed steps every sketch's covariance error (device evaluator) is checked
+against the oracle's stored result for that sketch.
 
-Prints one JSON line with the metric, the dominant kernel's roofline (stage
-times come from HIP events the library records on its stream during the
-timed steps), the covariance error of the GPU sketch (device evaluator) and the
-CPU oracle timed on the same stream, with the oracle's own covariance error.
+Extra legs: FD l = 100 on the Random Noisy 100,000 x 1,000 stream (single
+sketch, per-stage times), and the d = 3,072 shape of the power-law workload
+with each product precision (matrix-core rates).
 
-`--copy-calibration` instead runs a plain device copy of a known size (the
-reference kernel for scaling the FETCH_SIZE / WRITE_SIZE hardware counters).
+Prints one JSON line.  `--copy-calibration BYTES` instead runs a plain device
+copy of a known size (the reference for scaling FETCH_SIZE / WRITE_SIZE).
 """
 import argparse
 import hashlib
@@ -32,172 +38,47 @@ PEAK_FP8 = 5.0e15        # dense FP8 MFMA, FLOP/s
 PEAK_HBM = 8.0e12        # bytes/s
 METRIC = "rows/sec sketched at fixed cov-err/||A||_F^2; batched+bf16 vs plain FD, 1 GPU"
 CSRC = os.path.join(ROOT, "paper_1501_06561_amd", "csrc")
-# Sources that define each stage's kernels; a traffic figure measured with the
-# hardware counters is only quoted while these are unchanged.
-STAGE_SOURCES = {
-    "eig": ["kernels_eig.hip", "fdsk_jacobi.hpp", "fdsk_device.hpp", "fdsk_kernels.hpp"],
-    "gram": ["kernels_stream.hip", "fdsk_device.hpp", "fdsk_kernels.hpp"],
-    "rebuild": ["kernels_stream.hip", "fdsk_device.hpp", "fdsk_kernels.hpp"],
-    "shrink": ["kernels_stream.hip", "fdsk_device.hpp", "fdsk_kernels.hpp"],
-    "ingest": ["kernels_stream.hip", "fdsk_device.hpp", "fdsk_kernels.hpp"],
-    "tridiag": ["kernels_trid.hip", "fdsk_device.hpp", "fdsk_kernels.hpp"],
-    "dc": ["kernels_trid.hip", "fdsk_device.hpp", "fdsk_kernels.hpp"],
-    "backtr": ["kernels_trid.hip", "fdsk_device.hpp", "fdsk_kernels.hpp"],
+GOLDEN = os.path.join(ROOT, "tests", "golden")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_batch_512.json")
+
+# Kernels behind each profiled stage and the sources that define them (a
+# counter-measured traffic figure is quoted only while these are unchanged).
+STAGE_KERNELS = {
+    "ingest": ("kg_ingest", ["kernels_stream.hip"]),
+    "gram": ("kg_split_bf16+kg_gram_bf16<3>+kg_mirror (fp64: kg_gram)", ["kernels_lowp.hip", "kernels_stream.hip"]),
+    "tridiag_head": ("kg_tridiag", ["kernels_trid.hip"]),
+    "tridiag": ("kg_tridiag_reg", ["kernels_trid.hip"]),
+    "dc": ("kg_dc", ["kernels_trid.hip"]),
+    "backtr": ("kg_backtr", ["kernels_trid.hip"]),
+    "shrink": ("kg_shrink", ["kernels_stream.hip"]),
+    "rebuild": ("kg_rebuild_bf16<3> (fp64: kg_rebuild)", ["kernels_lowp.hip", "kernels_stream.hip"]),
 }
-KERNELS = {"eig": "k_eig_lds/k_eig_blk (Jacobi)", "gram": "k_gram_f64+k_gram_reduce",
-           "rebuild": "k_rebuild_f64", "shrink": "k_shrink", "ingest": "k_ingest",
-           "tridiag": "k_tridiag_reg (m <= 208) / k_tridiag", "dc": "k_dc", "backtr": "k_backtr"}
-
-
-def kernel_name(stage, m):
-    """The kernel a stage runs at buffer size m."""
-    if stage == "tridiag":
-        return "k_tridiag_reg" if m <= 208 else "k_tridiag"
-    return KERNELS[stage]
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_random_noisy_100k_x1000.json")
+COMMON_SOURCES = ["fdsk_device.hpp", "fdsk_kernels.hpp", "fdsk_batch.hpp"]
 
 
 def sources_digest(stage):
     h = hashlib.sha256()
-    for name in STAGE_SOURCES[stage]:
+    for name in STAGE_KERNELS[stage][1] + COMMON_SOURCES:
         with open(os.path.join(CSRC, name), "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]
 
 
-def measured_traffic(stage, l, variant):
+def measured_traffic(stage):
     """HBM bytes per launch of the stage's kernel from the committed counter
-    summary, or None if there is none for this configuration or the kernel
-    sources changed since it was taken."""
+    summary, or None when there is none or the kernel's sources changed."""
     try:
         with open(TRAFFIC_FILE) as f:
             rec = json.load(f)
     except (OSError, ValueError):
         return None
-    for e in rec.get("entries", []):
-        if e.get("stage") == stage and e.get("l") == l and e.get("variant") == variant:
-            if e.get("sources_sha256_16") != sources_digest(stage):
-                return None
-            return e.get("bytes_per_launch")
-    return None
-
-
-def batched_leg(S, n_max, seq_sketches, seed=(4, 0)):
-    """The many-sketch workload (d ~ U{64..2048}, l ~ U{16..128}, n ~
-    U{1000..n_max}, Random Noisy rows with k = l/2, zeta = 10, fp32 on the
-    device): all sketches through the lock-step batch with FP64 and with
-    split-BF16 (x3) Gram/rebuild products, and the first `seq_sketches` of them
-    one after another through the single-sketch FP64 path.  Rows/s of each
-    (the sequential rate is measured on that prefix of the sketches)."""
-    import torch
-    from paper_1501_06561_amd import fdsketch, synth
-    d, l, n = synth.batch_shapes(S, seed=seed, n_range=(1000, n_max))
-    mats = [synth.random_noisy_device(int(n[i]), int(d[i]), max(1, int(l[i]) // 2), 10.0,
-                                      (seed[0], seed[1], i)) for i in range(S)]
-    rows = int(n.sum())
-    # Warm both paths (first launches load the kernels).
-    w = fdsketch.FDSketchBatch([dict(d=int(d[i]), l=int(l[i])) for i in range(2)])
-    w.append([m[:300] for m in mats[:2]])
-    w.finalize()
-    w.close()
-    torch.cuda.synchronize()
-    out = {"workload": f"{S} sketches, d~U{{64..2048}}, l~U{{16..128}}, n~U{{1000..{n_max}}}, "
-                       "random noisy k=l/2 zeta=10, fp32 rows on device",
-           "rows": rows, "unit": "rows/s"}
-    for prec in ("fp64", "bf16x3"):
-        b = fdsketch.FDSketchBatch([dict(d=int(d[i]), l=int(l[i]), precision=prec) for i in range(S)])
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        b.append(mats)
-        b.finalize()
-        torch.cuda.synchronize()
-        dt = time.perf_counter() - t0
-        if prec == "fp64":
-            out["reduce_steps"] = sum(b.stats(i)["n_reduce"] for i in range(S))
-            out["value"] = rows / dt
-            out["ms"] = dt * 1e3
-        else:
-            out["value_bf16x3"] = rows / dt
-            out["ms_bf16x3"] = dt * 1e3
-        b.close()
-    k = min(seq_sketches, S)
-    sks = [fdsketch.FDSketch(int(d[i]), int(l[i])) for i in range(k)]
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for sk, m in zip(sks, mats[:k]):
-        sk.append(m)
-        sk.finalize()
-    torch.cuda.synchronize()
-    t_seq = time.perf_counter() - t0
-    for sk in sks:
-        sk.close()
-    out["sequential_value"] = int(n[:k].sum()) / t_seq
-    out["sequential_sample"] = f"first {k} sketches ({int(n[:k].sum())} rows), single-sketch FP64 path"
-    out["speedup_vs_sequential"] = out["value"] / out["sequential_value"]
-    out["speedup_bf16x3_vs_sequential"] = out["value_bf16x3"] / out["sequential_value"]
-    out["dtype"] = "f64 (bf16x3: split-bf16 Gram/rebuild, f64 eigensolve)"
-    return out
-
-
-def precision_leg(rows, l=256, d=3072, seed=(3, 0)):
-    """The power-law workload's shape (d = 3,072, bf16 rows, l = 256, buffer
-    512 rows): a prefix of `rows` rows sketched with FP64, BF16, split-BF16
-    (x3) and FP8 (x3, Gram only) products.  Per precision: rows/s, the Gram
-    and rebuild launches' matrix-core utilisation (their multiply-adds, all
-    passes, over the launch time, against the dtype's dense peak) and the
-    covariance error's distance from the FP64 sketch's."""
-    import numpy as np
-    import torch
-    from paper_1501_06561_amd import fdsketch, synth
-    A = synth.power_law(rows, d, r=300, seed=seed, chunk=rows)
-    bits = torch.from_numpy(synth.bf16_bits(A).view(np.int16)).view(torch.bfloat16).cuda()
-    m = 2 * l
-    keep = l - 1
-    npass = {"fp64": 1, "bf16": 1, "bf16x3": 3, "fp8x3": 3}
-    peak_gram = {"fp64": PEAK_FP64, "bf16": PEAK_BF16, "bf16x3": PEAK_BF16, "fp8x3": PEAK_FP8}
-    peak_rebuild = {"fp64": PEAK_FP64, "bf16": PEAK_BF16, "bf16x3": PEAK_BF16, "fp8x3": PEAK_BF16}
-    out = {"workload": f"power-law sigma_i = i^-0.8 over 300 directions + N(0,1e-2), {rows} x {d} "
-                       f"bf16 rows, FD l = {l} (buffer {m} rows), "
-                       + ("tridiagonal divide-and-conquer" if m <= 512 else "block Jacobi") + " eigensolver",
-           "rows": rows}
-    cov64 = None
-    for prec in ("fp64", "bf16", "bf16x3", "fp8x3"):
-        sk = fdsketch.FDSketch(d, l, "fd", precision=prec, profile=True)
-        sk.append(bits[:m + 1])                      # warm the kernels
-        sk.finalize()
-        sk.reset()
-        sk.profile()
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        sk.append(bits)
-        sk.finalize()
-        torch.cuda.synchronize()
-        dt = time.perf_counter() - t0
-        prof = sk.profile()
-        ev = sk.error(bits, k=10, method=0)
-        sk.close()
-        g_ms, g_n = prof["gram"]
-        r_ms, r_n = prof["rebuild"]
-        g_flop = npass[prec] * float(m * (m + 1) * d)
-        r_flop = npass[prec] * 2.0 * keep * m * d
-        g_tf = g_flop / (g_ms / max(g_n, 1) / 1e3) / 1e12 if g_n else None
-        r_tf = r_flop / (r_ms / max(r_n, 1) / 1e3) / 1e12 if r_n else None
-        if prec == "fp64":
-            cov64 = ev["cov_err"]
-        out[prec] = {
-            "rows_per_s": rows / dt,
-            "gram_us": g_ms / max(g_n, 1) * 1e3, "gram_TFLOPs": g_tf,
-            "gram_frac_of_peak": g_tf * 1e12 / peak_gram[prec] if g_tf else None,
-            "rebuild_us": r_ms / max(r_n, 1) * 1e3, "rebuild_TFLOPs": r_tf,
-            "rebuild_frac_of_peak": r_tf * 1e12 / peak_rebuild[prec] if r_tf else None,
-            "eig_ms_per_reduce": prof["eig"][0] / max(prof["eig"][1], 1),
-            "cov_err": ev["cov_err"], "abs_diff_vs_fp64": abs(ev["cov_err"] - cov64),
-        }
-    return out
+    e = rec.get("stages", {}).get(stage)
+    if not e or e.get("sources_sha256_16") != sources_digest(stage):
+        return None
+    return e.get("bytes_per_launch")
 
 
 def host_cpu():
-    """The host CPU's model name and logical core count."""
     name = None
     try:
         with open("/proc/cpuinfo") as f:
@@ -225,23 +106,209 @@ def copy_calibration(nbytes, reps):
                       "ms_per_copy": dt * 1e3, "GBps_read_plus_write": 2 * nbytes / dt / 1e9}))
 
 
-def stage_work(stage, m, keep, d, new_rows):
-    """Algorithmic work of one launch of a stage: (amount, unit kind, bound)."""
-    if stage == "eig":
-        return 9.0 * m ** 3, "flop", "alu"          # dense symmetric eigendecomposition
-    if stage == "tridiag":
-        return 4.0 / 3.0 * m ** 3, "flop", "alu"    # Householder reduction to tridiagonal
-    if stage == "dc":
-        return 8.0 / 3.0 * m ** 3, "flop", "alu"    # divide-and-conquer products, no deflation
-    if stage == "backtr":
-        return 2.0 * m ** 3, "flop", "alu"          # m-2 reflectors applied to m vectors
-    if stage == "gram":
-        return float(m * (m + 1) * d), "flop", "mfma"   # symmetric m x m x d
-    if stage == "rebuild":
-        return 2.0 * keep * m * d, "flop", "mfma"
-    if stage == "ingest":
-        return float(new_rows * d * (4 + 8)), "byte", "hbm"   # fp32 in, fp64 buffer out
-    return 0.0, "flop", "alu"
+def stage_table(prof, peak_of):
+    """Every profiled stage against its own roof: {stage: {...}}."""
+    out = {}
+    for name, (ms, launches, work) in prof.items():
+        if launches == 0:
+            continue
+        secs = ms / 1e3
+        if name == "ingest":
+            ach, unit, peak, bound = work / secs / 1e9, "GB/s", PEAK_HBM / 1e9, "hbm"
+        else:
+            pk, bound = peak_of(name)
+            ach, unit, peak = work / secs / 1e12, "TFLOP/s", pk / 1e12
+        out[name] = {"ms": ms, "launches": launches, "avg_launch_us": ms / launches * 1e3,
+                     "work_per_launch": work / launches, "achieved": ach, "unit": unit, "peak": peak,
+                     "frac": ach / peak if peak else None, "bound": bound}
+    return out
+
+
+def make_batch_rows(S, seed):
+    """The 512-sketch workload's rows, drawn by the seeded generator on the
+    host (16 threads) and moved to the device as fp32."""
+    import numpy as np
+    import torch
+    from paper_1501_06561_amd import synth
+    d, l, n = synth.batch_shapes(S, seed=seed)
+
+    def one(i):
+        return torch.from_numpy(synth.batch_sketch_rows(i, int(n[i]), int(d[i]), int(l[i]), seed=seed)).cuda()
+    rows = synth.parallel_map(one, range(S), workers=16)
+    torch.cuda.synchronize()
+    return np.asarray(d), np.asarray(l), np.asarray(n), rows
+
+
+def batch_parity(rows, outs, l, precision, golden):
+    """Per-sketch covariance error of the GPU sketches (device evaluator)
+    against the oracle's stored value for the same sketch."""
+    from paper_1501_06561_amd import fdsketch as F
+    worst_abs, worst_rel, bad = 0.0, 0.0, []
+    for i, (A, B) in enumerate(zip(rows, outs)):
+        ce = F.evaluate(A, B, k=10, method=0)["cov_err"]
+        co = golden[i]["cov_err"]
+        diff = abs(ce - co)
+        worst_abs = max(worst_abs, diff)
+        worst_rel = max(worst_rel, diff / co if co > 0 else 0.0)
+        ok = diff <= (1e-6 * co + 1e-12 if precision == "fp64" else 1e-3)
+        if not ok:
+            bad.append(i)
+    bar = "|cov_gpu - cov_oracle| <= 1e-6 cov_oracle + 1e-12" if precision == "fp64" else \
+        "|cov_gpu - cov_oracle| <= 1e-3"
+    return {"sketches": len(outs), "failed": bad, "max_abs_diff": worst_abs, "max_rel_diff": worst_rel,
+            "bar": bar, "ok": not bad}
+
+
+def run_batch(cfgs, rows, steps, warmup, profile=False, graph=False):
+    """Steps of reset + append + finalize on one batch: (ms per step, per-step
+    ms, outputs of the last step, batch)."""
+    import torch
+    from paper_1501_06561_amd import fdsketch as F
+    b = F.FDSketchBatch(cfgs, profile=profile, graph=graph)
+    outs = None
+    for _ in range(warmup):
+        b.reset()
+        b.append(rows)
+        outs = b.finalize()
+    torch.cuda.synchronize()
+    per = []
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        ts = time.perf_counter()
+        b.reset()
+        b.append(rows)
+        outs = b.finalize()            # synchronises the batch's stream
+        per.append((time.perf_counter() - ts) * 1e3)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / max(steps, 1)
+    return ms, per, outs, b
+
+
+def sequential_leg(d, l, rows, k):
+    """Plain FP64 FD, the first k sketches one after another through the
+    single-sketch path (sketches created beforehand, as the batch is)."""
+    import torch
+    from paper_1501_06561_amd import fdsketch as F
+    sks = [F.FDSketch(int(d[i]), int(l[i])) for i in range(k)]
+    # Warm every kernel shape once (first launches load code objects).
+    for sk, A in zip(sks[:8], rows[:8]):
+        sk.append(A[: 2 * sk.l + 1])
+        sk.finalize()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    outs = []
+    for sk, A in zip(sks, rows[:k]):
+        sk.reset()
+        sk.append(A)
+        outs.append(sk.finalize())
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    for sk in sks:
+        sk.close()
+    return dt, outs
+
+
+def single_stream_leg(l=100):
+    """FD on the Random Noisy 100,000 x 1,000 fp32 stream (k = 50, zeta = 10,
+    seed (2, 0)) through the single-sketch path: rows/s and per-stage times."""
+    import numpy as np
+    import torch
+    from paper_1501_06561_amd import fdsketch as F, synth
+    W = synth.WORKLOADS["c2_random_noisy_100k_x1000"]
+    A = synth.random_noisy(W["n"], W["d"], W["k"], W["zeta"], seed=W["seed"], dtype=np.float32)
+    At = torch.from_numpy(A).cuda()
+    sk = F.FDSketch(W["d"], l, "fd", profile=True)
+    sk.append(At)
+    sk.finalize()
+    sk.reset()
+    sk.profile()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sk.append(At)
+    B = sk.finalize()
+    dt = time.perf_counter() - t0
+    prof = sk.profile()
+    st = sk.stats()
+    ev = sk.error(At, k=10, method=0)
+    sk.close()
+    table = stage_table(prof, lambda s_: (PEAK_FP64, "fp64 mfma" if s_ in ("gram", "rebuild") else "fp64 alu"))
+    return {"workload": "random_noisy_100k_x1000_fp32, FD l = 100 (buffer 200 rows), FP64",
+            "rows_per_s": W["n"] / dt, "ms": dt * 1e3, "reduce_steps": st["n_reduce"],
+            "cov_err": ev["cov_err"], "stages": table,
+            "eig_ms_per_reduce": prof["eig"][0] / max(prof["eig"][1], 1)}, A, B
+
+
+def precision_leg(rows, l=256, d=3072, seed=(3, 0)):
+    """The power-law workload's shape (d = 3,072, bf16 rows, l = 256, buffer
+    512 rows): a prefix of `rows` rows sketched with FP64, split-BF16 (x3) and
+    FP8 (x3, Gram only) products.  Per precision: rows/s, the Gram and
+    rebuild launches' rate (their multiply-adds, all passes, over the launch
+    time, against the dtype's dense peak) and the covariance error's distance
+    from the FP64 sketch's."""
+    import numpy as np
+    import torch
+    from paper_1501_06561_amd import fdsketch as F, synth
+    A = synth.power_law(rows, d, r=300, seed=seed, chunk=rows)
+    bits = torch.from_numpy(synth.bf16_bits(A).view(np.int16)).view(torch.bfloat16).cuda()
+    m = 2 * l
+    peak_gram = {"fp64": PEAK_FP64, "bf16x3": PEAK_BF16, "fp8x3": PEAK_FP8}
+    peak_rebuild = {"fp64": PEAK_FP64, "bf16x3": PEAK_BF16, "fp8x3": PEAK_BF16}
+    out = {"workload": f"power-law sigma_i = i^-0.8 over 300 directions + N(0,1e-2), {rows} x {d} "
+                       f"bf16 rows, FD l = {l} (buffer {m} rows)", "rows": rows}
+    cov64 = None
+    for prec in ("fp64", "bf16x3", "fp8x3"):
+        sk = F.FDSketch(d, l, "fd", precision=prec, profile=True)
+        sk.append(bits[:m + 1])
+        sk.finalize()
+        sk.reset()
+        sk.profile()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sk.append(bits)
+        sk.finalize()
+        dt = time.perf_counter() - t0
+        prof = sk.profile()
+        ev = sk.error(bits, k=10, method=0)
+        sk.close()
+        if prec == "fp64":
+            cov64 = ev["cov_err"]
+        g_ms, g_n, g_w = prof["gram"]
+        r_ms, r_n, r_w = prof["rebuild"]
+        out[prec] = {
+            "rows_per_s": rows / dt,
+            "gram_us": g_ms / max(g_n, 1) * 1e3, "gram_TFLOPs": g_w / (g_ms / 1e3) / 1e12,
+            "gram_frac_of_peak": g_w / (g_ms / 1e3) / peak_gram[prec],
+            "rebuild_us": r_ms / max(r_n, 1) * 1e3, "rebuild_TFLOPs": r_w / (r_ms / 1e3) / 1e12,
+            "rebuild_frac_of_peak": r_w / (r_ms / 1e3) / peak_rebuild[prec],
+            "eig_ms_per_reduce": prof["eig"][0] / max(prof["eig"][1], 1),
+            "cov_err": ev["cov_err"], "abs_diff_vs_fp64": abs(ev["cov_err"] - cov64),
+        }
+    return out
+
+
+def cpu_baseline_leg(d, l, n, seed, seconds):
+    """The oracle (NumPy FP64, LAPACK SVD of the buffer) on the first
+    sketches of the same workload until about `seconds` of CPU work."""
+    import numpy as np
+    import oracle
+    from paper_1501_06561_amd import synth
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max((p.get("num_threads", 1) for p in threadpool_info()), default=1)
+    except Exception:
+        cores = os.cpu_count()
+    done_rows, spent, k = 0, 0.0, 0
+    while spent < seconds and k < len(n):
+        A = synth.batch_sketch_rows(k, int(n[k]), int(d[k]), int(l[k]), seed=seed).astype(np.float64)
+        t = time.perf_counter()
+        oracle.fd_sketch(A, int(l[k]))
+        spent += time.perf_counter() - t
+        done_rows += int(n[k])
+        k += 1
+    return {"value": done_rows / spent, "unit": "rows/s", "cores": cores, "kind": "oracle",
+            "sample": f"the first {k} of the 512 sketches ({done_rows} rows), FD at each sketch's l, "
+                      f"NumPy FP64 with LAPACK's SVD of the buffer, {spent:.1f} s",
+            "host": host_cpu()}
 
 
 def main():
@@ -249,26 +316,19 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--variant", default="fd", choices=["fd", "isvd", "alpha", "fast_alpha"])
-    ap.add_argument("--l", type=int, default=100)
-    ap.add_argument("--alpha", type=float, default=0.2)
-    ap.add_argument("--cpu-rows", type=int, default=100_000,
-                    help="prefix of the stream the CPU oracle sketches for the baseline")
+    ap.add_argument("--seq", type=int, default=512,
+                    help="sketches of the plain FP64 one-after-another leg (0 skips it)")
+    ap.add_argument("--no-parity", action="store_true", help="skip the per-sketch oracle check")
+    ap.add_argument("--graph", action="store_true",
+                    help="headline through per-class HIP graphs instead of direct launches")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the single-stream and precision legs")
+    ap.add_argument("--prec-rows", type=int, default=8_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--eig", default="auto", choices=["auto", "jacobi"],
-                    help="eigensolver: tridiagonal divide and conquer (m <= 512) or Jacobi")
-    ap.add_argument("--rows", type=int, default=100_000,
-                    help="rows of the stream to sketch (profiling runs use a prefix)")
-    ap.add_argument("--batch-sketches", type=int, default=512,
-                    help="sketches in the many-sketch leg (0 skips it)")
-    ap.add_argument("--batch-nmax", type=int, default=50_000,
-                    help="largest rows per sketch in the many-sketch leg")
-    ap.add_argument("--batch-seq", type=int, default=64,
-                    help="sketches of the many-sketch leg also run one after another")
-    ap.add_argument("--prec-rows", type=int, default=8_000,
-                    help="rows of the d = 3,072 precision leg (0 skips it)")
-    ap.add_argument("--cpu-1thread-rows", type=int, default=20_000,
-                    help="prefix the oracle also sketches with one BLAS thread (0 skips it)")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--profile-only", action="store_true",
+                    help="one warm-up and one step of the split-BF16 batch, nothing else "
+                         "(for hardware-counter runs)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run a plain device copy of BYTES (counter reference) and exit")
     args = ap.parse_args()
@@ -276,142 +336,109 @@ def main():
         copy_calibration(args.copy_calibration, max(args.steps, 1))
         return
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the sketch of one "
-              "stream is a sequential chain of ReduceRank steps and this build has no "
-              "multi-GPU path.", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}): the batch is sharded "
+              "across GPUs only by design (independent sketches), not in this build.",
+              file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
     import torch
 
-    from paper_1501_06561_amd import fdsketch, synth
+    from paper_1501_06561_amd import synth
 
-    N, d, k, zeta, seed = 100_000, 1000, 50, 10.0, (2, 0)
-    A = synth.random_noisy(N, d, k, zeta, seed=seed, dtype=np.float32)
-    n = max(1, min(args.rows, N))
-    A = A[:n]
-    At = torch.from_numpy(A).cuda()
-    l = args.l
-    sk = fdsketch.FDSketch(d, l, args.variant, args.alpha, profile=True, eig=args.eig)
-    m = 2 * l
+    W = synth.WORKLOADS["c4_batch_512"]
+    S, seed = W["S"], tuple(W["seed"])
+    t_gen = time.perf_counter()
+    d, l, n, rows = make_batch_rows(S, seed)
+    t_gen = time.perf_counter() - t_gen
+    total_rows = int(n.sum())
+    cfg = lambda prec: [dict(d=int(d[i]), l=int(l[i]), precision=prec) for i in range(S)]
+    graph = args.graph
+    print(f"[bench] rows drawn and resident: {total_rows} rows in {t_gen:.1f} s", file=sys.stderr, flush=True)
 
-    def step():
-        sk.reset()
-        sk.append(At)
-        return sk.finalize()
+    if args.profile_only:
+        ms, per, outs, b = run_batch(cfg("bf16x3"), rows, 1, 1, graph=graph)
+        b.close()
+        print(json.dumps({"profile_only": True, "ms": ms, "rows": total_rows}))
+        return
 
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    sk.profile()                      # drop warmup marks
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    per_step = []
-    for _ in range(args.steps):
-        ts = time.perf_counter()
-        B = step()                    # finalize synchronises the stream
-        per_step.append((time.perf_counter() - ts) * 1e3)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    prof = sk.profile()
-    st = sk.stats()
-    ms_per_step = (t1 - t0) * 1e3 / args.steps
-    value = n / (ms_per_step / 1e3)
+    # Headline: the split-BF16 batch.
+    ms, per, outs_bf, b = run_batch(cfg("bf16x3"), rows, args.steps, args.warmup, graph=graph)
+    st_bf = [b.stats(i) for i in range(S)]
+    b.close()
+    value = total_rows / (ms / 1e3)
+    print(f"[bench] batch bf16x3: {ms:.1f} ms/step, {value:.4g} rows/s", file=sys.stderr, flush=True)
 
-    # Dominant stage and its roofline.
-    keep = {"fd": l - 1, "isvd": l - 1, "alpha": l - 1}.get(args.variant)
-    if keep is None:
-        s_ = int(np.ceil(args.alpha * l * (1 - 1e-12)))
-        keep = (l - s_) + (s_ + 1) // 2 - 1
-    # The dominant kernel: the eigensolve is timed per kernel when it is the
-    # tridiagonal route, as one stage when it is a Jacobi solver.
-    split = prof["tridiag"][1] > 0
-    kernel_stages = [s_ for s_ in prof if prof[s_][1] > 0 and not (split and s_ == "eig")]
-    dom = max(kernel_stages, key=lambda s_: prof[s_][0])
-    tot_ms, launches = prof[dom]
-    avg_s = tot_ms / max(launches, 1) / 1e3
-    work, kind, bound = stage_work(dom, m, keep, d, m - keep)
-    if kind == "byte":
-        roof = {"bound": "hbm", "achieved": work / avg_s / 1e9, "peak": PEAK_HBM / 1e9,
-                "unit": "GB/s"}
-    else:
-        roof = {"bound": bound, "achieved": work / avg_s / 1e12, "peak": PEAK_FP64 / 1e12,
-                "unit": "TFLOP/s"}
-    roof["frac"] = roof["achieved"] / roof["peak"]
-    roof["traffic"] = measured_traffic(dom, l, args.variant)
-    roof["kernel"] = kernel_name(dom, m)
-    roof["stage"] = dom
-    roof["avg_launch_us"] = avg_s * 1e6
-    roof["work_per_launch"] = work
+    # The same batch in FP64.
+    ms64, per64, outs_64, b = run_batch(cfg("fp64"), rows, 1, 1, graph=graph)
+    b.close()
+    print(f"[bench] batch fp64: {ms64:.1f} ms", file=sys.stderr, flush=True)
+    # The other launch mode of the split-BF16 batch (graph replay or direct).
+    ms_alt, per_alt, _, b = run_batch(cfg("bf16x3"), rows, args.steps, 1, graph=not graph)
+    b.close()
+    print(f"[bench] batch bf16x3 {'direct' if graph else 'graph'}: {ms_alt:.1f} ms", file=sys.stderr,
+          flush=True)
 
-    # Every stage against its own roof.
-    kernels = {}
-    for s_ in kernel_stages:
-        t_ms, nl = prof[s_]
-        a_s = t_ms / max(nl, 1) / 1e3
-        w, kd, bd = stage_work(s_, m, keep, d, m - keep)
-        if kd == "byte":
-            kernels[s_] = {"avg_launch_us": a_s * 1e6, "achieved": w / a_s / 1e9, "unit": "GB/s",
-                           "peak": PEAK_HBM / 1e9, "frac": w / a_s / PEAK_HBM, "bound": "hbm"}
-        else:
-            kernels[s_] = {"avg_launch_us": a_s * 1e6, "achieved": w / a_s / 1e12, "unit": "TFLOP/s",
-                           "peak": PEAK_FP64 / 1e12, "frac": w / a_s / PEAK_FP64,
-                           "bound": "fp64 mfma" if bd == "mfma" else "fp64 alu"}
-    # End to end: the time the roofs allow (input bytes at HBM rate, the GEMMs
-    # and a 9 m^3 eigendecomposition per ReduceRank at the FP64 peak) over the
-    # measured time.
-    nrr = st["n_reduce"]              # stats restart with every step (sketch_reset)
-    t_bytes = n * d * 4 / PEAK_HBM
-    t_gemm = nrr * (m * (m + 1) * d + 2.0 * keep * m * d) / PEAK_FP64
-    t_eig = nrr * 9.0 * m ** 3 / PEAK_FP64
-    t_min = max(t_bytes, t_gemm, t_eig)
-    alg_roof = {"t_min_ms": t_min * 1e3, "t_meas_ms": ms_per_step, "frac": t_min * 1e3 / ms_per_step,
-                "terms_ms": {"input_bytes_at_hbm": t_bytes * 1e3, "gemm_at_fp64_peak": t_gemm * 1e3,
-                             "eig_9m3_at_fp64_peak": t_eig * 1e3}}
+    # One profiled step of each precision: per-stage times on the class streams.
+    ms_p, _, _, bp = run_batch(cfg("bf16x3"), rows, 1, 0, profile=True)
+    prof_bf = bp.profile()
+    bp.close()
+    ms_p64, _, _, bp = run_batch(cfg("fp64"), rows, 1, 0, profile=True)
+    prof_64 = bp.profile()
+    bp.close()
+    peak_bf = lambda s_: ((PEAK_BF16, "bf16 mfma") if s_ in ("gram", "rebuild") else (PEAK_FP64, "fp64 alu"))
+    peak_64 = lambda s_: ((PEAK_FP64, "fp64 mfma") if s_ in ("gram", "rebuild") else (PEAK_FP64, "fp64 alu"))
+    stages_bf = stage_table({k_: v for k_, v in prof_bf.items() if k_ != "eig"}, peak_bf)
+    stages_64 = stage_table({k_: v for k_, v in prof_64.items() if k_ != "eig"}, peak_64)
+    dom = max(stages_bf, key=lambda s_: stages_bf[s_]["ms"])
+    e = stages_bf[dom]
+    roof = {"bound": "hbm" if e["bound"] == "hbm" else ("mfma" if "mfma" in e["bound"] else "alu"),
+            "achieved": e["achieved"], "peak": e["peak"], "unit": e["unit"], "frac": e["frac"],
+            "traffic": measured_traffic(dom), "kernel": STAGE_KERNELS[dom][0], "stage": dom,
+            "avg_launch_us": e["avg_launch_us"], "work_per_launch": e["work_per_launch"],
+            "launches": e["launches"],
+            "note": "a launch serves every sketch of its round and size class; achieved = the "
+                    "algorithmic flops of those sketches / the launch time (HIP events on the class "
+                    "stream, one profiled step of the same batch)"}
 
-    # Covariance error of the GPU sketch on the device evaluator (untimed).
-    ev = sk.error(At, k=10, method=0)
-    sk.close()
-    del At
-    batched = (batched_leg(args.batch_sketches, args.batch_nmax, args.batch_seq)
-               if args.batch_sketches > 0 else None)
-    prec = precision_leg(args.prec_rows) if args.prec_rows > 0 else None
+    # Plain FP64 FD, one sketch after another.
+    seq = None
+    if args.seq > 0:
+        k = min(args.seq, S)
+        dt_seq, outs_seq = sequential_leg(d, l, rows, k)
+        seq_rows = int(n[:k].sum())
+        seq = {"value": seq_rows / dt_seq, "unit": "rows/s", "ms": dt_seq * 1e3, "sketches": k,
+               "rows": seq_rows, "path": "single-sketch FP64 path, sketches one after another"}
+        print(f"[bench] sequential fp64: {dt_seq:.1f} s", file=sys.stderr, flush=True)
+
+    # Parity of every sketch against the oracle's stored result.
+    parity = None
+    gpath = os.path.join(GOLDEN, "c4_batch_512.json")
+    if not args.no_parity and os.path.exists(gpath):
+        with open(gpath) as f:
+            gold = json.load(f)["sketches"]
+        parity = {"bf16x3": batch_parity(rows, outs_bf, l, "bf16x3", gold),
+                  "fp64": batch_parity(rows, outs_64, l, "fp64", gold)}
+        if seq is not None and seq["sketches"] == S:
+            parity["sequential_fp64"] = batch_parity(rows, outs_seq, l, "fp64", gold)
+    elif not args.no_parity:
+        parity = {"skipped": "no stored oracle results (tests/golden/c4_batch_512.json)"}
+    print("[bench] parity done", file=sys.stderr, flush=True)
+    del outs_bf, outs_64
+    if seq is not None:
+        del outs_seq
+
+    extra_single = extra_prec = None
+    if not args.no_extra:
+        extra_single, _, _ = single_stream_leg()
+        if args.prec_rows > 0:
+            extra_prec = precision_leg(args.prec_rows)
 
     cpu = None
-    cov_oracle = None
     if not args.no_cpu_baseline:
-        import oracle
-        try:
-            from threadpoolctl import threadpool_info
-            cores = max((p.get("num_threads", 1) for p in threadpool_info()), default=1)
-        except Exception:
-            cores = os.cpu_count()
-        rows = min(args.cpu_rows, n)
-        A64 = A[:rows].astype(np.float64)
-        t = time.perf_counter()
-        Bo = oracle.fd_sketch(A64, l, args.variant, args.alpha)
-        dt = time.perf_counter() - t
-        if rows == n:
-            cov_oracle = oracle.cov_err(A64, Bo)
-        cpu = {"value": rows / dt, "unit": "rows/s", "cores": cores, "kind": "oracle",
-               "sample": (f"first {rows} of the {n} rows of the same stream" if rows < n
-                          else f"the whole {n}-row stream") +
-                         f", same variant and l (NumPy FP64, LAPACK SVD of the buffer), {dt:.1f} s",
-               "host": host_cpu()}
-        r1 = min(args.cpu_1thread_rows, n)
-        if r1 > 0:
-            try:
-                from threadpoolctl import threadpool_limits
-                with threadpool_limits(limits=1):
-                    t = time.perf_counter()
-                    oracle.fd_sketch(A[:r1].astype(np.float64), l, args.variant, args.alpha)
-                    dt1 = time.perf_counter() - t
-                cpu["value_1_thread"] = r1 / dt1
-                cpu["sample_1_thread"] = f"first {r1} rows, one BLAS thread, {dt1:.1f} s"
-            except Exception as e:      # threadpoolctl missing: report without it
-                cpu["value_1_thread"] = None
-                cpu["sample_1_thread"] = f"not measured ({type(e).__name__})"
+        cpu = cpu_baseline_leg(d, l, n, seed, args.cpu_seconds)
 
+    n_rr = int(sum(s_["n_reduce"] for s_ in st_bf))
     out = {
         "metric": METRIC,
         "value": value,
@@ -419,31 +446,41 @@ def main():
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms_per_step,
-        "ms_per_step_median": float(np.median(per_step)),
+        "ms_per_step": ms,
+        "ms_per_step_median": float(np.median(per)),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "bf16x3+f64",
         "data": "synthetic",
-        "config": {"workload": "random_noisy_100k_x1000_fp32" if n == N else
-                   f"random_noisy_100k_x1000_fp32_first_{n}_rows", "n": n, "d": d, "k": k,
-                   "zeta": zeta, "variant": args.variant, "l": l, "buffer_rows": m,
-                   "alpha": args.alpha if args.variant in ("alpha", "fast_alpha") else None,
-                   "eigensolver": "tridiagonal divide and conquer" if split else "Jacobi"},
+        "config": {"workload": "batch_512_random_noisy_fp32",
+                   "sketches": S, "rows": total_rows, "d": "U{64..2048}", "l": "U{16..128}",
+                   "n": "U{1000..50000}", "k": "l/2", "zeta": 10.0, "variant": "fd", "buffer_rows": "2l",
+                   "products": "split-bf16 x3 Gram and rebuild, fp32 accumulation",
+                   "eigensolver": "fp64 Householder tridiagonal + divide and conquer",
+                   "launch": "per-class HIP graphs, replayed" if graph else
+                             "direct launches, one stream per size class",
+                   "reduce_steps": n_rr},
+        "plain_fd_fp64_sequential": seq,
+        "speedup_vs_plain_fd": value / seq["value"] if seq else None,
+        "batch_fp64": {"value": total_rows / (ms64 / 1e3), "ms": ms64},
+        ("batch_bf16x3_direct" if graph else "batch_bf16x3_graph"):
+            {"value": total_rows / (ms_alt / 1e3), "ms_per_step": ms_alt,
+             "ms_per_step_median": float(np.median(per_alt))},
         "roofline": roof,
-        "kernels": kernels,
-        "algorithmic_roofline": alg_roof,
+        "stages_batch_bf16x3": stages_bf,
+        "stages_batch_fp64": stages_64,
+        "profiled_step_ms": {"bf16x3": ms_p, "fp64": ms_p64},
+        "parity": parity,
         "cpu_baseline": cpu,
-        "stages_ms_per_step": {s: prof[s][0] / args.steps for s in prof},
-        "batched": batched,
-        "precision_leg": prec,
-        "cov_err": ev["cov_err"],
-        "cov_err_oracle": cov_oracle,
-        "reduce_steps": st["n_reduce"],
-        "eig_sweeps_avg": st["eig_sweeps"] / max(st["n_reduce"], 1),
+        "single_stream": extra_single,
+        "precision_leg": extra_prec,
+        "input_generation_s": t_gen,
     }
     print(json.dumps(out))
+    if parity and any(isinstance(v, dict) and v.get("ok") is False for v in parity.values()):
+        print("[bench] PARITY FAILED", file=sys.stderr, flush=True)
+        sys.exit(1)
 
 
 if __name__ == "__main__":

@@ -86,8 +86,10 @@ typedef enum { FDSK_F64 = 0, FDSK_F32 = 1, FDSK_BF16 = 2 } fdsk_dtype;  /* BF16 
 typedef enum { FDSK_P_FP64 = 0, FDSK_P_BF16 = 1, FDSK_P_BF16X3 = 2, FDSK_P_FP8X3 = 3 } fdsk_precision;
 typedef enum { FDSK_MEM_HOST = 0, FDSK_MEM_DEVICE = 1 } fdsk_mem;
 
-#define FDSK_FLAG_PROFILE 1u       /* record per-stage HIP events (see sketch_profile) */
+#define FDSK_FLAG_PROFILE 1u       /* record per-stage HIP events (sketch_profile, sketch_batch_profile) */
 #define FDSK_FLAG_EIG_JACOBI 2u    /* always use the Jacobi eigensolver (see fdsk_eigh) */
+#define FDSK_FLAG_GRAPH 4u         /* batches: run each append call through HIP graphs captured
+                                      per size class (see sketch_batch_append) */
 
 enum {
   FDSK_OK = 0,
@@ -106,7 +108,8 @@ typedef struct {
   fdsk_variant variant;
   double alpha;           /* (0, 1]; used by FDSK_ALPHA and FDSK_FAST_ALPHA */
   fdsk_precision precision;
-  uint32_t flags;         /* 0, or FDSK_FLAG_PROFILE and/or FDSK_FLAG_EIG_JACOBI */
+  uint32_t flags;         /* FDSK_FLAG_* bits: PROFILE and EIG_JACOBI for single sketches;
+                             PROFILE and GRAPH (the same for every sketch) for batches */
 } fdsk_config;
 
 typedef struct {
@@ -194,17 +197,26 @@ int sketch_stats(const fdsk_sketch* s, fdsk_report* out);
  * not finalized) keeping its allocations and stream.  Stream-ordered. */
 int sketch_reset(fdsk_sketch* s);
 
-/* Per-stage device time, measured with HIP events on the sketch's stream
- * when the sketch was created with FDSK_FLAG_PROFILE (otherwise zeros).
- * Totals since create/reset; synchronises the stream.  EIG is the whole
- * eigensolve; with the tridiagonal route its three kernels are also timed on
- * their own (TRIDIAG + DC + BACKTR = EIG up to event overhead). */
+/* Per-stage device time, measured with HIP events on the stream each stage
+ * runs on, when the sketch was created with FDSK_FLAG_PROFILE (otherwise
+ * zeros).  Totals since create/reset; synchronises the stream.  Resource
+ * accounting only: no step of the method.  EIG is the whole eigensolve; with
+ * the tridiagonal route its kernels are also timed on their own (TRIDIAG_HEAD
+ * + TRIDIAG + DC + BACKTR = EIG up to event overhead; TRIDIAG_HEAD is the
+ * packed-triangle part of the reduction of buffers above 208 rows, which
+ * single sketches count under TRIDIAG).  work[] is the algorithmic work of
+ * the timed launches, computed on the host from the sizes: bytes for INGEST
+ * (rows read plus buffer rows written), flops otherwise: Gram m(m+1)d per
+ * product pass, Householder tridiagonal reduction 4/3 m^3, divide and conquer
+ * 4/3 m^3, back-transformation 2 m^2 per wanted eigenvector, rebuild
+ * 2 (t-1) m d per pass, shrink 0 (m = buffer rows, d = row length). */
 enum { FDSK_STAGE_INGEST = 0, FDSK_STAGE_GRAM = 1, FDSK_STAGE_EIG = 2, FDSK_STAGE_SHRINK = 3,
        FDSK_STAGE_REBUILD = 4, FDSK_STAGE_TRIDIAG = 5, FDSK_STAGE_DC = 6, FDSK_STAGE_BACKTR = 7,
-       FDSK_STAGE_COUNT = 8 };
+       FDSK_STAGE_TRIDIAG_HEAD = 8, FDSK_STAGE_COUNT = 9 };
 typedef struct {
   double ms[FDSK_STAGE_COUNT];       /* summed stage durations */
   int64_t launches[FDSK_STAGE_COUNT];
+  double work[FDSK_STAGE_COUNT];     /* summed algorithmic work (bytes or flops, see above) */
 } fdsk_profile;
 int sketch_profile(fdsk_sketch* s, fdsk_profile* out);
 
@@ -256,15 +268,29 @@ int fdsk_eigh(const double* G, int32_t m, int64_t ldg, double* lam, double* V, i
  * ------------------------------------------------------------------------ */
 typedef struct fdsk_batch fdsk_batch;
 
-/* Create S sketches from cfgs[0..S-1] (flags 0, buffer rows <= 256).
+/* Create S sketches from cfgs[0..S-1] (buffer rows <= 256; flags 0,
+ * FDSK_FLAG_PROFILE and/or FDSK_FLAG_GRAPH, the same for every sketch).
  * Errors: EINVAL, EUNSUPPORTED, ENOMEM, EDEVICE. */
 int sketch_batch_create(int32_t S, const fdsk_config* cfgs, void* hip_stream, fdsk_batch** out);
 
-/* Append rows[i] (n_rows[i] x d_i, leading dimension strides[i], device
- * pointers only, common dtype) to sketch i for every i.  n_rows[i] may be 0
- * (rows[i] may then be NULL).  Returns when the work has completed (the rows
- * may be overwritten afterwards).  Errors: EINVAL, ESTATE (after finalize),
- * EUNSUPPORTED (host memory), ENOMEM, EDEVICE. */
+/* Append rows[i] (n_rows[i] x d_i, leading dimension strides[i], common
+ * dtype) to sketch i for every i.  n_rows[i] may be 0 (rows[i] may then be
+ * NULL).  mem FDSK_MEM_DEVICE: device pointers, read in stream order.
+ * mem FDSK_MEM_HOST: host pointers, staged through one device buffer holding
+ * every sketch's rows of the call (allocated for the call and freed after
+ * it).  Returns when the work has completed (the rows may be overwritten
+ * afterwards).
+ *
+ * Launches: each size class of buffer rows runs its rounds on a stream of
+ * its own (the classes overlap), ordered after the batch's stream, which
+ * then waits for all of them.  With FDSK_FLAG_GRAPH (and without
+ * FDSK_FLAG_PROFILE) each class's launches of the call are captured into a
+ * HIP graph on its stream, instantiated and launched there; the batch keeps
+ * the last graphs with the task lists they read, and a later call whose
+ * schedule is identical (the same row pointers, counts and strides, from
+ * the same sketch states, e.g. after sketch_batch_reset) replays them
+ * without capturing again.  Errors: EINVAL, ESTATE (after finalize), ENOMEM,
+ * EDEVICE. */
 int sketch_batch_append(fdsk_batch* b, const void* const* rows, const int64_t* n_rows,
                         const int64_t* strides, fdsk_dtype dtype, fdsk_mem mem, int32_t grid_size);
 
@@ -279,7 +305,24 @@ int sketch_batch_finalize(fdsk_batch* b, void* const* B_out, const int64_t* ldb,
 /* Accumulators of sketch `index` (as sketch_stats).  Synchronises. */
 int sketch_batch_stats(const fdsk_batch* b, int32_t index, fdsk_report* out);
 
+/* Return every sketch of the batch to its empty state (all rows free,
+ * accumulators zero, not finalized), keeping its allocations, streams and
+ * the cached graph.  Stream-ordered.  Errors: EINVAL, EDEVICE. */
+int sketch_batch_reset(fdsk_batch* b);
+
+/* Per-stage device time of the batch's launches since create/reset (HIP
+ * events recorded on the stream of each size class; the batch must have
+ * been created with FDSK_FLAG_PROFILE, which launches rounds directly).
+ * Fields as sketch_profile; a launch serves every sketch of its round and
+ * class, and work[] sums their algorithmic work.  Synchronises.  Resource
+ * accounting only.  Errors: EINVAL, EDEVICE. */
+int sketch_batch_profile(fdsk_batch* b, fdsk_profile* out);
+
+/* Free everything the batch owns (waits for its streams first).  NULL is
+ * ok.  Resource management only: no step of the method. */
 void sketch_batch_destroy(fdsk_batch* b);
+/* Message of the batch's last error ("" if none); NULL: the last create
+ * failure.  Valid until the next call on the batch. */
 const char* sketch_batch_last_error(const fdsk_batch* b);
 
 /* Library build information (static string). */

@@ -39,6 +39,26 @@ struct fdsk_batch {
   bool finalized = false;
   int err = 0;
   std::string msg;
+  // Stage profiling (FDSK_FLAG_PROFILE): event pairs with the launch's
+  // algorithmic work, recorded on the class streams.
+  bool profile = false;
+  std::vector<hipEvent_t> ev_pool;
+  struct Mark { int stage; hipEvent_t a, b; double work; };
+  std::vector<Mark> marks;
+  // The captured graph of the last append call and the task lists it reads
+  // (owned by the cache, so other calls cannot overwrite them).
+  bool use_graph = false;
+  struct GraphCache {
+    bool valid = false;
+    int dt = 0, cap = 0;
+    std::vector<GroupIngest> hi[kClasses];
+    std::vector<GroupRR> hr[kClasses];
+    std::vector<size_t> oi[kClasses], orr[kClasses];
+    void* d_tasks[kClasses] = {};
+    size_t tasks_cap[kClasses] = {};
+    hipGraph_t graph[kClasses] = {};
+    hipGraphExec_t exec[kClasses] = {};
+  } gc;
 };
 
 namespace {
@@ -111,9 +131,9 @@ struct Staged {
 
 // Sort each round's ReduceRanks in descending order of buffer rows, so that
 // the longest workgroups are dispatched first (the order changes no result:
-// every task works on its own sketch), flatten, and upload on stream st into
-// the task buffer (grown if needed; callers synchronise before reusing it).
-int stage_plan(fdsk_batch* b, Plan& p, hipStream_t st, void*& d_tasks, size_t& tasks_cap, Staged& sg) {
+// every task works on its own sketch), and flatten the rounds into one task
+// list per kind with each round's offsets.
+void flatten_plan(const fdsk_batch* b, Plan& p, Staged& sg) {
   for (auto& v : p.rr)
     std::stable_sort(v.begin(), v.end(), [b](const GroupRR& x, const GroupRR& y) {
       return b->sk[x.sk].m > b->sk[y.sk].m;
@@ -121,6 +141,25 @@ int stage_plan(fdsk_batch* b, Plan& p, hipStream_t st, void*& d_tasks, size_t& t
   size_t ni = 0, nr = 0;
   for (auto& v : p.ing) ni += v.size();
   for (auto& v : p.rr) nr += v.size();
+  sg.hi.reserve(ni);
+  sg.hr.reserve(nr);
+  const size_t rounds = std::max(p.ing.size(), p.rr.size());
+  sg.oi.assign(rounds + 1, 0);
+  sg.orr.assign(rounds + 1, 0);
+  for (size_t r = 0; r < rounds; ++r) {
+    sg.oi[r] = sg.hi.size();
+    sg.orr[r] = sg.hr.size();
+    if (r < p.ing.size()) sg.hi.insert(sg.hi.end(), p.ing[r].begin(), p.ing[r].end());
+    if (r < p.rr.size()) sg.hr.insert(sg.hr.end(), p.rr[r].begin(), p.rr[r].end());
+  }
+  sg.oi[rounds] = sg.hi.size();
+  sg.orr[rounds] = sg.hr.size();
+}
+
+// Upload a flattened plan on stream st into the task buffer (grown if
+// needed; callers synchronise before reusing it).
+int upload_plan(fdsk_batch* b, Staged& sg, hipStream_t st, void*& d_tasks, size_t& tasks_cap) {
+  const size_t ni = sg.hi.size(), nr = sg.hr.size();
   const size_t ing_bytes = (ni * sizeof(GroupIngest) + 255) / 256 * 256;
   const size_t bytes = ing_bytes + nr * sizeof(GroupRR) + 256;
   if (bytes > tasks_cap) {
@@ -135,19 +174,6 @@ int stage_plan(fdsk_batch* b, Plan& p, hipStream_t st, void*& d_tasks, size_t& t
       return berr(b, FDSK_ENOMEM, "batch task lists of %zu bytes", bytes);
     tasks_cap = bytes;
   }
-  sg.hi.reserve(ni);
-  sg.hr.reserve(nr);
-  const size_t rounds = std::max(p.ing.size(), p.rr.size());
-  sg.oi.assign(rounds + 1, 0);
-  sg.orr.assign(rounds + 1, 0);
-  for (size_t r = 0; r < rounds; ++r) {
-    sg.oi[r] = sg.hi.size();
-    sg.orr[r] = sg.hr.size();
-    if (r < p.ing.size()) sg.hi.insert(sg.hi.end(), p.ing[r].begin(), p.ing[r].end());
-    if (r < p.rr.size()) sg.hr.insert(sg.hr.end(), p.rr[r].begin(), p.rr[r].end());
-  }
-  sg.oi[rounds] = sg.hi.size();
-  sg.orr[rounds] = sg.hr.size();
   sg.d_ing = static_cast<GroupIngest*>(d_tasks);
   sg.d_rr = reinterpret_cast<GroupRR*>(static_cast<char*>(d_tasks) + ing_bytes);
   hipError_t e = hipSuccess;
@@ -158,8 +184,39 @@ int stage_plan(fdsk_batch* b, Plan& p, hipStream_t st, void*& d_tasks, size_t& t
   return 0;
 }
 
+int stage_plan(fdsk_batch* b, Plan& p, hipStream_t st, void*& d_tasks, size_t& tasks_cap, Staged& sg) {
+  flatten_plan(b, p, sg);
+  return upload_plan(b, sg, st, d_tasks, tasks_cap);
+}
+
+hipEvent_t take_event(fdsk_batch* b) {
+  hipEvent_t e = nullptr;
+  if (!b->ev_pool.empty()) {
+    e = b->ev_pool.back();
+    b->ev_pool.pop_back();
+  } else if (hipEventCreate(&e) != hipSuccess) {
+    e = nullptr;
+  }
+  return e;
+}
+
+// Profiling: an event on the stream before a stage's launches (or nullptr).
+hipEvent_t mark(fdsk_batch* b, hipStream_t st) {
+  if (!b->profile) return nullptr;
+  hipEvent_t e = take_event(b);
+  if (e && hipEventRecord(e, st) != hipSuccess) return nullptr;
+  return e;
+}
+
+void add_mark(fdsk_batch* b, int stage, hipEvent_t a, hipStream_t st, double work) {
+  if (!a) return;
+  hipEvent_t e = mark(b, st);
+  if (e) b->marks.push_back({stage, a, e, work});
+}
+
 // Launch round r of a staged plan on stream st, at most `cap` sketches per
-// launch.
+// launch.  With profiling, each stage's launches are bracketed by events and
+// credited with the algorithmic work of their tasks.
 hipError_t launch_round(fdsk_batch* b, const Plan& p, const Staged& sg, size_t r, int dt, int cap,
                         hipStream_t st) {
   hipError_t e = hipSuccess;
@@ -167,16 +224,24 @@ hipError_t launch_round(fdsk_batch* b, const Plan& p, const Staged& sg, size_t r
   static const std::vector<GroupRR> empty_r;
   const auto& vi = r < p.ing.size() ? p.ing[r] : empty_i;
   const auto& vr = r < p.rr.size() ? p.rr[r] : empty_r;
+  const double es = static_cast<double>(dtype_bytes(static_cast<fdsk_dtype>(dt)));
   for (size_t c0 = 0; c0 < vi.size() && e == hipSuccess; c0 += cap) {
     const int nt = static_cast<int>(std::min<size_t>(cap, vi.size() - c0));
     int max_f = 0;
-    for (int t = 0; t < nt; ++t) max_f = std::max(max_f, vi[c0 + t].f);
+    double bytes = 0.0;
+    for (int t = 0; t < nt; ++t) {
+      max_f = std::max(max_f, vi[c0 + t].f);
+      bytes += static_cast<double>(vi[c0 + t].f) * b->sk[vi[c0 + t].sk].d * (es + 8.0);
+    }
+    hipEvent_t a = mark(b, st);
     e = launch_group_ingest(b->d_sk, sg.d_ing + sg.oi[r] + c0, nt, max_f, dt, st);
+    add_mark(b, FDSK_STAGE_INGEST, a, st, bytes);
   }
   for (size_t c0 = 0; c0 < vr.size() && e == hipSuccess; c0 += cap) {
     const int nt = static_cast<int>(std::min<size_t>(cap, vr.size() - c0));
     int max_mp = 0, max_m = 0, max_ldc = 0, max_keep = 0;
     bool p0 = false, p1 = false, p3 = false;   // precisions present in this launch
+    double w_gram = 0, w_head = 0, w_trid = 0, w_dc = 0, w_bt = 0, w_reb = 0;
     for (int t = 0; t < nt; ++t) {
       const GroupSketch& s = b->sk[vr[c0 + t].sk];
       max_mp = std::max(max_mp, s.mp);
@@ -186,14 +251,46 @@ hipError_t launch_round(fdsk_batch* b, const Plan& p, const Staged& sg, size_t r
       p0 |= s.npass == 0;
       p1 |= s.npass == 1;
       p3 |= s.npass == 3;
+      const double m = s.m, d = s.d, np = std::max(s.npass, 1);
+      w_gram += np * m * (m + 1.0) * d;
+      // Householder reduction: 4/3 n^3 over n columns, split between the
+      // packed-triangle head (the first m - 208 columns) and the registers.
+      const double hcols = std::max(0.0, m - 208.0), tail = m - hcols;
+      w_head += 4.0 / 3.0 * (m * m * m - tail * tail * tail);
+      w_trid += 4.0 / 3.0 * tail * tail * tail;
+      w_dc += 4.0 / 3.0 * m * m * m;
+      w_bt += 2.0 * m * m * std::min(s.m, s.l);
+      w_reb += np * 2.0 * s.rp.keep * m * d;
     }
     const GroupRR* tt = sg.d_rr + sg.orr[r] + c0;
+    hipEvent_t a = mark(b, st);
     if (p1 || p3) e = launch_group_gram_lowp(b->d_sk, tt, nt, max_mp, max_ldc, p1, p3, st);
     if (e == hipSuccess) e = launch_group_gram(b->d_sk, tt, nt, max_mp, p0, st);
-    if (e == hipSuccess) e = launch_group_eig(b->d_sk, tt, nt, max_m, st);
-    if (e == hipSuccess) e = launch_group_shrink_rebuild(b->d_sk, tt, nt, max_ldc, max_keep, p0, st);
+    add_mark(b, FDSK_STAGE_GRAM, a, st, w_gram);
+    hipEvent_t eig0 = mark(b, st);
+    if (e == hipSuccess && max_m > 208) {
+      a = mark(b, st);
+      e = launch_group_tridiag_head(b->d_sk, tt, nt, max_m, st);
+      add_mark(b, FDSK_STAGE_TRIDIAG_HEAD, a, st, w_head);
+    }
+    a = mark(b, st);
+    if (e == hipSuccess) e = launch_group_tridiag(b->d_sk, tt, nt, max_m, st);
+    add_mark(b, FDSK_STAGE_TRIDIAG, a, st, w_trid);
+    a = mark(b, st);
+    if (e == hipSuccess) e = launch_group_dc(b->d_sk, tt, nt, st);
+    add_mark(b, FDSK_STAGE_DC, a, st, w_dc);
+    a = mark(b, st);
+    if (e == hipSuccess) e = launch_group_backtr(b->d_sk, tt, nt, max_m, st);
+    add_mark(b, FDSK_STAGE_BACKTR, a, st, w_bt);
+    add_mark(b, FDSK_STAGE_EIG, eig0, st, w_head + w_trid + w_dc + w_bt);
+    a = mark(b, st);
+    if (e == hipSuccess) e = launch_group_shrink(b->d_sk, tt, nt, st);
+    add_mark(b, FDSK_STAGE_SHRINK, a, st, 0.0);
+    a = mark(b, st);
+    if (e == hipSuccess && p0) e = launch_group_rebuild(b->d_sk, tt, nt, max_ldc, max_keep, st);
     if (e == hipSuccess && (p1 || p3))
       e = launch_group_rebuild_lowp(b->d_sk, tt, nt, max_ldc, max_keep, p1, p3, st);
+    add_mark(b, FDSK_STAGE_REBUILD, a, st, w_reb);
   }
   return e;
 }
@@ -212,31 +309,68 @@ int run_plan(fdsk_batch* b, Plan& p, int dt, int cap) {
   return 0;
 }
 
-// The same for one plan per size class, each on its own stream after the
-// caller's stream, rounds interleaved across the classes as they are
-// enqueued; the caller's stream waits for all of them and is synchronised.
-int run_class_plans(fdsk_batch* b, Plan* plans, int dt, int cap) {
+int ensure_lanes(fdsk_batch* b) {
   constexpr int K = fdsk_batch::kClasses;
-  hipError_t e = hipSuccess;
-  if (!b->ev_in) {
-    e = hipEventCreateWithFlags(&b->ev_in, hipEventDisableTiming);
-    for (int g = 0; g < K && e == hipSuccess; ++g) {
-      e = hipStreamCreateWithFlags(&b->lane[g], hipStreamNonBlocking);
-      if (e == hipSuccess) e = hipEventCreateWithFlags(&b->ev_out[g], hipEventDisableTiming);
+  if (b->ev_in) return 0;
+  hipError_t e = hipEventCreateWithFlags(&b->ev_in, hipEventDisableTiming);
+  for (int g = 0; g < K && e == hipSuccess; ++g) {
+    e = hipStreamCreateWithFlags(&b->lane[g], hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&b->ev_out[g], hipEventDisableTiming);
+  }
+  if (e != hipSuccess) return berr(b, FDSK_EDEVICE, "batch streams: %s", hipGetErrorString(e));
+  return 0;
+}
+
+template <class T>
+bool same_list(const std::vector<T>& a, const std::vector<T>& b) {
+  return a.size() == b.size() && (a.empty() || std::memcmp(a.data(), b.data(), a.size() * sizeof(T)) == 0);
+}
+
+// Whether the cached graph launches exactly the flattened plans sg.
+bool cache_matches(const fdsk_batch* b, const Staged* sg, int dt, int cap) {
+  const auto& c = b->gc;
+  if (!c.valid || c.dt != dt || c.cap != cap) return false;
+  for (int g = 0; g < fdsk_batch::kClasses; ++g)
+    if (!same_list(c.hi[g], sg[g].hi) || !same_list(c.hr[g], sg[g].hr) || !same_list(c.oi[g], sg[g].oi) ||
+        !same_list(c.orr[g], sg[g].orr))
+      return false;
+  return true;
+}
+
+void drop_graph(fdsk_batch* b) {
+  auto& c = b->gc;
+  for (int g = 0; g < fdsk_batch::kClasses; ++g) {
+    if (c.exec[g]) (void)hipGraphExecDestroy(c.exec[g]);
+    if (c.graph[g]) (void)hipGraphDestroy(c.graph[g]);
+    c.exec[g] = nullptr;
+    c.graph[g] = nullptr;
+  }
+  c.valid = false;
+}
+
+// The cached per-class graphs launched on the class streams, after the
+// caller's stream, which then waits for all of them.
+hipError_t launch_graphs(fdsk_batch* b) {
+  constexpr int K = fdsk_batch::kClasses;
+  hipError_t e = hipEventRecord(b->ev_in, b->stream);
+  for (int g = 0; g < K && e == hipSuccess; ++g)
+    if (b->gc.exec[g]) {
+      e = hipStreamWaitEvent(b->lane[g], b->ev_in, 0);
+      if (e == hipSuccess) e = hipGraphLaunch(b->gc.exec[g], b->lane[g]);
+      if (e == hipSuccess) e = hipEventRecord(b->ev_out[g], b->lane[g]);
+      if (e == hipSuccess) e = hipStreamWaitEvent(b->stream, b->ev_out[g], 0);
     }
-    if (e != hipSuccess) return berr(b, FDSK_EDEVICE, "batch streams: %s", hipGetErrorString(e));
-  }
-  Staged sg[K];
-  size_t rounds = 0;
-  bool used[K] = {};
-  for (int g = 0; g < K; ++g) {
-    used[g] = !plans[g].ing.empty() || !plans[g].rr.empty();
-    if (!used[g]) continue;
-    int rc = stage_plan(b, plans[g], b->lane[g], b->d_tasks_c[g], b->tasks_cap_c[g], sg[g]);
-    if (rc) return rc;
-    rounds = std::max(rounds, std::max(plans[g].ing.size(), plans[g].rr.size()));
-  }
-  e = hipEventRecord(b->ev_in, b->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+  return e;
+}
+
+// Enqueue every round of the class plans: each class on its own stream,
+// after `origin` (event ev_in), rounds interleaved across the classes as
+// they are enqueued; `origin` then waits for all of them.
+hipError_t enqueue_classes(fdsk_batch* b, Plan* plans, const Staged* sg, const bool* used, size_t rounds,
+                           int dt, int cap, hipStream_t origin) {
+  constexpr int K = fdsk_batch::kClasses;
+  hipError_t e = hipEventRecord(b->ev_in, origin);
   for (int g = 0; g < K && e == hipSuccess; ++g)
     if (used[g]) e = hipStreamWaitEvent(b->lane[g], b->ev_in, 0);
   for (size_t r = 0; r < rounds && e == hipSuccess; ++r)
@@ -245,8 +379,82 @@ int run_class_plans(fdsk_batch* b, Plan* plans, int dt, int cap) {
   for (int g = 0; g < K && e == hipSuccess; ++g)
     if (used[g]) {
       e = hipEventRecord(b->ev_out[g], b->lane[g]);
-      if (e == hipSuccess) e = hipStreamWaitEvent(b->stream, b->ev_out[g], 0);
+      if (e == hipSuccess) e = hipStreamWaitEvent(origin, b->ev_out[g], 0);
     }
+  return e;
+}
+
+// Run one plan per size class, each on its own stream ordered after the
+// caller's stream, which then waits for all of them.  Direct launches enqueue
+// the rounds as they are planned.  Graph: each class's rounds are captured
+// from its own stream into a graph of their own (the classes stay
+// concurrent), instantiated and launched there; a call with the same
+// schedule as the cached graphs replays them.  Everything is synchronised
+// before returning (the host task lists and the task buffers are reused by
+// the next call).
+int run_class_plans(fdsk_batch* b, Plan* plans, int dt, int cap) {
+  constexpr int K = fdsk_batch::kClasses;
+  int rc = ensure_lanes(b);
+  if (rc) return rc;
+  Staged sg[K];
+  size_t rounds = 0;
+  bool used[K] = {};
+  for (int g = 0; g < K; ++g) {
+    used[g] = !plans[g].ing.empty() || !plans[g].rr.empty();
+    if (!used[g]) continue;
+    flatten_plan(b, plans[g], sg[g]);
+    rounds = std::max(rounds, std::max(plans[g].ing.size(), plans[g].rr.size()));
+  }
+  hipError_t e = hipSuccess;
+  const bool graph = b->use_graph && !b->profile;
+  if (graph && cache_matches(b, sg, dt, cap)) {
+    e = launch_graphs(b);
+    if (e != hipSuccess) return berr(b, FDSK_EDEVICE, "batch graph launch: %s", hipGetErrorString(e));
+    return 0;
+  }
+  if (graph) {
+    drop_graph(b);
+    auto& c = b->gc;
+    for (int g = 0; g < K; ++g)
+      if (used[g]) {
+        rc = upload_plan(b, sg[g], b->stream, c.d_tasks[g], c.tasks_cap[g]);
+        if (rc) return rc;
+      }
+    e = hipStreamSynchronize(b->stream);     // task lists in place before any replay
+    for (int g = 0; g < K && e == hipSuccess; ++g) {
+      if (!used[g]) continue;
+      e = hipStreamBeginCapture(b->lane[g], hipStreamCaptureModeRelaxed);
+      if (e != hipSuccess) break;
+      for (size_t r = 0; r < rounds && e == hipSuccess; ++r)
+        e = launch_round(b, plans[g], sg[g], r, dt, cap, b->lane[g]);
+      hipGraph_t gr = nullptr;
+      const hipError_t ee = hipStreamEndCapture(b->lane[g], &gr);
+      if (e == hipSuccess) e = ee;
+      c.graph[g] = gr;
+      if (e == hipSuccess) e = hipGraphInstantiate(&c.exec[g], gr, nullptr, nullptr, 0);
+    }
+    if (e == hipSuccess) e = launch_graphs(b);
+    if (e != hipSuccess) {
+      drop_graph(b);
+      return berr(b, FDSK_EDEVICE, "batch graph: %s", hipGetErrorString(e));
+    }
+    c.valid = true;
+    c.dt = dt;
+    c.cap = cap;
+    for (int g = 0; g < K; ++g) {
+      c.hi[g] = std::move(sg[g].hi);
+      c.hr[g] = std::move(sg[g].hr);
+      c.oi[g] = std::move(sg[g].oi);
+      c.orr[g] = std::move(sg[g].orr);
+    }
+    return 0;
+  }
+  for (int g = 0; g < K; ++g)
+    if (used[g]) {
+      rc = upload_plan(b, sg[g], b->lane[g], b->d_tasks_c[g], b->tasks_cap_c[g]);
+      if (rc) return rc;
+    }
+  e = enqueue_classes(b, plans, sg, used, rounds, dt, cap, b->stream);
   // Synchronise every class stream (the host copies above and the task
   // buffers are reused), then the caller's.
   for (int g = 0; g < K; ++g)
@@ -289,11 +497,17 @@ int sketch_batch_create(int32_t S, const fdsk_config* cfgs, void* hip_stream, fd
                   "sketch %d: single-pass BF16 is not a sketching precision (use FDSK_P_BF16X3)", i);
     if (c.precision != FDSK_P_FP64 && c.precision != FDSK_P_BF16X3)
       return berr(nullptr, FDSK_EINVAL, "sketch %d: unknown precision", i);
-    if (c.flags != 0) return berr(nullptr, FDSK_EUNSUPPORTED, "sketch %d: batched sketches take no flags", i);
+    if (c.flags & ~(FDSK_FLAG_PROFILE | FDSK_FLAG_GRAPH))
+      return berr(nullptr, FDSK_EUNSUPPORTED, "sketch %d: batched sketches take only the PROFILE and GRAPH flags",
+                  i);
+    if (c.flags != cfgs[0].flags)
+      return berr(nullptr, FDSK_EINVAL, "sketch %d: every sketch of a batch takes the same flags", i);
   }
   fdsk_batch* b = new fdsk_batch;
   b->S = S;
   b->stream = static_cast<hipStream_t>(hip_stream);
+  b->profile = (cfgs[0].flags & FDSK_FLAG_PROFILE) != 0;
+  b->use_graph = (cfgs[0].flags & FDSK_FLAG_GRAPH) != 0;
   b->cfg.assign(cfgs, cfgs + S);
   b->sk.resize(S);
   b->occ.assign(S, 0);
@@ -368,7 +582,7 @@ int sketch_batch_append(fdsk_batch* b, const void* const* rows, const int64_t* n
   if (b->err) return b->err;
   if (b->finalized) return berr(b, FDSK_ESTATE, "append after finalize");
   if (!rows || !n_rows || !strides) return berr(b, FDSK_EINVAL, "null argument");
-  if (mem != FDSK_MEM_DEVICE) return berr(b, FDSK_EUNSUPPORTED, "batched rows must be on the device");
+  if (mem != FDSK_MEM_DEVICE && mem != FDSK_MEM_HOST) return berr(b, FDSK_EINVAL, "bad mem kind");
   const size_t es = dtype_bytes(dtype);
   if (es == 0) return berr(b, FDSK_EINVAL, "bad dtype");
   if (grid_size < 0) return berr(b, FDSK_EINVAL, "grid_size < 0");
@@ -376,6 +590,35 @@ int sketch_batch_append(fdsk_batch* b, const void* const* rows, const int64_t* n
     if (n_rows[i] < 0) return berr(b, FDSK_EINVAL, "sketch %d: n_rows < 0", i);
     if (n_rows[i] > 0 && (!rows[i] || strides[i] < b->sk[i].d))
       return berr(b, FDSK_EINVAL, "sketch %d: bad rows or stride", i);
+  }
+  // Host rows: every sketch's rows of the call packed into one device
+  // buffer (leading dimension d_i), then the device path.
+  std::vector<const void*> drows(rows, rows + b->S);
+  std::vector<int64_t> dstrides(strides, strides + b->S);
+  void* stage = nullptr;
+  if (mem == FDSK_MEM_HOST) {
+    size_t total = 0;
+    for (int i = 0; i < b->S; ++i) total += static_cast<size_t>(n_rows[i]) * b->sk[i].d * es;
+    if (total > 0) {
+      if (hipMalloc(&stage, total) != hipSuccess)
+        return berr(b, FDSK_ENOMEM, "staging %zu bytes of host rows", total);
+      size_t off = 0;
+      hipError_t e = hipSuccess;
+      for (int i = 0; i < b->S && e == hipSuccess; ++i) {
+        if (n_rows[i] == 0) continue;
+        const size_t rb = static_cast<size_t>(b->sk[i].d) * es;
+        char* dst = static_cast<char*>(stage) + off;
+        e = hipMemcpy2DAsync(dst, rb, rows[i], strides[i] * es, rb, n_rows[i], hipMemcpyHostToDevice, b->stream);
+        drows[i] = dst;
+        dstrides[i] = b->sk[i].d;
+        off += rb * n_rows[i];
+      }
+      if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+      if (e != hipSuccess) {
+        (void)hipFree(stage);
+        return berr(b, FDSK_EDEVICE, "staging host rows: %s", hipGetErrorString(e));
+      }
+    }
   }
   // Lay out every sketch's ingests and ReduceRanks of this call by round,
   // one plan per size class.
@@ -388,8 +631,8 @@ int sketch_batch_append(fdsk_batch* b, const void* const* rows, const int64_t* n
     while (pos < n_rows[i]) {
       const int f = static_cast<int>(std::min<int64_t>(D.m - b->occ[i], n_rows[i] - pos));
       GroupIngest t;
-      t.src = static_cast<const char*>(rows[i]) + pos * strides[i] * static_cast<int64_t>(es);
-      t.stride = strides[i];
+      t.src = static_cast<const char*>(drows[i]) + pos * dstrides[i] * static_cast<int64_t>(es);
+      t.stride = dstrides[i];
       t.sk = i;
       t.f = f;
       t.row0 = b->occ[i];
@@ -408,7 +651,9 @@ int sketch_batch_append(fdsk_batch* b, const void* const* rows, const int64_t* n
     }
     b->rows_in[i] += n_rows[i];
   }
-  return run_class_plans(b, plans, static_cast<int>(dtype), grid_size > 0 ? grid_size : b->S);
+  const int rc = run_class_plans(b, plans, static_cast<int>(dtype), grid_size > 0 ? grid_size : b->S);
+  if (stage) (void)hipFree(stage);   // run_class_plans synchronised every stream
+  return rc;
 }
 
 int sketch_batch_finalize(fdsk_batch* b, void* const* B_out, const int64_t* ldb, fdsk_dtype out_dtype,
@@ -507,9 +752,54 @@ int sketch_batch_stats(const fdsk_batch* cb, int32_t index, fdsk_report* out) {
   return 0;
 }
 
+int sketch_batch_reset(fdsk_batch* b) {
+  if (!b) return berr(nullptr, FDSK_EINVAL, "null batch");
+  // Rows beyond a sketch's occupancy are never read before they are written
+  // again (a reduction runs on a full buffer; finalize zeroes the free rows
+  // first), so only the accumulators and the host schedule start over.
+  hipError_t e = hipMemsetAsync(b->d_stats, 0, sizeof(DevStats) * b->S, b->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+  if (e != hipSuccess) return berr(b, FDSK_EDEVICE, "batch reset: %s", hipGetErrorString(e));
+  std::fill(b->occ.begin(), b->occ.end(), 0);
+  std::fill(b->cur.begin(), b->cur.end(), 0);
+  std::fill(b->new0.begin(), b->new0.end(), 0);
+  std::fill(b->rows_in.begin(), b->rows_in.end(), 0);
+  std::fill(b->rows_out.begin(), b->rows_out.end(), 0);
+  b->finalized = false;
+  b->err = 0;
+  b->msg.clear();
+  for (auto& mk : b->marks) {
+    b->ev_pool.push_back(mk.a);
+    b->ev_pool.push_back(mk.b);
+  }
+  b->marks.clear();
+  std::sort(b->ev_pool.begin(), b->ev_pool.end());
+  b->ev_pool.erase(std::unique(b->ev_pool.begin(), b->ev_pool.end()), b->ev_pool.end());
+  return 0;
+}
+
+int sketch_batch_profile(fdsk_batch* b, fdsk_profile* out) {
+  if (!b || !out) return berr(b, FDSK_EINVAL, "null argument");
+  hipError_t e = hipStreamSynchronize(b->stream);
+  for (int g = 0; g < fdsk_batch::kClasses && e == hipSuccess; ++g)
+    if (b->lane[g]) e = hipStreamSynchronize(b->lane[g]);
+  if (e != hipSuccess) return berr(b, FDSK_EDEVICE, "batch profile: %s", hipGetErrorString(e));
+  std::memset(out, 0, sizeof *out);
+  for (auto& mk : b->marks) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, mk.a, mk.b) == hipSuccess) {
+      out->ms[mk.stage] += ms;
+      out->launches[mk.stage] += 1;
+      out->work[mk.stage] += mk.work;
+    }
+  }
+  return 0;
+}
+
 void sketch_batch_destroy(fdsk_batch* b) {
   if (!b) return;
   (void)hipStreamSynchronize(b->stream);
+  drop_graph(b);
   for (int g = 0; g < fdsk_batch::kClasses; ++g) {
     if (b->lane[g]) {
       (void)hipStreamSynchronize(b->lane[g]);
@@ -517,7 +807,15 @@ void sketch_batch_destroy(fdsk_batch* b) {
     }
     if (b->ev_out[g]) (void)hipEventDestroy(b->ev_out[g]);
     if (b->d_tasks_c[g]) (void)hipFree(b->d_tasks_c[g]);
+    if (b->gc.d_tasks[g]) (void)hipFree(b->gc.d_tasks[g]);
   }
+  for (auto& mk : b->marks) {
+    b->ev_pool.push_back(mk.a);
+    b->ev_pool.push_back(mk.b);
+  }
+  std::sort(b->ev_pool.begin(), b->ev_pool.end());
+  b->ev_pool.erase(std::unique(b->ev_pool.begin(), b->ev_pool.end()), b->ev_pool.end());
+  for (auto e : b->ev_pool) (void)hipEventDestroy(e);
   if (b->ev_in) (void)hipEventDestroy(b->ev_in);
   if (b->d_tasks) (void)hipFree(b->d_tasks);
   if (b->arena) (void)hipFree(b->arena);

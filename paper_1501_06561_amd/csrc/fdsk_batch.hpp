@@ -60,11 +60,17 @@ hipError_t launch_group_gram_lowp(const GroupSketch* sk, const GroupRR* t, int n
                                   bool one, bool three, hipStream_t s);
 hipError_t launch_group_rebuild_lowp(const GroupSketch* sk, const GroupRR* t, int nt, int max_ldc,
                                      int max_keep, bool one, bool three, hipStream_t s);
-hipError_t launch_group_eig(const GroupSketch* sk, const GroupRR* t, int nt, int max_m, hipStream_t s);
-// Shrink for every task; the FP64 rebuild only for tasks with npass 0 (when
-// fp64 is set).
-hipError_t launch_group_shrink_rebuild(const GroupSketch* sk, const GroupRR* t, int nt, int max_ldc,
-                                       int max_keep, bool fp64, hipStream_t s);
+// The eigensolve of the tridiagonal route in its three stages (the head of
+// the reduction only for buffers above the register capacity).
+hipError_t launch_group_tridiag_head(const GroupSketch* sk, const GroupRR* t, int nt, int max_m,
+                                     hipStream_t s);
+hipError_t launch_group_tridiag(const GroupSketch* sk, const GroupRR* t, int nt, int max_m, hipStream_t s);
+hipError_t launch_group_dc(const GroupSketch* sk, const GroupRR* t, int nt, hipStream_t s);
+hipError_t launch_group_backtr(const GroupSketch* sk, const GroupRR* t, int nt, int max_m, hipStream_t s);
+hipError_t launch_group_shrink(const GroupSketch* sk, const GroupRR* t, int nt, hipStream_t s);
+// The FP64 rebuild for tasks with npass 0.
+hipError_t launch_group_rebuild(const GroupSketch* sk, const GroupRR* t, int nt, int max_ldc, int max_keep,
+                                hipStream_t s);
 hipError_t launch_group_zero(const GroupSketch* sk, const GroupSpan* t, int nt, hipStream_t s);
 hipError_t launch_group_pending(const GroupSketch* sk, const GroupSpan* t, int nt, hipStream_t s);
 

@@ -53,7 +53,7 @@ struct fdsk_sketch {
   // Stage profiling (FDSK_FLAG_PROFILE): event pairs recorded on the stream.
   bool profile = false;
   std::vector<hipEvent_t> ev_pool;
-  struct Mark { int stage; hipEvent_t a, b; };
+  struct Mark { int stage; hipEvent_t a, b; double work; };
   std::vector<Mark> marks;
 };
 
@@ -132,8 +132,18 @@ hipEvent_t mark(fdsk_sketch* s) {
   return e;
 }
 
-void add_mark(fdsk_sketch* s, int stage, hipEvent_t a, hipEvent_t b) {
-  if (a && b) s->marks.push_back({stage, a, b});
+void add_mark(fdsk_sketch* s, int stage, hipEvent_t a, hipEvent_t b, double work) {
+  if (a && b) s->marks.push_back({stage, a, b, work});
+}
+
+// Algorithmic work of the stages of one ReduceRank on m buffer rows (the
+// figures sketch_profile reports, see the header).
+double passes(const fdsk_sketch* s) { return s->cfg.precision == FDSK_P_FP64 ? 1.0 : 3.0; }
+double work_gram(const fdsk_sketch* s) { return passes(s) * s->m * (s->m + 1.0) * s->d; }
+double work_tridiag(const fdsk_sketch* s) { return 4.0 / 3.0 * s->m * s->m * (double)s->m; }
+double work_dc(const fdsk_sketch* s) { return 4.0 / 3.0 * s->m * s->m * (double)s->m; }
+double work_backtr(const fdsk_sketch* s) {
+  return 2.0 * s->m * s->m * (double)std::min(s->m, s->l);
 }
 
 // Gram and eigensolve of the current buffer: lam and V on the device.
@@ -158,15 +168,15 @@ int spectrum(fdsk_sketch* s) {
     hipEvent_t t2 = mark(s);
     HIPCHK(s, launch_backtr(s->m, s->mp, s->V, wk, s->stream));
     hipEvent_t t3 = mark(s);
-    add_mark(s, FDSK_STAGE_TRIDIAG, e1, t1);
-    add_mark(s, FDSK_STAGE_DC, t1, t2);
-    add_mark(s, FDSK_STAGE_BACKTR, t2, t3);
+    add_mark(s, FDSK_STAGE_TRIDIAG, e1, t1, work_tridiag(s));
+    add_mark(s, FDSK_STAGE_DC, t1, t2, work_dc(s));
+    add_mark(s, FDSK_STAGE_BACKTR, t2, t3, work_backtr(s));
   } else {
     HIPCHK(s, launch_eig(s->G, s->m, s->mp, s->lam, s->V, wk, s->stream));
   }
   hipEvent_t e2 = mark(s);
-  add_mark(s, 1, e0, e1);
-  add_mark(s, 2, e1, e2);
+  add_mark(s, FDSK_STAGE_GRAM, e0, e1, work_gram(s));
+  add_mark(s, FDSK_STAGE_EIG, e1, e2, work_tridiag(s) + work_dc(s) + work_backtr(s));
   return 0;
 }
 
@@ -187,8 +197,8 @@ int shrink_rebuild(fdsk_sketch* s, const RuleParams& rp, int new0, int new1, con
     if (s->cfg.precision == FDSK_P_FP8X3) HIPCHK(s, launch_split_bf16(src, s->ldc, s->mp, s->bfw, s->stream));
     HIPCHK(s, launch_rebuild_lowp(s->Ut, src, s->ldc, s->mp, rp.keep, dst, npass, s->bfw, s->stream));
   }
-  add_mark(s, 3, e2, e3);
-  add_mark(s, 4, e3, mark(s));
+  add_mark(s, FDSK_STAGE_SHRINK, e2, e3, 0.0);
+  add_mark(s, FDSK_STAGE_REBUILD, e3, mark(s), passes(s) * 2.0 * rp.keep * s->m * (double)s->d);
   return 0;
 }
 
@@ -217,7 +227,7 @@ int ingest_device(fdsk_sketch* s, const char* src, int64_t n, int64_t stride, fd
     HIPCHK(s, launch_ingest(src + i * stride * es, static_cast<int>(dt), stride, f, s->d,
                             s->C[s->cur], s->ldc, s->occ, s->rownorm, s->stream));
     if (!count) HIPCHK(s, launch_zero_rows(s->rownorm, 1, s->occ, s->occ + f, s->stream));
-    add_mark(s, 0, a, mark(s));
+    add_mark(s, FDSK_STAGE_INGEST, a, mark(s), static_cast<double>(f) * s->d * (es + 8.0));
     s->occ += f;
     i += f;
     if (count) s->n_rows += f;
@@ -542,6 +552,7 @@ int sketch_profile(fdsk_sketch* s, fdsk_profile* out) {
     if (hipEventElapsedTime(&ms, mk.a, mk.b) == hipSuccess) {
       out->ms[mk.stage] += ms;
       out->launches[mk.stage] += 1;
+      out->work[mk.stage] += mk.work;
     }
   }
   // Events are shared between neighbouring marks; return each once.

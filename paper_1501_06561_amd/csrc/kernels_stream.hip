@@ -542,12 +542,15 @@ hipError_t launch_group_gram(const GroupSketch* sk, const GroupRR* t, int nt, in
   return hipGetLastError();
 }
 
-hipError_t launch_group_shrink_rebuild(const GroupSketch* sk, const GroupRR* t, int nt, int max_ldc,
-                                       int max_keep, bool fp64, hipStream_t s) {
+hipError_t launch_group_shrink(const GroupSketch* sk, const GroupRR* t, int nt, hipStream_t s) {
   if (nt <= 0) return hipSuccess;
   hipLaunchKernelGGL(kg_shrink, dim3(nt), dim3(1024), 0, s, sk, t);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess || max_keep <= 0 || !fp64) return e;
+  return hipGetLastError();
+}
+
+hipError_t launch_group_rebuild(const GroupSketch* sk, const GroupRR* t, int nt, int max_ldc, int max_keep,
+                                hipStream_t s) {
+  if (nt <= 0 || max_keep <= 0) return hipSuccess;
   hipLaunchKernelGGL(kg_rebuild, dim3(max_ldc / 64, (max_keep + 31) / 32, nt), dim3(256), 0, s, sk, t);
   return hipGetLastError();
 }

@@ -1303,6 +1303,8 @@ hipError_t launch_tridiag(const double* G, int m, int mp, EigWork wk, hipStream_
     hipLaunchKernelGGL((k_tridiag_reg<2, 4>), dim3(1), dim3(RNT), 0, s, G, m, mp, wk.W, 0);
   else if (m <= 128)
     hipLaunchKernelGGL((k_tridiag_reg<4, 8>), dim3(1), dim3(RNT), 0, s, G, m, mp, wk.W, 0);
+  else if (m <= 192)
+    hipLaunchKernelGGL((k_tridiag_reg<6, 12>), dim3(1), dim3(RNT), 0, s, G, m, mp, wk.W, 0);
   else if (m <= kTridRegMax)
     hipLaunchKernelGGL((k_tridiag_reg<7, 13>), dim3(1), dim3(RNT), 0, s, G, m, mp, wk.W, 0);
   else {
@@ -1352,18 +1354,21 @@ hipError_t launch_eig_trid(const double* G, int m, int mp, double* lam, double* 
 }
 
 // ------------------------------------------------------ grouped (batches)
-// Every size class in one launch, so that a round's reductions of different
-// sizes share the machine instead of running one class after another.
-// Buffers above the register capacity continue the packed-triangle head.
+// One launch per stage over the tasks of a round.  The host groups sketches
+// into classes of buffer rows (<= 64, <= 128, <= 208, <= 256) and launches
+// each class on its own, so every launch below is instantiated for its
+// class: the small classes do not carry the register footprint of the large
+// ones.  Buffers above the register capacity continue the packed-triangle
+// head.
+template <int RP, int CP>
 __global__ __launch_bounds__(RNT) void kg_tridiag_reg(const GroupSketch* __restrict__ SK,
                                                       const GroupRR* __restrict__ T) {
   const GroupSketch& s = SK[T[blockIdx.x].sk];
-  if (s.m <= 64)
-    tridiag_reg_body<2, 4>(s.G, s.m, s.mp, s.W, 0);
-  else if (s.m <= 128)
-    tridiag_reg_body<4, 8>(s.G, s.m, s.mp, s.W, 0);
-  else
-    tridiag_reg_body<7, 13>(s.G, s.m, s.mp, s.W, max(0, s.m - kTridRegMax));
+  const int h = max(0, s.m - kTridRegMax), n = s.m - h;
+  // The host launches each class with the instance that holds its largest
+  // block, so this never skips a task; it keeps the register indexing in range.
+  if (n > 32 * RP || n > 16 * CP) return;
+  tridiag_reg_body<RP, CP>(s.G, s.m, s.mp, s.W, h);
 }
 
 // The head of the reduction of buffers above the register capacity.
@@ -1403,22 +1408,36 @@ hipError_t launch_group_backtr(const GroupSketch* sk, const GroupRR* t, int nt, 
   return hipGetLastError();
 }
 
-hipError_t launch_group_eig(const GroupSketch* sk, const GroupRR* t, int nt, int max_m, hipStream_t s) {
+hipError_t launch_group_tridiag_head(const GroupSketch* sk, const GroupRR* t, int nt, int max_m,
+                                     hipStream_t s) {
+  if (nt <= 0 || max_m <= kTridRegMax) return hipSuccess;
+  if (max_m > kBatchMax) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(kg_tridiag, dim3(nt), dim3(HNT), 0, s, sk, t);
+  return hipGetLastError();
+}
+
+hipError_t launch_group_tridiag(const GroupSketch* sk, const GroupRR* t, int nt, int max_m, hipStream_t s) {
   if (nt <= 0) return hipSuccess;
   if (max_m > kBatchMax) return hipErrorInvalidValue;
-  hipError_t e = hipSuccess;
-  if (max_m > kTridRegMax) {
-    hipLaunchKernelGGL(kg_tridiag, dim3(nt), dim3(HNT), 0, s, sk, t);
-    e = hipGetLastError();
-  }
-  if (e == hipSuccess) {
-    hipLaunchKernelGGL(kg_tridiag_reg, dim3(nt), dim3(RNT), 0, s, sk, t);
-    e = hipGetLastError();
-  }
-  if (e != hipSuccess) return e;
+  if (max_m <= 64)
+    hipLaunchKernelGGL((kg_tridiag_reg<2, 4>), dim3(nt), dim3(RNT), 0, s, sk, t);
+  else if (max_m <= 128)
+    hipLaunchKernelGGL((kg_tridiag_reg<4, 8>), dim3(nt), dim3(RNT), 0, s, sk, t);
+  else
+    hipLaunchKernelGGL((kg_tridiag_reg<7, 13>), dim3(nt), dim3(RNT), 0, s, sk, t);
+  return hipGetLastError();
+}
+
+hipError_t launch_group_dc(const GroupSketch* sk, const GroupRR* t, int nt, hipStream_t s) {
+  if (nt <= 0) return hipSuccess;
   hipLaunchKernelGGL(kg_dc, dim3(nt), dim3(TNT), 0, s, sk, t);
-  e = hipGetLastError();
-  if (e == hipSuccess) e = launch_group_backtr<1, false, 1, 64>(sk, t, nt, max_m, s);
+  return hipGetLastError();
+}
+
+hipError_t launch_group_backtr(const GroupSketch* sk, const GroupRR* t, int nt, int max_m, hipStream_t s) {
+  if (nt <= 0) return hipSuccess;
+  if (max_m > kBatchMax) return hipErrorInvalidValue;
+  hipError_t e = launch_group_backtr<1, false, 1, 64>(sk, t, nt, max_m, s);
   if (e == hipSuccess) e = launch_group_backtr<2, false, 65, 128>(sk, t, nt, max_m, s);
   if (e == hipSuccess) e = launch_group_backtr<4, false, 129, kTridMax>(sk, t, nt, max_m, s);
   if (e == hipSuccess) e = launch_group_backtr<4, true, kTridMax + 1, kBatchMax>(sk, t, nt, max_m, s);

@@ -7,8 +7,10 @@ has no fallback.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes
 import os
+import weakref
 
 import numpy as np
 
@@ -27,7 +29,8 @@ EXPORTS = ("sketch_create", "sketch_append_rows", "sketch_merge", "sketch_finali
            "fdsk_evaluate", "sketch_stats", "sketch_destroy", "sketch_last_error", "fdsk_version",
            "fdsk_gram", "fdsk_eigh", "sketch_reset", "sketch_profile", "sketch_batch_create",
            "sketch_batch_append", "sketch_batch_finalize", "sketch_batch_stats",
-           "sketch_batch_destroy", "sketch_batch_last_error")
+           "sketch_batch_reset", "sketch_batch_profile", "sketch_batch_destroy",
+           "sketch_batch_last_error")
 
 
 class FdskConfig(ctypes.Structure):
@@ -50,14 +53,21 @@ class FdskReport(ctypes.Structure):
         return {name: getattr(self, name) for name, _ in self._fields_ if name != "reserved"}
 
 
-STAGES = ("ingest", "gram", "eig", "shrink", "rebuild", "tridiag", "dc", "backtr")
+STAGES = ("ingest", "gram", "eig", "shrink", "rebuild", "tridiag", "dc", "backtr", "tridiag_head")
 FLAG_PROFILE = 1
 FLAG_EIG_JACOBI = 2
+FLAG_GRAPH = 4
 EIG_METHODS = {"auto": 0, "jacobi": 1}
 
 
 class FdskProfile(ctypes.Structure):
-    _fields_ = [("ms", ctypes.c_double * 8), ("launches", ctypes.c_int64 * 8)]
+    _fields_ = [("ms", ctypes.c_double * 9), ("launches", ctypes.c_int64 * 9),
+                ("work", ctypes.c_double * 9)]
+
+    def as_dict(self):
+        """{stage: (total_ms, launches, algorithmic work)}; work is bytes for
+        ingest and flops for the other stages."""
+        return {name: (self.ms[i], self.launches[i], self.work[i]) for i, name in enumerate(STAGES)}
 
 
 class FdskError(RuntimeError):
@@ -67,6 +77,19 @@ class FdskError(RuntimeError):
 
 
 _lib = None
+# Library objects still open.  They are closed at interpreter exit, before the
+# HIP runtime and any profiler attached to the process shut down, instead of
+# whenever the garbage collector reaches them during teardown.
+_live = weakref.WeakSet()
+
+
+@atexit.register
+def _close_all():
+    for obj in list(_live):
+        try:
+            obj.close()
+        except Exception:
+            pass
 
 
 def _init_device_runtime():
@@ -111,6 +134,8 @@ def lib():
     L.sketch_batch_finalize.argtypes = [vp, ctypes.POINTER(vp), ctypes.POINTER(i64), cint, cint,
                                         i32, ctypes.POINTER(i32)]
     L.sketch_batch_stats.argtypes = [vp, i32, ctypes.POINTER(FdskReport)]
+    L.sketch_batch_reset.argtypes = [vp]
+    L.sketch_batch_profile.argtypes = [vp, ctypes.POINTER(FdskProfile)]
     L.sketch_batch_destroy.argtypes = [vp]
     L.sketch_batch_destroy.restype = None
     L.sketch_batch_last_error.argtypes = [vp]
@@ -120,7 +145,8 @@ def lib():
     for f in ("sketch_create", "sketch_append_rows", "sketch_merge", "sketch_finalize", "sketch_error",
               "fdsk_evaluate", "sketch_stats", "fdsk_gram", "fdsk_eigh", "sketch_reset",
               "sketch_profile", "sketch_batch_create", "sketch_batch_append",
-              "sketch_batch_finalize", "sketch_batch_stats"):
+              "sketch_batch_finalize", "sketch_batch_stats", "sketch_batch_reset",
+              "sketch_batch_profile"):
         getattr(L, f).restype = cint
     _lib = L
     return L
@@ -207,6 +233,7 @@ class FDSketch:
         h = ctypes.c_void_p()
         _check(lib().sketch_create(ctypes.byref(cfg), _stream_handle(self._stream), ctypes.byref(h)))
         self._h = h
+        _live.add(self)
 
     def _on_stream(self, t):
         """A device tensor made on the current stream and read by the library
@@ -243,10 +270,10 @@ class FDSketch:
         return self
 
     def profile(self):
-        """{stage: (total_ms, launches)} since create/reset (needs profile=True)."""
+        """{stage: (total_ms, launches, work)} since create/reset (needs profile=True)."""
         p = FdskProfile()
         _check(lib().sketch_profile(self._h, ctypes.byref(p)), self._h)
-        return {name: (p.ms[i], p.launches[i]) for i, name in enumerate(STAGES)}
+        return p.as_dict()
 
     def stats(self):
         rep = FdskReport()
@@ -324,49 +351,52 @@ def _check_batch(rc, handle=None):
 class FDSketchBatch:
     """Many independent sketches advanced together in lock-step rounds: one schedule per
     class of buffer rows, each class on its own library stream ordered after the batch's
-    stream, and one launch per stage and round over the class's active sketches."""
+    stream, and one launch per stage and round over the class's active sketches.  With
+    graph=True (and profile=False) each append call runs through HIP graphs captured per
+    size class (replayed when the next call has the same schedule, e.g. after reset())."""
 
-    def __init__(self, configs, stream=None):
+    def __init__(self, configs, stream=None, profile=False, graph=False):
         """configs: list of dicts with keys d, l and optionally variant, alpha, buffer_rows,
-        precision ("fp64", "bf16", "bf16x3")."""
+        precision ("fp64", "bf16x3")."""
         self.S = len(configs)
+        flags = (FLAG_PROFILE if profile else 0) | (FLAG_GRAPH if graph else 0)
         arr = (FdskConfig * self.S)()
         self.shapes = []
         for i, c in enumerate(configs):
             arr[i] = FdskConfig(int(c["d"]), int(c["l"]), int(c.get("buffer_rows", 0)),
                                 VARIANTS[c.get("variant", "fd")], float(c.get("alpha", 0.2)),
-                                PRECISIONS[c.get("precision", "fp64")], 0)
+                                PRECISIONS[c.get("precision", "fp64")], flags)
             self.shapes.append((int(c["l"]), int(c["d"])))
         self._stream = _bound_stream(stream)
         h = ctypes.c_void_p()
         _check_batch(lib().sketch_batch_create(self.S, arr, _stream_handle(self._stream), ctypes.byref(h)))
         self._h = h
+        _live.add(self)
 
     def append(self, rows_list, grid_size=0):
-        """rows_list[i]: 2-D cuda tensor for sketch i (or None for no rows)."""
-        torch = _torch()
+        """rows_list[i]: 2-D matrix for sketch i (or None for no rows): all cuda
+        tensors, or all host arrays / CPU tensors."""
         ptrs = (ctypes.c_void_p * self.S)()
         ns = (ctypes.c_int64 * self.S)()
         strides = (ctypes.c_int64 * self.S)()
-        dt = None
+        dt, mem = None, None
         keep = []
         for i, t in enumerate(rows_list):
             if t is None or t.shape[0] == 0:
                 ptrs[i], ns[i], strides[i] = None, 0, self.shapes[i][1]
                 continue
-            if t.stride(1) != 1:
-                t = t.contiguous()
-            keep.append(t)
-            code = _dtype_code(t)
+            ptr, n, stride, code, m, kept = _rows_arg(t)
+            keep.append(kept)
             if dt is None:
-                dt = code
-            elif dt != code:
-                raise ValueError("all sketches of one append call share a dtype")
-            ptrs[i], ns[i], strides[i] = t.data_ptr(), t.shape[0], t.stride(0)
+                dt, mem = code, m
+            elif dt != code or mem != m:
+                raise ValueError("all sketches of one append call share a dtype and a memory kind")
+            ptrs[i], ns[i], strides[i] = ptr, n, stride
         # Inputs made on the current stream, read on the batch's stream.
         _order_after_current(self._stream, *keep)
         _check_batch(lib().sketch_batch_append(self._h, ptrs, ns, strides, F64 if dt is None else dt,
-                                               MEM_DEVICE, int(grid_size)), self._h)
+                                               MEM_DEVICE if mem is None else mem, int(grid_size)),
+                     self._h)
         return self
 
     def finalize(self, dtype=None, grid_size=0):
@@ -380,6 +410,16 @@ class FDSketchBatch:
                                                  int(grid_size), rows), self._h)
         self.rows_out = list(rows)
         return outs
+
+    def reset(self):
+        _check_batch(lib().sketch_batch_reset(self._h), self._h)
+        return self
+
+    def profile(self):
+        """{stage: (total_ms, launches, work)} since create/reset (needs profile=True)."""
+        p = FdskProfile()
+        _check_batch(lib().sketch_batch_profile(self._h, ctypes.byref(p)), self._h)
+        return p.as_dict()
 
     def stats(self, i):
         rep = FdskReport()

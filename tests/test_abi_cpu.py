@@ -62,7 +62,8 @@ def test_create_rejects_bad_config(cfg, code):
     (dict(precision=3), -6),                   # FP8 Gram: single sketches only
     (dict(precision=1), -6),                   # one BF16 pass: fdsk_gram only
     (dict(l=200), -6),                         # 400 buffer rows > 256
-    (dict(flags=1), -6),
+    (dict(flags=1), -1),                       # flags differ between the sketches
+    (dict(flags=2), -6),                       # Jacobi: single sketches only
 ])
 def test_batch_create_rejects_bad_config(cfg, code):
     good = F.FdskConfig(64, 8, 0, 0, 0.2, 0, 0)
@@ -87,6 +88,14 @@ def test_null_handles_are_rejected():
     L.sketch_destroy(None)
 
 
+def test_batch_null_handles_are_rejected():
+    L = F.lib()
+    assert L.sketch_batch_reset(None) == -1
+    assert L.sketch_batch_profile(None, ctypes.byref(F.FdskProfile())) == -1
+    L.sketch_batch_destroy(None)
+
+
 def test_struct_layouts_match_header():
+    assert ctypes.sizeof(F.FdskProfile) == 9 * 8 * 3
     assert ctypes.sizeof(F.FdskConfig) == 40
     assert ctypes.sizeof(F.FdskReport) == 9 * 8 + 2 * 8 + 4 * 4 + 8

@@ -157,3 +157,64 @@ def test_batch_reduced_precision_mixed():
         assert abs(ce - co) <= tol, (cfg, ce, co)
         assert b.stats(i)["n_reduce"] == oracle.fd_sketch(A, cfg["l"], "fd", return_state=True)[1].n_rr
     b.close()
+
+
+def test_batch_graph_capture_and_replay_match_direct_launches():
+    """With graphs on, each append of a batch runs through HIP graphs captured
+    per size class; after a reset an append with the same schedule replays
+    them.  The sketches of
+    the first (captured) call and of three replays, with eager GPU work and
+    synchronisations in between, equal those of direct launches bit for bit.
+    Buffers in all four size classes."""
+    cfgs, mats = _make_batch(3, 12, (40, 260), (6, 128), (200, 1800))
+    ref, ref_st = _run(cfgs, mats)
+    b0 = F.FDSketchBatch(cfgs, graph=False)
+    tens = [torch.from_numpy(A).cuda() for A in mats]
+    b0.append(tens)
+    direct = [o.cpu().numpy() for o in b0.finalize()]
+    b0.close()
+    b = F.FDSketchBatch(cfgs, graph=True)
+    for rep in range(4):
+        b.reset()
+        b.append(tens)
+        outs = [o.cpu().numpy() for o in b.finalize()]
+        for i, (a, o) in enumerate(zip(direct, outs)):
+            assert np.array_equal(a, o), (rep, i)
+            st = b.stats(i)
+            assert st["n_reduce"] == ref_st[i]["n_reduce"] and st["fro2_A"] == ref_st[i]["fro2_A"]
+        torch.randn(1 << 20, device="cuda").sum().item()    # eager work between replays
+    b.close()
+    for a, o in zip(ref, direct):
+        assert np.array_equal(a, o)
+
+
+def test_batch_host_rows_match_device_rows():
+    cfgs, mats = _make_batch(4, 6, (30, 150), (5, 60), (100, 900))
+    ref, _ = _run(cfgs, mats)
+    b = F.FDSketchBatch(cfgs)
+    b.append([np.ascontiguousarray(A) for A in mats])
+    outs = [o.cpu().numpy() for o in b.finalize()]
+    b.close()
+    for a, o in zip(ref, outs):
+        assert np.array_equal(a, o)
+
+
+def test_batch_profile_covers_every_stage():
+    """FDSK_FLAG_PROFILE on a batch: every stage of the rounds is timed on the
+    class streams with its algorithmic work, and the sketches are unchanged."""
+    cfgs, mats = _make_batch(5, 8, (40, 300), (10, 128), (300, 1200), variants=("fd",))
+    ref, _ = _run(cfgs, mats)
+    b = F.FDSketchBatch(cfgs, profile=True)
+    b.append([torch.from_numpy(A).cuda() for A in mats])
+    outs = [o.cpu().numpy() for o in b.finalize()]
+    prof = b.profile()
+    b.close()
+    for a, o in zip(ref, outs):
+        assert np.array_equal(a, o)
+    for stage in ("ingest", "gram", "eig", "tridiag", "dc", "backtr", "shrink", "rebuild"):
+        ms, launches, work = prof[stage]
+        assert launches > 0 and ms > 0, stage
+        if stage != "shrink":
+            assert work > 0, stage
+    if any(2 * c["l"] > 208 for c in cfgs):    # buffers above 208 rows: the packed-triangle head
+        assert prof["tridiag_head"][1] > 0

@@ -1,0 +1,236 @@
+"""Parity at the workloads' own sizes, against stored oracle results.
+
+The oracle takes minutes to hours on these streams, so its results were
+computed once on the CPU by ``tests/golden/make_golden.py`` (which calls only
+``oracle/`` and the seeded generators) and stored under ``tests/golden/``.
+Each test regenerates the same rows from the same seeds, sketches them on the
+GPU and compares what is unique about a sketch (Algorithm 1 fixes B only up to
+a left rotation): the covariance error, the squared singular values of B,
+Delta, the total shrinkage, ||A||_F^2 and the number of ReduceRank steps.
+
+Tolerances (the bars of the design notes): FP64 arithmetic, covariance error
+within 1e-6 relative of the oracle's; reduced-precision products (split-BF16,
+FP8 with split compensation), covariance error within 1e-3 of ||A||_F^2 and
+||B_gpu^T B_gpu - B_oracle^T B_oracle||_2 <= 1e-3 ||A||_F^2 where the
+oracle's B is stored.  The GPU sketch's covariance error comes from the
+oracle's own dense evaluator (A^T A formed on the host) where that is cheap
+(100,000 x 1,000), else from the device evaluator, which is pinned against
+the oracle's evaluator in test_gpu_eval.py up to 8,192 columns.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1501_06561_amd import synth
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from paper_1501_06561_amd import fdsketch as F  # noqa: E402
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def golden(name):
+    with open(os.path.join(GOLDEN, name + ".json")) as f:
+        return json.load(f)
+
+
+def gram_diff_norm(B1, B2):
+    """||B1^T B1 - B2^T B2||_2, exactly: both row spaces lie in the span of
+    the orthonormal columns Q of [B1; B2]^T, so the difference equals
+    Q (X1^T X1 - X2^T X2) Q^T with Xi = Bi Q, whose spectral norm is that of
+    the small middle matrix."""
+    B1 = np.asarray(B1, dtype=np.float64)
+    B2 = np.asarray(B2, dtype=np.float64)
+    Q, _ = np.linalg.qr(np.vstack([B1, B2]).T)
+    X1, X2 = B1 @ Q, B2 @ Q
+    w = np.linalg.eigvalsh(X1.T @ X1 - X2.T @ X2)
+    return float(max(abs(w[0]), abs(w[-1])))
+
+
+def sigma2(B, l):
+    s = np.linalg.svd(np.asarray(B, dtype=np.float64), compute_uv=False)
+    out = np.zeros(l)
+    out[:min(l, s.size)] = s[:l] ** 2
+    return out
+
+
+def check_accumulators(st, rec, fa, delta_rtol=1e-8, stot_tol=1e-9):
+    assert st["n_reduce"] == rec["n_rr"], (st["n_reduce"], rec["n_rr"])
+    assert st["n_rows"] == rec["n_rows"]
+    assert abs(st["fro2_A"] - rec["fro2A"]) <= 1e-12 * fa
+    assert abs(st["delta_sum"] - rec["Delta"]) <= delta_rtol * max(rec["Delta"], 1e-300) + 1e-12 * fa
+    assert abs(st["shrink_total"] - rec["Stot"]) <= stot_tol * fa
+    assert st["eig_unconverged"] == 0
+
+
+def sketch_whole(A_dev, d, l, variant="fd", alpha=0.2, precision="fp64"):
+    sk = F.FDSketch(d, l, variant, alpha, precision=precision)
+    sk.append(A_dev)
+    B = sk.finalize().cpu().numpy()
+    st = sk.stats()
+    sk.close()
+    return B, st
+
+
+# ---------------------------------------------------------------- 100k x 1,000
+
+@pytest.fixture(scope="module")
+def random_noisy_100k():
+    W = synth.WORKLOADS["c2_random_noisy_100k_x1000"]
+    A = synth.random_noisy(W["n"], W["d"], W["k"], W["zeta"], seed=W["seed"], dtype=np.float32)
+    A64 = A.astype(np.float64)
+    return A, torch.from_numpy(A).cuda(), oracle.gram(A64), oracle.fro2(A64)
+
+
+@pytest.mark.parametrize("l", [50, 100, 200])
+@pytest.mark.parametrize("variant", ["fd", "alpha", "fast_alpha", "isvd"])
+def test_random_noisy_100k_x1000_whole_stream(random_noisy_100k, variant, l):
+    """Every variant (Sections 2.3 and 3.1, alpha = 0.2) at every sketch size
+    of the workload, over all 100,000 fp32 rows, FP64 arithmetic."""
+    A, Ad, AtA, fa = random_noisy_100k
+    rec = golden("c2_random_noisy_100k_x1000")["cases"][f"{variant}_l{l}"]
+    B, st = sketch_whole(Ad, A.shape[1], l, variant, 0.2)
+    ce = oracle.cov_err_gram(AtA, fa, B)
+    assert abs(ce - rec["cov_err"]) <= 1e-6 * rec["cov_err"], (ce, rec["cov_err"])
+    # FD's update is a Lipschitz spectral map; the keep/shrink rules of the
+    # other variants can amplify rounding near ties, hence the wider bar.
+    s_tol = 1e-9 if variant == "fd" else 1e-7
+    assert np.max(np.abs(sigma2(B, l) - np.array(rec["sigma2"]))) <= s_tol * fa
+    check_accumulators(st, rec, fa)
+    assert abs(fa - oracle.fro2(B) - st["shrink_total"]) <= 1e-9 * fa
+
+
+@pytest.fixture(scope="module")
+def rotating_100k():
+    W = synth.WORKLOADS["c2_rotating_adversarial_100k_x1000"]
+    A = synth.rotating_adversarial(W["blocks"], W["block_rows"], W["d"], W["theta"], W["zeta"],
+                                   seed=W["seed"], dtype=np.float32)
+    A64 = A.astype(np.float64)
+    return A, torch.from_numpy(A).cuda(), oracle.gram(A64), oracle.fro2(A64)
+
+
+@pytest.mark.parametrize("l", [50, 100, 200])
+@pytest.mark.parametrize("variant", ["fd", "isvd", "alpha"])
+def test_rotating_adversarial_100k_x1000_whole_stream(rotating_100k, variant, l):
+    """The stream whose dominant direction turns by 0.05 rad every 500 rows."""
+    A, Ad, AtA, fa = rotating_100k
+    rec = golden("c2_rotating_adversarial_100k_x1000")["cases"][f"{variant}_l{l}"]
+    B, st = sketch_whole(Ad, A.shape[1], l, variant, 0.2)
+    ce = oracle.cov_err_gram(AtA, fa, B)
+    assert abs(ce - rec["cov_err"]) <= 1e-6 * rec["cov_err"], (ce, rec["cov_err"])
+    s_tol = 1e-9 if variant == "fd" else 1e-7
+    assert np.max(np.abs(sigma2(B, l) - np.array(rec["sigma2"]))) <= s_tol * fa
+    check_accumulators(st, rec, fa)
+
+
+# ------------------------------------------------------- power law, 200k x 3,072
+
+def test_power_law_200k_x3072_bf16_rows_bf16x3_whole_stream():
+    """FD l = 256 (buffer 512 rows) on all 200,000 bf16 rows, split-BF16 Gram
+    and rebuild; eigensolve, shrink and accumulators in FP64."""
+    W = synth.WORKLOADS["c3_power_law_200k_x3072"]
+    rec = golden("c3_power_law_200k_x3072")["cases"]["fd_l256"]
+    Bo = np.load(os.path.join(GOLDEN, "c3_power_law_200k_x3072_B.npy")).astype(np.float64)
+    A = synth.power_law(W["n"], W["d"], r=W["r"], exponent=W["exponent"], noise_var=W["noise_var"],
+                        seed=W["seed"], chunk=W["chunk"])
+    bits = torch.from_numpy(synth.bf16_bits(A).view(np.int16)).view(torch.bfloat16).cuda()
+    del A
+    B, st = sketch_whole(bits, W["d"], W["l"], precision="bf16x3")
+    fa = rec["fro2A"]
+    assert gram_diff_norm(B, Bo) <= 1e-3 * fa
+    ev = F.evaluate(bits, torch.from_numpy(B).cuda(), k=10, method=0)
+    assert abs(ev["cov_err"] - rec["cov_err"]) <= 1e-3, (ev["cov_err"], rec["cov_err"])
+    assert st["n_reduce"] == rec["n_rr"]
+    assert abs(st["fro2_A"] - fa) <= 1e-12 * fa
+    assert abs(st["shrink_total"] - rec["Stot"]) <= 1e-3 * fa
+    assert abs(st["delta_sum"] - rec["Delta"]) <= 1e-3 * fa
+    assert st["eig_unconverged"] == 0
+
+
+# ------------------------------------------------------------ 512 sketches
+
+@pytest.fixture(scope="module")
+def batch_512():
+    W = synth.WORKLOADS["c4_batch_512"]
+    d, l, n = synth.batch_shapes(W["S"], seed=W["seed"])
+    rows = synth.parallel_map(
+        lambda i: torch.from_numpy(synth.batch_sketch_rows(i, int(n[i]), int(d[i]), int(l[i]))).cuda(),
+        range(W["S"]), workers=16)
+    return d, l, n, rows, golden("c4_batch_512")["sketches"]
+
+
+@pytest.mark.parametrize("precision", ["fp64", "bf16x3"])
+def test_batch_512_sketches_full_size(batch_512, precision):
+    """All 512 sketches (d ~ U{64..2048}, l ~ U{16..128}, n ~ U{1000..50000})
+    advanced together, every one at its full length, against the oracle's
+    result for that sketch."""
+    d, l, n, rows, recs = batch_512
+    S = len(rows)
+    b = F.FDSketchBatch([dict(d=int(d[i]), l=int(l[i]), precision=precision) for i in range(S)])
+    b.append(rows)
+    outs = b.finalize()
+    stats = [b.stats(i) for i in range(S)]
+    b.close()
+    worst = 0.0
+    for i in range(S):
+        rec = recs[i]
+        assert (rec["d"], rec["l"], rec["n"]) == (int(d[i]), int(l[i]), int(n[i]))
+        fa = rec["fro2A"]
+        ce = F.evaluate(rows[i], outs[i], k=10, method=0)["cov_err"]
+        if precision == "fp64":
+            assert abs(ce - rec["cov_err"]) <= 1e-6 * rec["cov_err"] + 1e-12, (i, ce, rec["cov_err"])
+            B = outs[i].cpu().numpy()
+            assert np.max(np.abs(sigma2(B, rec["l"]) - np.array(rec["sigma2"]))) <= 1e-9 * fa, i
+            check_accumulators(stats[i], rec, fa)
+        else:
+            worst = max(worst, abs(ce - rec["cov_err"]))
+            assert abs(ce - rec["cov_err"]) <= 1e-3, (i, ce, rec["cov_err"])
+            assert stats[i]["n_reduce"] == rec["n_rr"]
+            assert abs(stats[i]["fro2_A"] - fa) <= 1e-12 * fa
+            assert abs(stats[i]["shrink_total"] - rec["Stot"]) <= 1e-3 * fa
+    print(f"{precision}: worst |cov-err difference| {worst:.3e}")
+
+
+# ------------------------------------------------ 1,000,000 x 8,192 in chunks
+
+def test_random_noisy_1m_x8192_alpha_l512_fp8x3_whole_stream():
+    """alpha-FD (alpha = 0.2, l = 512, buffer 1,024 rows) over the whole
+    1,000,000-row stream appended in 4,096-row chunks, FP8 Gram with split
+    compensation (rebuild split-BF16), FP64 eigensolve and accumulators.
+    The covariance error of the GPU sketch is taken by the matrix-free device
+    evaluator over the whole stream."""
+    W = synth.WORKLOADS["c5_random_noisy_1m_x8192"]
+    rec = golden("c5_random_noisy_1m_x8192")["cases"]["alpha_l512"]
+    Bo = np.load(os.path.join(GOLDEN, "c5_random_noisy_1m_x8192_B.npy")).astype(np.float64)
+    d, l = W["d"], W["l"]
+    U = synth.random_noisy_basis(d, W["k"], tuple(W["seed"]))
+    sizes = synth.chunk_sizes(W["n"], W["chunk"])
+    A = torch.empty((W["n"], d), dtype=torch.float32, device="cuda")
+    sk = F.FDSketch(d, l, "alpha", W["alpha"], precision="fp8x3")
+    r0 = 0
+    for g0 in range(0, len(sizes), 16):
+        group = list(range(g0, min(g0 + 16, len(sizes))))
+        chunks = synth.parallel_map(
+            lambda c: synth.random_noisy_chunk(U, sizes[c], W["zeta"], tuple(W["seed"]) + (c + 1,)),
+            group, workers=16)
+        for X in chunks:
+            A[r0:r0 + X.shape[0]].copy_(torch.from_numpy(X))
+            sk.append(A[r0:r0 + X.shape[0]])
+            r0 += X.shape[0]
+    B = sk.finalize().cpu().numpy()
+    st = sk.stats()
+    sk.close()
+    fa = rec["fro2A"]
+    assert gram_diff_norm(B, Bo) <= 1e-3 * fa
+    ev = F.evaluate(A, torch.from_numpy(B).cuda(), k=10, method=1)
+    assert abs(ev["cov_err"] - rec["cov_err"]) <= 1e-3, (ev["cov_err"], rec["cov_err"])
+    assert st["n_reduce"] == rec["n_rr"]
+    assert abs(st["fro2_A"] - fa) <= 1e-12 * fa
+    assert abs(st["shrink_total"] - rec["Stot"]) <= 1e-3 * fa
+    assert abs(st["delta_sum"] - rec["Delta"]) <= 1e-3 * fa
+    assert st["eig_unconverged"] == 0
