@@ -100,9 +100,11 @@ enum { EIG_AUTO = 0, EIG_JACOBI = 1 };
 constexpr int kMaxSweeps = 40;
 constexpr int kLdsEigMax = 100;   // single-workgroup solver limit (G and V in LDS)
 constexpr int kTridMax = 200;     // back-transformation with the reflectors staged in LDS
-constexpr int kTridGlobalMax = 512;  // tridiagonal route (packed triangle in the workspace above 208)
+constexpr int kTridGlobalMax = 1024; // tridiagonal route (packed triangle above 208 rows, the full
+                                     // matrix in the S1 workspace above kTridLargeMin)
+constexpr int kTridLargeMin = 256;   // orders above this reduce one column per two launches
 constexpr int kBatchMax = 256;    // buffer rows of a batched sketch
-constexpr int kDcMax = 512;       // divide and conquer: O(n) state in LDS
+constexpr int kDcMax = 1024;      // divide and conquer: O(n) state in LDS
 // Eigen-decomposition of the symmetric m x m G (leading dimension mp): lam
 // (m values, any order) and V (column j = eigenvector of lam[j], leading
 // dimension mp).  m <= kTridGlobalMax goes through the tridiagonal route unless

@@ -620,30 +620,31 @@ __global__ __launch_bounds__(RNT) void k_tridiag_reg(const double* __restrict__ 
 // ------------------------------------------------------ divide and conquer
 namespace {
 
+template <int NMAX>
 struct DcSmem {
-  double D[kDcMax];      // eigenvalues per position of the current blocks
-  double Ds[kDcMax];     // sorted d (deflation rotations applied), then the roots
-  double Zs[kDcMax];     // sorted z
-  double dh[kDcMax];     // compact non-deflated d
-  double zh[kDcMax];     // compact non-deflated z
-  double zg[kDcMax];     // z recomputed from the roots
-  double ddf[kDcMax];    // compact deflated eigenvalues
-  double rc[kDcMax];     // deflation rotations of a merge, in scan order
-  double rs[kDcMax];
-  double tau[kDcMax];    // root offsets from their poles
-  short rp[kDcMax];      // rotation operands (sorted positions)
-  short rj[kDcMax];
-  short perm[kDcMax];    // sorted position -> local column
-  short dest[kDcMax];    // sorted position -> compact column
-  short org[kDcMax];     // root -> compact index of its pole
-  short src[kDcMax];     // compact column -> local column of the level's input
-  int kk[kDcMax / 2];    // non-deflated count per merge
-  int nrot[kDcMax / 2];  // deflation rotations per merge
-  int tile0[kDcMax / 2 + 1];
-  int rot_any[kDcMax / 2];  // the merge needs the sequential deflation scan
-  char zdef[kDcMax];        // 1 z-deflated, 2 rotation candidate, 0 otherwise
-  double rv[kDcMax];        // last merge: final eigenvalue of each column (ranking)
-  char want[kDcMax];        // last merge: the column's eigenvector is wanted
+  double D[NMAX];      // eigenvalues per position of the current blocks
+  double Ds[NMAX];     // sorted d (deflation rotations applied), then the roots
+  double Zs[NMAX];     // sorted z
+  double dh[NMAX];     // compact non-deflated d
+  double zh[NMAX];     // compact non-deflated z
+  double zg[NMAX];     // z recomputed from the roots
+  double ddf[NMAX];    // compact deflated eigenvalues
+  double rc[NMAX];     // deflation rotations of a merge, in scan order
+  double rs[NMAX];
+  double tau[NMAX];    // root offsets from their poles
+  short rp[NMAX];      // rotation operands (sorted positions)
+  short rj[NMAX];
+  short perm[NMAX];    // sorted position -> local column
+  short dest[NMAX];    // sorted position -> compact column
+  short org[NMAX];     // root -> compact index of its pole
+  short src[NMAX];     // compact column -> local column of the level's input
+  int kk[NMAX / 2];    // non-deflated count per merge
+  int nrot[NMAX / 2];  // deflation rotations per merge
+  int tile0[NMAX / 2 + 1];
+  int rot_any[NMAX / 2];  // the merge needs the sequential deflation scan
+  char zdef[NMAX];        // 1 z-deflated, 2 rotation candidate, 0 otherwise
+  double rv[NMAX];        // last merge: final eigenvalue of each column (ranking)
+  char want[NMAX];        // last merge: the column's eigenvector is wanted
   int clo;                  // last merge: first wanted non-deflated column
   int cfirst;               // last merge: first column tile of its products
 };
@@ -779,10 +780,11 @@ __device__ int secular_root(const double* dd, const double* zz, int kk, int i, d
 // non-deflated roots (they are a suffix: the roots ascend), and the wanted
 // columns are flagged (1.0 / 0.0) at W[P + 3n + 1 + j] for the
 // back-transformation.  Other columns of Z are left undefined.
+template <int NMAX>
 __device__ __forceinline__ void dc_body(double* __restrict__ W, int n, double* __restrict__ Z, int ldz,
                                         double* __restrict__ Qc, double* __restrict__ U,
                                         double* __restrict__ lam, DevStats* __restrict__ st, int nvec) {
-  __shared__ DcSmem S;
+  __shared__ DcSmem<NMAX> S;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int P = n * (n + 1) / 2;
   const double* dG = W + P + n;
@@ -1195,10 +1197,11 @@ __device__ __forceinline__ void dc_body(double* __restrict__ W, int n, double* _
   if (tid == 0 && st) atomicAdd(&st->eig_sweeps, 1ull);
 }
 
+template <int NMAX>
 __global__ __launch_bounds__(TNT) void k_dc(double* __restrict__ W, int n, double* __restrict__ Z, int ldz,
                                             double* __restrict__ Qc, double* __restrict__ U,
                                             double* __restrict__ lam, DevStats* __restrict__ st, int nvec) {
-  dc_body(W, n, Z, ldz, Qc, U, lam, st, nvec);
+  dc_body<NMAX>(W, n, Z, ldz, Qc, U, lam, st, nvec);
 }
 
 // ---------------------------------------------------------- back-transform
@@ -1297,6 +1300,197 @@ __global__ __launch_bounds__(BNT) void k_backtr(const double* __restrict__ W, in
   backtr_body<NPL, GA>(W, n, Z, ldz, blockIdx.x);
 }
 
+// ------------------------------------------- reduce, large orders (> 512)
+// The same Householder reduction for buffers too large for one CU's
+// registers: the full symmetric matrix (scaled by 2^-s) lives in the S1
+// workspace (row-major, leading dimension mp) and every column takes two
+// ordinary launches over blocks of LRB rows; the kernel boundaries are the
+// only synchronisation.  Block b always owns rows [LRB b, LRB b + LRB), so
+// the same rows stay on the same XCD (and in its L2) from column to column.
+//  * k_ltr_reflect: every block forms the reflector of column k from row k
+//    (the column by symmetry) in the same order, so all hold bitwise-equal
+//    tau and v; the block owning row k+1 writes the packed reflector, tau,
+//    d_k and e_k (the layout of the other reductions) and v; each block then
+//    forms p_i = tau (A v)_i for its rows and its rows' share of p.v.
+//  * k_ltr_update: c = (tau/2) p.v from the shares (added in block order),
+//    w = p - c v, and A -= v w^T + w v^T on the block's rows of the trailing
+//    block.
+// Scratch: v, p and the shares in S2.
+constexpr int LRB = 8;          // rows per block
+constexpr int LNT = 256;        // threads per block
+
+// Deterministic block sum (fixed order), returned to every thread.
+__device__ __forceinline__ double ltr_block_sum(double v, double* red) {
+  v = wave_sum(v);
+  const int w = threadIdx.x >> 6;
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) red[w] = v;
+  __syncthreads();
+  double t = 0.0;
+#pragma unroll
+  for (int q = 0; q < LNT / 64; ++q) t += red[q];
+  return t;
+}
+
+__global__ __launch_bounds__(1024) void k_ltr_scale(const double* __restrict__ G, int n, int ldg,
+                                                    double* __restrict__ W) {
+  __shared__ double red[16];
+  double amax = 0.0;
+  for (int i = threadIdx.x >> 6; i < n; i += 16)
+    for (int j = threadIdx.x & 63; j <= i; j += 64) amax = fmax(amax, fabs(G[static_cast<int64_t>(i) * ldg + j]));
+  amax = wave_max(amax);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = amax;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double g = 0.0;
+    for (int q = 0; q < 16; ++q) g = fmax(g, red[q]);
+    const int sexp = (g > 0.0 && g < INFINITY) ? ilogb(g) : 0;
+    W[n * (n + 1) / 2 + 3 * n] = ldexp(1.0, sexp);
+  }
+}
+
+// A (row-major, lda) = the symmetric matrix whose lower triangle is G's,
+// times 2^-s; one block per row.
+__global__ __launch_bounds__(LNT) void k_ltr_load(const double* __restrict__ G, int n, int ldg,
+                                                  const double* __restrict__ W, double* __restrict__ A, int lda) {
+  const int i = blockIdx.x;
+  const double sc = 1.0 / W[n * (n + 1) / 2 + 3 * n];   // an exact power of two
+  for (int j = threadIdx.x; j < n; j += LNT) {
+    const double g = (j <= i) ? G[static_cast<int64_t>(i) * ldg + j] : G[static_cast<int64_t>(j) * ldg + i];
+    A[static_cast<int64_t>(i) * lda + j] = g * sc;
+  }
+}
+
+__global__ __launch_bounds__(LNT) void k_ltr_reflect(double* __restrict__ A, int lda, int n, int k,
+                                                     double* __restrict__ W, double* __restrict__ S2) {
+  __shared__ double vs[kTridGlobalMax];
+  __shared__ double red[LNT / 64];
+  __shared__ double prow[LRB][LNT / LRB];
+  const int r0 = blockIdx.x * LRB;
+  if (r0 + LRB <= k + 1) return;                 // every row of the block is finished
+  const int tid = threadIdx.x, k1 = k + 1;
+  const int P = n * (n + 1) / 2;
+  const double* rk = A + static_cast<int64_t>(k) * lda;
+  double s2 = 0.0;
+  for (int j = k + 2 + tid; j < n; j += LNT) s2 = fma(rk[j], rk[j], s2);
+  s2 = ltr_block_sum(s2, red);
+  const double alpha = rk[k1];
+  double tau = 0.0, beta = alpha, scale = 0.0;
+  if (s2 > 0.0) {
+    const double mu = sqrt(alpha * alpha + s2);
+    beta = (alpha >= 0.0) ? -mu : mu;
+    tau = (beta - alpha) / beta;
+    scale = 1.0 / (alpha - beta);
+  }
+  for (int j = k1 + tid; j < n; j += LNT) vs[j] = (j == k1) ? 1.0 : rk[j] * scale;
+  __syncthreads();
+  double* vg = S2;                // v
+  double* pg = S2 + lda;          // p
+  double* sh = S2 + 2 * lda;      // shares of p.v, one per block
+  if (blockIdx.x == k1 / LRB) {
+    const int ck = colstart(k, n);
+    for (int j = k1 + tid; j < n; j += LNT) {
+      vg[j] = vs[j];
+      if (j >= k + 2) W[ck + j - k] = vs[j];
+    }
+    if (tid == 0) {
+      const double dk = rk[k];
+      W[ck] = dk;
+      W[ck + 1] = 1.0;
+      W[P + k] = tau;
+      W[P + n + k] = dk;
+      W[P + 2 * n + k] = beta;
+    }
+  }
+  // p_i for the block's rows: LNT/LRB threads per row, then a fixed-order
+  // sum of their partials.
+  const int r = tid / (LNT / LRB), q = tid % (LNT / LRB);
+  const int i = r0 + r;
+  double acc = 0.0;
+  if (i > k && i < n) {
+    const double* ai = A + static_cast<int64_t>(i) * lda;
+    for (int j = k1 + q; j < n; j += LNT / LRB) acc = fma(ai[j], vs[j], acc);
+  }
+  prow[r][q] = acc;
+  __syncthreads();
+  if (tid < LRB) {
+    const int ir = r0 + tid;
+    double y = 0.0;
+    for (int t = 0; t < LNT / LRB; ++t) y += prow[tid][t];
+    const double p = (ir > k && ir < n) ? tau * y : 0.0;
+    if (ir < n) pg[ir] = p;
+    prow[tid][0] = (ir > k && ir < n) ? p * vs[ir] : 0.0;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    double d = 0.0;
+    for (int t = 0; t < LRB; ++t) d += prow[t][0];
+    sh[blockIdx.x] = d;
+  }
+}
+
+__global__ __launch_bounds__(LNT) void k_ltr_update(double* __restrict__ A, int lda, int n, int k,
+                                                    const double* __restrict__ W, const double* __restrict__ S2) {
+  __shared__ double ws[kTridGlobalMax];
+  __shared__ double vsh[kTridGlobalMax];
+  const int r0 = blockIdx.x * LRB;
+  if (r0 + LRB <= k + 1) return;
+  const int tid = threadIdx.x, k1 = k + 1;
+  const int P = n * (n + 1) / 2;
+  const double tau = W[P + k];
+  if (tau == 0.0) return;                        // H_k = I: nothing to update
+  const double* vg = S2;
+  const double* pg = S2 + lda;
+  const double* sh = S2 + 2 * lda;
+  double dot = 0.0;
+  for (int b = k1 / LRB; b < static_cast<int>(gridDim.x); ++b) dot += sh[b];
+  const double c = 0.5 * tau * dot;
+  for (int j = k1 + tid; j < n; j += LNT) {
+    const double v = vg[j];
+    vsh[j] = v;
+    ws[j] = fma(-c, v, pg[j]);
+  }
+  __syncthreads();
+  for (int r = 0; r < LRB; ++r) {
+    const int i = r0 + r;
+    if (i <= k || i >= n) continue;
+    const double vi = vsh[i], wi = ws[i];
+    double* ai = A + static_cast<int64_t>(i) * lda;
+    for (int j = k1 + tid; j < n; j += LNT) ai[j] = fma(-vi, ws[j], fma(-wi, vsh[j], ai[j]));
+  }
+}
+
+__global__ void k_ltr_finish(const double* __restrict__ A, int lda, int n, double* __restrict__ W) {
+  if (threadIdx.x != 0) return;
+  const int P = n * (n + 1) / 2;
+  const double d2 = A[static_cast<int64_t>(n - 2) * lda + n - 2];
+  const double e2 = A[static_cast<int64_t>(n - 1) * lda + n - 2];
+  const double d1 = A[static_cast<int64_t>(n - 1) * lda + n - 1];
+  W[P + n + n - 2] = d2;
+  W[P + 2 * n + n - 2] = e2;
+  W[P + n - 2] = 0.0;
+  W[colstart(n - 2, n)] = d2;
+  W[colstart(n - 2, n) + 1] = e2;
+  W[P + n + n - 1] = d1;
+  W[P + n - 1] = 0.0;
+  W[P + 2 * n + n - 1] = 0.0;
+  W[colstart(n - 1, n)] = d1;
+}
+
+hipError_t launch_tridiag_large(const double* G, int m, int mp, EigWork wk, hipStream_t s) {
+  if (m < 3 || m > kTridGlobalMax || mp < m) return hipErrorInvalidValue;
+  const int nb = (m + LRB - 1) / LRB;
+  if (2 * mp + nb > mp * mp) return hipErrorInvalidValue;   // S2 holds v, p and the shares
+  hipLaunchKernelGGL(k_ltr_scale, dim3(1), dim3(1024), 0, s, G, m, mp, wk.W);
+  hipLaunchKernelGGL(k_ltr_load, dim3(m), dim3(LNT), 0, s, G, m, mp, wk.W, wk.S1, mp);
+  for (int k = 0; k + 2 < m; ++k) {
+    hipLaunchKernelGGL(k_ltr_reflect, dim3(nb), dim3(LNT), 0, s, wk.S1, mp, m, k, wk.W, wk.S2);
+    hipLaunchKernelGGL(k_ltr_update, dim3(nb), dim3(LNT), 0, s, wk.S1, mp, m, k, wk.W, wk.S2);
+  }
+  hipLaunchKernelGGL(k_ltr_finish, dim3(1), dim3(64), 0, s, wk.S1, mp, m, wk.W);
+  return hipGetLastError();
+}
+
 hipError_t launch_tridiag(const double* G, int m, int mp, EigWork wk, hipStream_t s) {
   if (m < 1 || m > kTridGlobalMax || mp < m) return hipErrorInvalidValue;
   if (m <= 64)
@@ -1310,6 +1504,7 @@ hipError_t launch_tridiag(const double* G, int m, int mp, EigWork wk, hipStream_
   else {
     // The first m - kTridRegMax columns on the packed triangle in W, the
     // rest in registers.
+    if (m > kTridLargeMin) return launch_tridiag_large(G, m, mp, wk, s);
     const int h = m - kTridRegMax;
     if (m <= 256)
       hipLaunchKernelGGL(k_tridiag<4>, dim3(1), dim3(HNT), 0, s, G, m, mp, wk.W, h);
@@ -1324,8 +1519,12 @@ hipError_t launch_tridiag(const double* G, int m, int mp, EigWork wk, hipStream_
 
 hipError_t launch_dc(int m, int mp, double* lam, double* V, EigWork wk, hipStream_t s, int nvec) {
   if (m < 1 || m > kDcMax || mp < m) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_dc, dim3(1), dim3(TNT), 0, s, wk.W, m, V, mp, wk.S1, wk.S2, lam, wk.st,
-                     nvec < 1 ? m : nvec);
+  if (m <= 512)
+    hipLaunchKernelGGL(k_dc<512>, dim3(1), dim3(TNT), 0, s, wk.W, m, V, mp, wk.S1, wk.S2, lam, wk.st,
+                       nvec < 1 ? m : nvec);
+  else
+    hipLaunchKernelGGL(k_dc<kDcMax>, dim3(1), dim3(TNT), 0, s, wk.W, m, V, mp, wk.S1, wk.S2, lam, wk.st,
+                       nvec < 1 ? m : nvec);
   return hipGetLastError();
 }
 
@@ -1340,8 +1539,10 @@ hipError_t launch_backtr(int m, int mp, double* V, EigWork wk, hipStream_t s) {
     hipLaunchKernelGGL((k_backtr<4, false>), dim3(grid), dim3(BNT), 0, s, wk.W, m, V, mp);
   else if (m <= 256)
     hipLaunchKernelGGL((k_backtr<4, true>), dim3(grid), dim3(BNT), 0, s, wk.W, m, V, mp);
-  else
+  else if (m <= 512)
     hipLaunchKernelGGL((k_backtr<8, true>), dim3(grid), dim3(BNT), 0, s, wk.W, m, V, mp);
+  else
+    hipLaunchKernelGGL((k_backtr<16, true>), dim3(grid), dim3(BNT), 0, s, wk.W, m, V, mp);
   return hipGetLastError();
 }
 
@@ -1382,7 +1583,7 @@ __global__ __launch_bounds__(HNT) void kg_tridiag(const GroupSketch* __restrict_
 __global__ __launch_bounds__(TNT) void kg_dc(const GroupSketch* __restrict__ SK,
                                              const GroupRR* __restrict__ T) {
   const GroupSketch& s = SK[T[blockIdx.x].sk];
-  dc_body(s.W, s.m, s.V, s.mp, s.S1, s.S2, s.lam, s.st, min(s.m, s.l));
+  dc_body<kBatchMax>(s.W, s.m, s.V, s.mp, s.S1, s.S2, s.lam, s.st, min(s.m, s.l));
 }
 
 // Size class [LO, HI] of buffer rows, with the LDS staging sized for it;

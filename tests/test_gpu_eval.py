@@ -62,3 +62,32 @@ def test_zero_matrix_is_rejected():
         F.evaluate(torch.zeros(10, 8, dtype=torch.float64, device="cuda"),
                    torch.zeros(2, 8, dtype=torch.float64, device="cuda"))
     assert e.value.code == -1
+
+
+def test_evaluate_dense_2048_columns_matches_oracle():
+    """The dense device evaluator at the widest rows of the 512-sketch
+    workload (d = 2,048) against the oracle's dense eigvalsh."""
+    A = synth.random_noisy(3000, 2048, 40, 10.0, seed=(44, 0))
+    B = oracle.fd_sketch(A[:1500], 64)
+    rep = F.evaluate(torch.from_numpy(A).cuda(), torch.from_numpy(B).cuda(), k=10, method=0)
+    ce = oracle.cov_err(A, B)
+    assert abs(rep["cov_err"] - ce) <= 1e-9 * ce
+
+
+@pytest.mark.parametrize("method", [0, 1])
+def test_evaluate_8192_columns_matches_stored_oracle(method):
+    """Both device evaluators at 8,192 columns (the 1M x 8,192 stream's
+    width) on its first 4,096-row chunk with B = 0.9 times its first 512 rows,
+    against the oracle's dense value stored by tests/golden/make_golden.py."""
+    import json
+    import os
+    with open(os.path.join(os.path.dirname(__file__), "golden", "eval_random_noisy_4096_x8192.json")) as f:
+        rec = json.load(f)
+    W = synth.WORKLOADS["c5_random_noisy_1m_x8192"]
+    U = synth.random_noisy_basis(W["d"], W["k"], tuple(W["seed"]))
+    A = synth.random_noisy_chunk(U, W["chunk"], W["zeta"], tuple(W["seed"]) + (1,), dtype=np.float32)
+    Ad = torch.from_numpy(A).cuda()
+    B = 0.9 * Ad[:512].double()
+    rep = F.evaluate(Ad, B, k=10, method=method)
+    assert abs(rep["fro2_A"] - rec["fro2A"]) <= 1e-12 * rec["fro2A"]
+    assert abs(rep["cov_err"] - rec["cov_err"]) <= 1e-9 * rec["cov_err"], (rep["cov_err"], rec["cov_err"])
