@@ -251,6 +251,26 @@ int fdsk_gram(const double* C, int32_t rows, int64_t d, int64_t ldc, double* G, 
 int fdsk_eigh(const double* G, int32_t m, int64_t ldg, double* lam, double* V, int64_t ldv,
               int32_t method, void* hip_stream);
 
+/* fdsk_eigh_noalloc: fdsk_eigh (method FDSK_EIG_AUTO, the tridiagonal route)
+ * for callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation.  It calls
+ * no allocating routine; its workspace is a static device array of
+ * FDSK_NOALLOC_SCRATCH_BYTES that the library holds on each GPU it runs on
+ * until the process ends.  Sizes: 1 <= m <= FDSK_NOALLOC_EIGH_MAX (else
+ * EUNSUPPORTED).  G, lam, V: device pointers as in fdsk_eigh (G m x m,
+ * leading dimension ldg; lam m values, any order; V row-major, column j the
+ * eigenvector of lam[j]).  Stream-ordered on hip_stream and asynchronous: it
+ * returns once the work is enqueued (no synchronisation), so it may be
+ * captured into a graph.  Every call on one GPU shares that GPU's scratch
+ * and leaves the last call's contents in it (each call clears what it needs
+ * first): calls that overlap on one GPU, on different streams or from
+ * different threads, race.  Errors (message via sketch_last_error(NULL)):
+ * EINVAL, EUNSUPPORTED, EDEVICE. */
+#define FDSK_NOALLOC_SCRATCH_BYTES (16u << 20)
+#define FDSK_NOALLOC_EIGH_MAX 512
+int fdsk_eigh_noalloc(const double* G, int32_t m, int64_t ldg, double* lam, double* V, int64_t ldv,
+                      void* hip_stream);
+
 /* ------------------------------------------------------------------------
  * Many independent sketches advanced together (Algorithm 1 for each).
  *

@@ -121,6 +121,10 @@ hipError_t launch_tridiag(const double* G, int m, int mp, EigWork wk, hipStream_
 // others are left undefined); m or less than 1 for all.
 hipError_t launch_dc(int m, int mp, double* lam, double* V, EigWork wk, hipStream_t s, int nvec);
 hipError_t launch_backtr(int m, int mp, double* V, EigWork wk, hipStream_t s);
+// The message sketch_last_error(NULL) returns (entry points without a
+// sketch object).
+void set_last_error(const char* msg);
+
 inline bool eig_uses_trid(int m, const EigWork& wk) {
   return wk.method != EIG_JACOBI && m <= kTridGlobalMax && wk.S1 && wk.S2;
 }

@@ -284,6 +284,8 @@ int check_device_flags(fdsk_sketch* s) {
 
 }  // namespace
 
+void fdsk::set_last_error(const char* msg) { g_last_error = msg ? msg : ""; }
+
 extern "C" {
 
 const char* fdsk_version(void) {

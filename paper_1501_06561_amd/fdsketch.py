@@ -30,7 +30,7 @@ EXPORTS = ("sketch_create", "sketch_append_rows", "sketch_merge", "sketch_finali
            "fdsk_gram", "fdsk_eigh", "sketch_reset", "sketch_profile", "sketch_batch_create",
            "sketch_batch_append", "sketch_batch_finalize", "sketch_batch_stats",
            "sketch_batch_reset", "sketch_batch_profile", "sketch_batch_destroy",
-           "sketch_batch_last_error")
+           "sketch_batch_last_error", "fdsk_eigh_noalloc")
 
 
 class FdskConfig(ctypes.Structure):
@@ -142,11 +142,12 @@ def lib():
     L.sketch_batch_last_error.restype = ctypes.c_char_p
     L.sketch_profile.argtypes = [vp, ctypes.POINTER(FdskProfile)]
     L.fdsk_eigh.argtypes = [vp, i32, i64, vp, vp, i64, i32, vp]
+    L.fdsk_eigh_noalloc.argtypes = [vp, i32, i64, vp, vp, i64, vp]
     for f in ("sketch_create", "sketch_append_rows", "sketch_merge", "sketch_finalize", "sketch_error",
               "fdsk_evaluate", "sketch_stats", "fdsk_gram", "fdsk_eigh", "sketch_reset",
               "sketch_profile", "sketch_batch_create", "sketch_batch_append",
               "sketch_batch_finalize", "sketch_batch_stats", "sketch_batch_reset",
-              "sketch_batch_profile"):
+              "sketch_batch_profile", "fdsk_eigh_noalloc"):
         getattr(L, f).restype = cint
     _lib = L
     return L
