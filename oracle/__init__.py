@@ -13,6 +13,9 @@ fd        -- the streaming sketch (Algorithm 1 with the ReduceRank rules of
              an independent covariance-form re-derivation; a frequent-items
              counter simulation for rows that are scaled basis vectors.
 evaluate  -- the error measures of Section 1.1 (covariance and projection error).
+rsketch   -- the hashing and sampling sketches the paper compares against
+             (Section 2.2 Hashing and OSNAP, Section 3.2 Priority and VarOpt
+             sampling), with the counter-based generator they draw from.
 """
 from .fd import (FD, ISVD, ALPHA, FAST_ALPHA, SSD, CFD, VARIANTS, ALL_VARIANTS, rule_indices, alpha_eff,
                  reduce_rank, SketchOracle, fd_sketch, fd_covariance_form,
