@@ -345,6 +345,81 @@ void sketch_batch_destroy(fdsk_batch* b);
  * failure.  Valid until the next call on the batch. */
 const char* sketch_batch_last_error(const fdsk_batch* b);
 
+/* ------------------------------------------------------------------------
+ * Hashing and sampling sketches: the paper's fast competitors of the
+ * Frequent Directions family, each reading every row once.
+ *
+ * FDSK_RS_HASH (Section 2.2, "Sparse Random Projections", Hashing): B = S A
+ *   with S l x n, one nonzero per column: row i of A is added, with sign
+ *   sigma(i), to row h(i) of B.
+ * FDSK_RS_OSNAP (same paragraph): s independent such matrices of l/s rows
+ *   stacked, each scaled by 1/sqrt(s) (so E[B^T B] = A^T A).
+ * FDSK_RS_PRIORITY (Section 3.2, "Priority Sampling"): row i has weight
+ *   w_i = ||a_i||^2, u_i ~ Unif(0,1) and priority w_i / u_i; the l rows of
+ *   largest priority are kept (ties: earlier rows), each rescaled to squared
+ *   norm max(w_i, tau) with tau the (l+1)-th largest priority of the stream
+ *   (0 while at most l rows arrived).
+ * FDSK_RS_VAROPT (Section 3.2, "VarOpt Sampling"): each append call is one
+ *   merge step: the reservoir (adjusted weights w^) and the call's rows
+ *   (w^ = w) are the candidates; tau solves sum min(1, w^/tau) = l over
+ *   them; candidates with w^ >= tau stay; the others are chosen by
+ *   systematic sampling with probabilities w^/tau (positions
+ *   (q + u_c) C/(l - t), q < l - t, over the running sum C of those
+ *   probabilities in candidate order: the reservoir's rows, then the call's
+ *   rows in stream order; u_c the call's uniform) and then carry w^ = tau.
+ *   Exactly l rows are kept and sum w^ = ||A||_F^2.  Rows are output as
+ *   a_i sqrt(w^_i / w_i).
+ * Random numbers (counter-based SplitMix64, Steele, Lea and Flood 2014):
+ *   mix(x) = the SplitMix64 output for state x (x + 0x9E3779B97F4A7C15,
+ *   then xor-shift 30 / multiply 0xBF58476D1CE4E5B9, xor-shift 27 / multiply
+ *   0x94D049BB133111EB, xor-shift 31); r(i, j) = mix(mix(key ^ i) ^ j) for
+ *   the stream index i of a row:
+ *   h_j(i) = ((r(i, 2j) >> 32) * (l/s)) >> 32 in instance j, sigma_j(i) = -1
+ *   when the top bit of r(i, 2j+1) is set, u_i = ((r(i, 0) >> 11) + 1/2)
+ *   2^-53, and u_c = the same uniform of index 2^62 + c for the c-th
+ *   non-empty append call (from 0).
+ * Conventions as for the FD sketches (return codes, stream order, host or
+ * device rows with a leading dimension, staging of host rows).
+ * ------------------------------------------------------------------------ */
+enum { FDSK_RS_HASH = 0, FDSK_RS_OSNAP = 1, FDSK_RS_PRIORITY = 2, FDSK_RS_VAROPT = 3 };
+typedef struct fdsk_rsketch fdsk_rsketch;
+typedef struct {
+  double fro2_A;        /* ||A||_F^2 of the rows appended */
+  double tau;           /* current threshold (Priority, VarOpt; 0 otherwise) */
+  double weight_sum;    /* sum of the kept rows' adjusted weights (after finalize) */
+  int64_t n_rows;
+  int32_t rows_kept;    /* rows of B that may be nonzero */
+  int32_t reserved;
+} fdsk_rs_stats;
+
+/* Create a sketch of kind FDSK_RS_* with l output rows over rows of length
+ * d; s is OSNAP's number of stacked instances (1..8, dividing l; ignored
+ * otherwise); key seeds the generator.  Errors: EINVAL, EUNSUPPORTED (l
+ * above 2^24), ENOMEM. */
+int rsketch_create(int32_t kind, int64_t d, int32_t l, int32_t s, uint64_t key, void* hip_stream,
+                   fdsk_rsketch** out);
+/* Append n rows (n x d, leading dimension stride, dtype, host or device);
+ * each call is one step of the stream (one merge step for VarOpt).
+ * Errors: EINVAL, ESTATE (after finalize), ENOMEM, EDEVICE, EUNSUPPORTED
+ * (more than 2^30 rows in one call). */
+int rsketch_append(fdsk_rsketch* s, const void* rows, int64_t n, int64_t stride, fdsk_dtype dtype,
+                   fdsk_mem mem);
+/* Write B (l x d, leading dimension ldb, F64 or F32, host or device as
+ * mem); for the sampling kinds also the stream index of every kept row to
+ * index_out (rows_out entries, same memory kind; may be NULL).
+ * Synchronises.  Errors: EINVAL, ESTATE, ENOMEM, EDEVICE. */
+int rsketch_finalize(fdsk_rsketch* s, void* B_out, int64_t ldb, fdsk_dtype out_dtype, fdsk_mem mem,
+                     int64_t* index_out, int32_t* rows_out);
+/* ||A||_F^2, tau, the adjusted weight sum and counts (Section 3.2's
+ * quantities).  Synchronises. */
+int rsketch_stats(const fdsk_rsketch* s, fdsk_rs_stats* out);
+/* Free everything the sketch owns (waits for its stream).  NULL is ok.
+ * Resource management only. */
+void rsketch_destroy(fdsk_rsketch* s);
+/* Last error message of the sketch ("" if none); NULL: the last create
+ * failure. */
+const char* rsketch_last_error(const fdsk_rsketch* s);
+
 /* Library build information (static string). */
 const char* fdsk_version(void);
 

@@ -28,7 +28,7 @@ FLAGS = [
     "-I" + os.path.join(ROOT, "include"), "-I" + CSRC,
 ]
 SOURCES = ["kernels_stream.hip", "kernels_eig.hip", "kernels_trid.hip", "kernels_eval.hip",
-           "kernels_lowp.hip", "noalloc.hip",
+           "kernels_lowp.hip", "noalloc.hip", "rsketch.hip",
            "eval_host.cpp", "batch_host.cpp", "fdsketch.cpp"]
 
 

@@ -30,7 +30,8 @@ EXPORTS = ("sketch_create", "sketch_append_rows", "sketch_merge", "sketch_finali
            "fdsk_gram", "fdsk_eigh", "sketch_reset", "sketch_profile", "sketch_batch_create",
            "sketch_batch_append", "sketch_batch_finalize", "sketch_batch_stats",
            "sketch_batch_reset", "sketch_batch_profile", "sketch_batch_destroy",
-           "sketch_batch_last_error", "fdsk_eigh_noalloc")
+           "sketch_batch_last_error", "fdsk_eigh_noalloc", "rsketch_create", "rsketch_append",
+           "rsketch_finalize", "rsketch_stats", "rsketch_destroy", "rsketch_last_error")
 
 
 class FdskConfig(ctypes.Structure):
@@ -68,6 +69,17 @@ class FdskProfile(ctypes.Structure):
         """{stage: (total_ms, launches, algorithmic work)}; work is bytes for
         ingest and flops for the other stages."""
         return {name: (self.ms[i], self.launches[i], self.work[i]) for i, name in enumerate(STAGES)}
+
+
+class FdskRsStats(ctypes.Structure):
+    _fields_ = [("fro2_A", ctypes.c_double), ("tau", ctypes.c_double), ("weight_sum", ctypes.c_double),
+                ("n_rows", ctypes.c_int64), ("rows_kept", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_ if name != "reserved"}
+
+
+RS_KINDS = {"hash": 0, "osnap": 1, "priority": 2, "varopt": 3}
 
 
 class FdskError(RuntimeError):
@@ -143,11 +155,20 @@ def lib():
     L.sketch_profile.argtypes = [vp, ctypes.POINTER(FdskProfile)]
     L.fdsk_eigh.argtypes = [vp, i32, i64, vp, vp, i64, i32, vp]
     L.fdsk_eigh_noalloc.argtypes = [vp, i32, i64, vp, vp, i64, vp]
+    L.rsketch_create.argtypes = [i32, i64, i32, i32, ctypes.c_uint64, vp, ctypes.POINTER(vp)]
+    L.rsketch_append.argtypes = [vp, vp, i64, i64, cint, cint]
+    L.rsketch_finalize.argtypes = [vp, vp, i64, cint, cint, vp, ctypes.POINTER(i32)]
+    L.rsketch_stats.argtypes = [vp, ctypes.POINTER(FdskRsStats)]
+    L.rsketch_destroy.argtypes = [vp]
+    L.rsketch_destroy.restype = None
+    L.rsketch_last_error.argtypes = [vp]
+    L.rsketch_last_error.restype = ctypes.c_char_p
     for f in ("sketch_create", "sketch_append_rows", "sketch_merge", "sketch_finalize", "sketch_error",
               "fdsk_evaluate", "sketch_stats", "fdsk_gram", "fdsk_eigh", "sketch_reset",
               "sketch_profile", "sketch_batch_create", "sketch_batch_append",
               "sketch_batch_finalize", "sketch_batch_stats", "sketch_batch_reset",
-              "sketch_batch_profile", "fdsk_eigh_noalloc"):
+              "sketch_batch_profile", "fdsk_eigh_noalloc", "rsketch_create", "rsketch_append",
+              "rsketch_finalize", "rsketch_stats"):
         getattr(L, f).restype = cint
     _lib = L
     return L
@@ -430,6 +451,66 @@ class FDSketchBatch:
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:
             lib().sketch_batch_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class RSketch:
+    """One hashing or sampling sketch (Hashing, OSNAP, Priority or VarOpt;
+    see the rsketch_* declarations in include/fdsketch.h)."""
+
+    def __init__(self, kind, d, l, s=4, key=0, stream=None):
+        self.kind, self.d, self.l = kind, int(d), int(l)
+        self._stream = _bound_stream(stream)
+        h = ctypes.c_void_p()
+        rc = lib().rsketch_create(RS_KINDS[kind], self.d, self.l, int(s), ctypes.c_uint64(int(key)),
+                                  _stream_handle(self._stream), ctypes.byref(h))
+        if rc != 0:
+            msg = lib().rsketch_last_error(None)
+            raise FdskError(rc, msg.decode() if msg else "")
+        self._h = h
+        _live.add(self)
+
+    def _check(self, rc):
+        if rc != 0:
+            msg = lib().rsketch_last_error(self._h)
+            raise FdskError(rc, msg.decode() if msg else "")
+
+    def append(self, rows):
+        ptr, n, stride, dt, mem, keep = _rows_arg(rows)
+        _order_after_current(self._stream, keep)
+        self._check(lib().rsketch_append(self._h, ctypes.c_void_p(ptr), n, stride, dt, mem))
+        return self
+
+    def finalize(self, dtype=None, device="cuda"):
+        """(B, indices of the kept rows or None for the hashing kinds)."""
+        torch = _torch()
+        dtype = dtype or torch.float64
+        out = torch.empty((self.l, self.d), dtype=dtype, device=device)
+        idx = torch.full((self.l,), -1, dtype=torch.int64, device=device)
+        rows = ctypes.c_int32()
+        mem = MEM_DEVICE if out.is_cuda else MEM_HOST
+        self._check(lib().rsketch_finalize(self._h, ctypes.c_void_p(out.data_ptr()), out.stride(0),
+                                           _dtype_code(out), mem, ctypes.c_void_p(idx.data_ptr()),
+                                           ctypes.byref(rows)))
+        self.rows_out = rows.value
+        if self.kind in ("hash", "osnap"):
+            return out, None
+        return out, idx[:rows.value]
+
+    def stats(self):
+        st = FdskRsStats()
+        self._check(lib().rsketch_stats(self._h, ctypes.byref(st)))
+        return st.as_dict()
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().rsketch_destroy(self._h)
             self._h = ctypes.c_void_p()
 
     def __del__(self):

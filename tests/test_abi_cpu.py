@@ -99,3 +99,18 @@ def test_struct_layouts_match_header():
     assert ctypes.sizeof(F.FdskProfile) == 9 * 8 * 3
     assert ctypes.sizeof(F.FdskConfig) == 40
     assert ctypes.sizeof(F.FdskReport) == 9 * 8 + 2 * 8 + 4 * 4 + 8
+
+
+@pytest.mark.parametrize("kind,d,l,s,code", [
+    (7, 10, 8, 4, -1),        # unknown kind
+    (0, 0, 8, 4, -1),         # d = 0
+    (2, 10, 0, 4, -1),        # l = 0
+    (1, 10, 10, 4, -1),       # OSNAP: s must divide l
+    (1, 10, 8, 9, -1),        # OSNAP: s <= 8
+])
+def test_rsketch_create_rejects_bad_arguments(kind, d, l, s, code):
+    h = ctypes.c_void_p()
+    rc = F.lib().rsketch_create(kind, d, l, s, ctypes.c_uint64(0), None, ctypes.byref(h))
+    assert rc == code
+    assert not h.value
+    assert F.lib().rsketch_last_error(None)
