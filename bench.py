@@ -286,6 +286,89 @@ def precision_leg(rows, l=256, d=3072, seed=(3, 0)):
     return out
 
 
+def rsketch_leg(A, reps=10, l=1000):
+    """The hashing and sampling sketches (Sections 2.2 and 3.2) over the
+    Random Noisy 100,000 x 1,000 fp32 block appended `reps` times (one append
+    call per block): rows/s, the HBM rate of the row reads (n d 4 bytes)
+    against 8 TB/s, and each sketch's covariance error over the whole stream
+    (device evaluator)."""
+    import torch
+    from paper_1501_06561_amd import fdsketch as F
+    At = A if A.is_cuda else A.cuda()
+    n1, d = At.shape
+    out = {"workload": f"random_noisy_100k_x1000_fp32 appended {reps} times ({n1 * reps} rows), l = {l}, "
+                       "OSNAP s = 4", "bytes_per_row": d * 4}
+    full = At.repeat(reps, 1)
+    for kind in ("hash", "osnap", "priority", "varopt"):
+        sk = F.RSketch(kind, d, l, s=4, key=1)
+        sk.append(At[: 2 * l])              # first launches load the kernels
+        sk.close()
+        sk = F.RSketch(kind, d, l, s=4, key=1)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            sk.append(At)
+        e1.record()
+        B, _ = sk.finalize()
+        ms = e0.elapsed_time(e1)
+        sk.close()
+        rows = n1 * reps
+        ev = F.evaluate(full, B, k=10, method=0)
+        out[kind] = {"rows_per_s": rows / (ms / 1e3), "ms": ms,
+                     "read_GBps": rows * d * 4 / (ms / 1e3) / 1e9,
+                     "frac_of_hbm": rows * d * 4 / (ms / 1e3) / PEAK_HBM, "cov_err": ev["cov_err"]}
+    del full
+    return out
+
+
+def large_stream_leg(rows_limit=None):
+    """alpha-FD (alpha = 0.2, l = 512, buffer 1,024 rows) over the Random
+    Noisy 1,000,000 x 8,192 stream (rank 512, zeta = 20), fp32 rows resident
+    in HBM and appended in 4,096-row chunks, FP8 Gram with split
+    compensation: rows/s and per-stage times."""
+    import torch
+    from paper_1501_06561_amd import fdsketch as F, synth
+    W = synth.WORKLOADS["c5_random_noisy_1m_x8192"]
+    d, l = W["d"], W["l"]
+    U = synth.random_noisy_basis(d, W["k"], tuple(W["seed"]))
+    sizes = synth.chunk_sizes(W["n"] if rows_limit is None else rows_limit, W["chunk"])
+    n = sum(sizes)
+    A = torch.empty((n, d), dtype=torch.float32, device="cuda")
+    r0 = 0
+    for g0 in range(0, len(sizes), 16):
+        grp = list(range(g0, min(g0 + 16, len(sizes))))
+        chunks = synth.parallel_map(
+            lambda c: synth.random_noisy_chunk(U, sizes[c], W["zeta"], tuple(W["seed"]) + (c + 1,)), grp, 16)
+        for X in chunks:
+            A[r0:r0 + X.shape[0]].copy_(torch.from_numpy(X))
+            r0 += X.shape[0]
+    sk = F.FDSketch(d, l, "alpha", W["alpha"], precision="fp8x3", profile=True)
+    sk.append(A[: 2 * l + 1])
+    sk.finalize()
+    sk.reset()
+    sk.profile()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    r0 = 0
+    for c in sizes:
+        sk.append(A[r0:r0 + c])
+        r0 += c
+    sk.finalize()
+    dt = time.perf_counter() - t0
+    prof = sk.profile()
+    st = sk.stats()
+    sk.close()
+    del A
+    table = stage_table({k_: v for k_, v in prof.items() if k_ != "eig"},
+                        lambda s_: ((PEAK_FP8, "fp8 mfma") if s_ == "gram" else (PEAK_BF16, "bf16 mfma")
+                                    if s_ == "rebuild" else (PEAK_FP64, "fp64 alu")))
+    return {"workload": f"random_noisy_1m_x8192_fp32 ({n} rows in 4,096-row chunks), alpha-FD alpha = 0.2, "
+                        "l = 512 (buffer 1,024 rows), FP8x3 Gram, split-BF16 rebuild, FP64 eigensolve",
+            "rows_per_s": n / dt, "s": dt, "reduce_steps": st["n_reduce"],
+            "eig_ms_per_reduce": prof["eig"][0] / max(prof["eig"][1], 1), "stages": table}
+
+
 def cpu_baseline_leg(d, l, n, seed, seconds):
     """The oracle (NumPy FP64, LAPACK SVD of the buffer) on the first
     sketches of the same workload until about `seconds` of CPU work."""
@@ -324,6 +407,15 @@ def main():
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the single-stream and precision legs")
     ap.add_argument("--prec-rows", type=int, default=8_000)
+    ap.add_argument("--precision-only", action="store_true",
+                    help="only the precision leg (for matrix-core counter runs)")
+    ap.add_argument("--large-stream", action="store_true",
+                    help="only the 1,000,000 x 8,192 alpha-FD stream (FP8 Gram), about a minute")
+    ap.add_argument("--single-only", action="store_true",
+                    help="only the single-sketch FD l = 100 leg on the 100,000 x 1,000 stream "
+                         "(for hardware-counter runs)")
+    ap.add_argument("--prec-l", type=int, default=256)
+    ap.add_argument("--prec-d", type=int, default=3072)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--profile-only", action="store_true",
@@ -345,6 +437,16 @@ def main():
     import torch
 
     from paper_1501_06561_amd import synth
+
+    if args.precision_only:
+        print(json.dumps({"precision_leg": precision_leg(args.prec_rows, l=args.prec_l, d=args.prec_d)}))
+        return
+    if args.single_only:
+        print(json.dumps({"single_stream": single_stream_leg()[0]}))
+        return
+    if args.large_stream:
+        print(json.dumps({"large_stream": large_stream_leg()}))
+        return
 
     W = synth.WORKLOADS["c4_batch_512"]
     S, seed = W["S"], tuple(W["seed"])
@@ -428,9 +530,13 @@ def main():
     if seq is not None:
         del outs_seq
 
-    extra_single = extra_prec = None
+    extra_single = extra_prec = extra_rs = None
     if not args.no_extra:
-        extra_single, _, _ = single_stream_leg()
+        extra_single, A_c2, _ = single_stream_leg()
+        print("[bench] single stream done", file=sys.stderr, flush=True)
+        extra_rs = rsketch_leg(torch.from_numpy(A_c2))
+        del A_c2
+        print("[bench] hashing / sampling done", file=sys.stderr, flush=True)
         if args.prec_rows > 0:
             extra_prec = precision_leg(args.prec_rows)
 
@@ -474,6 +580,7 @@ def main():
         "parity": parity,
         "cpu_baseline": cpu,
         "single_stream": extra_single,
+        "hashing_sampling": extra_rs,
         "precision_leg": extra_prec,
         "input_generation_s": t_gen,
     }

@@ -119,7 +119,9 @@ typedef struct {
   double fro2_A;              /* ||A||_F^2 (FP64 accumulation) */
   double fro2_B;              /* ||B||_F^2 */
   double delta_sum;           /* Delta = sum of delta_i (Section 3.1) */
-  double shrink_total;        /* total squared mass removed by the rules */
+  double shrink_total;        /* total squared mass removed by the rules (reduced-precision
+                                 single sketches other than CFD: measured per reduction as
+                                 ||C||_F^2 before minus after, in FP64 from the rows) */
   double lambda_max;          /* largest eigenvalue of A^T A - B^T B */
   double lambda_min;          /* smallest eigenvalue of A^T A - B^T B */
   int64_t n_rows;             /* rows appended */

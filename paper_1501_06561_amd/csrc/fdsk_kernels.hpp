@@ -30,6 +30,13 @@ struct DevStats {
 // and keep = l rows are written; comp = 1 applies the FD rule first (the
 // reduction just run is re-evaluated from the same spectrum), comp = 2 takes
 // the spectrum as it is.  Only the shrink total and fro2A are updated.
+//
+// mass != 0 (reduced-precision products): the shrink leaves the shrink total
+// alone; it is measured instead as the buffer's squared Frobenius norm before
+// the reduction minus that of the rebuilt rows, both in FP64 from the rows
+// themselves (launch_row_mass / launch_mass_close), so that
+// ||A||_F^2 - ||B||_F^2 equals it however far the approximate Gram's
+// eigenvalues are off.
 struct RuleParams {
   int variant;
   int l;
@@ -37,6 +44,7 @@ struct RuleParams {
   int r;
   int keep;
   int comp;
+  int mass;
 };
 
 // Squared singular values at or below this fraction of the largest are
@@ -72,6 +80,11 @@ hipError_t launch_shrink(const double* lam, const double* V, int m, int mp, Rule
 hipError_t launch_rebuild(const double* Ut, const double* C, int ldc, int mp, int keep, double* out,
                           hipStream_t s);
 hipError_t launch_zero_rows(double* C, int ldc, int r0, int r1, hipStream_t s);
+// out[i] = ||C_i||^2 (FP64) for rows i < rows of a buffer with d columns.
+hipError_t launch_row_mass(const double* C, int ldc, int rows, int d, double* out, hipStream_t s);
+// st->Stot += sum(before[0:nb]) - sum(after[0:na]) (fixed order).
+hipError_t launch_mass_close(const double* before, int nb, const double* after, int na, DevStats* st,
+                             hipStream_t s);
 hipError_t launch_add_pending_norms(const double* rownorm, int new0, int new1, DevStats* st,
                                     hipStream_t s);
 hipError_t launch_merge_stats(DevStats* dst, const DevStats* src, const double* src_rownorm, int new0,

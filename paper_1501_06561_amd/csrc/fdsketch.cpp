@@ -34,6 +34,7 @@ struct fdsk_sketch {
   int cur = 0;
   double *G = nullptr, *Gpart = nullptr, *W = nullptr, *V = nullptr, *lam = nullptr,
          *Ut = nullptr, *rownorm = nullptr, *S1 = nullptr, *S2 = nullptr;
+  double *mass_b = nullptr, *mass_a = nullptr;   // row masses before / after a reduction
   void* q8 = nullptr;   // FP8 codes and scales of the buffer (FDSK_P_FP8X3)
   void* bfw = nullptr;  // the buffer's bf16 hi/lo halves (every reduced precision)
   int ksplit_max = 1;
@@ -110,6 +111,10 @@ RuleParams make_rule(const fdsk_config& c) {
     case FDSK_CFD: rp.t = c.l; rp.r = 0; break;
   }
   rp.keep = rp.t - 1;
+  // Reduced-precision products: the shrink total is measured from the rows
+  // (see RuleParams).  Compensative FD keeps the spectral count, its last
+  // step adding mass back from the previous reduction's spectrum.
+  rp.mass = (c.precision != FDSK_P_FP64 && c.variant != FDSK_CFD) ? 1 : 0;
   return rp;
 }
 
@@ -185,6 +190,7 @@ int shrink_rebuild(fdsk_sketch* s, const RuleParams& rp, int new0, int new1, con
                    double* dst) {
   const int npass = s->cfg.precision == FDSK_P_BF16 ? 1 : 3;
   hipEvent_t e2 = mark(s);
+  if (rp.mass) HIPCHK(s, launch_row_mass(src, s->ldc, s->m, s->d, s->mass_b, s->stream));
   HIPCHK(s, launch_shrink(s->lam, s->V, s->m, s->mp, rp, s->rownorm, new0, new1, s->Ut, s->st,
                           s->stream));
   hipEvent_t e3 = mark(s);
@@ -196,6 +202,10 @@ int shrink_rebuild(fdsk_sketch* s, const RuleParams& rp, int new0, int new1, con
     // splits the buffer first and rebuilds with split-BF16 x3.
     if (s->cfg.precision == FDSK_P_FP8X3) HIPCHK(s, launch_split_bf16(src, s->ldc, s->mp, s->bfw, s->stream));
     HIPCHK(s, launch_rebuild_lowp(s->Ut, src, s->ldc, s->mp, rp.keep, dst, npass, s->bfw, s->stream));
+  }
+  if (rp.mass) {
+    HIPCHK(s, launch_row_mass(dst, s->ldc, rp.keep, s->d, s->mass_a, s->stream));
+    HIPCHK(s, launch_mass_close(s->mass_b, s->m, s->mass_a, rp.keep, s->st, s->stream));
   }
   add_mark(s, FDSK_STAGE_SHRINK, e2, e3, 0.0);
   add_mark(s, FDSK_STAGE_REBUILD, e3, mark(s), passes(s) * 2.0 * rp.keep * s->m * (double)s->d);
@@ -352,6 +362,7 @@ int sketch_create(const fdsk_config* cfg, void* hip_stream, fdsk_sketch** out) {
          oUt = take(mp2 * 8), oLam = take(s->mp * 8), oRn = take(s->mp * 8),
          oSt = take(sizeof(DevStats)), oBar = take(4 * sizeof(unsigned)),
          oRot = take(kMaxSweeps * sizeof(int)), oS1 = take(mp2 * 8), oS2 = take(mp2 * 8),
+         oMb = take(s->mp * 8), oMa = take(s->mp * 8),
          oQ8 = take(c.precision == FDSK_P_FP8X3 ? fp8_workspace_bytes(s->mp, s->ldc) : 0),
          oBf = take(c.precision != FDSK_P_FP64 ? bf16_workspace_bytes(s->mp, s->ldc) : 0);
   hipError_t e = hipMalloc(&s->arena, off);
@@ -374,6 +385,8 @@ int sketch_create(const fdsk_config* cfg, void* hip_stream, fdsk_sketch** out) {
   s->rot = reinterpret_cast<int*>(a + oRot);
   s->S1 = reinterpret_cast<double*>(a + oS1);
   s->S2 = reinterpret_cast<double*>(a + oS2);
+  s->mass_b = reinterpret_cast<double*>(a + oMb);
+  s->mass_a = reinterpret_cast<double*>(a + oMa);
   s->q8 = (c.precision == FDSK_P_FP8X3) ? static_cast<void*>(a + oQ8) : nullptr;
   s->bfw = (c.precision != FDSK_P_FP64) ? static_cast<void*>(a + oBf) : nullptr;
   e = hipMemsetAsync(s->arena, 0, off, s->stream);

@@ -213,7 +213,7 @@ __device__ __forceinline__ void shrink_body(const double* __restrict__ lam_raw,
   if (tid == 0) {
     const double nrm = red2[0];
     st->fro2A += nrm;
-    st->Stot += red[0];
+    if (!rp.mass) st->Stot += red[0];
     if (!rp.comp) {
       st->Delta += delta;
       st->n_rr += 1;
@@ -408,6 +408,39 @@ hipError_t launch_rebuild(const double* Ut, const double* C, int ldc, int mp, in
   if (keep <= 0) return hipSuccess;
   dim3 grid(ldc / 64, (keep + 31) / 32);
   hipLaunchKernelGGL(k_rebuild_f64, grid, dim3(256), 0, s, Ut, C, ldc, mp, keep, out);
+  return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void k_row_mass(const double* __restrict__ C, int ldc, int d,
+                                                 double* __restrict__ out) {
+  __shared__ double red[4];
+  const double* c = C + static_cast<int64_t>(blockIdx.x) * ldc;
+  double v = 0.0;
+  for (int j = threadIdx.x; j < d; j += 256) v = fma(c[j], c[j], v);
+  v = wave_sum(v);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) out[blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
+}
+
+__global__ void k_mass_close(const double* __restrict__ before, int nb, const double* __restrict__ after, int na,
+                             DevStats* __restrict__ st) {
+  if (threadIdx.x != 0) return;
+  double b = 0.0, a = 0.0;
+  for (int i = 0; i < nb; ++i) b += before[i];
+  for (int i = 0; i < na; ++i) a += after[i];
+  st->Stot += b - a;
+}
+
+hipError_t launch_row_mass(const double* C, int ldc, int rows, int d, double* out, hipStream_t s) {
+  if (rows <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_row_mass, dim3(rows), dim3(256), 0, s, C, ldc, d, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_mass_close(const double* before, int nb, const double* after, int na, DevStats* st,
+                             hipStream_t s) {
+  hipLaunchKernelGGL(k_mass_close, dim3(1), dim3(64), 0, s, before, nb, after, na, st);
   return hipGetLastError();
 }
 

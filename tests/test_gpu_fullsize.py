@@ -149,6 +149,8 @@ def test_power_law_200k_x3072_bf16_rows_bf16x3_whole_stream():
     assert abs(st["fro2_A"] - fa) <= 1e-12 * fa
     assert abs(st["shrink_total"] - rec["Stot"]) <= 1e-3 * fa
     assert abs(st["delta_sum"] - rec["Delta"]) <= 1e-3 * fa
+    # The shrink total is measured from the rows: ||A||^2 - ||B||^2 = S_tot.
+    assert abs(fa - float(np.sum(B * B)) - st["shrink_total"]) <= 1e-9 * fa
     assert st["eig_unconverged"] == 0
 
 
@@ -226,11 +228,16 @@ def test_random_noisy_1m_x8192_alpha_l512_fp8x3_whole_stream():
     st = sk.stats()
     sk.close()
     fa = rec["fro2A"]
-    assert gram_diff_norm(B, Bo) <= 1e-3 * fa
+    gd = gram_diff_norm(B, Bo)
     ev = F.evaluate(A, torch.from_numpy(B).cuda(), k=10, method=1)
+    print(f"gram diff / fro2A {gd / fa:.3e}; cov-err gpu {ev['cov_err']:.6e} oracle {rec['cov_err']:.6e}; "
+          f"S_tot gpu {st['shrink_total']:.6e} oracle {rec['Stot']:.6e}; Delta gpu {st['delta_sum']:.6e} "
+          f"oracle {rec['Delta']:.6e}; ||A||^2 - ||B||^2 - S_tot (gpu) {(fa - float(np.sum(B * B)) - st['shrink_total']) / fa:.3e}")
+    assert gd <= 1e-3 * fa
     assert abs(ev["cov_err"] - rec["cov_err"]) <= 1e-3, (ev["cov_err"], rec["cov_err"])
     assert st["n_reduce"] == rec["n_rr"]
     assert abs(st["fro2_A"] - fa) <= 1e-12 * fa
     assert abs(st["shrink_total"] - rec["Stot"]) <= 1e-3 * fa
     assert abs(st["delta_sum"] - rec["Delta"]) <= 1e-3 * fa
+    assert abs(fa - float(np.sum(B * B)) - st["shrink_total"]) <= 1e-9 * fa
     assert st["eig_unconverged"] == 0
