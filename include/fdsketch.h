@@ -190,7 +190,8 @@ int fdsk_evaluate(const void* A, int64_t n, int64_t lda, fdsk_dtype a_dtype,
                   int64_t d, fdsk_mem mem, int32_t k, int32_t method, void* hip_stream,
                   fdsk_report* out);
 
-/* Accumulators so far: ||A||_F^2 (Section 1.1), Delta = sum of the delta_i
+/* Accumulators so far (Section 3.1: Properties 1-3 are stated in these
+ * quantities): ||A||_F^2 (Section 1.1), Delta = sum of the delta_i
  * and the total squared mass removed (the quantities of Properties 1-3,
  * Section 3.1), rows and reductions.  Synchronises the stream. */
 int sketch_stats(const fdsk_sketch* s, fdsk_report* out);
@@ -223,7 +224,8 @@ typedef struct {
 int sketch_profile(fdsk_sketch* s, fdsk_profile* out);
 
 /* Free everything the sketch owns (waits for its stream first). NULL is ok.
- * Resource management only: no step of the method. */
+ * Resource management only: no step of the method (the paper's sketches end
+ * with the output of finalize, Algorithm 1). */
 void sketch_destroy(fdsk_sketch* s);
 
 /* Message of the last error on this sketch ("" if none); valid until the
@@ -242,8 +244,8 @@ const char* sketch_last_error(const fdsk_sketch* s);
  * fdsk_eigh: eigen-decomposition G = V diag(lam) V^T of a symmetric m x m
  *   matrix (m <= 1024); lam unsorted, V's column j (V[i*ldv + j]) belongs to
  *   lam[j].  method FDSK_EIG_AUTO: Householder tridiagonalisation, divide and
- *   conquer and back-transformation for m <= 512, one-sided block Jacobi
- *   above; FDSK_EIG_JACOBI: the Jacobi solvers at every m (cyclic two-sided in
+ *   conquer and back-transformation at every m; FDSK_EIG_JACOBI: the Jacobi
+ *   solvers at every m (cyclic two-sided in
  *   LDS for m <= 100).  Errors: EINVAL, EUNSUPPORTED (m > 1024), ENOMEM,
  *   EDEVICE. */
 #define FDSK_EIG_AUTO 0

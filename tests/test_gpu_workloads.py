@@ -1,16 +1,19 @@
-"""Parity at the workloads' own sizes.
+"""Parity at the workloads' own shapes on prefixes the oracle finishes inline
+(the whole streams are in test_gpu_fullsize.py, against stored results).
 
-* Random Noisy 100,000 x 1,000 fp32 (the bench workload): the whole stream,
-  FD l = 100, against the oracle on the same rows.
-* Power-law 3,072 columns, bf16 rows, l = 256 (buffer 512 rows, block Jacobi
-  eigensolver), split-BF16 Gram/rebuild: the first 20,000 rows of the stream.
+* Random Noisy 100,000 x 1,000 fp32 (the single-stream workload): the whole
+  stream, FD l = 100, against the oracle on the same rows.
+* Power-law 3,072 columns, bf16 rows, l = 256 (buffer 512 rows, the
+  tridiagonal route with one pair of launches per column), split-BF16
+  Gram/rebuild: the first 20,000 rows of the stream.
 * Random Noisy 8,192 columns (rank 512, zeta = 20), alpha-FD with alpha = 0.2,
   l = 512 (buffer 1,024 rows), FP8 Gram: the first 4,096-row chunk of the
   stream.  The oracle's dense evaluator would need an 8,192 x 8,192
   eigendecomposition, so the two sketches are compared through
   ||B_gpu^T B_gpu - B_or^T B_or||_2 / ||A||_F^2, which bounds the difference
   of their covariance errors (triangle inequality), by power iteration on the
-  host, and through the device's matrix-free evaluator run on both.
+  host, and through the device's matrix-free evaluator run on both (pinned at
+  8,192 columns in test_gpu_eval.py).
 """
 import numpy as np
 import pytest
