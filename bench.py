@@ -471,6 +471,17 @@ def main():
     value = total_rows / (ms / 1e3)
     print(f"[bench] batch bf16x3: {ms:.1f} ms/step, {value:.4g} rows/s", file=sys.stderr, flush=True)
 
+    # The same batch with the launch-shape tuner off (fixed default shapes).
+    from paper_1501_06561_amd import fdsketch as F
+    mode = F.tune_mode()
+    F.tune_mode("off")
+    ms_fixed, _, _, b = run_batch(cfg("bf16x3"), rows, 1, 1, graph=graph)
+    b.close()
+    F.tune_mode(mode)
+    tuning = {"mode": mode, "cache": F.tune_path(), "fixed_shapes_ms_per_step": ms_fixed,
+              "choices": {k_: {"value": v_[0], "timings_us": v_[1]} for k_, v_ in F.tune_table().items()}}
+    print(f"[bench] batch bf16x3, fixed shapes: {ms_fixed:.1f} ms/step", file=sys.stderr, flush=True)
+
     # The same batch in FP64.
     ms64, per64, outs_64, b = run_batch(cfg("fp64"), rows, 1, 1, graph=graph)
     b.close()
@@ -574,6 +585,7 @@ def main():
             {"value": total_rows / (ms_alt / 1e3), "ms_per_step": ms_alt,
              "ms_per_step_median": float(np.median(per_alt))},
         "roofline": roof,
+        "tuning": tuning,
         "stages_batch_bf16x3": stages_bf,
         "stages_batch_fp64": stages_64,
         "profiled_step_ms": {"bf16x3": ms_p, "fp64": ms_p64},

@@ -424,6 +424,78 @@ void rsketch_destroy(fdsk_rsketch* s);
  * failure. */
 const char* rsketch_last_error(const fdsk_rsketch* s);
 
+/* ------------------------------------------------------------------------
+ * Launch-shape tuning of the Gram and rebuild products (the two matrix-core
+ * contractions of a ReduceRank, Algorithm 1).  Several launch shapes compute
+ * each product: the Gram's number of K slices summed afterwards (split-K) and
+ * the rebuild's rows per workgroup (32 or 64).  sketch_create and
+ * sketch_batch_create pick the shape per size bucket by timing every
+ * candidate once on the new sketch's own (still empty) workspaces; the
+ * choice is kept in a per-process table and persisted to a cache file, so
+ * later sketches and processes on the same kind of GPU reuse it.
+ *
+ * Keys name the device ("gfx950/256"), the product, the precision and the
+ * bucket:
+ *   <dev>|gram|p<P>|m<mp>|d<D>           single sketch, value = split-K count
+ *   <dev>|rebuild|p<P>|m<mp>|d<D>        single sketch, value = rows per workgroup
+ *   <dev>|bgram|p<P>|m<mp>|d<D>|n<N>     batch size class, value = K slice
+ *                                        length (0: one slice; else 256, 512
+ *                                        or 1024, raised to d/8 where larger)
+ *   <dev>|brebuild|p<P>|m<mp>|d<D>|n<N>  batch size class, rows per workgroup
+ * with P = 0 (FP64), 3 (BF16x3) or 8 (FP8x3), mp the buffer rows rounded up
+ * to 32 (the class's largest for batches), D the padded row length rounded
+ * up to a power of two (the class's largest), N the class's sketch count
+ * rounded up to a power of two.
+ *
+ * Choices change only the order in which partial sums are added; results of
+ * different choices differ by rounding (the rebuild's rows per workgroup
+ * change nothing).  A batch sketch's slice length is fixed at create, so
+ * its results still do not depend on how sketches are grouped into
+ * launches.  Mode (fdsk_tune_set_mode, or
+ * FDSK_TUNE=off|on|refresh in the environment at first use):
+ *   FDSK_TUNE_OFF      fixed defaults, no timing, the table is not read;
+ *   FDSK_TUNE_ON       (default) use the table, time on a miss;
+ *   FDSK_TUNE_REFRESH  time on every create and overwrite the table.
+ * Cache file: FDSK_TUNE_CACHE, else $XDG_CACHE_HOME/fdsketch/tune.tsv, else
+ * $HOME/.cache/fdsketch/tune.tsv ("" disables it); lines
+ * "key<TAB>value<TAB>candidate:microseconds ...", '#' starts a comment; read
+ * at first use, rewritten (temporary file, then rename) after each new
+ * choice.  A value set by hand is used only when it is one of the
+ * candidates of its key.  The table is process-wide and thread-safe.
+ * ------------------------------------------------------------------------ */
+#define FDSK_TUNE_OFF 0
+#define FDSK_TUNE_ON 1
+#define FDSK_TUNE_REFRESH 2
+/* Set / read the mode.  Errors: EINVAL (unknown mode). */
+int fdsk_tune_set_mode(int32_t mode);
+int fdsk_tune_get_mode(void);
+/* Value of key: 0 and *value set when present, 1 when absent; EINVAL for
+ * NULL arguments. */
+int fdsk_tune_lookup(const char* key, int32_t* value);
+/* Put key = value in the table (not written to the file until a later
+ * choice or fdsk_tune_save).  Errors: EINVAL (NULL/empty key, or a key
+ * holding a tab or newline). */
+int fdsk_tune_set(const char* key, int32_t value);
+/* Empty the table (the file is untouched). */
+int fdsk_tune_clear(void);
+/* Set the cache file used from now on (NULL or "": none); nothing is read. */
+int fdsk_tune_set_path(const char* path);
+/* Current cache file path ("" if none); valid until the next tune call. */
+const char* fdsk_tune_path(void);
+/* Merge the entries of path (NULL: the cache file) into the table.
+ * Errors: EINVAL (unreadable). */
+int fdsk_tune_load(const char* path);
+/* Write the table to path (NULL: the cache file).  Errors: EINVAL (no
+ * path), EDEVICE (the file could not be written; message from
+ * fdsk_tune_last_error). */
+int fdsk_tune_save(const char* path);
+/* The table as text (the cache file's lines) into buf (cap bytes, NUL
+ * terminated, truncated if short; buf may be NULL); returns the full
+ * length. */
+int32_t fdsk_tune_dump(char* buf, int64_t cap);
+/* Last load/save failure of the tuner ("" if none). */
+const char* fdsk_tune_last_error(void);
+
 /* Library build information (static string). */
 const char* fdsk_version(void);
 

@@ -29,7 +29,7 @@ FLAGS = [
 ]
 SOURCES = ["kernels_stream.hip", "kernels_eig.hip", "kernels_trid.hip", "kernels_eval.hip",
            "kernels_lowp.hip", "noalloc.hip", "rsketch.hip",
-           "eval_host.cpp", "batch_host.cpp", "fdsketch.cpp"]
+           "eval_host.cpp", "batch_host.cpp", "fdsketch.cpp", "tune.cpp"]
 
 
 def _compile(src: str) -> str:

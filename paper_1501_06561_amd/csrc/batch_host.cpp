@@ -12,6 +12,7 @@
 #include <vector>
 
 #include "fdsk_batch.hpp"
+#include "fdsk_tune.hpp"
 #include "fdsketch.h"
 
 using namespace fdsk;
@@ -36,6 +37,11 @@ struct fdsk_batch {
   hipEvent_t ev_in = nullptr, ev_out[kClasses] = {};
   void* d_tasks_c[kClasses] = {};
   size_t tasks_cap_c[kClasses] = {};
+  // The rebuild's tuned rows per workgroup per size class and precision (0
+  // FP64, 1 BF16x3); a launch takes its first task's class (the rows per
+  // workgroup change no result).  The Gram's tuned K slice length is each
+  // sketch's own (GroupSketch::kchunk).
+  int rebuild_rt[kClasses][2] = {{32, 32}, {32, 32}, {32, 32}, {32, 32}};
   bool finalized = false;
   int err = 0;
   std::string msg;
@@ -239,7 +245,7 @@ hipError_t launch_round(fdsk_batch* b, const Plan& p, const Staged& sg, size_t r
   }
   for (size_t c0 = 0; c0 < vr.size() && e == hipSuccess; c0 += cap) {
     const int nt = static_cast<int>(std::min<size_t>(cap, vr.size() - c0));
-    int max_mp = 0, max_m = 0, max_ldc = 0, max_keep = 0;
+    int max_mp = 0, max_m = 0, max_ldc = 0, max_keep = 0, ks = 1;
     bool p0 = false, p1 = false, p3 = false;   // precisions present in this launch
     double w_gram = 0, w_head = 0, w_trid = 0, w_dc = 0, w_bt = 0, w_reb = 0;
     for (int t = 0; t < nt; ++t) {
@@ -251,6 +257,8 @@ hipError_t launch_round(fdsk_batch* b, const Plan& p, const Staged& sg, size_t r
       p0 |= s.npass == 0;
       p1 |= s.npass == 1;
       p3 |= s.npass == 3;
+      const int kc = task_kchunk(s.kchunk, s.ldc);
+      ks = std::max(ks, (s.ldc + kc - 1) / kc);
       const double m = s.m, d = s.d, np = std::max(s.npass, 1);
       w_gram += np * m * (m + 1.0) * d;
       // Householder reduction: 4/3 n^3 over n columns, split between the
@@ -263,9 +271,10 @@ hipError_t launch_round(fdsk_batch* b, const Plan& p, const Staged& sg, size_t r
       w_reb += np * 2.0 * s.rp.keep * m * d;
     }
     const GroupRR* tt = sg.d_rr + sg.orr[r] + c0;
+    const int g = size_class(b->sk[vr[c0].sk].m);
     hipEvent_t a = mark(b, st);
-    if (p1 || p3) e = launch_group_gram_lowp(b->d_sk, tt, nt, max_mp, max_ldc, p1, p3, st);
-    if (e == hipSuccess) e = launch_group_gram(b->d_sk, tt, nt, max_mp, p0, st);
+    if (p1 || p3) e = launch_group_gram_lowp(b->d_sk, tt, nt, max_mp, max_ldc, p1, p3, ks, -1, st);
+    if (e == hipSuccess) e = launch_group_gram(b->d_sk, tt, nt, max_mp, p0, ks, -1, st);
     add_mark(b, FDSK_STAGE_GRAM, a, st, w_gram);
     hipEvent_t eig0 = mark(b, st);
     if (e == hipSuccess && max_m > 208) {
@@ -277,7 +286,7 @@ hipError_t launch_round(fdsk_batch* b, const Plan& p, const Staged& sg, size_t r
     if (e == hipSuccess) e = launch_group_tridiag(b->d_sk, tt, nt, max_m, st);
     add_mark(b, FDSK_STAGE_TRIDIAG, a, st, w_trid);
     a = mark(b, st);
-    if (e == hipSuccess) e = launch_group_dc(b->d_sk, tt, nt, st);
+    if (e == hipSuccess) e = launch_group_dc(b->d_sk, tt, nt, max_m, st);
     add_mark(b, FDSK_STAGE_DC, a, st, w_dc);
     a = mark(b, st);
     if (e == hipSuccess) e = launch_group_backtr(b->d_sk, tt, nt, max_m, st);
@@ -287,9 +296,10 @@ hipError_t launch_round(fdsk_batch* b, const Plan& p, const Staged& sg, size_t r
     if (e == hipSuccess) e = launch_group_shrink(b->d_sk, tt, nt, st);
     add_mark(b, FDSK_STAGE_SHRINK, a, st, 0.0);
     a = mark(b, st);
-    if (e == hipSuccess && p0) e = launch_group_rebuild(b->d_sk, tt, nt, max_ldc, max_keep, st);
+    if (e == hipSuccess && p0)
+      e = launch_group_rebuild(b->d_sk, tt, nt, max_ldc, max_keep, b->rebuild_rt[g][0], st);
     if (e == hipSuccess && (p1 || p3))
-      e = launch_group_rebuild_lowp(b->d_sk, tt, nt, max_ldc, max_keep, p1, p3, st);
+      e = launch_group_rebuild_lowp(b->d_sk, tt, nt, max_ldc, max_keep, p1, p3, b->rebuild_rt[g][1], st);
     add_mark(b, FDSK_STAGE_REBUILD, a, st, w_reb);
   }
   return e;
@@ -467,6 +477,87 @@ int run_class_plans(fdsk_batch* b, Plan* plans, int dt, int cap) {
   return 0;
 }
 
+// Pick every size class's Gram K slice length and rebuild rows per
+// workgroup (see fdsk_tune.hpp), per precision, on the new batch's zeroed
+// workspaces: one task per sketch of the class and precision, timed over
+// launches of all of them, a quarter, a sixteenth and one (the rounds of a
+// call hold fewer and fewer sketches as the short streams finish).  The
+// candidates write zeros into Gp, G and the second buffers.  The chosen
+// slice length goes into the sketches' descriptors (uploaded by the
+// caller).
+hipError_t tune_batch(fdsk_batch* b) {
+  constexpr int K = fdsk_batch::kClasses;
+  if (tune_mode() == TUNE_OFF) return hipSuccess;
+  const std::string dev = tune_device_tag();
+  std::vector<GroupRR> tasks[K][2];
+  for (int i = 0; i < b->S; ++i) {
+    const GroupSketch& D = b->sk[i];
+    tasks[size_class(D.m)][D.npass ? 1 : 0].push_back({i, 0, 0, 0});
+  }
+  size_t total = 0;
+  for (int g = 0; g < K; ++g)
+    for (int q = 0; q < 2; ++q) {
+      std::stable_sort(tasks[g][q].begin(), tasks[g][q].end(),
+                       [b](const GroupRR& x, const GroupRR& y) { return b->sk[x.sk].m > b->sk[y.sk].m; });
+      total += tasks[g][q].size();
+    }
+  GroupRR* d_t = nullptr;
+  hipError_t e = hipMalloc(&d_t, total * sizeof(GroupRR));
+  if (e != hipSuccess) return e;
+  size_t off = 0;
+  for (int g = 0; g < K && e == hipSuccess; ++g)
+    for (int q = 0; q < 2 && e == hipSuccess; ++q) {
+      const auto& v = tasks[g][q];
+      if (v.empty()) continue;
+      const GroupRR* tt = d_t + off;
+      e = hipMemcpy(d_t + off, v.data(), v.size() * sizeof(GroupRR), hipMemcpyHostToDevice);
+      off += v.size();
+      if (e != hipSuccess) break;
+      const int N = static_cast<int>(v.size());
+      int max_mp = 0, max_ldc = 0, max_keep = 0;
+      for (const auto& t : v) {
+        max_mp = std::max(max_mp, b->sk[t.sk].mp);
+        max_ldc = std::max(max_ldc, b->sk[t.sk].ldc);
+        max_keep = std::max(max_keep, b->sk[t.sk].rp.keep);
+      }
+      std::vector<int> counts{N};
+      for (int c : {(N + 3) / 4, (N + 15) / 16, 1})
+        if (c != counts.back()) counts.push_back(c);
+      const std::string key = "|p" + std::to_string(q ? 3 : 0) + "|m" + std::to_string(max_mp) + "|d" +
+                              std::to_string(tune_bucket(max_ldc)) + "|n" + std::to_string(tune_bucket(N));
+      hipStream_t st = b->stream;
+      const int kc = tune_pick(dev + "|bgram" + key, {0, 256, 512, 1024}, 0, st, [&](int cand) {
+        hipError_t ee = hipSuccess;
+        for (int nt : counts) {
+          int ks = 1;
+          for (int j = 0; j < nt; ++j) {
+            const int ldc = b->sk[v[j].sk].ldc, c = task_kchunk(cand, ldc);
+            ks = std::max(ks, (ldc + c - 1) / c);
+          }
+          if (q && ee == hipSuccess)
+            ee = launch_group_gram_lowp(b->d_sk, tt, nt, max_mp, max_ldc, false, true, ks, cand, st);
+          if (ee == hipSuccess) ee = launch_group_gram(b->d_sk, tt, nt, max_mp, !q, ks, cand, st);
+        }
+        return ee;
+      });
+      for (const auto& t : v) b->sk[t.sk].kchunk = kc;
+      if (max_keep > 32)
+        b->rebuild_rt[g][q] = tune_pick(dev + "|brebuild" + key, {32, 64}, 32, st, [&](int rt) {
+          hipError_t ee = hipSuccess;
+          for (int nt : counts) {
+            if (ee != hipSuccess) break;
+            ee = q ? launch_group_rebuild_lowp(b->d_sk, tt, nt, max_ldc, max_keep, false, true, rt, st)
+                   : launch_group_rebuild(b->d_sk, tt, nt, max_ldc, max_keep, rt, st);
+          }
+          return ee;
+        });
+    }
+  const hipError_t es = hipStreamSynchronize(b->stream);
+  if (e == hipSuccess) e = es;
+  (void)hipFree(d_t);
+  return e;
+}
+
 }  // namespace
 
 extern "C" {
@@ -539,7 +630,8 @@ int sketch_batch_create(int32_t S, const fdsk_config* cfgs, void* hip_stream, fd
     size_t* q = &o[static_cast<size_t>(i) * NB];
     q[0] = take(cb);
     q[1] = take(cb);
-    for (int k = 2; k < 9; ++k) q[k] = take(g);
+    q[2] = take(g * gp_parts(D.ldc));
+    for (int k = 3; k < 9; ++k) q[k] = take(g);
     q[9] = take(static_cast<size_t>(D.mp) * 8);
     q[10] = take(static_cast<size_t>(D.mp) * 8);
     q[11] = take(D.npass > 0 ? bf16_workspace_bytes(D.mp, D.ldc) : 0);
@@ -564,6 +656,10 @@ int sketch_batch_create(int32_t S, const fdsk_config* cfgs, void* hip_stream, fd
     D.st = b->d_stats + i;
   }
   e = hipMemsetAsync(b->arena, 0, off, b->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(b->d_sk, b->sk.data(), sizeof(GroupSketch) * S, hipMemcpyHostToDevice, b->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+  if (e == hipSuccess) e = tune_batch(b);
   if (e == hipSuccess)
     e = hipMemcpyAsync(b->d_sk, b->sk.data(), sizeof(GroupSketch) * S, hipMemcpyHostToDevice, b->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(b->stream);

@@ -12,6 +12,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <algorithm>
+
 #include "fdsk_kernels.hpp"
 
 namespace fdsk {
@@ -20,7 +22,7 @@ namespace fdsk {
 struct GroupSketch {
   double* C0;        // mp x ldc buffers (the rebuild writes the other one)
   double* C1;
-  double* Gp;        // mp x mp Gram, lower tiles
+  double* Gp;        // gp_parts(ldc) x mp x mp Gram partials, lower tiles
   double* G;         // mp x mp Gram, symmetric
   double* W;         // mp x mp reflectors / tridiagonal
   double* V;         // mp x mp eigenvectors (column-major)
@@ -33,6 +35,7 @@ struct GroupSketch {
   DevStats* st;
   int d, ldc, l, m, mp;
   int npass;         // Gram/rebuild products: 0 FP64, 1 BF16, 3 split-BF16 (compensated)
+  int kchunk;        // Gram K slice length (see task_kchunk), tuned per size class
   RuleParams rp;
 };
 
@@ -53,24 +56,41 @@ struct GroupSpan {        // rows [r0, r1) of C[cur] (zeroing, pending norms)
 // Launch shapes come from the host, which knows every task of the round.
 hipError_t launch_group_ingest(const GroupSketch* sk, const GroupIngest* t, int nt, int max_f, int dt,
                                hipStream_t s);
-// FP64 Gram for tasks with npass 0, then the symmetric mirror for every task.
-hipError_t launch_group_gram(const GroupSketch* sk, const GroupRR* t, int nt, int max_mp, bool fp64,
-                             hipStream_t s);
+// Gram products split along K: a task's row length is cut into slices of
+// task_kchunk(kc, ldc) columns, one partial per slice in the task's Gp,
+// which holds gp_parts(ldc) partials.  kc is the sketch's own slice length
+// (GroupSketch::kchunk: 0 = one slice, else 256, 512 or 1024), raised where
+// needed so that no task has more than kGpParts slices; it depends on the
+// sketch alone, so results do not depend on how tasks are grouped.
+constexpr int kGpParts = 8;
+inline int gp_parts(int ldc) { return std::max(1, std::min(kGpParts, (ldc + 255) / 256)); }
+__host__ __device__ inline int task_kchunk(int kc, int ldc) {
+  if (kc <= 0) return ldc;
+  const int lo = ((ldc + kGpParts - 1) / kGpParts + 63) / 64 * 64;
+  return kc > lo ? kc : lo;
+}
+// FP64 Gram for tasks with npass 0, then the sum of every task's partials
+// and the symmetric mirror.  ks: the largest slice count of the tasks (the
+// grid's K dimension).  kc >= 0 replaces every task's own kchunk (the
+// tuner's candidates); -1 uses them.
+hipError_t launch_group_gram(const GroupSketch* sk, const GroupRR* t, int nt, int max_mp, bool fp64, int ks,
+                             int kc, hipStream_t s);
 hipError_t launch_group_gram_lowp(const GroupSketch* sk, const GroupRR* t, int nt, int max_mp, int max_ldc,
-                                  bool one, bool three, hipStream_t s);
+                                  bool one, bool three, int ks, int kc, hipStream_t s);
+// Rebuilds with rt (32 or 64) rows per workgroup.
 hipError_t launch_group_rebuild_lowp(const GroupSketch* sk, const GroupRR* t, int nt, int max_ldc,
-                                     int max_keep, bool one, bool three, hipStream_t s);
+                                     int max_keep, bool one, bool three, int rt, hipStream_t s);
 // The eigensolve of the tridiagonal route in its three stages (the head of
 // the reduction only for buffers above the register capacity).
 hipError_t launch_group_tridiag_head(const GroupSketch* sk, const GroupRR* t, int nt, int max_m,
                                      hipStream_t s);
 hipError_t launch_group_tridiag(const GroupSketch* sk, const GroupRR* t, int nt, int max_m, hipStream_t s);
-hipError_t launch_group_dc(const GroupSketch* sk, const GroupRR* t, int nt, hipStream_t s);
+hipError_t launch_group_dc(const GroupSketch* sk, const GroupRR* t, int nt, int max_m, hipStream_t s);
 hipError_t launch_group_backtr(const GroupSketch* sk, const GroupRR* t, int nt, int max_m, hipStream_t s);
 hipError_t launch_group_shrink(const GroupSketch* sk, const GroupRR* t, int nt, hipStream_t s);
 // The FP64 rebuild for tasks with npass 0.
 hipError_t launch_group_rebuild(const GroupSketch* sk, const GroupRR* t, int nt, int max_ldc, int max_keep,
-                                hipStream_t s);
+                                int rt, hipStream_t s);
 hipError_t launch_group_zero(const GroupSketch* sk, const GroupSpan* t, int nt, hipStream_t s);
 hipError_t launch_group_pending(const GroupSketch* sk, const GroupSpan* t, int nt, hipStream_t s);
 

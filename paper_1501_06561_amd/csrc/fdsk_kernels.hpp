@@ -53,8 +53,20 @@ constexpr double kNullRel = 1e-12;
 
 hipError_t launch_ingest(const void* src, int dt, int64_t stride, int f, int d, double* C, int ldc,
                          int row0, double* rownorm, hipStream_t s);
+// Split-K count of the single-buffer Gram when none is requested: enough
+// K slices to give about 256 workgroups over ntiles output tiles, each slice
+// at least 256 columns.
+inline int gram_ksplit_default(int ntiles, int ldc) {
+  int k = (256 + ntiles - 1) / ntiles;
+  const int cap = ldc / 256 > 1 ? ldc / 256 : 1;
+  return k < cap ? k : cap;
+}
+// Gram G = C C^T of an mp-row buffer: ksplit_req K slices (0: the default
+// above), at most ksplit_max (Gpart holds ksplit_max mp x mp partials); the
+// slice length is rounded up to the kernel's K step, which may lower the
+// count.
 hipError_t launch_gram(const double* C, int ldc, int mp, double* Gpart, int ksplit_max, double* G,
-                       hipStream_t s);
+                       hipStream_t s, int ksplit_req = 0);
 hipError_t launch_gram_reduce(const double* Gpart, int ksplit, int mp, double* G, hipStream_t s);
 // BF16 matrix-core Gram / rebuild on the FP64 buffer; npass 1 = hi*hi,
 // 3 = hi*hi + hi*lo + lo*hi (split-bf16 compensation), FP32 accumulation.
@@ -62,7 +74,7 @@ hipError_t launch_gram_reduce(const double* Gpart, int ksplit, int mp, double* G
 // hi/lo halves (written by the Gram, read by the rebuild of the same
 // ReduceRank), or null to split inside the products.
 hipError_t launch_gram_lowp(const double* C, int ldc, int mp, double* Gpart, int ksplit_max, double* G,
-                            int npass, void* bfw, hipStream_t s);
+                            int npass, void* bfw, hipStream_t s, int ksplit_req = 0);
 size_t bf16_workspace_bytes(int mp, int ldc);
 // The buffer's hi/lo bf16 halves into bfw (for a rebuild whose Gram did not
 // write them: the FP8 path).
@@ -70,15 +82,17 @@ hipError_t launch_split_bf16(const double* C, int ldc, int mp, void* bfw, hipStr
 // FP8 (e4m3) compensated Gram: per-row scaled hi/lo codes of C in q8
 // (fp8_workspace_bytes), then three FP8 products per tile.
 hipError_t launch_gram_fp8(const double* C, int ldc, int mp, void* q8, double* Gpart, int ksplit_max,
-                           double* G, hipStream_t s);
+                           double* G, hipStream_t s, int ksplit_req = 0);
 size_t fp8_workspace_bytes(int mp, int ldc);
+// Rebuilds out[0:keep] = Ut[0:keep] C with rt (32 or 64) output rows per
+// workgroup (the lowp path without pre-split halves always uses 32).
 hipError_t launch_rebuild_lowp(const double* Ut, const double* C, int ldc, int mp, int keep, double* out,
-                               int npass, const void* bfw, hipStream_t s);
+                               int npass, const void* bfw, hipStream_t s, int rt = 32);
 hipError_t launch_shrink(const double* lam, const double* V, int m, int mp, RuleParams rp,
                          const double* rownorm, int new0, int new1, double* Ut, DevStats* st,
                          hipStream_t s);
 hipError_t launch_rebuild(const double* Ut, const double* C, int ldc, int mp, int keep, double* out,
-                          hipStream_t s);
+                          hipStream_t s, int rt = 32);
 hipError_t launch_zero_rows(double* C, int ldc, int r0, int r1, hipStream_t s);
 // out[i] = ||C_i||^2 (FP64) for rows i < rows of a buffer with d columns.
 hipError_t launch_row_mass(const double* C, int ldc, int rows, int d, double* out, hipStream_t s);

@@ -20,6 +20,7 @@
 #include "fdsk_kernels.hpp"
 #include "fdsk_eval.hpp"
 #include "fdsk_eval_api.hpp"
+#include "fdsk_tune.hpp"
 #include "fdsketch.h"
 
 using namespace fdsk;
@@ -37,7 +38,9 @@ struct fdsk_sketch {
   double *mass_b = nullptr, *mass_a = nullptr;   // row masses before / after a reduction
   void* q8 = nullptr;   // FP8 codes and scales of the buffer (FDSK_P_FP8X3)
   void* bfw = nullptr;  // the buffer's bf16 hi/lo halves (every reduced precision)
-  int ksplit_max = 1;
+  int ksplit_max = 1;   // Gram partials the workspace holds
+  int ksplit = 0;       // tuned Gram split-K count (0: the launch's default)
+  int rt = 32;          // tuned rebuild rows per workgroup
   DevStats* st = nullptr;
   unsigned* bar = nullptr;
   int* rot = nullptr;
@@ -151,19 +154,68 @@ double work_backtr(const fdsk_sketch* s) {
   return 2.0 * s->m * s->m * (double)std::min(s->m, s->l);
 }
 
+// The Gram of buffer C in the sketch's precision with ksplit K slices (0:
+// the launch's default count).
+hipError_t gram_launch(fdsk_sketch* s, const double* C, int ksplit) {
+  if (s->cfg.precision == FDSK_P_FP64)
+    return launch_gram(C, s->ldc, s->mp, s->Gpart, s->ksplit_max, s->G, s->stream, ksplit);
+  if (s->cfg.precision == FDSK_P_FP8X3)
+    return launch_gram_fp8(C, s->ldc, s->mp, s->q8, s->Gpart, s->ksplit_max, s->G, s->stream, ksplit);
+  const int npass = s->cfg.precision == FDSK_P_BF16 ? 1 : 3;
+  return launch_gram_lowp(C, s->ldc, s->mp, s->Gpart, s->ksplit_max, s->G, npass, s->bfw, s->stream, ksplit);
+}
+
+// Precision tag of the tuning keys: the Gram's arithmetic, and the rebuild's
+// (FP8X3 rebuilds with split-BF16 x3).
+int gram_tag(const fdsk_sketch* s) {
+  switch (s->cfg.precision) {
+    case FDSK_P_FP64: return 0;
+    case FDSK_P_BF16: return 1;
+    case FDSK_P_FP8X3: return 8;
+    default: return 3;
+  }
+}
+int rebuild_tag(const fdsk_sketch* s) { return s->cfg.precision == FDSK_P_FP64 ? 0 : 3; }
+
+// Pick the Gram's split-K count and the rebuild's rows per workgroup for
+// this sketch's sizes (see fdsk_tune.hpp).  Runs on the new sketch's zeroed
+// workspaces, which the candidates overwrite with zeros.
+int tune_shapes(fdsk_sketch* s) {
+  if (tune_mode() == TUNE_OFF) return 0;
+  const std::string dev = tune_device_tag();
+  const std::string sizes = "|m" + std::to_string(s->mp) + "|d" + std::to_string(tune_bucket(s->ldc));
+  // Gram: the default count and every power of two the workspace holds.
+  const int tile = s->cfg.precision == FDSK_P_FP64 || s->cfg.precision == FDSK_P_FP8X3 ? 32 : 64;
+  const int T = (s->mp + tile - 1) / tile;
+  const int dflt = std::min(gram_ksplit_default(T * (T + 1) / 2, s->ldc), s->ksplit_max);
+  std::vector<int> cand{dflt};
+  for (int k = 1; k <= s->ksplit_max; k *= 2)
+    if (k != dflt) cand.push_back(k);
+  s->ksplit = tune_pick(dev + "|gram|p" + std::to_string(gram_tag(s)) + sizes, cand, dflt, s->stream,
+                        [s](int k) { return gram_launch(s, s->C[0], k); });
+  // Rebuild: 32 or 64 rows per workgroup (64 only when more than 32 rows
+  // are kept).
+  const int keep = s->rp.keep;
+  if (keep > 32) {
+    const int npass = s->cfg.precision == FDSK_P_BF16 ? 1 : 3;
+    s->rt = tune_pick(dev + "|rebuild|p" + std::to_string(rebuild_tag(s)) + sizes, {32, 64}, 32, s->stream,
+                      [s, keep, npass](int rt) {
+                        if (s->cfg.precision == FDSK_P_FP64)
+                          return launch_rebuild(s->Ut, s->C[0], s->ldc, s->mp, keep, s->C[1], s->stream, rt);
+                        return launch_rebuild_lowp(s->Ut, s->C[0], s->ldc, s->mp, keep, s->C[1], npass, s->bfw,
+                                                   s->stream, rt);
+                      });
+  }
+  HIPCHK(s, hipStreamSynchronize(s->stream));
+  return 0;
+}
+
 // Gram and eigensolve of the current buffer: lam and V on the device.
 int spectrum(fdsk_sketch* s) {
   EigWork wk{s->W, s->bar, s->rot, s->st, s->S1, s->S2,
              (s->cfg.flags & FDSK_FLAG_EIG_JACOBI) ? EIG_JACOBI : EIG_AUTO};
   hipEvent_t e0 = mark(s);
-  const int npass = s->cfg.precision == FDSK_P_BF16 ? 1 : 3;
-  if (s->cfg.precision == FDSK_P_FP64)
-    HIPCHK(s, launch_gram(s->C[s->cur], s->ldc, s->mp, s->Gpart, s->ksplit_max, s->G, s->stream));
-  else if (s->cfg.precision == FDSK_P_FP8X3)
-    HIPCHK(s, launch_gram_fp8(s->C[s->cur], s->ldc, s->mp, s->q8, s->Gpart, s->ksplit_max, s->G, s->stream));
-  else
-    HIPCHK(s, launch_gram_lowp(s->C[s->cur], s->ldc, s->mp, s->Gpart, s->ksplit_max, s->G, npass, s->bfw,
-                               s->stream));
+  HIPCHK(s, gram_launch(s, s->C[s->cur], s->ksplit));
   hipEvent_t e1 = mark(s);
   if (eig_uses_trid(s->m, wk)) {
     HIPCHK(s, launch_tridiag(s->G, s->m, s->mp, wk, s->stream));
@@ -195,13 +247,13 @@ int shrink_rebuild(fdsk_sketch* s, const RuleParams& rp, int new0, int new1, con
                           s->stream));
   hipEvent_t e3 = mark(s);
   if (s->cfg.precision == FDSK_P_FP64)
-    HIPCHK(s, launch_rebuild(s->Ut, src, s->ldc, s->mp, rp.keep, dst, s->stream));
+    HIPCHK(s, launch_rebuild(s->Ut, src, s->ldc, s->mp, rp.keep, dst, s->stream, s->rt));
   else {
     // The bf16 paths read the halves the Gram of the same buffer wrote (src
     // is that buffer for every caller); the FP8 Gram wrote none, so FP8X3
     // splits the buffer first and rebuilds with split-BF16 x3.
     if (s->cfg.precision == FDSK_P_FP8X3) HIPCHK(s, launch_split_bf16(src, s->ldc, s->mp, s->bfw, s->stream));
-    HIPCHK(s, launch_rebuild_lowp(s->Ut, src, s->ldc, s->mp, rp.keep, dst, npass, s->bfw, s->stream));
+    HIPCHK(s, launch_rebuild_lowp(s->Ut, src, s->ldc, s->mp, rp.keep, dst, npass, s->bfw, s->stream, s->rt));
   }
   if (rp.mass) {
     HIPCHK(s, launch_row_mass(dst, s->ldc, rp.keep, s->d, s->mass_a, s->stream));
@@ -345,9 +397,9 @@ int sketch_create(const fdsk_config* cfg, void* hip_stream, fdsk_sketch** out) {
   s->rp = make_rule(c);
   s->stream = static_cast<hipStream_t>(hip_stream);
   s->profile = (c.flags & FDSK_FLAG_PROFILE) != 0;
-  const int T = s->mp / 32;
-  const int ntiles = T * (T + 1) / 2;
-  s->ksplit_max = std::max(1, std::min({(256 + ntiles - 1) / ntiles, s->ldc / 256, 16}));
+  // Gram partials: up to 16 K slices of at least 128 columns (the tuner's
+  // candidates).
+  s->ksplit_max = std::max(1, std::min(16, s->ldc / 128));
 
   const size_t mp2 = static_cast<size_t>(s->mp) * s->mp;
   const size_t cbuf = static_cast<size_t>(s->mp) * s->ldc;
@@ -396,6 +448,12 @@ int sketch_create(const fdsk_config* cfg, void* hip_stream, fdsk_sketch** out) {
     delete s;
     return set_err(nullptr, FDSK_EDEVICE, "initialising sketch memory failed: %s",
                    hipGetErrorString(e));
+  }
+  if (tune_shapes(s)) {
+    g_last_error = s->msg;
+    (void)hipFree(s->arena);
+    delete s;
+    return FDSK_EDEVICE;
   }
   *out = s;
   return 0;

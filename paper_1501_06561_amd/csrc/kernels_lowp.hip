@@ -268,25 +268,30 @@ __global__ __launch_bounds__(256) void k_gram_bf16t(const uint16_t* __restrict__
 }
 
 // out[0:keep, :] = Ut[0:keep, 0:mp] * C with C's hi/lo from the pre-split
-// arrays (Ut is split in the loop: it is small).  Tile 32 rows x 64 columns;
+// arrays (Ut is split in the loop: it is small).  Tile RT rows (32 or 64) x
+// 64 columns; wave w owns rows (w>>1)*RT/2.. as RT/32 16-row MFMA tiles.
 // C's 32x64 slab is staged transposed in LDS so that each B fragment is one
-// 16-byte read.
-template <int NPASS>
+// 16-byte read.  Ut rows past mp load as zero.
+template <int NPASS, int RT>
 __device__ __forceinline__ void rebuild_bf16t_body(const double* __restrict__ Ut, const uint16_t* __restrict__ H,
                                                    const uint16_t* __restrict__ L, int ldc, int mp, int keep,
                                                    double* __restrict__ out, int bx, int by) {
-  const int r0 = by * 32, c0 = bx * 64;
-  __shared__ double As[32][33];
+  static_assert(RT == 32 || RT == 64, "rebuild rows per workgroup");
+  constexpr int RA = RT / 32;
+  const int r0 = by * RT, c0 = bx * 64;
+  __shared__ double As[RT][33];
   __shared__ __attribute__((aligned(16))) uint16_t BhT[64][32 + kBpad];
   __shared__ __attribute__((aligned(16))) uint16_t BlT[NPASS == 3 ? 64 : 1][32 + kBpad];
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int wi = w >> 1, wj = w & 1, li = lane & 15, lq = lane >> 4;
-  f32x4 acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = {0.f, 0.f, 0.f, 0.f};
+  f32x4 acc[RA][2];
+#pragma unroll
+  for (int a = 0; a < RA; ++a) acc[a][0] = acc[a][1] = f32x4{0.f, 0.f, 0.f, 0.f};
   for (int k0 = 0; k0 < mp; k0 += 32) {
 #pragma unroll
-    for (int e = 0; e < 4; ++e) {
+    for (int e = 0; e < RT / 8; ++e) {
       const int idx = tid + e * 256, r = idx >> 5, c = idx & 31;
-      As[r][c] = Ut[static_cast<int64_t>(r0 + r) * mp + k0 + c];
+      As[r][c] = (r0 + r < mp) ? Ut[static_cast<int64_t>(r0 + r) * mp + k0 + c] : 0.0;
     }
     {
       const int kr = tid >> 3, nc = (tid & 7) * 8;
@@ -303,14 +308,6 @@ __device__ __forceinline__ void rebuild_bf16t_body(const double* __restrict__ Ut
       }
     }
     __syncthreads();
-    bf16x8_t ah, al;
-#pragma unroll
-    for (int t = 0; t < 8; ++t) {
-      __bf16 h, l;
-      split_bf16(As[wi * 16 + li][8 * lq + t], h, l);
-      ah[t] = h;
-      al[t] = l;
-    }
     const int n0 = wj * 32 + li, n1 = n0 + 16;
     const bf16x8_t b0h = *reinterpret_cast<const bf16x8_t*>(&BhT[n0][8 * lq]);
     const bf16x8_t b1h = *reinterpret_cast<const bf16x8_t*>(&BhT[n1][8 * lq]);
@@ -319,26 +316,39 @@ __device__ __forceinline__ void rebuild_bf16t_body(const double* __restrict__ Ut
       b0l = *reinterpret_cast<const bf16x8_t*>(&BlT[n0][8 * lq]);
       b1l = *reinterpret_cast<const bf16x8_t*>(&BlT[n1][8 * lq]);
     }
-    acc0 = mfma_split<NPASS>(ah, al, b0h, b0l, acc0);
-    acc1 = mfma_split<NPASS>(ah, al, b1h, b1l, acc1);
+#pragma unroll
+    for (int a = 0; a < RA; ++a) {
+      bf16x8_t ah, al;
+#pragma unroll
+      for (int t = 0; t < 8; ++t) {
+        __bf16 h, l;
+        split_bf16(As[wi * (RT / 2) + a * 16 + li][8 * lq + t], h, l);
+        ah[t] = h;
+        al[t] = l;
+      }
+      acc[a][0] = mfma_split<NPASS>(ah, al, b0h, b0l, acc[a][0]);
+      acc[a][1] = mfma_split<NPASS>(ah, al, b1h, b1l, acc[a][1]);
+    }
     __syncthreads();
   }
 #pragma unroll
-  for (int v = 0; v < 4; ++v) {
-    const int row = r0 + wi * 16 + 4 * lq + v;
-    if (row < keep) {
-      const int64_t o = static_cast<int64_t>(row) * ldc + c0 + wj * 32 + li;
-      out[o] = static_cast<double>(acc0[v]);
-      out[o + 16] = static_cast<double>(acc1[v]);
+  for (int a = 0; a < RA; ++a)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int row = r0 + wi * (RT / 2) + a * 16 + 4 * lq + v;
+      if (row < keep) {
+        const int64_t o = static_cast<int64_t>(row) * ldc + c0 + wj * 32 + li;
+        out[o] = static_cast<double>(acc[a][0][v]);
+        out[o + 16] = static_cast<double>(acc[a][1][v]);
+      }
     }
-  }
 }
 
-template <int NPASS>
+template <int NPASS, int RT>
 __global__ __launch_bounds__(256) void k_rebuild_bf16t(const double* __restrict__ Ut, const uint16_t* __restrict__ H,
                                                        const uint16_t* __restrict__ L, int ldc, int mp, int keep,
                                                        double* __restrict__ out) {
-  rebuild_bf16t_body<NPASS>(Ut, H, L, ldc, mp, keep, out, blockIdx.x, blockIdx.y);
+  rebuild_bf16t_body<NPASS, RT>(Ut, H, L, ldc, mp, keep, out, blockIdx.x, blockIdx.y);
 }
 
 hipError_t launch_split_bf16(const double* C, int ldc, int mp, void* bfw, hipStream_t s) {
@@ -350,7 +360,7 @@ hipError_t launch_split_bf16(const double* C, int ldc, int mp, void* bfw, hipStr
 }
 
 hipError_t launch_gram_lowp(const double* C, int ldc, int mp, double* Gpart, int ksplit_max, double* G,
-                            int npass, void* bfw, hipStream_t s) {
+                            int npass, void* bfw, hipStream_t s, int ksplit_req) {
   if (bfw) {
     const int rows64 = (mp + 63) / 64 * 64;
     uint16_t* H = static_cast<uint16_t*>(bfw);
@@ -360,9 +370,8 @@ hipError_t launch_gram_lowp(const double* C, int ldc, int mp, double* Gpart, int
     if (e != hipSuccess) return e;
     const int T = rows64 / kBt;
     const int ntiles = T * (T + 1) / 2;
-    int ksplit = (256 + ntiles - 1) / ntiles;
-    ksplit = std::min(ksplit, std::max(1, ldc / 256));
-    ksplit = std::min(ksplit, ksplit_max);
+    int ksplit = ksplit_req > 0 ? ksplit_req : gram_ksplit_default(ntiles, ldc);
+    ksplit = std::max(1, std::min(ksplit, ksplit_max));
     int kchunk = (ldc + ksplit - 1) / ksplit;
     kchunk = (kchunk + kBk - 1) / kBk * kBk;
     ksplit = (ldc + kchunk - 1) / kchunk;
@@ -376,9 +385,8 @@ hipError_t launch_gram_lowp(const double* C, int ldc, int mp, double* Gpart, int
   }
   const int T = mp / 32;
   const int ntiles = T * (T + 1) / 2;
-  int ksplit = (256 + ntiles - 1) / ntiles;
-  ksplit = std::min(ksplit, std::max(1, ldc / 256));
-  ksplit = std::min(ksplit, ksplit_max);
+  int ksplit = ksplit_req > 0 ? ksplit_req : gram_ksplit_default(ntiles, ldc);
+  ksplit = std::max(1, std::min(ksplit, ksplit_max));
   int kchunk = (ldc + ksplit - 1) / ksplit;
   kchunk = (kchunk + 31) / 32 * 32;
   ksplit = (ldc + kchunk - 1) / kchunk;
@@ -392,19 +400,26 @@ hipError_t launch_gram_lowp(const double* C, int ldc, int mp, double* Gpart, int
 }
 
 hipError_t launch_rebuild_lowp(const double* Ut, const double* C, int ldc, int mp, int keep, double* out,
-                               int npass, const void* bfw, hipStream_t s) {
+                               int npass, const void* bfw, hipStream_t s, int rt) {
   if (keep <= 0) return hipSuccess;
-  dim3 grid(ldc / 64, (keep + 31) / 32);
+  if (rt != 32 && rt != 64) return hipErrorInvalidValue;
   if (bfw) {
     const int rows64 = (mp + 63) / 64 * 64;
     const uint16_t* H = static_cast<const uint16_t*>(bfw);
     const uint16_t* L = H + static_cast<size_t>(rows64) * ldc;
-    if (npass == 3)
-      hipLaunchKernelGGL(k_rebuild_bf16t<3>, grid, dim3(256), 0, s, Ut, H, L, ldc, mp, keep, out);
+    const dim3 g(ldc / 64, (keep + rt - 1) / rt);
+    if (npass == 3 && rt == 64)
+      hipLaunchKernelGGL((k_rebuild_bf16t<3, 64>), g, dim3(256), 0, s, Ut, H, L, ldc, mp, keep, out);
+    else if (npass == 3)
+      hipLaunchKernelGGL((k_rebuild_bf16t<3, 32>), g, dim3(256), 0, s, Ut, H, L, ldc, mp, keep, out);
+    else if (rt == 64)
+      hipLaunchKernelGGL((k_rebuild_bf16t<1, 64>), g, dim3(256), 0, s, Ut, H, L, ldc, mp, keep, out);
     else
-      hipLaunchKernelGGL(k_rebuild_bf16t<1>, grid, dim3(256), 0, s, Ut, H, L, ldc, mp, keep, out);
+      hipLaunchKernelGGL((k_rebuild_bf16t<1, 32>), g, dim3(256), 0, s, Ut, H, L, ldc, mp, keep, out);
     return hipGetLastError();
   }
+  // Without pre-split halves: 32-row tiles, C split inside the product.
+  dim3 grid(ldc / 64, (keep + 31) / 32);
   if (npass == 3)
     hipLaunchKernelGGL(k_rebuild_bf16<3>, grid, dim3(256), 0, s, Ut, C, ldc, mp, keep, out);
   else
@@ -535,7 +550,7 @@ __global__ __launch_bounds__(256) void k_gram_fp8(const uint8_t* __restrict__ Qh
 }
 
 hipError_t launch_gram_fp8(const double* C, int ldc, int mp, void* q8, double* Gpart, int ksplit_max,
-                           double* G, hipStream_t s) {
+                           double* G, hipStream_t s, int ksplit_req) {
   uint8_t* Qh = static_cast<uint8_t*>(q8);
   uint8_t* Ql = Qh + static_cast<size_t>(mp) * ldc;
   double* sc = reinterpret_cast<double*>(Ql + static_cast<size_t>(mp) * ldc);
@@ -545,9 +560,8 @@ hipError_t launch_gram_fp8(const double* C, int ldc, int mp, void* q8, double* G
   if (e != hipSuccess) return e;
   const int T = mp / 32;
   const int ntiles = T * (T + 1) / 2;
-  int ksplit = (256 + ntiles - 1) / ntiles;
-  ksplit = std::min(ksplit, std::max(1, ldc / 256));
-  ksplit = std::min(ksplit, ksplit_max);
+  int ksplit = ksplit_req > 0 ? ksplit_req : gram_ksplit_default(ntiles, ldc);
+  ksplit = std::max(1, std::min(ksplit, ksplit_max));
   int kchunk = (ldc + ksplit - 1) / ksplit;
   kchunk = (kchunk + 31) / 32 * 32;
   ksplit = (ldc + kchunk - 1) / kchunk;
@@ -578,59 +592,72 @@ __global__ __launch_bounds__(256) void kg_split_bf16(const GroupSketch* __restri
                   blockIdx.x, blockIdx.y, gridDim.x);
 }
 
+// Split-K as the FP64 grouped Gram: K slice blockIdx.y of the task's slice
+// length into partial blockIdx.y of its Gp.
 template <int NPASS>
 __global__ __launch_bounds__(256) void kg_gram_bf16(const GroupSketch* __restrict__ SK,
-                                                    const GroupRR* __restrict__ T) {
+                                                    const GroupRR* __restrict__ T, int kc) {
   const GroupRR t = T[blockIdx.z];
   const GroupSketch& s = SK[t.sk];
   if (s.npass != NPASS) return;
   const int rows64 = (s.mp + 63) / 64 * 64, nt = rows64 / kBt;
   if (static_cast<int>(blockIdx.x) >= nt * (nt + 1) / 2) return;
-  gram_bf16t_body<NPASS>(s.bh, s.bh + static_cast<int64_t>(rows64) * s.ldc, s.ldc, s.mp, s.ldc, s.Gp,
-                         blockIdx.x, 0);
+  const int kchunk = task_kchunk(kc >= 0 ? kc : s.kchunk, s.ldc);
+  if (static_cast<int>(blockIdx.y) * kchunk >= s.ldc) return;
+  gram_bf16t_body<NPASS>(s.bh, s.bh + static_cast<int64_t>(rows64) * s.ldc, s.ldc, s.mp, kchunk, s.Gp,
+                         blockIdx.x, blockIdx.y);
 }
 
-template <int NPASS>
+template <int NPASS, int RT>
 __global__ __launch_bounds__(256) void kg_rebuild_bf16(const GroupSketch* __restrict__ SK,
                                                        const GroupRR* __restrict__ T) {
   const GroupRR t = T[blockIdx.z];
   const GroupSketch& s = SK[t.sk];
   if (s.npass != NPASS) return;
-  if (static_cast<int>(blockIdx.x) >= s.ldc / 64 || static_cast<int>(blockIdx.y) * 32 >= s.rp.keep) return;
+  if (static_cast<int>(blockIdx.x) >= s.ldc / 64 || static_cast<int>(blockIdx.y) * RT >= s.rp.keep) return;
   const int rows64 = (s.mp + 63) / 64 * 64;
-  rebuild_bf16t_body<NPASS>(s.Ut, s.bh, s.bh + static_cast<int64_t>(rows64) * s.ldc, s.ldc, s.mp, s.rp.keep,
-                            t.cur ? s.C0 : s.C1, blockIdx.x, blockIdx.y);
+  rebuild_bf16t_body<NPASS, RT>(s.Ut, s.bh, s.bh + static_cast<int64_t>(rows64) * s.ldc, s.ldc, s.mp,
+                                s.rp.keep, t.cur ? s.C0 : s.C1, blockIdx.x, blockIdx.y);
 }
 
 hipError_t launch_group_gram_lowp(const GroupSketch* sk, const GroupRR* t, int nt, int max_mp, int max_ldc,
-                                  bool one, bool three, hipStream_t s) {
+                                  bool one, bool three, int ks, int kc, hipStream_t s) {
   if (nt <= 0) return hipSuccess;
+  if (ks < 1 || ks > kGpParts || (kc > 0 && kc % 64)) return hipErrorInvalidValue;
   const int rows64 = (max_mp + 63) / 64 * 64, T = rows64 / kBt;
   hipLaunchKernelGGL(kg_split_bf16, dim3((max_ldc + 255) / 256, rows64, nt), dim3(256), 0, s, sk, t);
   hipError_t e = hipGetLastError();
-  const dim3 g(T * (T + 1) / 2, 1, nt);
+  const dim3 g(T * (T + 1) / 2, ks, nt);
   if (e == hipSuccess && one) {
-    hipLaunchKernelGGL(kg_gram_bf16<1>, g, dim3(256), 0, s, sk, t);
+    hipLaunchKernelGGL(kg_gram_bf16<1>, g, dim3(256), 0, s, sk, t, kc);
     e = hipGetLastError();
   }
   if (e == hipSuccess && three) {
-    hipLaunchKernelGGL(kg_gram_bf16<3>, g, dim3(256), 0, s, sk, t);
+    hipLaunchKernelGGL(kg_gram_bf16<3>, g, dim3(256), 0, s, sk, t, kc);
+    e = hipGetLastError();
+  }
+  return e;
+}
+
+template <int RT>
+hipError_t group_rebuild_lowp_rt(const GroupSketch* sk, const GroupRR* t, int nt, int max_ldc, int max_keep,
+                                 bool one, bool three, hipStream_t s) {
+  const dim3 g(max_ldc / 64, (max_keep + RT - 1) / RT, nt);
+  if (one) hipLaunchKernelGGL((kg_rebuild_bf16<1, RT>), g, dim3(256), 0, s, sk, t);
+  hipError_t e = hipGetLastError();
+  if (e == hipSuccess && three) {
+    hipLaunchKernelGGL((kg_rebuild_bf16<3, RT>), g, dim3(256), 0, s, sk, t);
     e = hipGetLastError();
   }
   return e;
 }
 
 hipError_t launch_group_rebuild_lowp(const GroupSketch* sk, const GroupRR* t, int nt, int max_ldc,
-                                     int max_keep, bool one, bool three, hipStream_t s) {
+                                     int max_keep, bool one, bool three, int rt, hipStream_t s) {
   if (nt <= 0 || max_keep <= 0) return hipSuccess;
-  const dim3 g(max_ldc / 64, (max_keep + 31) / 32, nt);
-  if (one) hipLaunchKernelGGL(kg_rebuild_bf16<1>, g, dim3(256), 0, s, sk, t);
-  hipError_t e = hipGetLastError();
-  if (e == hipSuccess && three) {
-    hipLaunchKernelGGL(kg_rebuild_bf16<3>, g, dim3(256), 0, s, sk, t);
-    e = hipGetLastError();
-  }
-  return e;
+  if (rt == 64) return group_rebuild_lowp_rt<64>(sk, t, nt, max_ldc, max_keep, one, three, s);
+  if (rt == 32) return group_rebuild_lowp_rt<32>(sk, t, nt, max_ldc, max_keep, one, three, s);
+  return hipErrorInvalidValue;
 }
 
 }  // namespace fdsk

@@ -242,24 +242,32 @@ __global__ __launch_bounds__(1024) void k_shrink(const double* __restrict__ lam_
 }
 
 // ---------------------------------------------------------------- rebuild
-// out[0:keep, :] = Ut[0:keep, 0:mp] * C[0:mp, :].  Tile 32 rows x 64 cols;
-// wave w owns rows (w>>1)*16.. and cols (w&1)*32.. (two 16x16 MFMA tiles).
+// out[0:keep, :] = Ut[0:keep, 0:mp] * C[0:mp, :].  Tile RT rows (32 or 64) x
+// 64 cols; wave w owns rows (w>>1)*RT/2.. and cols (w&1)*32.. as RT/32 x 2
+// 16x16 MFMA tiles, so a 64-row tile reads each column slab of C once for
+// twice the rows.  Ut rows past mp (the last tile of a 64-row launch) load
+// as zero; output rows past keep are not written.
+template <int RT>
 __device__ __forceinline__ void rebuild_body(const double* __restrict__ Ut, const double* __restrict__ C,
                                              int ldc, int mp, int keep, double* __restrict__ out, int bx,
                                              int by) {
-  const int r0 = by * 32, c0 = bx * 64;
-  __shared__ double As[32][33];
+  static_assert(RT == 32 || RT == 64, "rebuild rows per workgroup");
+  constexpr int RA = RT / 32;
+  const int r0 = by * RT, c0 = bx * 64;
+  __shared__ double As[RT][33];
   __shared__ double Bs[32][65];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int wi = w >> 1, wj = w & 1;
   const int li = lane & 15, lk = lane >> 4;
-  f64x4 acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = {0.0, 0.0, 0.0, 0.0};
+  f64x4 acc[RA][2];
+#pragma unroll
+  for (int a = 0; a < RA; ++a) acc[a][0] = acc[a][1] = f64x4{0.0, 0.0, 0.0, 0.0};
   for (int k0 = 0; k0 < mp; k0 += 32) {
 #pragma unroll
-    for (int e = 0; e < 4; ++e) {
+    for (int e = 0; e < RT / 8; ++e) {
       int idx = threadIdx.x + e * 256;
       int r = idx >> 5, c = idx & 31;
-      As[r][c] = Ut[static_cast<int64_t>(r0 + r) * mp + k0 + c];
+      As[r][c] = (r0 + r < mp) ? Ut[static_cast<int64_t>(r0 + r) * mp + k0 + c] : 0.0;
     }
 #pragma unroll
     for (int e = 0; e < 8; ++e) {
@@ -270,29 +278,35 @@ __device__ __forceinline__ void rebuild_body(const double* __restrict__ Ut, cons
     __syncthreads();
 #pragma unroll
     for (int k4 = 0; k4 < 8; ++k4) {
-      double a = As[wi * 16 + li][k4 * 4 + lk];
       double b0 = Bs[k4 * 4 + lk][wj * 32 + li];
       double b1 = Bs[k4 * 4 + lk][wj * 32 + 16 + li];
-      acc0 = mfma_f64(a, b0, acc0);
-      acc1 = mfma_f64(a, b1, acc1);
+#pragma unroll
+      for (int a = 0; a < RA; ++a) {
+        double av = As[wi * (RT / 2) + a * 16 + li][k4 * 4 + lk];
+        acc[a][0] = mfma_f64(av, b0, acc[a][0]);
+        acc[a][1] = mfma_f64(av, b1, acc[a][1]);
+      }
     }
     __syncthreads();
   }
 #pragma unroll
-  for (int v = 0; v < 4; ++v) {
-    int row = r0 + wi * 16 + lk + 4 * v;
-    if (row < keep) {
-      int64_t o = static_cast<int64_t>(row) * ldc + c0 + wj * 32 + li;
-      out[o] = acc0[v];
-      out[o + 16] = acc1[v];
+  for (int a = 0; a < RA; ++a)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      int row = r0 + wi * (RT / 2) + a * 16 + lk + 4 * v;
+      if (row < keep) {
+        int64_t o = static_cast<int64_t>(row) * ldc + c0 + wj * 32 + li;
+        out[o] = acc[a][0][v];
+        out[o + 16] = acc[a][1][v];
+      }
     }
-  }
 }
 
+template <int RT>
 __global__ __launch_bounds__(256) void k_rebuild_f64(const double* __restrict__ Ut,
                                                      const double* __restrict__ C, int ldc,
                                                      int mp, int keep, double* __restrict__ out) {
-  rebuild_body(Ut, C, ldc, mp, keep, out, blockIdx.x, blockIdx.y);
+  rebuild_body<RT>(Ut, C, ldc, mp, keep, out, blockIdx.x, blockIdx.y);
 }
 
 // --------------------------------------------------------------- helpers
@@ -373,12 +387,11 @@ hipError_t launch_ingest(const void* src, int dt, int64_t stride, int f, int d, 
 }
 
 hipError_t launch_gram(const double* C, int ldc, int mp, double* Gpart, int ksplit_max, double* G,
-                       hipStream_t s) {
+                       hipStream_t s, int ksplit_req) {
   const int T = mp / GT;
   const int ntiles = T * (T + 1) / 2;
-  int ksplit = (256 + ntiles - 1) / ntiles;
-  ksplit = std::min(ksplit, std::max(1, ldc / 256));
-  ksplit = std::min(ksplit, ksplit_max);
+  int ksplit = ksplit_req > 0 ? ksplit_req : gram_ksplit_default(ntiles, ldc);
+  ksplit = std::max(1, std::min(ksplit, ksplit_max));
   int kchunk = (ldc + ksplit - 1) / ksplit;
   kchunk = (kchunk + GK - 1) / GK * GK;
   ksplit = (ldc + kchunk - 1) / kchunk;
@@ -404,10 +417,14 @@ hipError_t launch_shrink(const double* lam, const double* V, int m, int mp, Rule
 }
 
 hipError_t launch_rebuild(const double* Ut, const double* C, int ldc, int mp, int keep, double* out,
-                          hipStream_t s) {
+                          hipStream_t s, int rt) {
   if (keep <= 0) return hipSuccess;
-  dim3 grid(ldc / 64, (keep + 31) / 32);
-  hipLaunchKernelGGL(k_rebuild_f64, grid, dim3(256), 0, s, Ut, C, ldc, mp, keep, out);
+  if (rt != 32 && rt != 64) return hipErrorInvalidValue;
+  dim3 grid(ldc / 64, (keep + rt - 1) / rt);
+  if (rt == 64)
+    hipLaunchKernelGGL(k_rebuild_f64<64>, grid, dim3(256), 0, s, Ut, C, ldc, mp, keep, out);
+  else
+    hipLaunchKernelGGL(k_rebuild_f64<32>, grid, dim3(256), 0, s, Ut, C, ldc, mp, keep, out);
   return hipGetLastError();
 }
 
@@ -503,20 +520,26 @@ __global__ __launch_bounds__(256) void kg_ingest(const GroupSketch* __restrict__
   ingest_body(t.src, dt, t.stride, s.d, t.cur ? s.C1 : s.C0, s.ldc, t.row0, s.rownorm, blockIdx.x);
 }
 
+// Split-K: K slice blockIdx.y of the task's slice length (task_kchunk) into
+// partial blockIdx.y of its Gp; slices past the task's row length return.
 __global__ __launch_bounds__(256) void kg_gram(const GroupSketch* __restrict__ SK,
-                                               const GroupRR* __restrict__ T) {
+                                               const GroupRR* __restrict__ T, int kc) {
   const GroupRR t = T[blockIdx.z];
   const GroupSketch& s = SK[t.sk];
   if (s.npass != 0) return;
   const int nt = s.mp / GT;
   if (static_cast<int>(blockIdx.x) >= nt * (nt + 1) / 2) return;
-  gram_body(t.cur ? s.C1 : s.C0, s.ldc, s.mp, s.ldc, s.Gp, blockIdx.x, 0);
+  const int kchunk = task_kchunk(kc >= 0 ? kc : s.kchunk, s.ldc);
+  if (static_cast<int>(blockIdx.y) * kchunk >= s.ldc) return;
+  gram_body(t.cur ? s.C1 : s.C0, s.ldc, s.mp, kchunk, s.Gp, blockIdx.x, blockIdx.y);
 }
 
+// Sum each task's partials in order and mirror the lower triangle into G.
 __global__ __launch_bounds__(256) void kg_mirror(const GroupSketch* __restrict__ SK,
-                                                 const GroupRR* __restrict__ T) {
+                                                 const GroupRR* __restrict__ T, int kc) {
   const GroupSketch& s = SK[T[blockIdx.y].sk];
-  gram_reduce_body(s.Gp, 1, s.mp, s.G, blockIdx.x, gridDim.x);
+  const int kchunk = task_kchunk(kc >= 0 ? kc : s.kchunk, s.ldc);
+  gram_reduce_body(s.Gp, (s.ldc + kchunk - 1) / kchunk, s.mp, s.G, blockIdx.x, gridDim.x);
 }
 
 __global__ __launch_bounds__(1024) void kg_shrink(const GroupSketch* __restrict__ SK,
@@ -526,14 +549,15 @@ __global__ __launch_bounds__(1024) void kg_shrink(const GroupSketch* __restrict_
   shrink_body(s.lam, s.V, s.m, s.mp, s.rp, s.rownorm, t.new0, t.new1, s.Ut, s.st);
 }
 
+template <int RT>
 __global__ __launch_bounds__(256) void kg_rebuild(const GroupSketch* __restrict__ SK,
                                                   const GroupRR* __restrict__ T) {
   const GroupRR t = T[blockIdx.z];
   const GroupSketch& s = SK[t.sk];
   if (s.npass != 0) return;
-  if (static_cast<int>(blockIdx.x) >= s.ldc / 64 || static_cast<int>(blockIdx.y) * 32 >= s.rp.keep) return;
-  rebuild_body(s.Ut, t.cur ? s.C1 : s.C0, s.ldc, s.mp, s.rp.keep, t.cur ? s.C0 : s.C1, blockIdx.x,
-               blockIdx.y);
+  if (static_cast<int>(blockIdx.x) >= s.ldc / 64 || static_cast<int>(blockIdx.y) * RT >= s.rp.keep) return;
+  rebuild_body<RT>(s.Ut, t.cur ? s.C1 : s.C0, s.ldc, s.mp, s.rp.keep, t.cur ? s.C0 : s.C1, blockIdx.x,
+                   blockIdx.y);
 }
 
 __global__ __launch_bounds__(256) void kg_zero(const GroupSketch* __restrict__ SK,
@@ -563,15 +587,16 @@ hipError_t launch_group_ingest(const GroupSketch* sk, const GroupIngest* t, int 
   return hipGetLastError();
 }
 
-hipError_t launch_group_gram(const GroupSketch* sk, const GroupRR* t, int nt, int max_mp, bool fp64,
-                             hipStream_t s) {
+hipError_t launch_group_gram(const GroupSketch* sk, const GroupRR* t, int nt, int max_mp, bool fp64, int ks,
+                             int kc, hipStream_t s) {
   if (nt <= 0) return hipSuccess;
+  if (ks < 1 || ks > kGpParts || (kc > 0 && kc % 64)) return hipErrorInvalidValue;
   const int T = max_mp / GT;
-  if (fp64) hipLaunchKernelGGL(kg_gram, dim3(T * (T + 1) / 2, 1, nt), dim3(256), 0, s, sk, t);
+  if (fp64) hipLaunchKernelGGL(kg_gram, dim3(T * (T + 1) / 2, ks, nt), dim3(256), 0, s, sk, t, kc);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const int nb = std::max(1, std::min(64, (max_mp * max_mp + 255) / 256));
-  hipLaunchKernelGGL(kg_mirror, dim3(nb, nt), dim3(256), 0, s, sk, t);
+  hipLaunchKernelGGL(kg_mirror, dim3(nb, nt), dim3(256), 0, s, sk, t, kc);
   return hipGetLastError();
 }
 
@@ -582,9 +607,14 @@ hipError_t launch_group_shrink(const GroupSketch* sk, const GroupRR* t, int nt, 
 }
 
 hipError_t launch_group_rebuild(const GroupSketch* sk, const GroupRR* t, int nt, int max_ldc, int max_keep,
-                                hipStream_t s) {
+                                int rt, hipStream_t s) {
   if (nt <= 0 || max_keep <= 0) return hipSuccess;
-  hipLaunchKernelGGL(kg_rebuild, dim3(max_ldc / 64, (max_keep + 31) / 32, nt), dim3(256), 0, s, sk, t);
+  if (rt == 64)
+    hipLaunchKernelGGL(kg_rebuild<64>, dim3(max_ldc / 64, (max_keep + 63) / 64, nt), dim3(256), 0, s, sk, t);
+  else if (rt == 32)
+    hipLaunchKernelGGL(kg_rebuild<32>, dim3(max_ldc / 64, (max_keep + 31) / 32, nt), dim3(256), 0, s, sk, t);
+  else
+    return hipErrorInvalidValue;
   return hipGetLastError();
 }
 

@@ -780,7 +780,7 @@ __device__ int secular_root(const double* dd, const double* zz, int kk, int i, d
 // non-deflated roots (they are a suffix: the roots ascend), and the wanted
 // columns are flagged (1.0 / 0.0) at W[P + 3n + 1 + j] for the
 // back-transformation.  Other columns of Z are left undefined.
-template <int NMAX>
+template <int NMAX, int NT>
 __device__ __forceinline__ void dc_body(double* __restrict__ W, int n, double* __restrict__ Z, int ldz,
                                         double* __restrict__ Qc, double* __restrict__ U,
                                         double* __restrict__ lam, DevStats* __restrict__ st, int nvec) {
@@ -798,12 +798,12 @@ __device__ __forceinline__ void dc_body(double* __restrict__ W, int n, double* _
   int levels = 0;
   for (int s = 1; s < n; s *= 2) ++levels;
   int cur = levels & 1;
-  for (int c = w; c < n; c += TNT / 64)
+  for (int c = w; c < n; c += NT / 64)
     for (int r = lane; r < n; r += 64) {
       Z[static_cast<int64_t>(c) * ldz + r] = (r == c) ? 1.0 : 0.0;
       Qc[static_cast<int64_t>(c) * ldz + r] = (r == c) ? 1.0 : 0.0;
     }
-  for (int i = tid; i < n; i += TNT) {
+  for (int i = tid; i < n; i += NT) {
     const double el = (i > 0) ? fabs(eG[i - 1]) : 0.0;
     const double er = (i < n - 1) ? fabs(eG[i]) : 0.0;
     S.D[i] = dG[i] - el - er;
@@ -819,7 +819,7 @@ __device__ __forceinline__ void dc_body(double* __restrict__ W, int n, double* _
     double* Out = cur ? Z : Qc;
     const int nm = (n + 2 * s - 1) / (2 * s);
     // 1. z from the boundary rows, sorted by eigenvalue within each merge.
-    for (int g = tid; g < n; g += TNT) {
+    for (int g = tid; g < n; g += NT) {
       const int b = g / (2 * s);
       int a, k1, k2;
       merge_geom(b, s, n, a, k1, k2);
@@ -842,7 +842,7 @@ __device__ __forceinline__ void dc_body(double* __restrict__ W, int n, double* _
     // 2. Deflation.  a) z-deflation flags (negligible rho |z_j|) and, for the
     //    other entries, whether the previous such entry is close enough for a
     //    Givens rotation (tested on the unrotated values).
-    for (int g = tid; g < n; g += TNT) {
+    for (int g = tid; g < n; g += NT) {
       const int b = g / (2 * s);
       int a, k1, k2;
       merge_geom(b, s, n, a, k1, k2);
@@ -863,7 +863,7 @@ __device__ __forceinline__ void dc_body(double* __restrict__ W, int n, double* _
       if (fabs((S.Ds[g] - S.Ds[a + p]) * c * sn) <= tol) S.zdef[g] = 2;
     }
     __syncthreads();
-    for (int g = tid; g < n; g += TNT) {
+    for (int g = tid; g < n; g += NT) {
       const int b = g / (2 * s);
       if (S.zdef[g] == 2) S.rot_any[b] = 1;
     }
@@ -872,7 +872,7 @@ __device__ __forceinline__ void dc_body(double* __restrict__ W, int n, double* _
     //    first, in sorted order, then the deflated ones).  Merges with one:
     //    the sequential scan below, where each rotation changes the pending
     //    entry's d and z.
-    for (int g = tid; g < n; g += TNT) {
+    for (int g = tid; g < n; g += NT) {
       const int b = g / (2 * s);
       int a, k1, k2;
       merge_geom(b, s, n, a, k1, k2);
@@ -898,7 +898,7 @@ __device__ __forceinline__ void dc_body(double* __restrict__ W, int n, double* _
         S.nrot[b] = 0;
       }
     }
-    for (int b = tid; b < nm; b += TNT) {
+    for (int b = tid; b < nm; b += NT) {
       int a, k1, k2;
       merge_geom(b, s, n, a, k1, k2);
       if (k2 == 0 || !S.rot_any[b]) continue;
@@ -974,7 +974,7 @@ __device__ __forceinline__ void dc_body(double* __restrict__ W, int n, double* _
     }
     // 3. Compact column dest[j] of the merge is the input's local column
     //    perm[j]; the products below read the input through this map.
-    for (int g = tid; g < n; g += TNT) {
+    for (int g = tid; g < n; g += NT) {
       const int b = g / (2 * s);
       int a, k1, k2;
       merge_geom(b, s, n, a, k1, k2);
@@ -982,7 +982,7 @@ __device__ __forceinline__ void dc_body(double* __restrict__ W, int n, double* _
       S.src[a + S.dest[g]] = S.perm[g];
     }
     // 4. Secular roots, four lanes per root.
-    for (int g = g4; g < n; g += TNT / 4) {
+    for (int g = g4; g < n; g += NT / 4) {
       const int b = g / (2 * s);
       int a, k1, k2;
       merge_geom(b, s, n, a, k1, k2);
@@ -1003,12 +1003,12 @@ __device__ __forceinline__ void dc_body(double* __restrict__ W, int n, double* _
       // Rank every final eigenvalue (the same expressions as below, so the
       // same doubles) and mark the nvec largest.
       const int nk0 = S.kk[0];
-      for (int c = tid; c < n; c += TNT) {
+      for (int c = tid; c < n; c += NT) {
         const double v = (c < nk0) ? S.dh[S.org[c]] + S.tau[c] : S.ddf[c - nk0];
         S.rv[c] = (v == v) ? v : -INFINITY;
       }
       __syncthreads();
-      for (int c = tid; c < n; c += TNT) {
+      for (int c = tid; c < n; c += NT) {
         const double vc = S.rv[c];
         int rank = 0;
         for (int j = 0; j < n; ++j) {
@@ -1030,7 +1030,7 @@ __device__ __forceinline__ void dc_body(double* __restrict__ W, int n, double* _
     }
     // 3b. Deflation rotations, in place on the input's columns (read only
     //    by the products and copies below), one thread per row.
-    for (int g = tid; g < n; g += TNT) {
+    for (int g = tid; g < n; g += NT) {
       const int b = g / (2 * s);
       int a, k1, k2;
       merge_geom(b, s, n, a, k1, k2);
@@ -1048,7 +1048,7 @@ __device__ __forceinline__ void dc_body(double* __restrict__ W, int n, double* _
     }
     // 5. z recomputed from the roots (Gu-Eisenstat), signs of z kept:
     //    rho z_i^2 = prod_j (lambda_j - d_i) / prod_{j != i} (d_j - d_i).
-    for (int g = g4; g < n; g += TNT / 4) {
+    for (int g = g4; g < n; g += NT / 4) {
       const int b = g / (2 * s);
       int a, k1, k2;
       merge_geom(b, s, n, a, k1, k2);
@@ -1071,7 +1071,7 @@ __device__ __forceinline__ void dc_body(double* __restrict__ W, int n, double* _
     __syncthreads();
     // 6. Secular eigenvectors, four lanes per root: U(i, j) = z_i / (d_i -
     //    lambda_j), normalised; U row-major within the merge's block.
-    for (int g = g4; g < n; g += TNT / 4) {
+    for (int g = g4; g < n; g += NT / 4) {
       const int b = g / (2 * s);
       int a, k1, k2;
       merge_geom(b, s, n, a, k1, k2);
@@ -1099,7 +1099,7 @@ __device__ __forceinline__ void dc_body(double* __restrict__ W, int n, double* _
     //    computes two vertically adjacent 16 x 16 tiles (sharing the U
     //    fragment).
     const int ntile = S.tile0[nm];
-    for (int t = w; t < ntile; t += TNT / 64) {
+    for (int t = w; t < ntile; t += NT / 64) {
       int b = 0;
       while (S.tile0[b + 1] <= t) ++b;
       int a, k1, k2;
@@ -1162,7 +1162,7 @@ __device__ __forceinline__ void dc_body(double* __restrict__ W, int n, double* _
     }
     // Deflated columns (compact index >= kk) are copied unchanged, and so
     // are the columns of a block with no partner at this level.
-    for (int g = w; g < n; g += TNT / 64) {
+    for (int g = w; g < n; g += NT / 64) {
       const int b = g / (2 * s);
       int a, k1, k2;
       merge_geom(b, s, n, a, k1, k2);
@@ -1180,7 +1180,7 @@ __device__ __forceinline__ void dc_body(double* __restrict__ W, int n, double* _
       for (int r = lane; r < k; r += 64) dst[r] = src[r];
     }
     __syncthreads();
-    for (int g = tid; g < n; g += TNT) {
+    for (int g = tid; g < n; g += NT) {
       const int b = g / (2 * s);
       int a, k1, k2;
       merge_geom(b, s, n, a, k1, k2);
@@ -1191,9 +1191,9 @@ __device__ __forceinline__ void dc_body(double* __restrict__ W, int n, double* _
     }
     __syncthreads();
   }
-  for (int i = tid; i < n; i += TNT) lam[i] = S.D[i] * scale;
+  for (int i = tid; i < n; i += NT) lam[i] = S.D[i] * scale;
   const bool flagged = n >= 2 && nvec < n;
-  for (int i = tid; i < n; i += TNT) W[P + 3 * n + 1 + i] = (!flagged || S.want[i]) ? 1.0 : 0.0;
+  for (int i = tid; i < n; i += NT) W[P + 3 * n + 1 + i] = (!flagged || S.want[i]) ? 1.0 : 0.0;
   if (tid == 0 && st) atomicAdd(&st->eig_sweeps, 1ull);
 }
 
@@ -1201,7 +1201,7 @@ template <int NMAX>
 __global__ __launch_bounds__(TNT) void k_dc(double* __restrict__ W, int n, double* __restrict__ Z, int ldz,
                                             double* __restrict__ Qc, double* __restrict__ U,
                                             double* __restrict__ lam, DevStats* __restrict__ st, int nvec) {
-  dc_body<NMAX>(W, n, Z, ldz, Qc, U, lam, st, nvec);
+  dc_body<NMAX, TNT>(W, n, Z, ldz, Qc, U, lam, st, nvec);
 }
 
 // ---------------------------------------------------------- back-transform
@@ -1580,10 +1580,15 @@ __global__ __launch_bounds__(HNT) void kg_tridiag(const GroupSketch* __restrict_
   tridiag_body<4>(s.G, s.m, s.mp, s.W, s.m - kTridRegMax);
 }
 
-__global__ __launch_bounds__(TNT) void kg_dc(const GroupSketch* __restrict__ SK,
-                                             const GroupRR* __restrict__ T) {
+// Divide and conquer per size class: LDS state for NMAX rows and NT = 4 NMAX
+// threads (one four-lane group per root of the widest merge), so the small
+// classes neither hold the large class's LDS nor wait on its barriers.
+template <int NMAX, int NT>
+__global__ __launch_bounds__(NT) void kg_dc(const GroupSketch* __restrict__ SK,
+                                            const GroupRR* __restrict__ T) {
   const GroupSketch& s = SK[T[blockIdx.x].sk];
-  dc_body<kBatchMax>(s.W, s.m, s.V, s.mp, s.S1, s.S2, s.lam, s.st, min(s.m, s.l));
+  if (s.m > NMAX) return;     // the host picks NMAX >= every task's order
+  dc_body<NMAX, NT>(s.W, s.m, s.V, s.mp, s.S1, s.S2, s.lam, s.st, min(s.m, s.l));
 }
 
 // Size class [LO, HI] of buffer rows, with the LDS staging sized for it;
@@ -1629,9 +1634,15 @@ hipError_t launch_group_tridiag(const GroupSketch* sk, const GroupRR* t, int nt,
   return hipGetLastError();
 }
 
-hipError_t launch_group_dc(const GroupSketch* sk, const GroupRR* t, int nt, hipStream_t s) {
+hipError_t launch_group_dc(const GroupSketch* sk, const GroupRR* t, int nt, int max_m, hipStream_t s) {
   if (nt <= 0) return hipSuccess;
-  hipLaunchKernelGGL(kg_dc, dim3(nt), dim3(TNT), 0, s, sk, t);
+  if (max_m > kBatchMax) return hipErrorInvalidValue;
+  if (max_m <= 64)
+    hipLaunchKernelGGL((kg_dc<64, 256>), dim3(nt), dim3(256), 0, s, sk, t);
+  else if (max_m <= 128)
+    hipLaunchKernelGGL((kg_dc<128, 512>), dim3(nt), dim3(512), 0, s, sk, t);
+  else
+    hipLaunchKernelGGL((kg_dc<kBatchMax, TNT>), dim3(nt), dim3(TNT), 0, s, sk, t);
   return hipGetLastError();
 }
 

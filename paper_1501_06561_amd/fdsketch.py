@@ -31,7 +31,10 @@ EXPORTS = ("sketch_create", "sketch_append_rows", "sketch_merge", "sketch_finali
            "sketch_batch_append", "sketch_batch_finalize", "sketch_batch_stats",
            "sketch_batch_reset", "sketch_batch_profile", "sketch_batch_destroy",
            "sketch_batch_last_error", "fdsk_eigh_noalloc", "rsketch_create", "rsketch_append",
-           "rsketch_finalize", "rsketch_stats", "rsketch_destroy", "rsketch_last_error")
+           "rsketch_finalize", "rsketch_stats", "rsketch_destroy", "rsketch_last_error",
+           "fdsk_tune_set_mode", "fdsk_tune_get_mode", "fdsk_tune_lookup", "fdsk_tune_set",
+           "fdsk_tune_clear", "fdsk_tune_set_path", "fdsk_tune_path", "fdsk_tune_load",
+           "fdsk_tune_save", "fdsk_tune_dump", "fdsk_tune_last_error")
 
 
 class FdskConfig(ctypes.Structure):
@@ -163,6 +166,23 @@ def lib():
     L.rsketch_destroy.restype = None
     L.rsketch_last_error.argtypes = [vp]
     L.rsketch_last_error.restype = ctypes.c_char_p
+    L.fdsk_tune_set_mode.argtypes = [i32]
+    L.fdsk_tune_get_mode.argtypes = []
+    L.fdsk_tune_lookup.argtypes = [ctypes.c_char_p, ctypes.POINTER(i32)]
+    L.fdsk_tune_set.argtypes = [ctypes.c_char_p, i32]
+    L.fdsk_tune_clear.argtypes = []
+    L.fdsk_tune_set_path.argtypes = [ctypes.c_char_p]
+    L.fdsk_tune_path.argtypes = []
+    L.fdsk_tune_path.restype = ctypes.c_char_p
+    L.fdsk_tune_load.argtypes = [ctypes.c_char_p]
+    L.fdsk_tune_save.argtypes = [ctypes.c_char_p]
+    L.fdsk_tune_dump.argtypes = [ctypes.c_char_p, i64]
+    L.fdsk_tune_dump.restype = i32
+    L.fdsk_tune_last_error.argtypes = []
+    L.fdsk_tune_last_error.restype = ctypes.c_char_p
+    for f in ("fdsk_tune_set_mode", "fdsk_tune_get_mode", "fdsk_tune_lookup", "fdsk_tune_set",
+              "fdsk_tune_clear", "fdsk_tune_set_path", "fdsk_tune_load", "fdsk_tune_save"):
+        getattr(L, f).restype = cint
     for f in ("sketch_create", "sketch_append_rows", "sketch_merge", "sketch_finalize", "sketch_error",
               "fdsk_evaluate", "sketch_stats", "fdsk_gram", "fdsk_eigh", "sketch_reset",
               "sketch_profile", "sketch_batch_create", "sketch_batch_append",
@@ -518,3 +538,74 @@ class RSketch:
             self.close()
         except Exception:
             pass
+
+
+# ----------------------------------------------------------------------------
+# Launch-shape tuning of the Gram and rebuild products (fdsk_tune_* in the
+# header): a process-wide table of choices persisted to a cache file.
+TUNE_MODES = {"off": 0, "on": 1, "refresh": 2}
+
+
+def tune_mode(mode=None):
+    """Set the tuning mode ("off", "on", "refresh") if given; return the
+    current one."""
+    L = lib()
+    if mode is not None:
+        rc = L.fdsk_tune_set_mode(TUNE_MODES[mode])
+        if rc != 0:
+            raise FdskError(rc, f"bad tuning mode {mode!r}")
+    cur = L.fdsk_tune_get_mode()
+    return {v: k for k, v in TUNE_MODES.items()}[cur]
+
+
+def tune_lookup(key):
+    """The tuned value of key, or None."""
+    v = ctypes.c_int32()
+    rc = lib().fdsk_tune_lookup(key.encode(), ctypes.byref(v))
+    if rc < 0:
+        raise FdskError(rc, "tune_lookup")
+    return v.value if rc == 0 else None
+
+
+def tune_set(key, value):
+    rc = lib().fdsk_tune_set(key.encode(), int(value))
+    if rc != 0:
+        raise FdskError(rc, f"bad tuning key {key!r}")
+
+
+def tune_clear():
+    lib().fdsk_tune_clear()
+
+
+def tune_path(path=None):
+    """Set the cache file if given ("" for none); return the current one."""
+    L = lib()
+    if path is not None:
+        L.fdsk_tune_set_path(path.encode())
+    return L.fdsk_tune_path().decode()
+
+
+def tune_load(path=None):
+    rc = lib().fdsk_tune_load(path.encode() if path is not None else None)
+    if rc != 0:
+        raise FdskError(rc, lib().fdsk_tune_last_error().decode())
+
+
+def tune_save(path=None):
+    rc = lib().fdsk_tune_save(path.encode() if path is not None else None)
+    if rc != 0:
+        raise FdskError(rc, lib().fdsk_tune_last_error().decode())
+
+
+def tune_table():
+    """The table as {key: (value, note)}."""
+    L = lib()
+    n = L.fdsk_tune_dump(None, 0)
+    buf = ctypes.create_string_buffer(n + 1)
+    L.fdsk_tune_dump(buf, n + 1)
+    out = {}
+    for line in buf.value.decode().splitlines():
+        parts = line.split("\t")
+        if len(parts) >= 2:
+            out[parts[0]] = (int(parts[1]), parts[2] if len(parts) > 2 else "")
+    return out
