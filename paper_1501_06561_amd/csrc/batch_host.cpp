@@ -319,12 +319,36 @@ int run_plan(fdsk_batch* b, Plan& p, int dt, int cap) {
   return 0;
 }
 
+// The class streams.  HIP maps ordinary streams onto a small per-process
+// pool of hardware queues (four by default) and shares a queue between
+// streams once the pool is used up; two classes on one queue run one after
+// the other.  Which streams end up sharing depends on every stream the
+// process created before, so the class streams are created with a CU mask
+// holding every CU: such a stream gets a hardware queue of its own and
+// still runs on the whole GPU.  Where that is refused, an ordinary
+// non-blocking stream is used.
+hipError_t create_lane(hipStream_t* st) {
+  int dev = 0;
+  hipDeviceProp_t p{};
+  hipError_t e = hipGetDevice(&dev);
+  if (e == hipSuccess) e = hipGetDeviceProperties(&p, dev);
+  if (e == hipSuccess && p.multiProcessorCount > 0) {
+    const int ncu = p.multiProcessorCount;
+    std::vector<uint32_t> mask((ncu + 31) / 32, 0u);
+    for (int c = 0; c < ncu; ++c) mask[c / 32] |= 1u << (c % 32);
+    if (hipExtStreamCreateWithCUMask(st, static_cast<uint32_t>(mask.size()), mask.data()) == hipSuccess)
+      return hipSuccess;
+    (void)hipGetLastError();
+  }
+  return hipStreamCreateWithFlags(st, hipStreamNonBlocking);
+}
+
 int ensure_lanes(fdsk_batch* b) {
   constexpr int K = fdsk_batch::kClasses;
   if (b->ev_in) return 0;
   hipError_t e = hipEventCreateWithFlags(&b->ev_in, hipEventDisableTiming);
   for (int g = 0; g < K && e == hipSuccess; ++g) {
-    e = hipStreamCreateWithFlags(&b->lane[g], hipStreamNonBlocking);
+    e = create_lane(&b->lane[g]);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&b->ev_out[g], hipEventDisableTiming);
   }
   if (e != hipSuccess) return berr(b, FDSK_EDEVICE, "batch streams: %s", hipGetErrorString(e));
