@@ -245,7 +245,7 @@ hipError_t launch_round(fdsk_batch* b, const Plan& p, const Staged& sg, size_t r
   }
   for (size_t c0 = 0; c0 < vr.size() && e == hipSuccess; c0 += cap) {
     const int nt = static_cast<int>(std::min<size_t>(cap, vr.size() - c0));
-    int max_mp = 0, max_m = 0, max_ldc = 0, max_keep = 0, ks = 1;
+    int max_mp = 0, max_m = 0, max_ldc = 0, max_keep = 0, ks = 1, max_c = 0;
     bool p0 = false, p1 = false, p3 = false;   // precisions present in this launch
     double w_gram = 0, w_head = 0, w_trid = 0, w_dc = 0, w_bt = 0, w_reb = 0;
     for (int t = 0; t < nt; ++t) {
@@ -254,6 +254,7 @@ hipError_t launch_round(fdsk_batch* b, const Plan& p, const Staged& sg, size_t r
       max_m = std::max(max_m, s.m);
       max_ldc = std::max(max_ldc, s.ldc);
       max_keep = std::max(max_keep, s.rp.keep);
+      max_c = std::max(max_c, std::min(s.m, s.l));
       p0 |= s.npass == 0;
       p1 |= s.npass == 1;
       p3 |= s.npass == 3;
@@ -289,7 +290,7 @@ hipError_t launch_round(fdsk_batch* b, const Plan& p, const Staged& sg, size_t r
     if (e == hipSuccess) e = launch_group_dc(b->d_sk, tt, nt, max_m, st);
     add_mark(b, FDSK_STAGE_DC, a, st, w_dc);
     a = mark(b, st);
-    if (e == hipSuccess) e = launch_group_backtr(b->d_sk, tt, nt, max_m, st);
+    if (e == hipSuccess) e = launch_group_backtr(b->d_sk, tt, nt, max_m, max_c, st);
     add_mark(b, FDSK_STAGE_BACKTR, a, st, w_bt);
     add_mark(b, FDSK_STAGE_EIG, eig0, st, w_head + w_trid + w_dc + w_bt);
     a = mark(b, st);

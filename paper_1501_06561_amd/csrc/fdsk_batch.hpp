@@ -86,7 +86,9 @@ hipError_t launch_group_tridiag_head(const GroupSketch* sk, const GroupRR* t, in
                                      hipStream_t s);
 hipError_t launch_group_tridiag(const GroupSketch* sk, const GroupRR* t, int nt, int max_m, hipStream_t s);
 hipError_t launch_group_dc(const GroupSketch* sk, const GroupRR* t, int nt, int max_m, hipStream_t s);
-hipError_t launch_group_backtr(const GroupSketch* sk, const GroupRR* t, int nt, int max_m, hipStream_t s);
+// max_c: the most eigenvectors any task wants (min(m, l)).
+hipError_t launch_group_backtr(const GroupSketch* sk, const GroupRR* t, int nt, int max_m, int max_c,
+                               hipStream_t s);
 hipError_t launch_group_shrink(const GroupSketch* sk, const GroupRR* t, int nt, hipStream_t s);
 // The FP64 rebuild for tasks with npass 0.
 hipError_t launch_group_rebuild(const GroupSketch* sk, const GroupRR* t, int nt, int max_ldc, int max_keep,

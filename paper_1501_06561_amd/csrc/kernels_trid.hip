@@ -1300,6 +1300,146 @@ __global__ __launch_bounds__(BNT) void k_backtr(const double* __restrict__ W, in
   backtr_body<NPL, GA>(W, n, Z, ldz, blockIdx.x);
 }
 
+// The same product in blocks of 16 reflectors (compact WY form): the
+// reflectors k0 .. k0+15 multiply to I - V T V^T, with V their vectors
+// (n x 16) and T upper triangular, T_jj = tau_j and column i above the
+// diagonal -tau_i T(0:i, 0:i) V(:, 0:i)^T v_i.  Q Z = H_0 H_1 ... H_{n-3} Z
+// applies the blocks from the last to the first, each as
+// Z -= V (T (V^T Z)), all three products on FP64 matrix cores.  A wave holds
+// 16 wanted columns of Z in registers for the whole product, as MFMA
+// accumulators: lane l keeps rows 16r + l/16 + 4v (v = 0..3) of column l%16
+// for row tile r.  Entry v of that tile is also the B operand of the K
+// slice of rows 16r + 4v .. 16r + 4v + 3, so V^T Z reads Z from the
+// accumulators directly.  Rows of V above k0 + 1 are zero and their tiles
+// are skipped.  Block cb takes the wanted columns 16 NWV cb .. ; RTM row
+// tiles cover n <= 16 RTM.
+template <int RTM, int NWV>
+__device__ __forceinline__ void backtr_wy_body(const double* __restrict__ W, int n, double* __restrict__ Z,
+                                               int ldz, int cb) {
+  constexpr int NT = 64 * NWV;
+  __shared__ double Vs[16 * RTM][17];
+  __shared__ double Gp[NWV][16][17];
+  __shared__ double Gs[16][17];
+  __shared__ double Ts[16][17];
+  __shared__ double tau_s[16];
+  __shared__ int cols[NWV][16];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  const int P = n * (n + 1) / 2;
+  const double* flags = W + P + 3 * n + 1;
+  // This wave's 16 wanted columns: wanted columns 16 (NWV cb + w) + j.
+  const int base = 16 * (NWV * cb + w);
+  if (lane < 16) cols[w][lane] = -1;
+  int seen = 0;
+  for (int c0 = 0; c0 < n; c0 += 64) {
+    const bool f = (c0 + lane < n) && flags[c0 + lane] != 0.0;
+    const unsigned long long msk = __ballot(f);
+    const int pos = seen + __popcll(msk & ((1ull << lane) - 1ull));
+    if (f && pos >= base && pos < base + 16) cols[w][pos - base] = c0 + lane;
+    seen += __popcll(msk);
+  }
+  if (16 * NWV * cb >= seen) return;     // the whole block: no wanted column (uniform)
+  __syncthreads();
+  const int rt = (n + 15) / 16;
+  const int col = cols[w][li];
+  f64x4 Zt[RTM];
+#pragma unroll
+  for (int r = 0; r < RTM; ++r) {
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int row = 16 * r + lk + 4 * v;
+      Zt[r][v] = (r < rt && col >= 0 && row < n) ? Z[static_cast<int64_t>(col) * ldz + row] : 0.0;
+    }
+  }
+  const int nref = n - 2;
+  for (int k0 = ((nref - 1) / 16) * 16; nref > 0 && k0 >= 0; k0 -= 16) {
+    const int rlo = (k0 + 1) / 16;     // first row tile holding a nonzero of V
+    // Stage V (rows 16 rlo .. 16 rt; consecutive threads read consecutive
+    // rows of one packed column) and tau.
+    const int rows = 16 * (rt - rlo);
+    for (int e = tid; e < 16 * rows; e += NT) {
+      const int q = e / rows, i = 16 * rlo + e % rows, k = k0 + q;
+      double v = 0.0;
+      if (k < nref && i < n) v = (i == k + 1) ? 1.0 : (i > k + 1 ? W[colstart(k, n) + i - k] : 0.0);
+      Vs[i][q] = v;
+    }
+    if (tid < 16) tau_s[tid] = (k0 + tid < nref) ? W[P + k0 + tid] : 0.0;
+    __syncthreads();
+    // G = V^T V on matrix cores: each wave sums its share of the row tiles
+    // (A = V^T and B = V take the same value per lane), then the partials
+    // are added in wave order.
+    {
+      f64x4 g = {0.0, 0.0, 0.0, 0.0};
+      for (int r = rlo + w; r < rt; r += NWV) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const double x = Vs[16 * r + 4 * u + lk][li];
+          g = mfma_f64(x, x, g);
+        }
+      }
+#pragma unroll
+      for (int v = 0; v < 4; ++v) Gp[w][lk + 4 * v][li] = g[v];
+    }
+    __syncthreads();
+    for (int e = tid; e < 256; e += NT) {
+      double g = 0.0;
+#pragma unroll
+      for (int q = 0; q < NWV; ++q) g += Gp[q][e / 16][e % 16];
+      Gs[e / 16][e % 16] = g;
+    }
+    __syncthreads();
+    // T, one row per lane: T(j, i) needs only row j's earlier entries.
+    if (tid < 16) {
+      const int j = tid;
+      double trow[16];
+#pragma unroll
+      for (int i = 0; i < 16; ++i) trow[i] = 0.0;
+      trow[j] = tau_s[j];
+#pragma unroll
+      for (int i = 1; i < 16; ++i) {
+        if (i > j) {
+          double acc = 0.0;
+#pragma unroll
+          for (int q = 0; q < 16; ++q)
+            if (q >= j && q < i) acc = fma(trow[q], Gs[q][i], acc);
+          trow[i] = -tau_s[i] * acc;
+        }
+      }
+#pragma unroll
+      for (int i = 0; i < 16; ++i) Ts[j][i] = trow[i];
+    }
+    __syncthreads();
+    // Wt = V^T Z, Yt = T Wt, Z -= V Yt.
+    f64x4 Wt = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int r = 0; r < RTM; ++r)
+      if (r >= rlo && r < rt) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) Wt = mfma_f64(Vs[16 * r + 4 * u + lk][li], Zt[r][u], Wt);
+      }
+    f64x4 Yt = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int u = 0; u < 4; ++u) Yt = mfma_f64(Ts[li][4 * u + lk], Wt[u], Yt);
+#pragma unroll
+    for (int r = 0; r < RTM; ++r)
+      if (r >= rlo && r < rt) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) Zt[r] = mfma_f64(-Vs[16 * r + li][4 * u + lk], Yt[u], Zt[r]);
+      }
+    __syncthreads();
+  }
+  if (col >= 0) {
+#pragma unroll
+    for (int r = 0; r < RTM; ++r)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int row = 16 * r + lk + 4 * v;
+        if (r < rt && row < n) Z[static_cast<int64_t>(col) * ldz + row] = Zt[r][v];
+      }
+  }
+}
+
+
 // ------------------------------------------- reduce, large orders (> 512)
 // The same Householder reduction for buffers too large for one CU's
 // registers: the full symmetric matrix (scaled by 2^-s) lives in the S1
@@ -1604,6 +1744,26 @@ __global__ __launch_bounds__(NT) void kg_backtr(const GroupSketch* __restrict__ 
   backtr_body<NPL, GA, NT>(s.W, s.m, s.V, s.mp, blockIdx.x);
 }
 
+// The blocked back-transformation per size class [LO, HI]: RTM row tiles,
+// NWV waves (16 wanted columns each) per workgroup.
+template <int RTM, int NWV, int LO, int HI>
+__global__ __launch_bounds__(64 * NWV) void kg_backtr_wy(const GroupSketch* __restrict__ SK,
+                                                         const GroupRR* __restrict__ T) {
+  const GroupSketch& s = SK[T[blockIdx.y].sk];
+  if (s.m < LO || s.m > HI) return;
+  if (static_cast<int>(blockIdx.x) * 16 * NWV >= min(s.m, s.l)) return;
+  backtr_wy_body<RTM, NWV>(s.W, s.m, s.V, s.mp, blockIdx.x);
+}
+
+template <int RTM, int NWV, int LO, int HI>
+hipError_t launch_group_backtr_wy(const GroupSketch* sk, const GroupRR* t, int nt, int max_m, int max_c,
+                                  hipStream_t s) {
+  if (max_m < LO) return hipSuccess;
+  const dim3 g((max_c + 16 * NWV - 1) / (16 * NWV), nt);
+  hipLaunchKernelGGL((kg_backtr_wy<RTM, NWV, LO, HI>), g, dim3(64 * NWV), 0, s, sk, t);
+  return hipGetLastError();
+}
+
 template <int NPL, bool GA, int LO, int HI>
 hipError_t launch_group_backtr(const GroupSketch* sk, const GroupRR* t, int nt, int max_m, hipStream_t s) {
   constexpr int NT = GA ? BNT : 1024;
@@ -1646,13 +1806,14 @@ hipError_t launch_group_dc(const GroupSketch* sk, const GroupRR* t, int nt, int 
   return hipGetLastError();
 }
 
-hipError_t launch_group_backtr(const GroupSketch* sk, const GroupRR* t, int nt, int max_m, hipStream_t s) {
+hipError_t launch_group_backtr(const GroupSketch* sk, const GroupRR* t, int nt, int max_m, int max_c,
+                               hipStream_t s) {
   if (nt <= 0) return hipSuccess;
   if (max_m > kBatchMax) return hipErrorInvalidValue;
   hipError_t e = launch_group_backtr<1, false, 1, 64>(sk, t, nt, max_m, s);
-  if (e == hipSuccess) e = launch_group_backtr<2, false, 65, 128>(sk, t, nt, max_m, s);
-  if (e == hipSuccess) e = launch_group_backtr<4, false, 129, kTridMax>(sk, t, nt, max_m, s);
-  if (e == hipSuccess) e = launch_group_backtr<4, true, kTridMax + 1, kBatchMax>(sk, t, nt, max_m, s);
+  if (e == hipSuccess) e = launch_group_backtr_wy<8, 4, 65, 128>(sk, t, nt, max_m, max_c, s);
+  if (e == hipSuccess) e = launch_group_backtr_wy<13, 4, 129, 208>(sk, t, nt, max_m, max_c, s);
+  if (e == hipSuccess) e = launch_group_backtr_wy<16, 4, 209, kBatchMax>(sk, t, nt, max_m, max_c, s);
   return e;
 }
 
