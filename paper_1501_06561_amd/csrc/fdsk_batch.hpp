@@ -31,7 +31,8 @@ struct GroupSketch {
   double* S2;
   double* lam;       // mp
   double* rownorm;   // mp
-  uint16_t* bh;      // bf16 halves of the buffer (npass > 0): hi then lo, rows64 x ldc each
+  uint16_t* bh0;     // bf16 halves of C0 / C1 (npass > 0): hi then lo, rows64 x ldc each,
+  uint16_t* bh1;     // written by the ingest and the rebuild beside the FP64 rows
   DevStats* st;
   int d, ldc, l, m, mp;
   int npass;         // Gram/rebuild products: 0 FP64, 1 BF16, 3 split-BF16 (compensated)

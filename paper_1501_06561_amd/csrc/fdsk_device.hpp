@@ -30,6 +30,11 @@ __device__ __forceinline__ uint16_t f32_to_bf16_bits(float x) {
 __device__ __forceinline__ float bf16_bits_to_f32(uint16_t b) {
   return __uint_as_float(static_cast<uint32_t>(b) << 16);
 }
+// The split-BF16 halves of a double: hi = bf16(float(x)), lo = bf16(float(x - hi)).
+__device__ __forceinline__ void split_bits(double x, uint16_t& hb, uint16_t& lb) {
+  hb = f32_to_bf16_bits(static_cast<float>(x));
+  lb = f32_to_bf16_bits(static_cast<float>(x - static_cast<double>(bf16_bits_to_f32(hb))));
+}
 
 // Data-parallel-primitive (DPP) move of a double: both 32-bit halves go
 // through the same lane permutation.  Lanes whose row is masked off (or whose

@@ -171,11 +171,7 @@ __device__ __forceinline__ void split_bf16_body(const double* __restrict__ C, in
                                                 int bx, int r, int nbx) {
   for (int c = bx * 256 + threadIdx.x; c < ldc; c += nbx * 256) {
     uint16_t hb = 0, lb = 0;
-    if (r < mp) {
-      const double x = C[static_cast<int64_t>(r) * ldc + c];
-      hb = f32_to_bf16_bits(static_cast<float>(x));
-      lb = f32_to_bf16_bits(static_cast<float>(x - static_cast<double>(bf16_bits_to_f32(hb))));
-    }
+    if (r < mp) split_bits(C[static_cast<int64_t>(r) * ldc + c], hb, lb);
     H[static_cast<int64_t>(r) * ldc + c] = hb;
     L[static_cast<int64_t>(r) * ldc + c] = lb;
   }
@@ -275,7 +271,9 @@ __global__ __launch_bounds__(256) void k_gram_bf16t(const uint16_t* __restrict__
 template <int NPASS, int RT>
 __device__ __forceinline__ void rebuild_bf16t_body(const double* __restrict__ Ut, const uint16_t* __restrict__ H,
                                                    const uint16_t* __restrict__ L, int ldc, int mp, int keep,
-                                                   double* __restrict__ out, int bx, int by) {
+                                                   double* __restrict__ out, int bx, int by,
+                                                   uint16_t* __restrict__ Ho = nullptr,
+                                                   uint16_t* __restrict__ Lo = nullptr) {
   static_assert(RT == 32 || RT == 64, "rebuild rows per workgroup");
   constexpr int RA = RT / 32;
   const int r0 = by * RT, c0 = bx * 64;
@@ -338,8 +336,18 @@ __device__ __forceinline__ void rebuild_bf16t_body(const double* __restrict__ Ut
       const int row = r0 + wi * (RT / 2) + a * 16 + 4 * lq + v;
       if (row < keep) {
         const int64_t o = static_cast<int64_t>(row) * ldc + c0 + wj * 32 + li;
-        out[o] = static_cast<double>(acc[a][0][v]);
-        out[o + 16] = static_cast<double>(acc[a][1][v]);
+        const double x0 = static_cast<double>(acc[a][0][v]), x1 = static_cast<double>(acc[a][1][v]);
+        out[o] = x0;
+        out[o + 16] = x1;
+        if (Ho) {
+          uint16_t hb, lb;
+          split_bits(x0, hb, lb);
+          Ho[o] = hb;
+          Lo[o] = lb;
+          split_bits(x1, hb, lb);
+          Ho[o + 16] = hb;
+          Lo[o + 16] = lb;
+        }
       }
     }
 }
@@ -577,21 +585,11 @@ size_t fp8_workspace_bytes(int mp, int ldc) {
 
 // ------------------------------------------------------ grouped (batches)
 // Tasks of sketches with another precision return at once (the FP64 kernels
-// of kernels_stream.hip take those).  As for a single sketch, the buffer is
-// split into its bf16 halves once per ReduceRank (s.bh: hi rows then lo
-// rows, rows64 x ldc each), read by the Gram (one K pass per tile, lower
-// 64 x 64 tiles into Gp) and by the rebuild of the same task.
-__global__ __launch_bounds__(256) void kg_split_bf16(const GroupSketch* __restrict__ SK,
-                                                     const GroupRR* __restrict__ T) {
-  const GroupRR t = T[blockIdx.z];
-  const GroupSketch& s = SK[t.sk];
-  if (s.npass == 0) return;
-  const int rows64 = (s.mp + 63) / 64 * 64;
-  if (static_cast<int>(blockIdx.y) >= rows64 || static_cast<int>(blockIdx.x) * 256 >= s.ldc) return;
-  split_bf16_body(t.cur ? s.C1 : s.C0, s.ldc, s.mp, s.bh, s.bh + static_cast<int64_t>(rows64) * s.ldc,
-                  blockIdx.x, blockIdx.y, gridDim.x);
-}
-
+// of kernels_stream.hip take those).  Each buffer keeps its bf16 halves
+// beside its FP64 rows (s.bh0 for C0, s.bh1 for C1: hi rows then lo rows,
+// rows64 x ldc each): the ingest and the rebuild write them with the rows
+// (the same split as k_split_bf16, so the same bits), and the Gram and the
+// next rebuild read them; no separate split pass runs.
 // Split-K as the FP64 grouped Gram: K slice blockIdx.y of the task's slice
 // length into partial blockIdx.y of its Gp.
 template <int NPASS>
@@ -604,8 +602,9 @@ __global__ __launch_bounds__(256) void kg_gram_bf16(const GroupSketch* __restric
   if (static_cast<int>(blockIdx.x) >= nt * (nt + 1) / 2) return;
   const int kchunk = task_kchunk(kc >= 0 ? kc : s.kchunk, s.ldc);
   if (static_cast<int>(blockIdx.y) * kchunk >= s.ldc) return;
-  gram_bf16t_body<NPASS>(s.bh, s.bh + static_cast<int64_t>(rows64) * s.ldc, s.ldc, s.mp, kchunk, s.Gp,
-                         blockIdx.x, blockIdx.y);
+  const uint16_t* H = t.cur ? s.bh1 : s.bh0;
+  gram_bf16t_body<NPASS>(H, H + static_cast<int64_t>(rows64) * s.ldc, s.ldc, s.mp, kchunk, s.Gp, blockIdx.x,
+                         blockIdx.y);
 }
 
 template <int NPASS, int RT>
@@ -615,9 +614,11 @@ __global__ __launch_bounds__(256) void kg_rebuild_bf16(const GroupSketch* __rest
   const GroupSketch& s = SK[t.sk];
   if (s.npass != NPASS) return;
   if (static_cast<int>(blockIdx.x) >= s.ldc / 64 || static_cast<int>(blockIdx.y) * RT >= s.rp.keep) return;
-  const int rows64 = (s.mp + 63) / 64 * 64;
-  rebuild_bf16t_body<NPASS, RT>(s.Ut, s.bh, s.bh + static_cast<int64_t>(rows64) * s.ldc, s.ldc, s.mp,
-                                s.rp.keep, t.cur ? s.C0 : s.C1, blockIdx.x, blockIdx.y);
+  const int64_t half = static_cast<int64_t>((s.mp + 63) / 64 * 64) * s.ldc;
+  const uint16_t* H = t.cur ? s.bh1 : s.bh0;
+  uint16_t* Ho = t.cur ? s.bh0 : s.bh1;
+  rebuild_bf16t_body<NPASS, RT>(s.Ut, H, H + half, s.ldc, s.mp, s.rp.keep, t.cur ? s.C0 : s.C1, blockIdx.x,
+                                blockIdx.y, Ho, Ho + half);
 }
 
 hipError_t launch_group_gram_lowp(const GroupSketch* sk, const GroupRR* t, int nt, int max_mp, int max_ldc,
@@ -625,8 +626,7 @@ hipError_t launch_group_gram_lowp(const GroupSketch* sk, const GroupRR* t, int n
   if (nt <= 0) return hipSuccess;
   if (ks < 1 || ks > kGpParts || (kc > 0 && kc % 64)) return hipErrorInvalidValue;
   const int rows64 = (max_mp + 63) / 64 * 64, T = rows64 / kBt;
-  hipLaunchKernelGGL(kg_split_bf16, dim3((max_ldc + 255) / 256, rows64, nt), dim3(256), 0, s, sk, t);
-  hipError_t e = hipGetLastError();
+  hipError_t e = hipSuccess;
   const dim3 g(T * (T + 1) / 2, ks, nt);
   if (e == hipSuccess && one) {
     hipLaunchKernelGGL(kg_gram_bf16<1>, g, dim3(256), 0, s, sk, t, kc);

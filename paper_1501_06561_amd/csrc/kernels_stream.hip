@@ -13,16 +13,27 @@ namespace fdsk {
 // ----------------------------------------------------------------- ingest
 // One workgroup per row: convert to FP64, zero the pad columns, and store the
 // row's squared norm (FP64) for the ||A||_F^2 accumulator.
+// With H (and L) set, the row's split-BF16 halves are written there too
+// (same row, leading dimension ldc).
 __device__ __forceinline__ void ingest_body(const void* __restrict__ src, int dt, int64_t stride, int d,
                                             double* __restrict__ C, int ldc, int row0,
-                                            double* __restrict__ rownorm, int i) {
+                                            double* __restrict__ rownorm, int i,
+                                            uint16_t* __restrict__ H = nullptr,
+                                            uint16_t* __restrict__ L = nullptr) {
   const int64_t base = static_cast<int64_t>(i) * stride;
-  double* dst = C + static_cast<int64_t>(row0 + i) * ldc;
+  const int64_t ro = static_cast<int64_t>(row0 + i) * ldc;
+  double* dst = C + ro;
   double acc = 0.0;
   for (int c = threadIdx.x; c < ldc; c += blockDim.x) {
     double v = (c < d) ? load_as_f64(src, base + c, dt) : 0.0;
     dst[c] = v;
     acc += v * v;
+    if (H) {
+      uint16_t hb, lb;
+      split_bits(v, hb, lb);
+      H[ro + c] = hb;
+      L[ro + c] = lb;
+    }
   }
   __shared__ double red[4];
   acc = wave_sum(acc);
@@ -517,7 +528,9 @@ __global__ __launch_bounds__(256) void kg_ingest(const GroupSketch* __restrict__
   const GroupIngest t = T[blockIdx.y];
   if (static_cast<int>(blockIdx.x) >= t.f) return;
   const GroupSketch& s = SK[t.sk];
-  ingest_body(t.src, dt, t.stride, s.d, t.cur ? s.C1 : s.C0, s.ldc, t.row0, s.rownorm, blockIdx.x);
+  uint16_t* H = s.npass ? (t.cur ? s.bh1 : s.bh0) : nullptr;
+  uint16_t* L = H ? H + static_cast<int64_t>((s.mp + 63) / 64 * 64) * s.ldc : nullptr;
+  ingest_body(t.src, dt, t.stride, s.d, t.cur ? s.C1 : s.C0, s.ldc, t.row0, s.rownorm, blockIdx.x, H, L);
 }
 
 // Split-K: K slice blockIdx.y of the task's slice length (task_kchunk) into
@@ -567,6 +580,11 @@ __global__ __launch_bounds__(256) void kg_zero(const GroupSketch* __restrict__ S
   double* p = (t.cur ? s.C1 : s.C0) + static_cast<int64_t>(t.r0) * s.ldc;
   const int64_t n = static_cast<int64_t>(t.r1 - t.r0) * s.ldc;
   for (int64_t e = blockIdx.x * 256LL + threadIdx.x; e < n; e += 256LL * gridDim.x) p[e] = 0.0;
+  if (s.npass) {     // and the rows' bf16 halves
+    uint16_t* H = (t.cur ? s.bh1 : s.bh0) + static_cast<int64_t>(t.r0) * s.ldc;
+    uint16_t* L = H + static_cast<int64_t>((s.mp + 63) / 64 * 64) * s.ldc;
+    for (int64_t e = blockIdx.x * 256LL + threadIdx.x; e < n; e += 256LL * gridDim.x) H[e] = L[e] = 0;
+  }
 }
 
 __global__ void kg_pending(const GroupSketch* __restrict__ SK, const GroupSpan* __restrict__ T, int nt) {
