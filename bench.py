@@ -369,6 +369,28 @@ def large_stream_leg(rows_limit=None):
             "eig_ms_per_reduce": prof["eig"][0] / max(prof["eig"][1], 1), "stages": table}
 
 
+def gram_only_leg(reps=20):
+    """Only the Gram products (fdsk_gram) at the buffer shapes of the
+    reduced-precision workloads, for hardware-counter runs: FP64 and
+    split-BF16 x3 on 512 x 3,072, FP8 x3 on 1,024 x 8,192."""
+    import numpy as np
+    import torch
+    from paper_1501_06561_amd import fdsketch as F, synth
+    out = {}
+    for name, m, d, prec in (("fp64_512x3072", 512, 3072, "fp64"), ("bf16x3_512x3072", 512, 3072, "bf16x3"),
+                             ("fp8x3_1024x8192", 1024, 8192, "fp8x3")):
+        C = torch.from_numpy(synth.random_noisy(m, d, m // 4, 10.0, seed=(8, m))).cuda()
+        F.gram(C, prec)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            F.gram(C, prec)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / reps
+        out[name] = {"ms_per_call": ms, "calls": reps, "flops_per_call": (1 if prec == "fp64" else 3) * m * (m + 1) * d}
+    return out
+
+
 def cpu_baseline_leg(d, l, n, seed, seconds):
     """The oracle (NumPy FP64, LAPACK SVD of the buffer) on the first
     sketches of the same workload until about `seconds` of CPU work."""
@@ -421,6 +443,8 @@ def main():
     ap.add_argument("--profile-only", action="store_true",
                     help="one warm-up and one step of the split-BF16 batch, nothing else "
                          "(for hardware-counter runs)")
+    ap.add_argument("--gram-only", action="store_true",
+                    help="only the Gram products at the reduced-precision buffer shapes (for counter runs)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run a plain device copy of BYTES (counter reference) and exit")
     args = ap.parse_args()
@@ -438,6 +462,9 @@ def main():
 
     from paper_1501_06561_amd import synth
 
+    if args.gram_only:
+        print(json.dumps({"gram_only": gram_only_leg()}))
+        return
     if args.precision_only:
         print(json.dumps({"precision_leg": precision_leg(args.prec_rows, l=args.prec_l, d=args.prec_d)}))
         return
@@ -487,7 +514,7 @@ def main():
     b.close()
     print(f"[bench] batch fp64: {ms64:.1f} ms", file=sys.stderr, flush=True)
     # The other launch mode of the split-BF16 batch (graph replay or direct).
-    ms_alt, per_alt, _, b = run_batch(cfg("bf16x3"), rows, args.steps, 1, graph=not graph)
+    ms_alt, per_alt, _, b = run_batch(cfg("bf16x3"), rows, 1, 1, graph=not graph)
     b.close()
     print(f"[bench] batch bf16x3 {'direct' if graph else 'graph'}: {ms_alt:.1f} ms", file=sys.stderr,
           flush=True)
