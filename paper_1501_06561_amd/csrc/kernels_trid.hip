@@ -13,7 +13,8 @@
 //   form A <- A - v w^T - w v^T, w = p - (tau/2)(p.v) v, p = tau A v.
 //
 // * k_dc: eigen-decomposition T = Z diag(lambda) Z^T by Cuppen's divide and
-//   conquer, bottom up from 1 x 1 blocks.  Every off-diagonal e_b is a tear:
+//   conquer, bottom up from 2 x 2 blocks (each diagonalised by one Jacobi
+//   rotation in closed form).  Every other off-diagonal e_b is a tear:
 //   the two neighbouring diagonal entries lose |e_b|, and merging the blocks on
 //   both sides of b is the rank-one problem D + rho z z^T with rho = |e_b| and
 //   z = (last row of the left block's eigenvectors, sign(e_b) x first row of
@@ -795,8 +796,10 @@ __device__ __forceinline__ void dc_body(double* __restrict__ W, int n, double* _
   // the one that makes the last level write Z.  Both start as I: a level
   // reads, within its merge blocks, entries that no earlier level wrote
   // (between two blocks of the level before), and those must be zero.
+  // The first level (pairs of 1 x 1 blocks) is solved in closed form below,
+  // so the merge levels start from blocks of 2.
   int levels = 0;
-  for (int s = 1; s < n; s *= 2) ++levels;
+  for (int s = 2; s < n; s *= 2) ++levels;
   int cur = levels & 1;
   for (int c = w; c < n; c += NT / 64)
     for (int r = lane; r < n; r += 64) {
@@ -809,10 +812,39 @@ __device__ __forceinline__ void dc_body(double* __restrict__ W, int n, double* _
     S.D[i] = dG[i] - el - er;
   }
   __syncthreads();
+  // Each pair (2p, 2p+1) with its own off-diagonal restored is the 2 x 2
+  // block [[a, e], [e, c]]; one Jacobi rotation diagonalises it exactly:
+  // zeta = (c - a) / 2e, t the smaller root of t^2 + 2 zeta t = 1,
+  // eigenvalues a - t e and c + t e with vectors (cs, -sn) and (sn, cs).
+  // A last single index (n odd) is a 1 x 1 block already.
+  {
+    double* In0 = cur ? Qc : Z;
+    for (int p = tid; p < n / 2; p += NT) {
+      const int i = 2 * p;
+      const double e = eG[i], ae = fabs(e);
+      const double a = S.D[i] + ae, c = S.D[i + 1] + ae;
+      double cs = 1.0, sn = 0.0, l0 = a, l1 = c;
+      if (e != 0.0) {
+        const double zeta = (c - a) / (2.0 * e);
+        const double t = copysign(1.0, zeta) / (fabs(zeta) + sqrt(fma(zeta, zeta, 1.0)));
+        cs = 1.0 / sqrt(fma(t, t, 1.0));
+        sn = t * cs;
+        l0 = a - t * e;
+        l1 = c + t * e;
+      }
+      S.D[i] = l0;
+      S.D[i + 1] = l1;
+      In0[static_cast<int64_t>(i) * ldz + i] = cs;
+      In0[static_cast<int64_t>(i) * ldz + i + 1] = -sn;
+      In0[static_cast<int64_t>(i + 1) * ldz + i] = sn;
+      In0[static_cast<int64_t>(i + 1) * ldz + i + 1] = cs;
+    }
+  }
+  __syncthreads();
   const double eps = 1.1102230246251565e-16;
   // Four lanes per root in the per-root steps.
   const int g4 = tid >> 2, q4 = tid & 3;
-  for (int s = 1; s < n; s *= 2, cur ^= 1) {
+  for (int s = 2; s < n; s *= 2, cur ^= 1) {
     // Selected, not indexed from a local array, so that the loads below
     // stay global (flat loads would also count against the LDS counter).
     const double* In = cur ? Qc : Z;
