@@ -13,9 +13,9 @@
 //   form A <- A - v w^T - w v^T, w = p - (tau/2)(p.v) v, p = tau A v.
 //
 // * k_dc: eigen-decomposition T = Z diag(lambda) Z^T by Cuppen's divide and
-//   conquer, bottom up from 2 x 2 blocks (each diagonalised by one Jacobi
-//   rotation in closed form).  Every other off-diagonal e_b is a tear:
-//   the two neighbouring diagonal entries lose |e_b|, and merging the blocks on
+//   conquer, bottom up from 4 x 4 blocks (each diagonalised by a few cyclic
+//   Jacobi sweeps in one thread).  Every off-diagonal e_b between two blocks
+//   is a tear: the two neighbouring diagonal entries lose |e_b|, and merging the blocks on
 //   both sides of b is the rank-one problem D + rho z z^T with rho = |e_b| and
 //   z = (last row of the left block's eigenvectors, sign(e_b) x first row of
 //   the right block's).  Per merge: sort, deflate (negligible rho z_i, or two
@@ -796,10 +796,11 @@ __device__ __forceinline__ void dc_body(double* __restrict__ W, int n, double* _
   // the one that makes the last level write Z.  Both start as I: a level
   // reads, within its merge blocks, entries that no earlier level wrote
   // (between two blocks of the level before), and those must be zero.
-  // The first level (pairs of 1 x 1 blocks) is solved in closed form below,
-  // so the merge levels start from blocks of 2.
+  // The first two levels are replaced by blocks of 4 (the last one possibly
+  // smaller) solved directly below, so the merge levels start from blocks
+  // of 4.
   int levels = 0;
-  for (int s = 2; s < n; s *= 2) ++levels;
+  for (int s = 4; s < n; s *= 2) ++levels;
   int cur = levels & 1;
   for (int c = w; c < n; c += NT / 64)
     for (int r = lane; r < n; r += 64) {
@@ -812,39 +813,76 @@ __device__ __forceinline__ void dc_body(double* __restrict__ W, int n, double* _
     S.D[i] = dG[i] - el - er;
   }
   __syncthreads();
-  // Each pair (2p, 2p+1) with its own off-diagonal restored is the 2 x 2
-  // block [[a, e], [e, c]]; one Jacobi rotation diagonalises it exactly:
-  // zeta = (c - a) / 2e, t the smaller root of t^2 + 2 zeta t = 1,
-  // eigenvalues a - t e and c + t e with vectors (cs, -sn) and (sn, cs).
-  // A last single index (n odd) is a 1 x 1 block already.
+  // Block p (rows 4p .. 4p + k - 1, k <= 4) with its inner off-diagonals
+  // restored, diagonalised by one thread with cyclic Jacobi: six sweeps
+  // over the six planes, rotation (cs, sn) from zeta = (a_qq - a_pp) / 2a_pq
+  // and t the smaller root of t^2 + 2 zeta t = 1 (quadratic convergence:
+  // four by four blocks reach rounding level in about three sweeps).
   {
     double* In0 = cur ? Qc : Z;
-    for (int p = tid; p < n / 2; p += NT) {
-      const int i = 2 * p;
-      const double e = eG[i], ae = fabs(e);
-      const double a = S.D[i] + ae, c = S.D[i + 1] + ae;
-      double cs = 1.0, sn = 0.0, l0 = a, l1 = c;
-      if (e != 0.0) {
-        const double zeta = (c - a) / (2.0 * e);
-        const double t = copysign(1.0, zeta) / (fabs(zeta) + sqrt(fma(zeta, zeta, 1.0)));
-        cs = 1.0 / sqrt(fma(t, t, 1.0));
-        sn = t * cs;
-        l0 = a - t * e;
-        l1 = c + t * e;
+    for (int p = tid; 4 * p < n; p += NT) {
+      const int i0 = 4 * p, k = min(4, n - i0);
+      double A[4][4], V[4][4];
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          A[r][c] = 0.0;
+          V[r][c] = (r == c) ? 1.0 : 0.0;
+        }
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        if (j < k) {
+          const double inl = (j > 0) ? fabs(eG[i0 + j - 1]) : 0.0;
+          const double inr = (j < k - 1) ? fabs(eG[i0 + j]) : 0.0;
+          A[j][j] = S.D[i0 + j] + inl + inr;
+          if (j < k - 1) A[j][j + 1] = A[j + 1][j] = eG[i0 + j];
+        }
+      for (int sweep = 0; sweep < 6; ++sweep) {
+#pragma unroll
+        for (int pq = 0; pq < 6; ++pq) {
+          const int pp = pq < 3 ? 0 : (pq < 5 ? 1 : 2);
+          const int qq = pq < 3 ? pq + 1 : (pq < 5 ? pq - 1 : 3);
+          const double apq = A[pp][qq];
+          if (qq < k && apq != 0.0) {
+            const double zeta = (A[qq][qq] - A[pp][pp]) / (2.0 * apq);
+            const double t = copysign(1.0, zeta) / (fabs(zeta) + sqrt(fma(zeta, zeta, 1.0)));
+            const double cs = 1.0 / sqrt(fma(t, t, 1.0)), sn = t * cs;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+              if (r != pp && r != qq) {
+                const double arp = A[r][pp], arq = A[r][qq];
+                A[r][pp] = A[pp][r] = cs * arp - sn * arq;
+                A[r][qq] = A[qq][r] = sn * arp + cs * arq;
+              }
+            }
+            A[pp][pp] -= t * apq;
+            A[qq][qq] += t * apq;
+            A[pp][qq] = A[qq][pp] = 0.0;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+              const double vrp = V[r][pp], vrq = V[r][qq];
+              V[r][pp] = cs * vrp - sn * vrq;
+              V[r][qq] = sn * vrp + cs * vrq;
+            }
+          }
+        }
       }
-      S.D[i] = l0;
-      S.D[i + 1] = l1;
-      In0[static_cast<int64_t>(i) * ldz + i] = cs;
-      In0[static_cast<int64_t>(i) * ldz + i + 1] = -sn;
-      In0[static_cast<int64_t>(i + 1) * ldz + i] = sn;
-      In0[static_cast<int64_t>(i + 1) * ldz + i + 1] = cs;
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        if (j < k) {
+          S.D[i0 + j] = A[j][j];
+#pragma unroll
+          for (int r = 0; r < 4; ++r)
+            if (r < k) In0[static_cast<int64_t>(i0 + j) * ldz + i0 + r] = V[r][j];
+        }
     }
   }
   __syncthreads();
   const double eps = 1.1102230246251565e-16;
   // Four lanes per root in the per-root steps.
   const int g4 = tid >> 2, q4 = tid & 3;
-  for (int s = 2; s < n; s *= 2, cur ^= 1) {
+  for (int s = 4; s < n; s *= 2, cur ^= 1) {
     // Selected, not indexed from a local array, so that the loads below
     // stay global (flat loads would also count against the LDS counter).
     const double* In = cur ? Qc : Z;
