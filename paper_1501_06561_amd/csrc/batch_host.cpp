@@ -638,7 +638,7 @@ int sketch_batch_create(int32_t S, const fdsk_config* cfgs, void* hip_stream, fd
     off += (bytes + 255) / 256 * 256;
     return o;
   };
-  constexpr int NB = 12;   // C0 C1 Gp G W V Ut S1 S2 lam rownorm bf16-halves (of C0, then C1)
+  constexpr int NB = 12;   // C0 C1 Gp G W V Ut S1 S2 lam rownorm bf16 halves (of C0, C1, then Ut)
   std::vector<size_t> o(static_cast<size_t>(S) * NB);
   for (int i = 0; i < S; ++i) {
     const fdsk_config& c = cfgs[i];
@@ -659,7 +659,8 @@ int sketch_batch_create(int32_t S, const fdsk_config* cfgs, void* hip_stream, fd
     for (int k = 3; k < 9; ++k) q[k] = take(g);
     q[9] = take(static_cast<size_t>(D.mp) * 8);
     q[10] = take(static_cast<size_t>(D.mp) * 8);
-    q[11] = take(D.npass > 0 ? 2 * bf16_workspace_bytes(D.mp, D.ldc) : 0);
+    q[11] = take(D.npass > 0 ? 2 * bf16_workspace_bytes(D.mp, D.ldc) +
+                                   4 * static_cast<size_t>(D.mp) * D.mp : 0);
   }
   const size_t oDesc = take(sizeof(GroupSketch) * S), oStats = take(sizeof(DevStats) * S);
   hipError_t e = hipMalloc(&b->arena, off);
@@ -679,6 +680,7 @@ int sketch_batch_create(int32_t S, const fdsk_config* cfgs, void* hip_stream, fd
     D.rownorm = reinterpret_cast<double*>(a + q[10]);
     D.bh0 = D.npass > 0 ? reinterpret_cast<uint16_t*>(a + q[11]) : nullptr;
     D.bh1 = D.npass > 0 ? D.bh0 + bf16_workspace_bytes(D.mp, D.ldc) / sizeof(uint16_t) : nullptr;
+    D.uh = D.npass > 0 ? D.bh1 + bf16_workspace_bytes(D.mp, D.ldc) / sizeof(uint16_t) : nullptr;
     D.st = b->d_stats + i;
   }
   e = hipMemsetAsync(b->arena, 0, off, b->stream);

@@ -33,6 +33,7 @@ struct GroupSketch {
   double* rownorm;   // mp
   uint16_t* bh0;     // bf16 halves of C0 / C1 (npass > 0): hi then lo, rows64 x ldc each,
   uint16_t* bh1;     // written by the ingest and the rebuild beside the FP64 rows
+  uint16_t* uh;      // Ut's split-BF16 halves (npass > 0): hi rows then lo rows, mp x mp each
   DevStats* st;
   int d, ldc, l, m, mp;
   int npass;         // Gram/rebuild products: 0 FP64, 1 BF16, 3 split-BF16 (compensated)

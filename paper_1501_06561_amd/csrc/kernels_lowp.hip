@@ -352,6 +352,92 @@ __device__ __forceinline__ void rebuild_bf16t_body(const double* __restrict__ Ut
     }
 }
 
+// The same product with Ut also pre-split (hi rows in Uh, lo rows mp x mp
+// further on, written by the shrink): each A fragment is one 16-byte load of
+// 8 consecutive bf16 of a Ut row, straight from global memory, so no Ut
+// staging or split runs in the loop.  Rows of Uh at or past keep hold
+// whatever they hold; they only reach output rows past keep, which are not
+// stored.
+template <int NPASS, int RT>
+__device__ __forceinline__ void rebuild_bf16u_body(const uint16_t* __restrict__ Uh, const uint16_t* __restrict__ H,
+                                                   const uint16_t* __restrict__ L, int ldc, int mp, int keep,
+                                                   double* __restrict__ out, int bx, int by,
+                                                   uint16_t* __restrict__ Ho, uint16_t* __restrict__ Lo) {
+  static_assert(RT == 32 || RT == 64, "rebuild rows per workgroup");
+  constexpr int RA = RT / 32;
+  const int r0 = by * RT, c0 = bx * 64;
+  __shared__ __attribute__((aligned(16))) uint16_t BhT[64][32 + kBpad];
+  __shared__ __attribute__((aligned(16))) uint16_t BlT[NPASS == 3 ? 64 : 1][32 + kBpad];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int wi = w >> 1, wj = w & 1, li = lane & 15, lq = lane >> 4;
+  const uint16_t* Ul = Uh + static_cast<int64_t>(mp) * mp;
+  f32x4 acc[RA][2];
+#pragma unroll
+  for (int a = 0; a < RA; ++a) acc[a][0] = acc[a][1] = f32x4{0.f, 0.f, 0.f, 0.f};
+  int64_t ua[RA];
+#pragma unroll
+  for (int a = 0; a < RA; ++a) {
+    const int row = min(r0 + wi * (RT / 2) + a * 16 + li, mp - 1);
+    ua[a] = static_cast<int64_t>(row) * mp + 8 * lq;
+  }
+  for (int k0 = 0; k0 < mp; k0 += 32) {
+    bf16x8_t ah[RA], al[RA];
+#pragma unroll
+    for (int a = 0; a < RA; ++a) {
+      ah[a] = *reinterpret_cast<const bf16x8_t*>(Uh + ua[a] + k0);
+      al[a] = (NPASS == 3) ? *reinterpret_cast<const bf16x8_t*>(Ul + ua[a] + k0) : ah[a];
+    }
+    {
+      const int kr = tid >> 3, nc = (tid & 7) * 8;
+      const int64_t o = static_cast<int64_t>(k0 + kr) * ldc + c0 + nc;
+      const uint4 hv = *reinterpret_cast<const uint4*>(H + o);
+      const uint16_t* hs = reinterpret_cast<const uint16_t*>(&hv);
+#pragma unroll
+      for (int t = 0; t < 8; ++t) BhT[nc + t][kr] = hs[t];
+      if (NPASS == 3) {
+        const uint4 lv = *reinterpret_cast<const uint4*>(L + o);
+        const uint16_t* ls = reinterpret_cast<const uint16_t*>(&lv);
+#pragma unroll
+        for (int t = 0; t < 8; ++t) BlT[nc + t][kr] = ls[t];
+      }
+    }
+    __syncthreads();
+    const int n0 = wj * 32 + li, n1 = n0 + 16;
+    const bf16x8_t b0h = *reinterpret_cast<const bf16x8_t*>(&BhT[n0][8 * lq]);
+    const bf16x8_t b1h = *reinterpret_cast<const bf16x8_t*>(&BhT[n1][8 * lq]);
+    bf16x8_t b0l = b0h, b1l = b1h;
+    if (NPASS == 3) {
+      b0l = *reinterpret_cast<const bf16x8_t*>(&BlT[n0][8 * lq]);
+      b1l = *reinterpret_cast<const bf16x8_t*>(&BlT[n1][8 * lq]);
+    }
+#pragma unroll
+    for (int a = 0; a < RA; ++a) {
+      acc[a][0] = mfma_split<NPASS>(ah[a], al[a], b0h, b0l, acc[a][0]);
+      acc[a][1] = mfma_split<NPASS>(ah[a], al[a], b1h, b1l, acc[a][1]);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int a = 0; a < RA; ++a)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int row = r0 + wi * (RT / 2) + a * 16 + 4 * lq + v;
+      if (row < keep) {
+        const int64_t o = static_cast<int64_t>(row) * ldc + c0 + wj * 32 + li;
+        const double x0 = static_cast<double>(acc[a][0][v]), x1 = static_cast<double>(acc[a][1][v]);
+        out[o] = x0;
+        out[o + 16] = x1;
+        uint16_t hb, lb;
+        split_bits(x0, hb, lb);
+        Ho[o] = hb;
+        Lo[o] = lb;
+        split_bits(x1, hb, lb);
+        Ho[o + 16] = hb;
+        Lo[o + 16] = lb;
+      }
+    }
+}
+
 template <int NPASS, int RT>
 __global__ __launch_bounds__(256) void k_rebuild_bf16t(const double* __restrict__ Ut, const uint16_t* __restrict__ H,
                                                        const uint16_t* __restrict__ L, int ldc, int mp, int keep,
@@ -617,7 +703,7 @@ __global__ __launch_bounds__(256) void kg_rebuild_bf16(const GroupSketch* __rest
   const int64_t half = static_cast<int64_t>((s.mp + 63) / 64 * 64) * s.ldc;
   const uint16_t* H = t.cur ? s.bh1 : s.bh0;
   uint16_t* Ho = t.cur ? s.bh0 : s.bh1;
-  rebuild_bf16t_body<NPASS, RT>(s.Ut, H, H + half, s.ldc, s.mp, s.rp.keep, t.cur ? s.C0 : s.C1, blockIdx.x,
+  rebuild_bf16u_body<NPASS, RT>(s.uh, H, H + half, s.ldc, s.mp, s.rp.keep, t.cur ? s.C0 : s.C1, blockIdx.x,
                                 blockIdx.y, Ho, Ho + half);
 }
 

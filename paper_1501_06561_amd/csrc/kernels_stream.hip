@@ -130,10 +130,13 @@ __global__ void k_gram_reduce(const double* __restrict__ Gpart, int ksplit, int 
 // One workgroup.  Ranks the eigenvalues (descending, ties by index), applies
 // the variant's ReduceRank rule in FP64, updates the accumulators and writes
 // Ut = diag(rho) * U^T for the keep surviving rows, rho_j = sigma'_j/sigma_j.
+// With Uh set, Ut's rows also go out as their split-BF16 halves (hi rows in
+// Uh, lo rows mp x mp further on), for a rebuild that reads them directly.
 __device__ __forceinline__ void shrink_body(const double* __restrict__ lam_raw,
                                             const double* __restrict__ V, int m, int mp, RuleParams rp,
                                             const double* __restrict__ rownorm, int new0, int new1,
-                                            double* __restrict__ Ut, DevStats* __restrict__ st) {
+                                            double* __restrict__ Ut, DevStats* __restrict__ st,
+                                            uint16_t* __restrict__ Uh = nullptr) {
   __shared__ double lam[1024];
   __shared__ int perm[1024];
   __shared__ double rho[1024];
@@ -240,7 +243,16 @@ __device__ __forceinline__ void shrink_body(const double* __restrict__ lam_raw,
     const double r = live ? rho[q] : 0.0;
     const double* src = V + static_cast<int64_t>(live ? perm[q] : 0) * mp;
     double* dst = Ut + static_cast<int64_t>(q) * mp;
-    for (int i = lane; i < mp; i += 64) dst[i] = (live && i < m) ? r * src[i] : 0.0;
+    for (int i = lane; i < mp; i += 64) {
+      const double u = (live && i < m) ? r * src[i] : 0.0;
+      dst[i] = u;
+      if (Uh) {
+        uint16_t hb, lb;
+        split_bits(u, hb, lb);
+        Uh[static_cast<int64_t>(q) * mp + i] = hb;
+        Uh[static_cast<int64_t>(mp) * mp + static_cast<int64_t>(q) * mp + i] = lb;
+      }
+    }
   }
 }
 
@@ -559,7 +571,7 @@ __global__ __launch_bounds__(1024) void kg_shrink(const GroupSketch* __restrict_
                                                   const GroupRR* __restrict__ T) {
   const GroupRR t = T[blockIdx.x];
   const GroupSketch& s = SK[t.sk];
-  shrink_body(s.lam, s.V, s.m, s.mp, s.rp, s.rownorm, t.new0, t.new1, s.Ut, s.st);
+  shrink_body(s.lam, s.V, s.m, s.mp, s.rp, s.rownorm, t.new0, t.new1, s.Ut, s.st, s.npass ? s.uh : nullptr);
 }
 
 template <int RT>
