@@ -517,7 +517,7 @@ hipError_t tune_batch(fdsk_batch* b) {
   std::vector<GroupRR> tasks[K][2];
   for (int i = 0; i < b->S; ++i) {
     const GroupSketch& D = b->sk[i];
-    tasks[size_class(D.m)][D.npass ? 1 : 0].push_back({i, 0, 0, 0});
+    tasks[size_class(D.m)][D.npass ? 1 : 0].push_back({i, 0, 0, 0, 1});
   }
   size_t total = 0;
   for (int g = 0; g < K; ++g)
@@ -752,6 +752,7 @@ int sketch_batch_append(fdsk_batch* b, const void* const* rows, const int64_t* n
     Plan& p = plans[size_class(D.m)];
     int64_t pos = 0;
     size_t r = 0;
+    long last_rr = -1;               // round of this call's last ReduceRank of sketch i
     while (pos < n_rows[i]) {
       const int f = static_cast<int>(std::min<int64_t>(D.m - b->occ[i], n_rows[i] - pos));
       GroupIngest t;
@@ -761,18 +762,25 @@ int sketch_batch_append(fdsk_batch* b, const void* const* rows, const int64_t* n
       t.f = f;
       t.row0 = b->occ[i];
       t.cur = b->cur[i];
+      // Rows that fill the buffer are consumed by the ReduceRank that
+      // follows in this call.
+      t.w64 = (D.npass == 0 || b->occ[i] + f < D.m) ? 1 : 0;
+      t.pad = 0;
       if (p.ing.size() <= r) p.ing.resize(r + 1);
       p.ing[r].push_back(t);
       b->occ[i] += f;
       pos += f;
       if (b->occ[i] < D.m) break;
       if (p.rr.size() <= r) p.rr.resize(r + 1);
-      p.rr[r].push_back(GroupRR{i, b->cur[i], b->new0[i], D.m});
+      p.rr[r].push_back(GroupRR{i, b->cur[i], b->new0[i], D.m, D.npass == 0 ? 1 : 0});
+      last_rr = static_cast<long>(r);
       b->cur[i] ^= 1;
       b->occ[i] = D.rp.keep;
       b->new0[i] = D.rp.keep;
       ++r;
     }
+    // The last ReduceRank's rows may be copied out by finalize.
+    if (last_rr >= 0) p.rr[last_rr].back().w64 = 1;
     b->rows_in[i] += n_rows[i];
   }
   const int rc = run_class_plans(b, plans, static_cast<int>(dtype), grid_size > 0 ? grid_size : b->S);
@@ -808,7 +816,7 @@ int sketch_batch_finalize(fdsk_batch* b, void* const* B_out, const int64_t* ldb,
   for (int i = 0; i < b->S; ++i) {
     const GroupSketch& D = b->sk[i];
     if (b->occ[i] > D.l) {
-      p.rr[0].push_back(GroupRR{i, b->cur[i], b->new0[i], b->occ[i]});
+      p.rr[0].push_back(GroupRR{i, b->cur[i], b->new0[i], b->occ[i], 1});
       b->cur[i] ^= 1;
       b->occ[i] = D.rp.keep;
       b->new0[i] = D.rp.keep;

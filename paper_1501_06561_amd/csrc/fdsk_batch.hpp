@@ -41,14 +41,19 @@ struct GroupSketch {
   RuleParams rp;
 };
 
+// w64: write the FP64 rows too.  A split-BF16 sketch's products read only
+// the bf16 halves, so its FP64 rows are needed only where finalize may copy
+// them out: rows that no later ReduceRank of the same append call consumes.
+// The host knows which those are (the schedule does not depend on the
+// data); FP64 sketches always write them.
 struct GroupIngest {      // f rows of src (leading dimension stride) into rows row0.. of C[cur]
   const void* src;
   int64_t stride;
-  int sk, f, row0, cur;
+  int sk, f, row0, cur, w64, pad;
 };
 
 struct GroupRR {          // a ReduceRank of sketch sk on C[cur]; rows [new0, new1) are new
-  int sk, cur, new0, new1;
+  int sk, cur, new0, new1, w64;   // w64: the rebuild writes its FP64 rows
 };
 
 struct GroupSpan {        // rows [r0, r1) of C[cur] (zeroing, pending norms)

@@ -362,7 +362,7 @@ template <int NPASS, int RT>
 __device__ __forceinline__ void rebuild_bf16u_body(const uint16_t* __restrict__ Uh, const uint16_t* __restrict__ H,
                                                    const uint16_t* __restrict__ L, int ldc, int mp, int keep,
                                                    double* __restrict__ out, int bx, int by,
-                                                   uint16_t* __restrict__ Ho, uint16_t* __restrict__ Lo) {
+                                                   uint16_t* __restrict__ Ho, uint16_t* __restrict__ Lo, bool w64) {
   static_assert(RT == 32 || RT == 64, "rebuild rows per workgroup");
   constexpr int RA = RT / 32;
   const int r0 = by * RT, c0 = bx * 64;
@@ -425,8 +425,10 @@ __device__ __forceinline__ void rebuild_bf16u_body(const uint16_t* __restrict__ 
       if (row < keep) {
         const int64_t o = static_cast<int64_t>(row) * ldc + c0 + wj * 32 + li;
         const double x0 = static_cast<double>(acc[a][0][v]), x1 = static_cast<double>(acc[a][1][v]);
-        out[o] = x0;
-        out[o + 16] = x1;
+        if (w64) {
+          out[o] = x0;
+          out[o + 16] = x1;
+        }
         uint16_t hb, lb;
         split_bits(x0, hb, lb);
         Ho[o] = hb;
@@ -704,7 +706,7 @@ __global__ __launch_bounds__(256) void kg_rebuild_bf16(const GroupSketch* __rest
   const uint16_t* H = t.cur ? s.bh1 : s.bh0;
   uint16_t* Ho = t.cur ? s.bh0 : s.bh1;
   rebuild_bf16u_body<NPASS, RT>(s.uh, H, H + half, s.ldc, s.mp, s.rp.keep, t.cur ? s.C0 : s.C1, blockIdx.x,
-                                blockIdx.y, Ho, Ho + half);
+                                blockIdx.y, Ho, Ho + half, t.w64 != 0);
 }
 
 hipError_t launch_group_gram_lowp(const GroupSketch* sk, const GroupRR* t, int nt, int max_mp, int max_ldc,

@@ -19,14 +19,14 @@ __device__ __forceinline__ void ingest_body(const void* __restrict__ src, int dt
                                             double* __restrict__ C, int ldc, int row0,
                                             double* __restrict__ rownorm, int i,
                                             uint16_t* __restrict__ H = nullptr,
-                                            uint16_t* __restrict__ L = nullptr) {
+                                            uint16_t* __restrict__ L = nullptr, bool w64 = true) {
   const int64_t base = static_cast<int64_t>(i) * stride;
   const int64_t ro = static_cast<int64_t>(row0 + i) * ldc;
   double* dst = C + ro;
   double acc = 0.0;
   for (int c = threadIdx.x; c < ldc; c += blockDim.x) {
     double v = (c < d) ? load_as_f64(src, base + c, dt) : 0.0;
-    dst[c] = v;
+    if (w64) dst[c] = v;
     acc += v * v;
     if (H) {
       uint16_t hb, lb;
@@ -542,7 +542,8 @@ __global__ __launch_bounds__(256) void kg_ingest(const GroupSketch* __restrict__
   const GroupSketch& s = SK[t.sk];
   uint16_t* H = s.npass ? (t.cur ? s.bh1 : s.bh0) : nullptr;
   uint16_t* L = H ? H + static_cast<int64_t>((s.mp + 63) / 64 * 64) * s.ldc : nullptr;
-  ingest_body(t.src, dt, t.stride, s.d, t.cur ? s.C1 : s.C0, s.ldc, t.row0, s.rownorm, blockIdx.x, H, L);
+  ingest_body(t.src, dt, t.stride, s.d, t.cur ? s.C1 : s.C0, s.ldc, t.row0, s.rownorm, blockIdx.x, H, L,
+              t.w64 != 0 || s.npass == 0);
 }
 
 // Split-K: K slice blockIdx.y of the task's slice length (task_kchunk) into

@@ -218,3 +218,64 @@ def test_batch_profile_covers_every_stage():
             assert work > 0, stage
     if any(2 * c["l"] > 208 for c in cfgs):    # buffers above 208 rows: the packed-triangle head
         assert prof["tridiag_head"][1] > 0
+
+
+def test_batch_bf16x3_append_calls_match_one_call():
+    """Split-BF16 sketches keep FP64 rows only where finalize may copy them
+    out (rows no later ReduceRank of the same append call consumes).  Row
+    counts per call chosen so that calls end right after a ReduceRank, on an
+    exact buffer fill, in the middle of a fill, and so that finalize both
+    reduces once more (more than l rows held) and copies the rows as they
+    are (at most l held): every split gives the bits of one call."""
+    shapes = [(96, 20), (130, 33), (64, 8), (200, 50)]
+    cfgs, mats = [], []
+    for i, (d, l) in enumerate(shapes):
+        A = synth.to_bf16(synth.random_noisy(6 * l + 7 + i, d, max(1, l // 2), 10.0, seed=(64, i)))
+        cfgs.append(dict(d=d, l=l, variant="fd", alpha=0.2, precision="bf16x3"))
+        mats.append(A.astype(np.float64))
+    ref = None
+    for mode in ("one call", "chunks of l + 1", "exact fills"):
+        b = F.FDSketchBatch(cfgs)
+        tens = [torch.from_numpy(A).cuda() for A in mats]
+        if mode == "one call":
+            cuts = [[0, A.shape[0]] for A in mats]
+        elif mode == "chunks of l + 1":
+            cuts = [list(range(0, A.shape[0], l + 1)) + [A.shape[0]] for (d, l), A in zip(shapes, mats)]
+        else:
+            # 2l rows (an exact fill), then l + 1 (another exact fill), then the rest
+            cuts = [[0, 2 * l, 3 * l + 1, A.shape[0]] for (d, l), A in zip(shapes, mats)]
+        for c in range(max(len(x) for x in cuts) - 1):
+            b.append([t[x[c]:x[c + 1]] if c + 1 < len(x) else None for t, x in zip(tens, cuts)])
+        outs = [o.cpu().numpy() for o in b.finalize()]
+        b.close()
+        if ref is None:
+            ref = outs
+        else:
+            for a, o in zip(ref, outs):
+                assert np.array_equal(a, o), mode
+    for cfg, A, B in zip(cfgs, mats, ref):
+        Bo = oracle.fd_sketch(A, cfg["l"], "fd")
+        ce, co = oracle.cov_err(A, B), oracle.cov_err(A, Bo)
+        assert abs(ce - co) <= 1e-4, (cfg, ce, co)
+
+
+def test_batch_bf16x3_finalize_without_a_last_reduction():
+    """At most l rows held at finalize (no last ReduceRank): the FP64 rows
+    copied out are the last ReduceRank's rows and the rows appended after
+    it, split over several calls."""
+    d, l = 120, 16
+    A = synth.to_bf16(synth.random_noisy(2 * l + 1, d, 6, 10.0, seed=(65, 0))).astype(np.float64)
+    cfg = [dict(d=d, l=l, variant="fd", alpha=0.2, precision="bf16x3")]
+    # 2l rows: one ReduceRank, l - 1 rows kept; then 1 more row: l rows held.
+    b = F.FDSketchBatch(cfg)
+    t = torch.from_numpy(A).cuda()
+    b.append([t[:2 * l]])
+    b.append([t[2 * l:]])
+    B = b.finalize()[0].cpu().numpy()
+    st = b.stats(0)
+    b.close()
+    Bo, so = oracle.fd_sketch(A, l, "fd", return_state=True)
+    assert st["n_reduce"] == so.n_rr == 1
+    assert np.array_equal(B[l - 1], A[2 * l])     # the row appended after the reduction, as given
+    ce, co = oracle.cov_err(A, B), oracle.cov_err(A, Bo)
+    assert abs(ce - co) <= 1e-4, (ce, co)
