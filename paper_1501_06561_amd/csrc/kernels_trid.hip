@@ -1422,19 +1422,44 @@ __device__ __forceinline__ void backtr_wy_body(const double* __restrict__ W, int
     }
   }
   const int nref = n - 2;
-  for (int k0 = ((nref - 1) / 16) * 16; nref > 0 && k0 >= 0; k0 -= 16) {
-    const int rlo = (k0 + 1) / 16;     // first row tile holding a nonzero of V
-    // Stage V (rows 16 rlo .. 16 rt; consecutive threads read consecutive
-    // rows of one packed column) and tau.
-    const int rows = 16 * (rt - rlo);
-    for (int e = tid; e < 16 * rows; e += NT) {
-      const int q = e / rows, i = 16 * rlo + e % rows, k = k0 + q;
+  // A block's V (rows 16 rlo .. 16 rt, consecutive threads on consecutive
+  // rows of one packed column) and tau, fetched into registers one block
+  // ahead: the next block's loads are in flight while this block's products
+  // run, and are stored to LDS after them.
+  constexpr int PRE = (256 * RTM + NT - 1) / NT;
+  double pre[PRE];
+  double pre_tau = 0.0;
+  auto fetch = [&](int kb) {
+    const int rl = (kb + 1) / 16, rows = 16 * (rt - rl);
+#pragma unroll
+    for (int j = 0; j < PRE; ++j) {
+      const int e = tid + j * NT;
       double v = 0.0;
-      if (k < nref && i < n) v = (i == k + 1) ? 1.0 : (i > k + 1 ? W[colstart(k, n) + i - k] : 0.0);
-      Vs[i][q] = v;
+      if (e < 16 * rows) {
+        const int q = e / rows, i = 16 * rl + e % rows, k = kb + q;
+        if (k < nref && i < n) v = (i == k + 1) ? 1.0 : (i > k + 1 ? W[colstart(k, n) + i - k] : 0.0);
+      }
+      pre[j] = v;
     }
-    if (tid < 16) tau_s[tid] = (k0 + tid < nref) ? W[P + k0 + tid] : 0.0;
-    __syncthreads();
+    if (tid < 16) pre_tau = (kb + tid < nref) ? W[P + kb + tid] : 0.0;
+  };
+  auto store = [&](int kb) {
+    const int rl = (kb + 1) / 16, rows = 16 * (rt - rl);
+#pragma unroll
+    for (int j = 0; j < PRE; ++j) {
+      const int e = tid + j * NT;
+      if (e < 16 * rows) Vs[16 * rl + e % rows][e / rows] = pre[j];
+    }
+    if (tid < 16) tau_s[tid] = pre_tau;
+  };
+  const int kfirst = ((nref - 1) / 16) * 16;
+  if (nref > 0) {
+    fetch(kfirst);
+    store(kfirst);
+  }
+  __syncthreads();
+  for (int k0 = kfirst; nref > 0 && k0 >= 0; k0 -= 16) {
+    const int rlo = (k0 + 1) / 16;     // first row tile holding a nonzero of V
     // G = V^T V on matrix cores: each wave sums its share of the row tiles
     // (A = V^T and B = V take the same value per lane), then the partials
     // are added in wave order.
@@ -1479,14 +1504,19 @@ __device__ __forceinline__ void backtr_wy_body(const double* __restrict__ W, int
       for (int i = 0; i < 16; ++i) Ts[j][i] = trow[i];
     }
     __syncthreads();
-    // Wt = V^T Z, Yt = T Wt, Z -= V Yt.
-    f64x4 Wt = {0.0, 0.0, 0.0, 0.0};
+    if (k0 >= 16) fetch(k0 - 16);
+    // Wt = V^T Z, Yt = T Wt, Z -= V Yt.  Four partial Wt (one per K slice
+    // of a row tile) keep four products in flight.
+    f64x4 Wp[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) Wp[u] = f64x4{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
     for (int r = 0; r < RTM; ++r)
       if (r >= rlo && r < rt) {
 #pragma unroll
-        for (int u = 0; u < 4; ++u) Wt = mfma_f64(Vs[16 * r + 4 * u + lk][li], Zt[r][u], Wt);
+        for (int u = 0; u < 4; ++u) Wp[u] = mfma_f64(Vs[16 * r + 4 * u + lk][li], Zt[r][u], Wp[u]);
       }
+    const f64x4 Wt = (Wp[0] + Wp[1]) + (Wp[2] + Wp[3]);
     f64x4 Yt = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
     for (int u = 0; u < 4; ++u) Yt = mfma_f64(Ts[li][4 * u + lk], Wt[u], Yt);
@@ -1497,6 +1527,10 @@ __device__ __forceinline__ void backtr_wy_body(const double* __restrict__ W, int
         for (int u = 0; u < 4; ++u) Zt[r] = mfma_f64(-Vs[16 * r + li][4 * u + lk], Yt[u], Zt[r]);
       }
     __syncthreads();
+    if (k0 >= 16) {
+      store(k0 - 16);
+      __syncthreads();
+    }
   }
   if (col >= 0) {
 #pragma unroll
