@@ -50,15 +50,27 @@ __device__ __forceinline__ double dpp_f64(double v, double old) {
                               static_cast<long long>(static_cast<unsigned>(lo)));
 }
 
+// The same move for a control that writes every lane (a quad permutation or
+// a row mirror, all rows and banks enabled): no lane keeps an old value, so
+// none is supplied and the compiler does not have to initialise one.
+template <int CTRL>
+__device__ __forceinline__ double dpp_perm_f64(double v) {
+  const long long u = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_mov_dpp(static_cast<int>(u), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_mov_dpp(static_cast<int>(u >> 32), CTRL, 0xF, 0xF, false);
+  return __longlong_as_double((static_cast<long long>(hi) << 32) |
+                              static_cast<long long>(static_cast<unsigned>(lo)));
+}
+
 // Sum over each quad of lanes (4i .. 4i+3); every lane of the quad gets it.
 __device__ __forceinline__ double quad_sum(double v) {
-  v += dpp_f64<0xB1>(v, 0.0);   // quad_perm [1,0,3,2]
-  v += dpp_f64<0x4E>(v, 0.0);   // quad_perm [2,3,0,1]
+  v += dpp_perm_f64<0xB1>(v);   // quad_perm [1,0,3,2]
+  v += dpp_perm_f64<0x4E>(v);   // quad_perm [2,3,0,1]
   return v;
 }
 __device__ __forceinline__ double quad_prod(double v) {
-  v *= dpp_f64<0xB1>(v, 1.0);
-  v *= dpp_f64<0x4E>(v, 1.0);
+  v *= dpp_perm_f64<0xB1>(v);
+  v *= dpp_perm_f64<0x4E>(v);
   return v;
 }
 
@@ -67,8 +79,8 @@ __device__ __forceinline__ double quad_prod(double v) {
 // 16 results are bitwise equal).
 __device__ __forceinline__ double row16_sum(double v) {
   v = quad_sum(v);
-  v += dpp_f64<0x141>(v, 0.0);          // row_half_mirror
-  v += dpp_f64<0x140>(v, 0.0);          // row_mirror
+  v += dpp_perm_f64<0x141>(v);          // row_half_mirror
+  v += dpp_perm_f64<0x140>(v);          // row_mirror
   return v;
 }
 
@@ -77,8 +89,8 @@ __device__ __forceinline__ double row16_sum(double v) {
 // broadcasts accumulate the rows into lane 63, which is read back.
 __device__ __forceinline__ double wave_sum(double v) {
   v = quad_sum(v);
-  v += dpp_f64<0x141>(v, 0.0);          // row_half_mirror
-  v += dpp_f64<0x140>(v, 0.0);          // row_mirror
+  v += dpp_perm_f64<0x141>(v);          // row_half_mirror
+  v += dpp_perm_f64<0x140>(v);          // row_mirror
   v += dpp_f64<0x142, 0xA>(v, 0.0);     // row_bcast:15 into rows 1 and 3
   v += dpp_f64<0x143, 0xC>(v, 0.0);     // row_bcast:31 into rows 2 and 3
   const long long u = __double_as_longlong(v);

@@ -390,9 +390,15 @@ __global__ __launch_bounds__(HNT) void k_tridiag(const double* __restrict__ G, i
 //  * every wave forms c = (tau/2) p.v, then each thread applies
 //    A -= v w^T + w v^T to its own elements, w = p - c v, with no LDS
 //    traffic for A; the owners of column k+1 store it for the next step.
-// Two barriers per column.  Slots whose rows (per wave) or columns (for all
-// lanes) lie entirely in the finished part are skipped; v and w are zero
-// outside the trailing block, so partially finished slots need no masking.
+// Two barriers per column.  Column slots b < k1/16 hold finished columns
+// only and are skipped.  The columns are taken in groups of 16 with the
+// same first live slot B0, and each group is its own instantiation, so the
+// slot loops carry no per-column tests: the product reads its slots of v at
+// once, the update streams (v, p) three slots ahead.  Elements of finished
+// rows (and the finished columns of slot B0) take meaningless but finite
+// values: a finished row i has v_i = 0, so it is only multiplied by the
+// reflector (A_i <- A_i - tau (A_i v) v^T), and every later v is zero on
+// finished columns, so those elements are only ever multiplied by zero.
 // With h > 0 the kernel continues a reduction that k_tridiag took through
 // columns [0, h): it loads the trailing (ng-h) x (ng-h) block, already
 // scaled, from W's packed triangle and writes reflectors h.. in place.
@@ -400,14 +406,167 @@ constexpr int RNT = 512;
 constexpr int kTridRegMax = 208;   // 32 * 7 rows, 16 * 13 columns
 
 template <int RP, int CP>
+struct RegTrid {
+  static constexpr int NB = (32 * RP > 16 * CP) ? 32 * RP : 16 * CP;
+  static constexpr int NL = (NB + 63) / 64;    // strided entries per lane
+  double* colb0;    // column k (k even) / k+1 (k odd), 64 NL rows
+  double* colb1;
+  double* pv;       // p = tau A v
+  double* vv;       // this wave's copy of v
+  double* dsh;      // d, e and tau of each column, written out at the end
+  double* esh;
+  double* tsh;
+  double* W;        // packed reflectors (column h + k at colstart(h + k, ng))
+  int n, ng, h, bend, ti, tk, lane, wv;
+};
+
+// Columns k in [kb, ke) (all with k+1 in slot B0).
+template <int RP, int CP, int B0>
+__device__ __forceinline__ void tridiag_reg_cols(const RegTrid<RP, CP>& c, double (&A)[RP][CP], int kb,
+                                                 int ke) {
+  constexpr int NL = RegTrid<RP, CP>::NL;
+  constexpr int NS = CP - B0;        // live slots
+  constexpr int PF = NS < 3 ? NS : 3;  // update prefetch distance
+  const int lane = c.lane, wv = c.wv, ti = c.ti, tk = c.tk, n = c.n;
+  double* const vv = c.vv;
+  double* const pv = c.pv;
+  for (int k = kb; k < ke; ++k) {
+    const double* cb = (k & 1) ? c.colb1 : c.colb0;
+    double* nb = (k & 1) ? c.colb0 : c.colb1;
+    const int k1 = k + 1, tk1 = k1 & 15;
+    double xs[NL];
+#pragma unroll
+    for (int q = 0; q < NL; ++q) xs[q] = cb[lane + 64 * q];
+    const double alpha = cb[k1];
+    double s2 = 0.0;
+#pragma unroll
+    for (int q = 0; q < NL; ++q) {
+      const double x = (lane + 64 * q >= k + 2) ? xs[q] : 0.0;
+      s2 = fma(x, x, s2);
+    }
+    s2 = wave_sum(s2);
+    double tau = 0.0, beta = alpha, scale = 0.0;
+    if (s2 > 0.0) {
+      const double mu = sqrt(alpha * alpha + s2);
+      beta = (alpha >= 0.0) ? -mu : mu;
+      tau = (beta - alpha) / beta;
+      scale = 1.0 / (alpha - beta);
+    }
+    // This wave's copy of v: 0 up to k, 1 at k+1, x*scale below (0 beyond n,
+    // where x = 0).  LDS operations of one wave complete in order, so the
+    // wave reads its copy back after a wave barrier only (which keeps the
+    // compiler from moving the reads above the writes).
+#pragma unroll
+    for (int q = 0; q < NL; ++q) {
+      const int t = lane + 64 * q;
+      vv[t] = (t > k1) ? xs[q] * scale : ((t == k1) ? 1.0 : 0.0);
+    }
+    __builtin_amdgcn_wave_barrier();
+    // The reflector's entries below the subdiagonal: wave q stores rows
+    // lane + 64 q (every wave holds the same values).
+    {
+      const int ck = colstart(c.h + k, c.ng);
+#pragma unroll
+      for (int q = 0; q < NL; ++q) {
+        const int t = lane + 64 * q;
+        if (wv == q && t >= k + 2 && t < n) c.W[ck + t - k] = xs[q] * scale;
+      }
+    }
+    if (wv == RNT / 64 - 1 && lane == 0) {
+      c.dsh[k] = cb[k];
+      c.esh[k] = beta;
+      c.tsh[k] = tau;
+    }
+    if (tau != 0.0) {                  // the same in every wave
+      // p = tau A v over the live slots (v is zero on finished columns).
+      double vk[NS];
+#pragma unroll
+      for (int j = 0; j < NS; ++j) vk[j] = vv[tk + 16 * (B0 + j)];
+      double sp[RP];
+#pragma unroll
+      for (int a = 0; a < RP; ++a) sp[a] = 0.0;
+#pragma unroll
+      for (int j = 0; j < NS; ++j) {
+        if (B0 + j < c.bend) {
+#pragma unroll
+          for (int a = 0; a < RP; ++a) sp[a] = fma(A[a][B0 + j], vk[j], sp[a]);
+        }
+      }
+#pragma unroll
+      for (int a = 0; a < RP; ++a) {
+        const double t = row16_sum(sp[a]);
+        if (tk == 0) pv[ti + 32 * a] = tau * t;
+      }
+      __syncthreads();
+      // c = (tau/2) p.v (v is zero up to k and beyond n).
+      double dot = 0.0;
+#pragma unroll
+      for (int q = 0; q < NL; ++q) dot = fma(pv[lane + 64 * q], vv[lane + 64 * q], dot);
+      dot = wave_sum(dot);
+      const double cc = 0.5 * tau * dot;
+      // A -= v w^T + w v^T with w = p - c v.
+      double vr[RP], wr[RP];
+#pragma unroll
+      for (int a = 0; a < RP; ++a) {
+        vr[a] = vv[ti + 32 * a];
+        wr[a] = pv[ti + 32 * a];
+      }
+#pragma unroll
+      for (int a = 0; a < RP; ++a) wr[a] = fma(-cc, vr[a], wr[a]);
+      double nv[PF], np[PF];
+#pragma unroll
+      for (int j = 0; j < PF; ++j) {
+        nv[j] = vv[tk + 16 * (B0 + j)];
+        np[j] = pv[tk + 16 * (B0 + j)];
+      }
+#pragma unroll
+      for (int j = 0; j < NS; ++j) {
+        const double vk1 = nv[j % PF], pk1 = np[j % PF];
+        if (j + PF < NS) {
+          nv[j % PF] = vv[tk + 16 * (B0 + j + PF)];
+          np[j % PF] = pv[tk + 16 * (B0 + j + PF)];
+        }
+        if (B0 + j < c.bend) {
+          const double wk = fma(-cc, vk1, pk1);
+#pragma unroll
+          for (int a = 0; a < RP; ++a) A[a][B0 + j] = fma(-vr[a], wk, fma(-wr[a], vk1, A[a][B0 + j]));
+        }
+        if (j == 0 && tk == tk1) {
+#pragma unroll
+          for (int a = 0; a < RP; ++a) nb[ti + 32 * a] = A[a][B0];
+        }
+      }
+    } else {
+      if (tk == tk1) {
+#pragma unroll
+        for (int a = 0; a < RP; ++a) nb[ti + 32 * a] = A[a][B0];
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// Slot groups B0, B0+1, ..: the columns k with (k+1)/16 == B0.
+template <int RP, int CP, int B0>
+__device__ __forceinline__ void tridiag_reg_groups(const RegTrid<RP, CP>& c, double (&A)[RP][CP]) {
+  if constexpr (B0 < CP) {
+    const int kb = max(0, 16 * B0 - 1), ke = min(c.n - 2, 16 * B0 + 15);
+    if (kb >= ke) return;
+    tridiag_reg_cols<RP, CP, B0>(c, A, kb, ke);
+    tridiag_reg_groups<RP, CP, B0 + 1>(c, A);
+  }
+}
+
+template <int RP, int CP>
 __device__ __forceinline__ void tridiag_reg_body(const double* __restrict__ G, int ng, int ldg,
                                                  double* __restrict__ W, int h) {
+  using C = RegTrid<RP, CP>;
+  constexpr int NL = C::NL;
   const int n = ng - h;                 // order of the block reduced here
-  constexpr int NB = (32 * RP > 16 * CP) ? 32 * RP : 16 * CP;
-  constexpr int NL = (NB + 63) / 64;    // strided entries per lane
   __shared__ double colb[2][64 * NL];
   __shared__ double pv[64 * NL];
   __shared__ double vwave[RNT / 64][64 * NL];   // each wave's copy of v
+  __shared__ double dsh[64 * NL], esh[64 * NL], tsh[64 * NL];
   __shared__ double red[RNT / 64];
   // The wave index is made a scalar so that the slot tests below are
   // uniform branches.
@@ -460,133 +619,33 @@ __device__ __forceinline__ void tridiag_reg_body(const double* __restrict__ G, i
   double* tauG = W + P;
   double* dG = tauG + ng;
   double* eG = dG + ng;
-  // Column slots b < bend hold a column < n.
-  const int bend = (n + 15) >> 4;
-  double* const vv = vwave[wv];
-  for (int k = 0; k + 2 < n; ++k) {
-    const double* cb = colb[k & 1];
-    double* nb = colb[(k + 1) & 1];
-    const int k1 = k + 1, b1 = k1 >> 4, tk1 = k1 & 15;
-    // Column slots b >= b0 hold a column > k.  Every row slot is processed
-    // (a per-slot row test would become a select per element).
-    const int b0 = k1 >> 4;
-    double xs[NL];
-#pragma unroll
-    for (int q = 0; q < NL; ++q) xs[q] = cb[lane + 64 * q];
-    const double alpha = cb[k1];
-    double s2 = 0.0;
-#pragma unroll
-    for (int q = 0; q < NL; ++q) {
-      const double x = (lane + 64 * q >= k + 2) ? xs[q] : 0.0;
-      s2 = fma(x, x, s2);
-    }
-    s2 = wave_sum(s2);
-    double tau = 0.0, beta = alpha, scale = 0.0;
-    if (s2 > 0.0) {
-      const double mu = sqrt(alpha * alpha + s2);
-      beta = (alpha >= 0.0) ? -mu : mu;
-      tau = (beta - alpha) / beta;
-      scale = 1.0 / (alpha - beta);
-    }
-    // This wave's copy of v: 0 up to k, 1 at k+1, x*scale below (0 beyond n,
-    // where x = 0).  LDS operations of one wave complete in order, so the
-    // wave reads its copy back after a wave barrier only (which keeps the
-    // compiler from moving the reads above the writes).
-#pragma unroll
-    for (int q = 0; q < NL; ++q) {
-      const int t = lane + 64 * q;
-      vv[t] = (t > k1) ? xs[q] * scale : ((t == k1) ? 1.0 : 0.0);
-    }
-    __builtin_amdgcn_wave_barrier();
-    if (wv == 0) {
-      const int ck = colstart(h + k, ng);
-#pragma unroll
-      for (int q = 0; q < NL; ++q) {
-        const int t = lane + 64 * q;
-        if (t >= k + 2 && t < n) W[ck + t - k] = xs[q] * scale;
-      }
-      if (lane == 0) {
-        W[ck] = cb[k];
-        W[ck + 1] = 1.0;
-        tauG[h + k] = tau;
-        dG[h + k] = cb[k];
-        eG[h + k] = beta;
-      }
-    }
-    if (tau != 0.0) {                  // the same in every wave
-      // p = tau A v over the trailing block (v is zero on finished columns).
-      // Elements of finished rows and columns are updated below with
-      // meaningless values; they are never read again, as every later v is
-      // zero there.  The next slot's v is fetched before this slot's FMAs.
-      double sp[RP];
-#pragma unroll
-      for (int a = 0; a < RP; ++a) sp[a] = 0.0;
-      double nvk = vv[tk + 16 * b0];
-#pragma unroll
-      for (int b = 0; b < CP; ++b) {
-        if (b >= b0 && b < bend) {
-          const double vk = nvk;
-          if (b + 1 < CP) nvk = vv[tk + 16 * (b + 1)];
-#pragma unroll
-          for (int a = 0; a < RP; ++a) sp[a] = fma(A[a][b], vk, sp[a]);
-        }
-      }
-#pragma unroll
-      for (int a = 0; a < RP; ++a) {
-        const double t = row16_sum(sp[a]);
-        const int i = ti + 32 * a;
-        if (tk == 0 && i > k && i < n) pv[i] = tau * t;
-      }
-      __syncthreads();
-      // c = (tau/2) p.v (v is zero up to k; p is zero beyond n).
-      double dot = 0.0;
-#pragma unroll
-      for (int q = 0; q < NL; ++q) dot = fma(pv[lane + 64 * q], vv[lane + 64 * q], dot);
-      dot = wave_sum(dot);
-      const double c = 0.5 * tau * dot;
-      // A -= v w^T + w v^T with w = p - c v.
-      double vr[RP], wr[RP];
-#pragma unroll
-      for (int a = 0; a < RP; ++a) {
-        vr[a] = vv[ti + 32 * a];
-        wr[a] = pv[ti + 32 * a];
-      }
-#pragma unroll
-      for (int a = 0; a < RP; ++a) wr[a] = fma(-c, vr[a], wr[a]);
-      double nv = vv[tk + 16 * b0], np = pv[tk + 16 * b0];
-#pragma unroll
-      for (int b = 0; b < CP; ++b) {
-        if (b >= b0 && b < bend) {
-          const double vk = nv;
-          const double wk = fma(-c, vk, np);
-          if (b + 1 < CP) {
-            nv = vv[tk + 16 * (b + 1)];
-            np = pv[tk + 16 * (b + 1)];
-          }
-#pragma unroll
-          for (int a = 0; a < RP; ++a) A[a][b] = fma(-vr[a], wk, fma(-wr[a], vk, A[a][b]));
-          if (b == b1 && tk == tk1) {
-#pragma unroll
-            for (int a = 0; a < RP; ++a) {
-              const int i = ti + 32 * a;
-              if (i >= k1 && i < n) nb[i] = A[a][b];
-            }
-          }
-        }
-      }
-    } else {
-#pragma unroll
-      for (int b = 0; b < CP; ++b) {
-        if (b == b1 && tk == tk1) {
-#pragma unroll
-          for (int a = 0; a < RP; ++a) {
-            const int i = ti + 32 * a;
-            if (i >= k1 && i < n) nb[i] = A[a][b];
-          }
-        }
-      }
-    }
-    __syncthreads();
+  C c;
+  c.colb0 = colb[0];
+  c.colb1 = colb[1];
+  c.pv = pv;
+  c.vv = vwave[wv];
+  c.dsh = dsh;
+  c.esh = esh;
+  c.tsh = tsh;
+  c.W = W;
+  c.n = n;
+  c.ng = ng;
+  c.h = h;
+  c.bend = (n + 15) >> 4;               // column slots b < bend hold a column < n
+  c.ti = ti;
+  c.tk = tk;
+  c.lane = lane;
+  c.wv = wv;
+  tridiag_reg_groups<RP, CP, 0>(c, A);
+  // d, e and tau of columns [0, n-2), and each packed column's head
+  // (diagonal entry, then the reflector's leading 1).
+  for (int k = tid; k < n - 2; k += RNT) {
+    const int ck = colstart(h + k, ng);
+    W[ck] = dsh[k];
+    W[ck + 1] = 1.0;
+    dG[h + k] = dsh[k];
+    eG[h + k] = esh[k];
+    tauG[h + k] = tsh[k];
   }
   // Column n-2 is in colb[(n-2) & 1] (n >= 2); A(n-1, n-1) is with its owner.
   if (tid == 0) {
