@@ -32,15 +32,21 @@ def _check_eigh(Gm, tol=1e-11, method="auto"):
     return lam, V
 
 
+# Orders at the edges of the register reduction's column groups (16 columns
+# each, the last column k with k + 2 < m) and of its instances (64, 128, 192,
+# 208 rows).
+GROUP_EDGES = [4, 5, 17, 18, 19, 31, 32, 34, 48, 49, 50, 65, 66, 97, 113, 129, 145, 161, 177, 192, 193, 207]
+
+
 @pytest.mark.parametrize("method", ["auto", "jacobi"])
 @pytest.mark.parametrize("m", [1, 2, 3, 7, 33, 40, 64, 99, 100, 101, 128, 199, 200, 201, 208, 209, 230, 256, 257,
-                               333, 400, 512, 513, 777, 1024])
+                               333, 400, 512, 513, 777, 1024] + GROUP_EDGES)
 def test_eigh_random_psd(m, method):
     """"auto" is the tridiagonal divide-and-conquer route at every m (the
-    matrix in registers up to 208; up to 512 the first m - 208 columns on the
-    packed triangle in the workspace, the rest in registers; above 512 the
+    matrix in registers up to 208; up to 256 the first m - 208 columns on the
+    packed triangle in the workspace, the rest in registers; above 256 the
     full matrix in the workspace, two launches per column)."""
-    if method == "jacobi" and m in (3, 33, 64, 199, 201, 208, 209, 230, 257, 400, 777):
+    if method == "jacobi" and m in [3, 33, 64, 199, 201, 208, 209, 230, 257, 400, 777] + GROUP_EDGES:
         pytest.skip("sizes added for the divide-and-conquer route")
     rng = np.random.default_rng(m)
     X = rng.standard_normal((m, 2 * m + 3)) * np.geomspace(1, 1e-3, 2 * m + 3)
@@ -48,9 +54,9 @@ def test_eigh_random_psd(m, method):
 
 
 @pytest.mark.parametrize("method", ["auto", "jacobi"])
-@pytest.mark.parametrize("m", [40, 160, 200, 256, 400, 700])
+@pytest.mark.parametrize("m", [17, 40, 130, 160, 200, 256, 400, 700])
 def test_eigh_special_matrices(m, method):
-    if method == "jacobi" and m in (400, 700):
+    if method == "jacobi" and m in (17, 130, 400, 700):
         pytest.skip("size added for the divide-and-conquer route")
     rng = np.random.default_rng(m + 1)
     _check_eigh(np.diag(rng.uniform(0, 5, m)), method=method)       # already diagonal
