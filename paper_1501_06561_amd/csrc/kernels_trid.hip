@@ -1806,13 +1806,11 @@ hipError_t launch_tridiag(const double* G, int m, int mp, EigWork wk, hipStream_
     hipLaunchKernelGGL((k_tridiag_reg<7, 13>), dim3(1), dim3(RNT), 0, s, G, m, mp, wk.W, 0);
   else {
     // The first m - kTridRegMax columns on the packed triangle in W, the
-    // rest in registers.
+    // rest in registers (m <= kTridLargeMin = 256 = 64 * 4 rows here).
     if (m > kTridLargeMin) return launch_tridiag_large(G, m, mp, wk, s);
+    static_assert(kTridLargeMin <= 64 * 4, "the head's instance holds 256 rows");
     const int h = m - kTridRegMax;
-    if (m <= 256)
-      hipLaunchKernelGGL(k_tridiag<4>, dim3(1), dim3(HNT), 0, s, G, m, mp, wk.W, h);
-    else
-      hipLaunchKernelGGL(k_tridiag<8>, dim3(1), dim3(HNT), 0, s, G, m, mp, wk.W, h);
+    hipLaunchKernelGGL(k_tridiag<4>, dim3(1), dim3(HNT), 0, s, G, m, mp, wk.W, h);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL((k_tridiag_reg<7, 13>), dim3(1), dim3(RNT), 0, s, G, m, mp, wk.W, h);
